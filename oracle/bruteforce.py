@@ -1,0 +1,214 @@
+"""Brute-force references for tiny maps (<= ~12x12), used to pin the oracle.
+
+TEST INFRASTRUCTURE ONLY.  Written independently of ni_oracle.py: scalar
+Python loops over pixels and edges, explicit stacked *directed rows* exactly
+as the paper writes the systems (A_c, b_c, W_c of Eq. 14 and the quotient
+A_m, b_m, W_m of Eq. 16), dense minimum-norm least squares, and transitive
+closure for connectivity.  Different formulation, different code: a wrong
+sign, index or transposition in the oracle's vectorised Laplacian assembly
+shows up as a mismatch here.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _tau(cam, u, v):
+    if cam["proj"] == "persp":
+        return np.array([(u - cam["cx"]) / cam["fx"], (v - cam["cy"]) / cam["fy"], 1.0])
+    return np.array([0.0, 0.0, 1.0])
+
+
+def pair_model(n, cam, a, b):
+    """(usable, omega_{b->a}, gamma2_{b->a}, gamma2_{a->b}) of one neighbour
+    pair a=(u,v), b=(u',v') from the two-tangent-planes construction."""
+    (ua, va), (ub, vb) = a, b
+    na = n[va, ua].astype(np.float64)
+    nb = n[vb, ub].astype(np.float64)
+    horiz = va == vb
+    if cam["proj"] == "persp":
+        ta = _tau(cam, ua, va)
+        tb = _tau(cam, ub, vb)
+        tm = _tau(cam, 0.5 * (ua + ub), 0.5 * (va + vb))
+        daa, dam, dbb, dbm = na @ ta, na @ tm, nb @ tb, nb @ tm
+        if min(abs(daa), abs(dam), abs(dbb), abs(dbm)) == 0:
+            return False, 0.0, 0.0, 0.0
+        if (daa > 0) != (dam > 0) or (dbb > 0) != (dbm > 0):
+            return False, 0.0, 0.0, 0.0
+        # z_m from a's tangent plane equals z_m from b's: z_a daa/dam = z_b dbb/dbm
+        om = math.log(dam / daa) - math.log(dbm / dbb)
+        f = cam["fx"] if horiz else cam["fy"]
+        return True, om, (f * daa) ** 2, (f * dbb) ** 2
+    if na[2] == 0 or nb[2] == 0:
+        return False, 0.0, 0.0, 0.0
+    s = cam["pixel_pitch"]
+    du, dv = ub - ua, vb - va
+    # tangent plane at a reaches the midpoint column at z_a - s (na_x du/2 + na_y dv/2)/na_z
+    zm_from_a = -s * (na[0] * du / 2 + na[1] * dv / 2) / na[2]
+    zm_from_b = s * (nb[0] * du / 2 + nb[1] * dv / 2) / nb[2]
+    return True, zm_from_b - zm_from_a, na[2] ** 2, nb[2] ** 2
+
+
+def neighbour_pairs(H, W):
+    for v in range(H):
+        for u in range(W):
+            if u + 1 < W:
+                yield (u, v), (u + 1, v)
+            if v + 1 < H:
+                yield (u, v), (u, v + 1)
+
+
+def closure_labels(H, W, valid, linked):
+    """Labels by transitive closure of the boolean adjacency (Warshall);
+    label = rank of the component's smallest raster index."""
+    N = H * W
+    R = np.eye(N, dtype=bool)
+    for (a, b) in linked:
+        ia, ib = a[1] * W + a[0], b[1] * W + b[0]
+        R[ia, ib] = R[ib, ia] = True
+    for k in range(N):
+        R |= R[:, k:k + 1] & R[k:k + 1, :]
+    lab = -np.ones(N, dtype=np.int64)
+    roots = []
+    for p in range(N):
+        if valid.ravel()[p]:
+            root = int(np.flatnonzero(R[p] & valid.ravel())[0])
+            roots.append(root)
+            lab[p] = root
+    uniq = sorted(set(roots))
+    rank = {r: i for i, r in enumerate(uniq)}
+    out = np.array([rank[x] if x >= 0 else -1 for x in lab]).reshape(H, W)
+    return out, len(uniq)
+
+
+def model(normals, mask, cam, theta_c_deg):
+    H, W, _ = normals.shape
+    valid = np.asarray(mask) != 0
+    usable, similar = [], []
+    info = {}
+    for a, b in neighbour_pairs(H, W):
+        if not (valid[a[1], a[0]] and valid[b[1], b[0]]):
+            continue
+        ok, om, g2a, g2b = pair_model(normals, cam, a, b)
+        if not ok:
+            continue
+        usable.append((a, b))
+        info[(a, b)] = (om, g2a, g2b)
+        na = normals[a[1], a[0]].astype(np.float64)
+        nb = normals[b[1], b[0]].astype(np.float64)
+        if theta_c_deg > 0:
+            ang = math.degrees(math.acos(max(-1.0, min(1.0, float(na @ nb)))))
+            if ang < theta_c_deg:
+                similar.append((a, b))
+    return valid, usable, similar, info
+
+
+def fill_rows(normals, mask, cam, lab, info):
+    """Eq. 14-15 per component with explicit rows: for every usable edge
+    inside a component, rows b->a (+1 at a, -1 at b, rhs omega_{b->a}) and
+    a->b (+1 at b, -1 at a, rhs -omega_{b->a}), weights gamma^2/2.  Dense
+    minimum-norm weighted least squares (zero mean per component)."""
+    H, W = lab.shape
+    z = np.zeros((H, W))
+    for c in range(int(lab.max()) + 1 if lab.max() >= 0 else 0):
+        pix = [(u, v) for v in range(H) for u in range(W) if lab[v, u] == c]
+        col = {p: i for i, p in enumerate(pix)}
+        rows, rhs, wts = [], [], []
+        for (a, b), (om, g2a, g2b) in info.items():
+            if a in col and b in col:
+                r1 = np.zeros(len(pix)); r1[col[a]] = 1; r1[col[b]] = -1
+                rows.append(r1); rhs.append(om); wts.append(0.5 * g2a)
+                rows.append(-r1); rhs.append(-om); wts.append(0.5 * g2b)
+        if not rows:
+            continue
+        sw = np.sqrt(np.array(wts))
+        A = np.array(rows) * sw[:, None]
+        x = np.linalg.lstsq(A, np.array(rhs) * sw, rcond=None)[0]
+        x -= x.mean()
+        for p, i in col.items():
+            z[p[1], p[0]] = x[i]
+    return z
+
+
+def _sig(x, k):
+    if -k * x > 700:
+        return 0.0
+    return 1.0 / (1.0 + math.exp(-k * x))
+
+
+def _wout(chi, L, U, mode):
+    chi = abs(chi)
+    if mode == 0:
+        return 1.0
+    if mode == 2:
+        return 1.0 if chi < U else 0.0
+    if chi == 0:
+        return 1.0
+    lL, lU = math.log10(L), math.log10(U)
+    arg = 4.0 / (lL - lU) * (2.0 * math.log10(chi) - (lL + lU))
+    if -arg > 700:
+        return 0.0
+    return 1.0 / (1.0 + math.exp(-arg))
+
+
+def irls_rows(normals, mask, cam, lab, K, zfill, usable, info, params):
+    """Alg. 1's relative-scale loop with explicit inter-component rows.
+
+    Row b->a of inter edge (a, b): +1 at pi(a), -1 at pi(b),
+    rhs omega_{b->a} - (z_a - z_b) (Eq. 16); its weight is 1 in the
+    alignment iterations and gamma_{b->a}^2 sigma_k(gamma^2 ((z_{-b}-z_a)^2 -
+    (z_b-z_a)^2)) W^out otherwise, with -b the pixel across a from b.
+    Returns (S, energies)."""
+    H, W = lab.shape
+    usable_set = set(usable)
+    S = np.zeros(K)
+    energies = []
+    k = params["bini_k"]
+    inter = [(a, b) for (a, b) in usable if lab[a[1], a[0]] != lab[b[1], b[0]]]
+
+    def zval(p):
+        return zfill[p[1], p[0]] + S[lab[p[1], p[0]]]
+
+    def edge_ok(p, q):
+        return (p, q) in usable_set or (q, p) in usable_set
+
+    for t in range(params["irls_iters"]):
+        rows, rhs, wts, keys = [], [], [], []
+        for (a, b) in inter:
+            om, g2a, g2b = info[(a, b)]
+            za, zb = zval(a), zval(b)
+            chi = za - zb - om
+            if t < params["align_iters"]:
+                wba = wab = 1.0
+            else:
+                d = (b[0] - a[0], b[1] - a[1])
+                mb = (a[0] - d[0], a[1] - d[1])          # across a from b
+                ma = (b[0] + d[0], b[1] + d[1])          # across b from a
+                dm = (zval(mb) - za) if (0 <= mb[0] < W and 0 <= mb[1] < H and edge_ok(mb, a)) else 0.0
+                dm2 = (zval(ma) - zb) if (0 <= ma[0] < W and 0 <= ma[1] < H and edge_ok(b, ma)) else 0.0
+                wo = _wout(chi, params["out_L"], params["out_U"], params["outlier_mode"])
+                wba = g2a * _sig(g2a * (dm * dm - (zb - za) ** 2), k) * wo
+                wab = g2b * _sig(g2b * (dm2 * dm2 - (za - zb) ** 2), k) * wo
+            ca, cb = lab[a[1], a[0]], lab[b[1], b[0]]
+            r1 = np.zeros(K); r1[ca] = 1; r1[cb] = -1
+            rows.append(r1); rhs.append(om - (za - zb)); wts.append(wba)
+            rows.append(-r1); rhs.append(-om - (zb - za)); wts.append(wab)
+            keys.append(len(keys))
+        if not rows:
+            energies.append(0.0)
+            continue
+        wts = np.array(wts)
+        we = wts[0::2] + wts[1::2]
+        cut = we < params["w_cut_rel"] * we.max()
+        wts[0::2][cut] = 0.0
+        wts[1::2][cut] = 0.0
+        sw = np.sqrt(wts)
+        A = np.array(rows)
+        s = np.linalg.lstsq(A * sw[:, None], np.array(rhs) * sw, rcond=None)[0]
+        # minimum-norm: zero mean on every piece, 0 on isolated components
+        res = A @ s - np.array(rhs)
+        energies.append(float(np.sum(wts * res * res)))
+        S = S + s
+    return S, energies

@@ -1,0 +1,514 @@
+"""FP64 CPU oracle of component-based normal integration.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module:
+only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may call it.  It shares no code with the HIP library.
+
+It follows the method of "Towards Fast and Scalable Normal Integration using
+Continuous Components" (Milano et al., WACV 2026) step by step, with every
+linear system solved *exactly* (sparse direct factorisation of the
+gauge-fixed system) instead of by conjugate gradients:
+
+  edges()     model of continuity on log-depth (Sec. 3.1, Eq. 1) with the
+              central-camera coefficient of Eq. 3, the per-row factor
+              gamma = f n_a.tau_a (Eq. 7), and the normal-similarity test of
+              Sec. 3.3 (theta_ab < theta_c);
+  labels()    continuous components = connected components over similar
+              edges (Sec. 3.3), canonicalised to the minimum raster index;
+  fill()      per-component weighted least squares on the intra-component
+              edges with BiNI weights at z=0 (Sec. 3.3, Eq. 14-15);
+  irls()      relative-scale optimisation on the inter-component edges
+              (Sec. 3.4, Eq. 11-12 and 16-19; Alg. 1's main loop);
+  finalize()  log-depth = fill + scale, one gauge per connected region.
+
+Where the paper is silent or ambiguous (orthographic analogue of Eq. 3,
+gauge choices, the weight cut, threshold strictness, ...) the reading taken
+is stated where it is applied and tagged A1..A26.
+Every function here is pinned by tests/test_oracle_pins.py (printed values,
+closed forms, brute force on tiny maps, invariants).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from scipy.sparse.csgraph import connected_components
+
+# Method parameters.  Values in brackets are the paper's (Sec. 3.4, Sec. 4).
+DEFAULT_PARAMS = dict(
+    theta_c_deg=2.0,      # similarity threshold [2.0 deg on large maps]; <= 0: pixel level
+    irls_iters=15,        # T [15 on large maps]
+    align_iters=2,        # uniform-weight iterations t <= 1 [2]
+    bini_k=2.0,           # sigmoid sharpness k of Eq. 5 (value not given; A5)
+    out_L=1e-5,           # Eq. 18 lower threshold [1e-5]
+    out_U=1e-3,           # Eq. 18 upper threshold [1e-3]
+    outlier_mode=1,       # 0 off, 1 soft (Eq. 18), 2 hard (Suppl. ablation)
+    delta_e_max=0.0,      # relative-energy stop; 0 runs exactly T iterations (A13)
+    w_cut_rel=1e-8,       # quotient edges below this fraction of the max weight are cut (A16)
+)
+
+
+class NonFiniteInput(ValueError):
+    pass
+
+
+@dataclass
+class Edges:
+    H: int
+    W: int
+    proj: str
+    valid: np.ndarray       # bool [H, W]      pixel is a graph node
+    valid_r: np.ndarray     # bool [H, W]      edge (u,v)-(u+1,v) usable
+    valid_d: np.ndarray     # bool [H, W]      edge (u,v)-(u,v+1) usable
+    sim_r: np.ndarray       # bool [H, W]      ... and normals similar
+    sim_d: np.ndarray
+    omega_r: np.ndarray     # f64 [H, W]       omega_{b->a} for b = right neighbour
+    omega_d: np.ndarray     # f64 [H, W]       omega_{b->a} for b = lower neighbour
+    g2_h: np.ndarray        # f64 [H, W]       gamma^2 of horizontal rows ending at the pixel
+    g2_v: np.ndarray        # f64 [H, W]       gamma^2 of vertical rows ending at the pixel
+
+
+def ray_tables(cam, H, W):
+    """Ray direction tables tau(u, v) = ((u-cx)/fx, (v-cy)/fy, 1) at pixel
+    centres and at the midpoints between horizontal / vertical neighbours
+    (the interpolating subpixel m of Eq. 3, read as the midpoint: A2)."""
+    u = np.arange(W, dtype=np.float64)
+    v = np.arange(H, dtype=np.float64)
+    tx = (u - cam.cx) / cam.fx
+    ty = (v - cam.cy) / cam.fy
+    txm = ((u + 0.5) - cam.cx) / cam.fx
+    tym = ((v + 0.5) - cam.cy) / cam.fy
+    return tx, ty, txm, tym
+
+
+def _cam_get(cam, k):
+    return cam[k] if isinstance(cam, dict) else getattr(cam, k)
+
+
+class _Cam:
+    def __init__(self, cam):
+        self.proj = _cam_get(cam, "proj")
+        if self.proj not in ("ortho", "persp"):
+            raise ValueError("camera projection must be 'ortho' or 'persp'")
+        self.fx = float(_cam_get(cam, "fx"))
+        self.fy = float(_cam_get(cam, "fy"))
+        self.cx = float(_cam_get(cam, "cx"))
+        self.cy = float(_cam_get(cam, "cy"))
+        self.pixel_pitch = float(_cam_get(cam, "pixel_pitch"))
+
+
+def edges(normals, mask, cam, theta_c_deg) -> Edges:
+    """Per-edge quantities of the model of continuity (Sec. 3.1).
+
+    Perspective (Eq. 3): with the four dot products d_aa = n_a.tau_a,
+    d_am = n_a.tau_m, d_bb = n_b.tau_b, d_bm = n_b.tau_m,
+        omega_{b->a} = log( (d_am / d_aa) * (d_bb / d_bm) ),
+    the log-depth difference of two tangent planes that meet on the ray of the
+    midpoint m.  The edge is usable iff each tangent plane meets that ray in
+    front of the camera: d_aa, d_am non-zero of one sign and d_bb, d_bm
+    non-zero of one sign (A18).  gamma_{b->a} = f n_a.tau_a (Eq. 7) with f = fx
+    for horizontal and fy for vertical rows (A4).
+
+    Orthographic (A1): additive depth, the same two-tangent-plane construction
+    with parallel rays:
+        omega_{b->a} = s ( (n_ax du + n_ay dv)/(2 n_az) + (n_bx du + n_by dv)/(2 n_bz) ),
+    (du, dv) = b - a, s = pixel pitch; usable iff n_az, n_bz are non-zero;
+    gamma = n_z.
+
+    Similarity (Sec. 3.3): theta_ab < theta_c  <=>  n_a.n_b > cos(theta_c)
+    (A19), evaluated in FP64 from the FP32 inputs as
+    (n_ax n_bx + n_ay n_by) + n_az n_bz.  theta_c <= 0 marks no edge similar
+    (every pixel its own component, "theta_c = None").
+    """
+    cam = _Cam(cam)
+    n = np.asarray(normals)
+    if n.dtype not in (np.float32, np.float64) or n.ndim != 3 or n.shape[2] != 3:
+        raise TypeError("normals must be float32 (or float64) [H, W, 3]")
+    H, W, _ = n.shape
+    valid = np.asarray(mask) != 0
+    if not np.all(np.isfinite(n[valid])):
+        raise NonFiniteInput("non-finite normal inside the mask")
+    nx = n[..., 0].astype(np.float64)
+    ny = n[..., 1].astype(np.float64)
+    nz = n[..., 2].astype(np.float64)
+    nx = np.where(valid, nx, 0.0)
+    ny = np.where(valid, ny, 0.0)
+    nz = np.where(valid, nz, 0.0)
+
+    vr = np.zeros((H, W), bool)
+    vd = np.zeros((H, W), bool)
+    vr[:, :-1] = valid[:, :-1] & valid[:, 1:]
+    vd[:-1, :] = valid[:-1, :] & valid[1:, :]
+    om_r = np.zeros((H, W))
+    om_d = np.zeros((H, W))
+
+    if cam.proj == "persp":
+        tx, ty, txm, tym = ray_tables(cam, H, W)
+        TX, TY = tx[None, :], ty[:, None]
+        nt = (nx * TX + ny * TY) + nz                      # n_a . tau_a
+        # horizontal edges: midpoint ray (txm[u], ty[v], 1)
+        dam = (nx[:, :-1] * txm[None, :-1] + ny[:, :-1] * TY) + nz[:, :-1]
+        dbm = (nx[:, 1:] * txm[None, :-1] + ny[:, 1:] * TY) + nz[:, 1:]
+        daa, dbb = nt[:, :-1], nt[:, 1:]
+        ok = (daa != 0) & (dam != 0) & (dbb != 0) & (dbm != 0) \
+            & ((daa > 0) == (dam > 0)) & ((dbb > 0) == (dbm > 0))
+        vr[:, :-1] &= ok
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_r[:, :-1] = np.where(vr[:, :-1], np.log((dam / daa) * (dbb / dbm)), 0.0)
+        # vertical edges: midpoint ray (tx[u], tym[v], 1)
+        dam = (nx[:-1, :] * TX + ny[:-1, :] * tym[:-1, None]) + nz[:-1, :]
+        dbm = (nx[1:, :] * TX + ny[1:, :] * tym[:-1, None]) + nz[1:, :]
+        daa, dbb = nt[:-1, :], nt[1:, :]
+        ok = (daa != 0) & (dam != 0) & (dbb != 0) & (dbm != 0) \
+            & ((daa > 0) == (dam > 0)) & ((dbb > 0) == (dbm > 0))
+        vd[:-1, :] &= ok
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_d[:-1, :] = np.where(vd[:-1, :], np.log((dam / daa) * (dbb / dbm)), 0.0)
+        g2h = (cam.fx * nt) ** 2
+        g2v = (cam.fy * nt) ** 2
+    else:
+        s = cam.pixel_pitch
+        okz = nz != 0
+        vr[:, :-1] &= okz[:, :-1] & okz[:, 1:]
+        vd[:-1, :] &= okz[:-1, :] & okz[1:, :]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_r[:, :-1] = np.where(vr[:, :-1], s * (nx[:, :-1] / (2.0 * nz[:, :-1])
+                                                     + nx[:, 1:] / (2.0 * nz[:, 1:])), 0.0)
+            om_d[:-1, :] = np.where(vd[:-1, :], s * (ny[:-1, :] / (2.0 * nz[:-1, :])
+                                                     + ny[1:, :] / (2.0 * nz[1:, :])), 0.0)
+        g2h = nz ** 2
+        g2v = nz ** 2
+
+    sr = np.zeros((H, W), bool)
+    sd = np.zeros((H, W), bool)
+    if theta_c_deg > 0:
+        cth = math.cos(theta_c_deg * math.pi / 180.0)
+        dot_r = (nx[:, :-1] * nx[:, 1:] + ny[:, :-1] * ny[:, 1:]) + nz[:, :-1] * nz[:, 1:]
+        dot_d = (nx[:-1, :] * nx[1:, :] + ny[:-1, :] * ny[1:, :]) + nz[:-1, :] * nz[1:, :]
+        sr[:, :-1] = vr[:, :-1] & (dot_r > cth)
+        sd[:-1, :] = vd[:-1, :] & (dot_d > cth)
+    g2h = np.where(valid, g2h, 0.0)
+    g2v = np.where(valid, g2v, 0.0)
+    return Edges(H, W, cam.proj, valid, vr, vd, sr, sd, om_r, om_d, g2h, g2v)
+
+
+def _grid_graph(e: Edges, use_r, use_d):
+    """Sparse symmetric adjacency over the H*W raster indices."""
+    H, W = e.H, e.W
+    idx = np.arange(H * W).reshape(H, W)
+    a = np.concatenate([idx[use_r], idx[use_d]])
+    b = np.concatenate([idx[use_r] + 1, idx[use_d] + W])
+    G = sp.coo_matrix((np.ones(a.size), (a, b)), shape=(H * W, H * W))
+    return G
+
+
+def canonical_components(e: Edges, use_r, use_d):
+    """Connected components of the valid pixels over the given edges,
+    numbered by ascending minimum raster index (A20); -1 off the mask."""
+    H, W = e.H, e.W
+    N = H * W
+    ncomp, lab = connected_components(_grid_graph(e, use_r, use_d), directed=False)
+    valid = e.valid.ravel()
+    roots = np.full(ncomp, N, dtype=np.int64)
+    pix = np.arange(N)
+    np.minimum.at(roots, lab[valid], pix[valid])
+    used = roots < N
+    order = np.argsort(roots[used], kind="stable")
+    remap = np.full(ncomp, -1, dtype=np.int64)
+    remap[np.flatnonzero(used)[order]] = np.arange(order.size)
+    out = np.where(valid, remap[lab], -1).astype(np.int32)
+    return out.reshape(H, W), int(order.size)
+
+
+def labels(e: Edges):
+    """Continuous components (Sec. 3.3): connected components of the
+    subgraph of G_0 keeping only edges with theta_ab < theta_c."""
+    return canonical_components(e, e.sim_r, e.sim_d)
+
+
+def regions(e: Edges):
+    """Connected regions of G_0 itself (all usable edges)."""
+    return canonical_components(e, e.valid_r, e.valid_d)
+
+
+def _intra_system(e: Edges, lab):
+    """Normal equations A_c^T W_c A_c z = A_c^T W_c b_c of Eq. 14-15 for all
+    components at once (block diagonal).  Rows: both directed rows of every
+    usable edge with both ends in one component (A8, A9), weighted by
+    W = gamma^2 * sigma_k(0) = gamma^2 / 2 (a single reweighting pass from
+    z = 0: A7).  Per undirected edge the two rows fold into
+    w = (gamma^2_{b->a} + gamma^2_{a->b}) / 2 times (z_a - z_b - omega_{b->a})^2."""
+    H, W = e.H, e.W
+    N = H * W
+    idx = np.arange(N).reshape(H, W)
+    L = lab
+    in_r = e.valid_r.copy()
+    in_r[:, :-1] &= L[:, :-1] == L[:, 1:]
+    in_d = e.valid_d.copy()
+    in_d[:-1, :] &= L[:-1, :] == L[1:, :]
+    a_r = idx[in_r]
+    a_d = idx[in_d]
+    g2h = e.g2_h.ravel()
+    g2v = e.g2_v.ravel()
+    w_r = 0.5 * g2h[a_r] + 0.5 * g2h[a_r + 1]
+    w_d = 0.5 * g2v[a_d] + 0.5 * g2v[a_d + W]
+    a = np.concatenate([a_r, a_d])
+    b = np.concatenate([a_r + 1, a_d + W])
+    w = np.concatenate([w_r, w_d])
+    om = np.concatenate([e.omega_r[in_r], e.omega_d[in_d]])
+    Lap = sp.coo_matrix((np.concatenate([w, w, -w, -w]),
+                         (np.concatenate([a, b, a, b]), np.concatenate([a, b, b, a]))),
+                        shape=(N, N)).tocsr()
+    rhs = np.zeros(N)
+    np.add.at(rhs, a, w * om)
+    np.add.at(rhs, b, -w * om)
+    return Lap, rhs
+
+
+def _solve_pinned(Lap, rhs, groups, ngroups, active):
+    """Exact solution of a block-diagonal graph-Laplacian system with one
+    block per group: pin the minimum index of each group to zero, factorise
+    the remaining SPD system, then shift each group to zero mean (A15).
+    Nodes with active=False (e.g. off the mask) get 0."""
+    n = Lap.shape[0]
+    x = np.zeros(n)
+    nodes = np.flatnonzero(active)
+    if nodes.size == 0:
+        return x
+    g = groups[nodes]
+    first = np.full(ngroups, n, dtype=np.int64)
+    np.minimum.at(first, g, nodes)
+    keep = np.ones(n, bool)
+    keep[first[first < n]] = False
+    keep &= active
+    kidx = np.flatnonzero(keep)
+    if kidx.size:
+        A = Lap[kidx][:, kidx].tocsc()
+        x[kidx] = spla.spsolve(A, rhs[kidx]) if kidx.size > 1 else rhs[kidx] / A.toarray()[0, 0]
+    sums = np.zeros(ngroups)
+    cnt = np.zeros(ngroups)
+    np.add.at(sums, g, x[nodes])
+    np.add.at(cnt, g, 1.0)
+    x[nodes] -= sums[g] / cnt[g]
+    return x
+
+
+def fill(e: Edges, lab, K):
+    """Fill every component (Sec. 3.3, Eq. 15): exact solution of the
+    component's weighted normal equations, gauge = zero mean per component
+    (the minimum-norm solution that CG from z = 0 converges to; A15)."""
+    Lap, rhs = _intra_system(e, lab)
+    labf = lab.ravel()
+    active = labf >= 0
+    z = _solve_pinned(Lap, rhs, np.where(active, labf, 0), max(K, 1), active)
+    return z.reshape(e.H, e.W)
+
+
+@dataclass
+class InterEdges:
+    a: np.ndarray       # raster index of the left / upper pixel
+    b: np.ndarray       # raster index of the right / lower pixel
+    horiz: np.ndarray   # bool: b = a + 1 (else b = a + W)
+    omega: np.ndarray   # omega_{b->a}
+    c: np.ndarray       # pi(a)
+    d: np.ndarray       # pi(b)
+
+
+def inter_edges(e: Edges, lab) -> InterEdges:
+    """E_inter (Eq. 9): usable edges whose ends lie in different components."""
+    H, W = e.H, e.W
+    idx = np.arange(H * W).reshape(H, W)
+    L = lab
+    xr = e.valid_r.copy()
+    xr[:, :-1] &= L[:, :-1] != L[:, 1:]
+    xd = e.valid_d.copy()
+    xd[:-1, :] &= L[:-1, :] != L[1:, :]
+    a = np.concatenate([idx[xr], idx[xd]])
+    horiz = np.concatenate([np.ones(int(xr.sum()), bool), np.zeros(int(xd.sum()), bool)])
+    b = np.where(horiz, a + 1, a + W)
+    om = np.concatenate([e.omega_r[xr], e.omega_d[xd]])
+    lf = L.ravel()
+    return InterEdges(a, b, horiz, om, lf[a].astype(np.int64), lf[b].astype(np.int64))
+
+
+def sigmoid(x, k=1.0):
+    """sigma_k(x) = 1 / (1 + exp(-k x)) (Eq. 5); exp overflow gives 0."""
+    with np.errstate(over="ignore"):
+        return 1.0 / (1.0 + np.exp(-k * np.asarray(x, dtype=np.float64)))
+
+
+def outlier_weight(chi_abs, L=1e-5, U=1e-3, mode=1):
+    """W^out of Eq. 18 (mode 1): sigma_1( 4/(lL - lU) * (2 log10|chi| - (lL + lU)) )
+    with lX = log10(X); |chi| = 0 maps to 1 (A12).  Mode 2 is the hard
+    threshold of the supplementary ablation (0 if |chi| >= U else 1); mode 0
+    disables the reweighting."""
+    chi_abs = np.abs(np.asarray(chi_abs, dtype=np.float64))
+    if mode == 0:
+        return np.ones_like(chi_abs)
+    if mode == 2:
+        return (chi_abs < U).astype(np.float64)
+    lL, lU = math.log10(L), math.log10(U)
+    with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+        x = np.log10(chi_abs)
+        arg = 4.0 / (lL - lU) * (2.0 * x - (lL + lU))
+        out = 1.0 / (1.0 + np.exp(-arg))
+    return np.where(chi_abs == 0, 1.0, out)
+
+
+def edge_weights(e: Edges, ie: InterEdges, z, t, params):
+    """Per undirected inter edge, w_e = W_{b->a} + W_{a->b} (A9) and the
+    residual r_e = z_a - z_b - omega_{b->a} at the current log-depth (A11).
+
+    t < align_iters: every directed row weighs 1 (Alg. 1's alignment phase).
+    Otherwise (Eq. 5-7, 18-19), for the row ending at pixel a with the other
+    end b and the pixel -b opposite b across a:
+        W_{b->a} = g^2 sigma_k( g^2 ((z_{-b} - z_a)^2 - (z_b - z_a)^2) ) W^out(|r_e|)
+    with g^2 = gamma^2_{b->a}; a missing (unusable) edge (a, -b) contributes
+    (z_{-b} - z_a) = 0 (A6)."""
+    H, W = e.H, e.W
+    zf = z.ravel()
+    r = zf[ie.a] - zf[ie.b] - ie.omega
+    if t < params["align_iters"]:
+        return np.full(r.size, 2.0), r
+    k = params["bini_k"]
+    vr = e.valid_r.ravel()
+    vd = e.valid_d.ravel()
+    g2h = e.g2_h.ravel()
+    g2v = e.g2_v.ravel()
+    step = np.where(ie.horiz, 1, W)
+    # row b -> a: opposite pixel -b = a - step, edge (a - step, a)
+    ma = ie.a - step
+    has_ma = np.where(ie.horiz, (ie.a % W) > 0, ie.a >= W)
+    ma_c = np.where(has_ma, ma, 0)
+    ok_ma = has_ma & np.where(ie.horiz, vr[ma_c], vd[ma_c])
+    dm = np.where(ok_ma, zf[ma_c] - zf[ie.a], 0.0)
+    dp = zf[ie.b] - zf[ie.a]
+    g2a = np.where(ie.horiz, g2h[ie.a], g2v[ie.a])
+    Wba = g2a * sigmoid(g2a * (dm * dm - dp * dp), k)
+    # row a -> b: opposite pixel -a = b + step, edge (b, b + step)
+    ok_pb = np.where(ie.horiz, vr[ie.b], vd[ie.b])
+    pb = np.where(ok_pb, ie.b + step, 0)
+    dm2 = np.where(ok_pb, zf[pb] - zf[ie.b], 0.0)
+    dp2 = zf[ie.a] - zf[ie.b]
+    g2b = np.where(ie.horiz, g2h[ie.b], g2v[ie.b])
+    Wab = g2b * sigmoid(g2b * (dm2 * dm2 - dp2 * dp2), k)
+    wout = outlier_weight(r, params["out_L"], params["out_U"], params["outlier_mode"])
+    return (Wba + Wab) * wout, r
+
+
+def quotient_step(ie: InterEdges, K, w, r, w_cut_rel):
+    """One relative-scale solve (Eq. 16-17) on the quotient graph (Eq. 10).
+
+    Minimises sum_e w_e (r_e + s_c - s_d)^2 over s (c = pi(a), d = pi(b)).
+    Edges lighter than w_cut_rel * max_e w_e are dropped (A16); the remaining
+    weighted quotient graph splits into pieces, each solved exactly with zero
+    (unweighted) mean of s over its components (A15).  Returns (s, E_t, w).
+    """
+    w = np.array(w, dtype=np.float64)
+    if w.size:
+        wmax = w.max()
+        w[w < w_cut_rel * wmax] = 0.0
+    c, d = ie.c, ie.d
+    Q = sp.coo_matrix((np.concatenate([w, w, -w, -w]),
+                       (np.concatenate([c, d, c, d]), np.concatenate([c, d, d, c]))),
+                      shape=(K, K)).tocsr()
+    rhs = np.zeros(K)
+    np.add.at(rhs, c, -w * r)
+    np.add.at(rhs, d, w * r)
+    pos = w > 0
+    G = sp.coo_matrix((np.ones(int(pos.sum())), (c[pos], d[pos])), shape=(K, K))
+    npieces, piece = connected_components(G, directed=False)
+    s = _solve_pinned(Q, rhs, piece, npieces, np.ones(K, bool))
+    res = r + s[c] - s[d]
+    E = float(np.sum(w * res * res))
+    return s, E, w
+
+
+def irls(e: Edges, lab, K, zfill, params=None):
+    """Relative-scale optimisation (Sec. 3.4; Alg. 1's loop without merging).
+
+    z^(t) = zfill + S_pi; each iteration solves for s^(t) with the weights of
+    iteration t, then S += s (Eq. 12).  Stops after T iterations, or earlier
+    when delta_e_max > 0 and |E_t - E_{t-1}| / E_{t-1} < delta_e_max with
+    both t-1, t past the alignment phase (A13)."""
+    p = dict(DEFAULT_PARAMS)
+    if params:
+        p.update(params)
+    ie = inter_edges(e, lab)
+    S = np.zeros(K)
+    labf = lab.ravel()
+    valid = labf >= 0
+    energies = []
+    for t in range(int(p["irls_iters"])):
+        z = np.where(valid, zfill.ravel() + S[np.where(valid, labf, 0)], 0.0)
+        w, r = edge_weights(e, ie, z, t, p)
+        s, E, _ = quotient_step(ie, K, w, r, p["w_cut_rel"])
+        S += s
+        energies.append(E)
+        if p["delta_e_max"] > 0 and t >= p["align_iters"] + 1:
+            Ep = energies[-2]
+            if Ep == 0.0 or abs(E - Ep) / Ep < p["delta_e_max"]:
+                break
+    return S, energies, ie
+
+
+def finalize(e: Edges, lab, zfill, S):
+    """Output gauge: log-depth z = zfill + S_pi shifted to zero pixel mean over
+    every connected region of G_0 (A15); depth = exp(z) in perspective and
+    z itself (additive model) in orthographic mode.  Returns
+    (depth f64 [H, W] with NaN off the mask, log_scale f64 [K], z)."""
+    reg, R = regions(e)
+    labf = lab.ravel()
+    regf = reg.ravel()
+    valid = labf >= 0
+    z = np.where(valid, zfill.ravel() + S[np.where(valid, labf, 0)], 0.0)
+    sums = np.zeros(max(R, 1))
+    cnt = np.zeros(max(R, 1))
+    np.add.at(sums, regf[valid], z[valid])
+    np.add.at(cnt, regf[valid], 1.0)
+    shift = sums / np.maximum(cnt, 1.0)
+    z = np.where(valid, z - shift[np.where(valid, regf, 0)], np.nan)
+    K = S.size
+    comp_region = np.zeros(K, dtype=np.int64)
+    comp_region[labf[valid]] = regf[valid]
+    log_scale = S - shift[comp_region] if K else S
+    depth = np.exp(z) if e.proj == "persp" else z
+    return depth.reshape(e.H, e.W), log_scale, z.reshape(e.H, e.W)
+
+
+@dataclass
+class Result:
+    depth: np.ndarray
+    labels: np.ndarray
+    log_scale: np.ndarray
+    K: int
+    zfill: np.ndarray
+    logz: np.ndarray
+    energies: list
+    n_inter_edges: int
+    n_regions: int
+    extra: dict = field(default_factory=dict)
+
+
+def integrate(normals, mask, cam, params=None, labels_in=None, zfill_in=None) -> Result:
+    """The whole path: edges -> components -> fill -> relative scales -> output.
+
+    labels_in / zfill_in inject a partition or a fill (test hooks that mirror
+    the HIP library's staged entry points)."""
+    p = dict(DEFAULT_PARAMS)
+    if params:
+        p.update(params)
+    e = edges(normals, mask, cam, p["theta_c_deg"])
+    if labels_in is None:
+        lab, K = labels(e)
+    else:
+        lab = np.asarray(labels_in, dtype=np.int32)
+        K = int(lab.max()) + 1 if lab.size and lab.max() >= 0 else 0
+    zf = fill(e, lab, K) if zfill_in is None else np.where(lab >= 0, np.asarray(zfill_in, np.float64), 0.0)
+    S, energies, ie = irls(e, lab, K, zf, p)
+    depth, log_scale, logz = finalize(e, lab, zf, S)
+    _, R = regions(e)
+    return Result(depth, lab, log_scale, K, zf, logz, energies, int(ie.a.size), R)
