@@ -1,0 +1,180 @@
+/*
+ * ni.h -- C ABI of the MI355X (gfx950) library for component-based normal
+ * integration ("Towards Fast and Scalable Normal Integration using
+ * Continuous Components", Milano et al., WACV 2026).
+ *
+ * Problem (Sec. 3.1): given a normal map n(u, v), a validity mask and the
+ * camera intrinsics, recover log-depth z~ = log z such that neighbouring
+ * pixels satisfy the model of continuity z~_a - z~_b = omega_{b->a}
+ * (Eq. 1, with omega from Eq. 3).  The method (Sec. 3.2-3.4, Alg. 1):
+ *   (a) label continuous components: connected components over 4-neighbour
+ *       edges whose normals differ by less than theta_c (Sec. 3.3);
+ *   (b) fill every component independently: weighted least squares on its
+ *       intra-component edges, solved by preconditioned CG (Eq. 14-15);
+ *   (c) relative-scale IRLS: one additive log-scale per component from the
+ *       inter-component edges, with BiNI and outlier weights (Eq. 16-19).
+ *
+ * Conventions used by every entry point:
+ *   - pixel (u, v) = (column, row), centre at integer coordinates; raster
+ *     index p = v*W + u; arrays are row-major [H][W] (normals [H][W][3]).
+ *   - perspective rays tau(u, v) = ((u - cx)/fx, (v - cy)/fy, 1).
+ *   - orthographic mode (not in the paper): additive depth, the same
+ *     two-tangent-planes construction with parallel rays; depth is in the
+ *     unit of pixel_pitch and the per-component unknown is an offset.
+ *   - every device pointer must be a device (hipMalloc / torch CUDA) buffer
+ *     on the context's device; every host pointer a plain host buffer.  The
+ *     caller owns all of them; the library never frees a caller pointer.
+ *   - calls are stream-ordered on the context's stream (ni_set_stream) and
+ *     blocking: they return after the results are written.
+ *   - nothing throws across the ABI; every call returns ni_status and, on
+ *     error, ni_last_error(ctx) holds a message.  One context per thread;
+ *     contexts are independent.
+ */
+#ifndef NI_H
+#define NI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NI_ABI_VERSION 1
+#define NI_MAX_IRLS 64
+
+typedef enum {
+  NI_OK = 0,
+  NI_E_ARG = 1,       /* bad argument (null pointer, bad enum, bad size)      */
+  NI_E_SHAPE = 2,     /* output capacity too small (*K is still written)     */
+  NI_E_NONFINITE = 3, /* NaN/Inf normal inside the mask                        */
+  NI_E_NOMEM = 4,     /* device allocation failed                              */
+  NI_E_DEVICE = 5,    /* HIP runtime error                                     */
+  NI_E_NOTCONV = 6,   /* a CG solve hit its iteration cap (results written)   */
+  NI_E_MODEL = 7      /* bad warm-start weight blob / no model loaded          */
+} ni_status;
+
+typedef enum { NI_ORTHO = 0, NI_PERSP = 1 } ni_proj;
+
+typedef struct {
+  int32_t proj;        /* ni_proj                                            */
+  double fx, fy;       /* focal lengths in pixels (perspective)              */
+  double cx, cy;       /* principal point in pixels (perspective)            */
+  double pixel_pitch;  /* orthographic: metric size of one pixel             */
+} ni_camera;
+
+typedef struct {
+  double theta_c_deg;   /* similarity threshold theta_c (Sec. 3.3); <= 0 means
+                           every pixel is its own component (theta_c = None)  */
+  int32_t connectivity; /* 4 (only supported value)                           */
+  int32_t irls_iters;   /* T: relative-scale iterations (1..NI_MAX_IRLS)      */
+  int32_t align_iters;  /* leading uniform-weight iterations (Alg. 1: 2)      */
+  double bini_k;        /* sharpness k of the BiNI sigmoid (Eq. 5)            */
+  double out_L, out_U;  /* outlier thresholds of Eq. 18 (1e-5, 1e-3)          */
+  int32_t outlier_mode; /* 0 off, 1 soft (Eq. 18), 2 hard threshold at U      */
+  double delta_e_max;   /* relative-energy stop; 0 = run exactly T iterations */
+  double w_cut_rel;     /* quotient edges lighter than w_cut_rel * max weight
+                           are dropped before each relative-scale solve       */
+  double cg_rtol;       /* fill CG: stop at ||r_c|| <= cg_rtol * ||b_c||      */
+  int32_t cg_max_iter;  /* fill CG iteration cap per component                */
+  double q_rtol;        /* quotient CG: stop at ||r|| <= q_rtol * ||b||_abs   */
+  int32_t q_max_iter;   /* quotient CG iteration cap                          */
+  int32_t warm_start;   /* 0 zero start; 1 learned start (needs ni_unet_load) */
+  int32_t persistent;   /* fill large components in one persistent launch (1)
+                           or one launch per CG phase (0)                     */
+} ni_params;
+
+typedef struct {
+  int32_t K;             /* number of continuous components                   */
+  int32_t n_valid;       /* pixels inside the mask                            */
+  int32_t n_regions;     /* connected regions of the full pixel graph G_0     */
+  int32_t n_inter_edges; /* |E_inter|                                         */
+  int32_t n_pairs;       /* distinct neighbouring component pairs             */
+  int32_t irls_iters_run;
+  int32_t n_small, n_large;      /* components solved in LDS / grid-wide      */
+  int32_t fill_iters_max;        /* largest CG iteration count of a component */
+  int32_t fill_notconv;          /* components that hit cg_max_iter           */
+  int64_t fill_px_iters;         /* sum over components of n_c * iters_c      */
+  int64_t fill_large_px_iters;   /* same, grid-wide components only           */
+  int32_t fill_large_launches;   /* CG phase launches (0 when persistent)     */
+  int32_t warm_fallbacks;        /* components whose learned start was reset */
+  double fill_max_relres;        /* max_c ||r_c|| / ||b_c|| (recursive)       */
+  int32_t quot_iters[NI_MAX_IRLS];
+  double energy[NI_MAX_IRLS];    /* E_t of Alg. 1 per iteration               */
+  float ms_setup, ms_label, ms_segments, ms_assemble, ms_warm,
+        ms_fill_small, ms_fill_large, ms_irls, ms_finalize, ms_total;
+} ni_report;
+
+typedef struct ni_ctx ni_ctx;
+
+/* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
+ * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-8, cg_rtol 1e-6,
+ * cg_max_iter 50000, q_rtol 1e-12, q_max_iter 20000, zero start,
+ * persistent 1.  Returns NI_E_ARG on a null pointer. */
+ni_status ni_params_default(ni_params* p);
+
+/* Create a context on HIP device `device`; it owns a device workspace that
+ * grows on demand and is freed by ni_destroy.  *out is set to NULL on error. */
+ni_status ni_create(ni_ctx** out, int device);
+ni_status ni_destroy(ni_ctx* ctx);
+
+/* Stream for all later work (a hipStream_t, e.g. torch's
+ * torch.cuda.current_stream().cuda_stream); NULL selects the null stream. */
+ni_status ni_set_stream(ni_ctx* ctx, void* hip_stream);
+
+/* Whole path (Alg. 1 without merging): components, fill, relative scales.
+ *   normals   device f32 [H][W][3], read only; NaN/Inf allowed off the mask
+ *   mask      device u8  [H][W]; non-zero = valid pixel
+ *   depth     device f32 [H][W] out: exp(z~) (perspective) or z~ (ortho),
+ *             gauge: zero mean log-depth over every connected region of
+ *             the pixel graph; NaN off the mask
+ *   labels    device i32 [H][W] out: component id, ids numbered by
+ *             ascending smallest raster index; -1 off the mask
+ *   log_scale device f64 [cap] out: per-component log-scale s~_c in the
+ *             same gauge as depth
+ *   K         host out: number of components; if K > cap the call stops
+ *             with NI_E_SHAPE after labelling (call again with cap >= K)
+ *   rep       host out, may be NULL
+ * H, W in [1, 32767], H*W <= 2^28. */
+ni_status ni_integrate(ni_ctx* ctx, const float* normals, const uint8_t* mask,
+                       int32_t H, int32_t W, const ni_camera* cam,
+                       const ni_params* params, float* depth, int32_t* labels,
+                       double* log_scale, int64_t cap, int32_t* K,
+                       ni_report* rep);
+
+/* Stage (a) alone: component labels (Sec. 3.3), same layout as above. */
+ni_status ni_label(ni_ctx* ctx, const float* normals, const uint8_t* mask,
+                   int32_t H, int32_t W, const ni_camera* cam,
+                   const ni_params* params, int32_t* labels, int32_t* K,
+                   ni_report* rep);
+
+/* Stage (b) from given labels (Eq. 14-15): labels device i32 [H][W] in
+ * (ids 0..K-1 on valid pixels, each component 4-connected through usable
+ * edges, -1 off the mask); zfill device f32 [H][W] out: filled log-depth
+ * (ortho: depth), zero mean per component, 0 off the mask. */
+ni_status ni_fill(ni_ctx* ctx, const float* normals, const uint8_t* mask,
+                  int32_t H, int32_t W, const ni_camera* cam,
+                  const ni_params* params, const int32_t* labels, int32_t K,
+                  float* zfill, ni_report* rep);
+
+/* Stage (c) and output from given labels and fill (Eq. 16-19, Alg. 1):
+ * zfill device f32 [H][W] in; depth / log_scale out as in ni_integrate
+ * (cap >= K required). */
+ni_status ni_irls(ni_ctx* ctx, const float* normals, const uint8_t* mask,
+                  int32_t H, int32_t W, const ni_camera* cam,
+                  const ni_params* params, const int32_t* labels, int32_t K,
+                  const float* zfill, float* depth, double* log_scale,
+                  int64_t cap, ni_report* rep);
+
+/* Learned warm start: load the U-Net weight blob (host memory, format
+ * "NIUNET01", see ni_unet_blob_size) used when params->warm_start = 1. */
+ni_status ni_unet_load(ni_ctx* ctx, const void* blob, size_t nbytes);
+
+const char* ni_status_str(ni_status s);
+const char* ni_last_error(const ni_ctx* ctx);
+int32_t ni_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NI_H */

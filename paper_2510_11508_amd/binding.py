@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libni (include/ni.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Torch tensors provide device memory and the stream; the functions
+keep the C names (ni_integrate, ni_label, ni_fill, ni_irls, ...).  If the
+shared library is missing, loading fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libni.so")
+NI_MAX_IRLS = 64
+
+NI_OK, NI_E_ARG, NI_E_SHAPE, NI_E_NONFINITE, NI_E_NOMEM, NI_E_DEVICE, NI_E_NOTCONV, NI_E_MODEL = range(8)
+NI_ORTHO, NI_PERSP = 0, 1
+
+EXPORTED = ["ni_params_default", "ni_create", "ni_destroy", "ni_set_stream", "ni_integrate", "ni_label",
+            "ni_fill", "ni_irls", "ni_unet_load", "ni_status_str", "ni_last_error", "ni_abi_version"]
+
+
+class ni_camera(C.Structure):
+    _fields_ = [("proj", C.c_int32), ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double),
+                ("cy", C.c_double), ("pixel_pitch", C.c_double)]
+
+
+class ni_params(C.Structure):
+    _fields_ = [("theta_c_deg", C.c_double), ("connectivity", C.c_int32), ("irls_iters", C.c_int32),
+                ("align_iters", C.c_int32), ("bini_k", C.c_double), ("out_L", C.c_double),
+                ("out_U", C.c_double), ("outlier_mode", C.c_int32), ("delta_e_max", C.c_double),
+                ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
+                ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
+                ("persistent", C.c_int32)]
+
+
+class ni_report(C.Structure):
+    _fields_ = [("K", C.c_int32), ("n_valid", C.c_int32), ("n_regions", C.c_int32),
+                ("n_inter_edges", C.c_int32), ("n_pairs", C.c_int32), ("irls_iters_run", C.c_int32),
+                ("n_small", C.c_int32), ("n_large", C.c_int32), ("fill_iters_max", C.c_int32),
+                ("fill_notconv", C.c_int32), ("fill_px_iters", C.c_int64),
+                ("fill_large_px_iters", C.c_int64), ("fill_large_launches", C.c_int32),
+                ("warm_fallbacks", C.c_int32), ("fill_max_relres", C.c_double),
+                ("quot_iters", C.c_int32 * NI_MAX_IRLS), ("energy", C.c_double * NI_MAX_IRLS),
+                ("ms_setup", C.c_float), ("ms_label", C.c_float), ("ms_segments", C.c_float),
+                ("ms_assemble", C.c_float), ("ms_warm", C.c_float), ("ms_fill_small", C.c_float),
+                ("ms_fill_large", C.c_float), ("ms_irls", C.c_float), ("ms_finalize", C.c_float),
+                ("ms_total", C.c_float)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if name in ("quot_iters", "energy"):
+                v = list(v)[: max(self.irls_iters_run, 0)]
+            d[name] = v
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libni.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        P = C.POINTER
+        L.ni_params_default.argtypes = [P(ni_params)]
+        L.ni_create.argtypes = [P(vp), C.c_int]
+        L.ni_destroy.argtypes = [vp]
+        L.ni_set_stream.argtypes = [vp, vp]
+        L.ni_integrate.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, vp, vp, i64,
+                                   P(i32), P(ni_report)]
+        L.ni_label.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, P(i32), P(ni_report)]
+        L.ni_fill.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, P(ni_report)]
+        L.ni_irls.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, vp, vp, i64,
+                              P(ni_report)]
+        L.ni_unet_load.argtypes = [vp, vp, C.c_size_t]
+        L.ni_status_str.argtypes = [C.c_int]
+        L.ni_status_str.restype = C.c_char_p
+        L.ni_last_error.argtypes = [vp]
+        L.ni_last_error.restype = C.c_char_p
+        L.ni_abi_version.restype = C.c_int32
+        for name in EXPORTED:
+            if name not in ("ni_status_str", "ni_last_error", "ni_abi_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class NIError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib().ni_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def ni_params_default(**overrides) -> ni_params:
+    p = ni_params()
+    lib().ni_params_default(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def make_camera(cam) -> ni_camera:
+    """From a dict / object with proj ('ortho'|'persp'), fx, fy, cx, cy, pixel_pitch."""
+    g = (lambda k: cam[k]) if isinstance(cam, dict) else (lambda k: getattr(cam, k))
+    proj = g("proj")
+    return ni_camera(NI_PERSP if proj == "persp" else NI_ORTHO, float(g("fx")), float(g("fy")),
+                     float(g("cx")), float(g("cy")), float(g("pixel_pitch")))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _check_inputs(normals, mask):
+    import torch
+    if not (normals.is_cuda and mask.is_cuda):
+        raise ValueError("normals and mask must be device tensors")
+    if normals.dtype != torch.float32 or normals.dim() != 3 or normals.shape[2] != 3 or not normals.is_contiguous():
+        raise ValueError("normals must be contiguous float32 [H, W, 3]")
+    if mask.dtype != torch.uint8 or tuple(mask.shape) != tuple(normals.shape[:2]) or not mask.is_contiguous():
+        raise ValueError("mask must be contiguous uint8 [H, W]")
+    if normals.device != mask.device:
+        raise ValueError("normals and mask on different devices")
+    return normals.shape[0], normals.shape[1]
+
+
+class Context:
+    """Owns an ni_ctx on one device; calls run on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = lib().ni_create(C.byref(h), int(device))
+        if st != NI_OK:
+            raise NIError(st, "ni_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ni_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        import torch
+        lib().ni_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _raise(self, st):
+        if st != NI_OK:
+            raise NIError(st, lib().ni_last_error(self.h).decode())
+
+    def ni_integrate(self, normals, mask, cam, params=None, cap=None, raise_notconv=True):
+        import torch
+        H, W = _check_inputs(normals, mask)
+        p = params or ni_params_default()
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        dev = normals.device
+        depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        labels = torch.empty((H, W), dtype=torch.int32, device=dev)
+        if cap is None:
+            cap = H * W
+        log_scale = torch.empty((max(int(cap), 1),), dtype=torch.float64, device=dev)
+        K = C.c_int32(0)
+        rep = ni_report()
+        self._stream()
+        st = lib().ni_integrate(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p), _ptr(depth),
+                                _ptr(labels), _ptr(log_scale), int(cap), C.byref(K), C.byref(rep))
+        if st != NI_OK and not (st == NI_E_NOTCONV and not raise_notconv):
+            self._raise(st)
+        return dict(depth=depth, labels=labels, log_scale=log_scale[: K.value], K=K.value,
+                    report=rep.as_dict(), status=st)
+
+    def ni_label(self, normals, mask, cam, params=None):
+        import torch
+        H, W = _check_inputs(normals, mask)
+        p = params or ni_params_default()
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        labels = torch.empty((H, W), dtype=torch.int32, device=normals.device)
+        K = C.c_int32(0)
+        rep = ni_report()
+        self._stream()
+        self._raise(lib().ni_label(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
+                                   _ptr(labels), C.byref(K), C.byref(rep)))
+        return labels, K.value, rep.as_dict()
+
+    def ni_fill(self, normals, mask, cam, labels, K, params=None):
+        import torch
+        H, W = _check_inputs(normals, mask)
+        p = params or ni_params_default()
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        labels = labels.to(device=normals.device, dtype=torch.int32).contiguous()
+        z = torch.empty((H, W), dtype=torch.float32, device=normals.device)
+        rep = ni_report()
+        self._stream()
+        self._raise(lib().ni_fill(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
+                                  _ptr(labels), int(K), _ptr(z), C.byref(rep)))
+        return z, rep.as_dict()
+
+    def ni_irls(self, normals, mask, cam, labels, K, zfill, params=None):
+        import torch
+        H, W = _check_inputs(normals, mask)
+        p = params or ni_params_default()
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        labels = labels.to(device=normals.device, dtype=torch.int32).contiguous()
+        zfill = zfill.to(device=normals.device, dtype=torch.float32).contiguous()
+        depth = torch.empty((H, W), dtype=torch.float32, device=normals.device)
+        log_scale = torch.empty((max(int(K), 1),), dtype=torch.float64, device=normals.device)
+        rep = ni_report()
+        self._stream()
+        self._raise(lib().ni_irls(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
+                                  _ptr(labels), int(K), _ptr(zfill), _ptr(depth), _ptr(log_scale), int(K),
+                                  C.byref(rep)))
+        return depth, log_scale[: int(K)], rep.as_dict()
+
+    def ni_unet_load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._raise(lib().ni_unet_load(self.h, C.cast(buf, C.c_void_p), len(blob)))

@@ -1,0 +1,927 @@
+// C ABI of libni: argument validation, workspace, stage orchestration.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/ni.h"
+#include "ni_common.h"
+
+namespace nil {
+// ni_setup.hip
+hipError_t launch_setup(const float*, const uint8_t*, int, int, int, double, const double*, double, int,
+                        uint8_t*, float*, float*, float*, int*, hipStream_t);
+hipError_t grid_components(const uint8_t*, int, int, uint8_t, uint8_t, int*, int*, int*, int*, int*, int*,
+                           hipStream_t);
+// ni_fill.hip
+int fill_small_cap();
+int fill_chunk();
+hipError_t check_labels(const int*, const uint8_t*, int, int, int*, hipStream_t);
+hipError_t check_ids(const uint32_t*, int, int, int*, hipStream_t);
+hipError_t fill_segments(const int*, int, int, int*, int*, int*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                         uint32_t*, uint32_t*, int, int*, int*, int*, hipStream_t, int);
+hipError_t fill_assemble(const uint32_t*, int, int, int, const int*, const uint8_t*, const float*, const float*,
+                         const float*, const int*, double, double, float*, float*, float*, uint32_t*, float*,
+                         float*, hipStream_t);
+hipError_t fill_classify(const int*, int, int*, int*, int*, int*, int*, int*, int*, int*, hipStream_t);
+hipError_t fill_lists(const int*, const int*, const int*, const int*, const int*, const int*, const int*, int, int*,
+                      int*, int*, int*, hipStream_t);
+hipError_t fill_zero_grid(float*, int, hipStream_t);
+hipError_t fill_gather_x0(const uint32_t*, int, const float*, float*, hipStream_t);
+hipError_t fill_small(const int*, int, const int*, const float*, const float*, const float*, const uint32_t*,
+                      const float*, const float*, const float*, const uint32_t*, float*, double, int, int, int*,
+                      double*, int*, hipStream_t);
+struct LargeArgs {
+  const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start;
+  int* cnt;
+  double *part, *rho, *bb, *tol2, *alpha, *beta, *rr;
+  int *done, *iters, *active, *stats;
+  const float *cwr, *cwd, *cwu, *rhs, *dinv;
+  const uint32_t* coff;
+  float *x, *r, *z, *p0, *p1, *q;
+  double rtol;
+  int maxit;
+};
+hipError_t large_init(const LargeArgs&, int, int, hipStream_t);
+hipError_t large_step(const LargeArgs&, int, int, hipStream_t);
+int large_persistent_blocks(int);
+hipError_t large_persistent(const LargeArgs&, int, int, unsigned*, hipStream_t);
+hipError_t large_finish(const LargeArgs&, int, const uint32_t*, float*, hipStream_t);
+// ni_quot.hip
+hipError_t quot_inter_edges(const int*, const uint8_t*, int, int, int*, int*, int*, uint32_t*, int*, hipStream_t,
+                            int);
+hipError_t quot_sort_edges(uint32_t*, int, int, int, const int*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                           uint32_t*, int*, int*, int*, int*, hipStream_t);
+hipError_t quot_pairs(const uint32_t*, const int*, const int*, int, int, const int*, int, int*, int*, int*,
+                      hipStream_t);
+hipError_t quot_csr(const int*, const int*, int, int, uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                    uint32_t*, int*, int*, int*, hipStream_t);
+struct IrlsArgs {
+  const uint32_t* eidx;
+  int E, P, K, W;
+  const int* label;
+  const uint8_t* ebits;
+  const float *nt, *om_r, *om_d, *zfill;
+  const int *pair_start, *pair_lo, *pair_hi, *row_off;
+  const uint32_t* ent;
+  double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
+  double *s, *r, *z, *p0, *p1, *q, *part, *psum;
+  int *pcnt, *parent;
+  unsigned long long* wmax;
+  unsigned* bar;
+  double* energy_out;
+  int* qiters_out;
+  double* epart;
+  double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
+  int align, outlier_mode, q_maxit, qblocks;
+};
+int qcg_max_blocks(int);
+hipError_t irls_iteration(const IrlsArgs&, int, hipStream_t);
+// ni_final.hip
+hipError_t final_outputs(const int*, const float*, const double*, const int*, const uint32_t*, const int*,
+                         const int*, int, int, int, int, double*, int*, double*, double*, float*, double*,
+                         hipStream_t);
+// ni_unet.hip
+hipError_t unet_predict(struct UnetModel*, const float*, const uint8_t*, int, int, const ni_camera*, float*,
+                        void*, size_t, hipStream_t);
+size_t unet_workspace_bytes(int, int);
+int unet_load(struct UnetModel**, const void*, size_t, std::string*);
+void unet_free(struct UnetModel*);
+}  // namespace nil
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Fail {
+  ni_status s;
+};
+
+}  // namespace
+
+struct ni_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<Buf*> bufs;
+  // grid
+  Buf ebits, om_r, om_d, nt, parent, flag, scanv, pos, zgrid, tab, xwarm;
+  // compact / sort
+  Buf key, val, skey, spix, ktmp, vtmp, kout2, cwr, cwd, cwu, coff, rhs, dinv, x, r, z, p0, p1, q;
+  // components
+  Buf comp_off, fsmall, flarge, nchunk, spos, lpos, cbase, small_list, large_list, cnt, done, iters, active,
+      rho, bb, tol2, alpha, beta, rr, relres, S, qs, qr, qz, qp0, qp1, qq, diag, qrhs, babs, psum, pcnt, qparent,
+      csum, comp_rid;
+  // chunks
+  Buf chunk_comp, chunk_start, part;
+  // edges / pairs
+  Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
+      row_off, epart, qpart, rsum, rcnt;
+  // scratch
+  Buf scan_tmp, misc, unet_ws;
+  int* host = nullptr;  // pinned readback area (64 ints)
+  hipEvent_t ev[12] = {};
+  struct nil::UnetModel* unet = nullptr;
+  int persistent_blocks = -1, qcg_blocks = -1;
+
+  ni_ctx() {
+    Buf* all[] = {&ebits, &om_r, &om_d, &nt, &parent, &flag, &scanv, &pos, &zgrid, &tab, &xwarm, &key, &val,
+                  &skey, &spix, &ktmp, &vtmp, &kout2, &cwr, &cwd, &cwu, &coff, &rhs, &dinv, &x, &r, &z, &p0,
+                  &p1, &q, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
+                  &cnt, &done, &iters, &active, &rho, &bb, &tol2, &alpha, &beta, &rr, &relres, &S, &qs, &qr,
+                  &qz, &qp0, &qp1, &qq, &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
+                  &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
+                  &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &qpart, &rsum,
+                  &rcnt, &scan_tmp, &misc, &unet_ws};
+    bufs.assign(std::begin(all), std::end(all));
+  }
+};
+
+namespace {
+
+// misc device area layout (ints unless stated)
+enum {
+  M_COUNT = 0,    // [0..7] counters written by scans
+  M_ERR = 8,      // non-finite flag
+  M_STATS = 12,   // [12..15] fill stats
+  M_ACTIVE = 16,
+  M_BAR = 20,     // 2 unsigned (fill barrier)
+  M_QBAR = 24,    // 2 unsigned (quotient barrier)
+  M_WMAX = 32,    // u64 (8-byte aligned)
+  M_ENERGY = 64,  // NI_MAX_IRLS doubles (8-byte aligned)
+  M_QITERS = 64 + 2 * NI_MAX_IRLS,
+  M_TOTAL = 64 + 3 * NI_MAX_IRLS
+};
+
+void check(ni_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    throw Fail{e == hipErrorOutOfMemory ? NI_E_NOMEM : NI_E_DEVICE};
+  }
+}
+
+template <class T>
+T* ensure(ni_ctx* c, Buf& b, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  bytes = (bytes + 255) & ~size_t(255);
+  if (b.cap < bytes) {
+    if (b.p) check(c, hipFree(b.p), "hipFree");
+    b.p = nullptr;
+    b.cap = 0;
+    size_t want = std::max(bytes, b.cap + b.cap / 4);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      check(c, e, "hipMalloc");
+    }
+    b.cap = want;
+  }
+  return (T*)b.p;
+}
+
+template <class T>
+T* ptr(Buf& b) {
+  return (T*)b.p;
+}
+
+int* misc(ni_ctx* c) { return ptr<int>(c->misc); }
+
+void readback(ni_ctx* c, const void* dev, size_t bytes, void* host) {
+  check(c, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream), "readback");
+  check(c, hipStreamSynchronize(c->stream), "stream sync");
+}
+
+float ev_ms(ni_ctx* c, int a, int b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.f;
+  return ms;
+}
+
+void mark(ni_ctx* c, int i) { check(c, hipEventRecord(c->ev[i], c->stream), "event"); }
+
+struct Problem {
+  const float* normals;
+  const uint8_t* mask;
+  int H, W, P;
+  ni_camera cam;
+  ni_params prm;
+};
+
+ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                   const ni_camera* cam, const ni_params* prm, Problem* pb) {
+  if (!c) return NI_E_ARG;
+  c->err.clear();
+  auto bad = [&](const char* m) {
+    c->err = m;
+    return NI_E_ARG;
+  };
+  if (!normals || !mask || !cam || !prm) return bad("null input pointer");
+  if (H < 1 || W < 1 || H > 32767 || W > 32767 || (long long)H * W > (1ll << 28)) return bad("H, W out of range");
+  if (cam->proj != NI_ORTHO && cam->proj != NI_PERSP) return bad("camera proj must be NI_ORTHO or NI_PERSP");
+  if (cam->proj == NI_PERSP && !(cam->fx > 0 && cam->fy > 0 && isfinite(cam->cx) && isfinite(cam->cy)))
+    return bad("perspective camera needs fx, fy > 0 and finite cx, cy");
+  if (cam->proj == NI_ORTHO && !(cam->pixel_pitch > 0)) return bad("orthographic camera needs pixel_pitch > 0");
+  if (prm->connectivity != 4) return bad("only 4-connectivity is supported");
+  if (prm->irls_iters < 1 || prm->irls_iters > NI_MAX_IRLS) return bad("irls_iters out of range");
+  if (prm->align_iters < 0) return bad("align_iters < 0");
+  if (!(prm->cg_rtol > 0) || prm->cg_max_iter < 1 || !(prm->q_rtol > 0) || prm->q_max_iter < 1)
+    return bad("bad CG tolerance / iteration cap");
+  if (!(prm->out_L > 0 && prm->out_U > prm->out_L)) return bad("need 0 < out_L < out_U");
+  if (prm->outlier_mode < 0 || prm->outlier_mode > 2) return bad("outlier_mode must be 0, 1 or 2");
+  if (!(prm->w_cut_rel >= 0 && prm->w_cut_rel < 1)) return bad("w_cut_rel must be in [0, 1)");
+  if (!(prm->bini_k > 0)) return bad("bini_k must be > 0");
+  if (prm->warm_start && !c->unet) {
+    c->err = "warm_start needs a model (ni_unet_load)";
+    return NI_E_MODEL;
+  }
+  pb->normals = normals;
+  pb->mask = mask;
+  pb->H = H;
+  pb->W = W;
+  pb->P = H * W;
+  pb->cam = *cam;
+  pb->prm = *prm;
+  return NI_OK;
+}
+
+void ensure_misc(ni_ctx* c) {
+  if (!c->misc.p) {
+    ensure<int>(c, c->misc, M_TOTAL);
+    check(c, hipMemsetAsync(c->misc.p, 0, M_TOTAL * sizeof(int), c->stream), "memset");
+  }
+}
+
+void ensure_scan(ni_ctx* c, size_t n) {
+  size_t a = nil::scan_tmp_ints((int)std::min<size_t>(n, 1u << 30));
+  size_t b = nil::radix_tmp_ints((int)std::min<size_t>(n, 1u << 30));
+  ensure<int>(c, c->scan_tmp, std::max(a, b));
+}
+
+// ----------------------------------------------------------------- stages
+void stage_setup(ni_ctx* c, const Problem& pb) {
+  const int H = pb.H, W = pb.W, P = pb.P;
+  ensure_misc(c);
+  ensure<uint8_t>(c, c->ebits, P);
+  ensure<float>(c, c->om_r, P);
+  ensure<float>(c, c->om_d, P);
+  ensure<float>(c, c->nt, P);
+  ensure<int>(c, c->parent, P);
+  ensure<int>(c, c->flag, 2 * (size_t)P);
+  ensure<int>(c, c->scanv, 2 * (size_t)P);
+  ensure<int>(c, c->pos, P);
+  ensure<float>(c, c->zgrid, P);
+  ensure_scan(c, 2 * (size_t)P);
+  // ray tables in FP64 on the host: tau = ((u - cx)/fx, (v - cy)/fy, 1) at
+  // pixel centres and at the midpoints u + 1/2, v + 1/2
+  std::vector<double> t(2 * (size_t)W + 2 * (size_t)H, 0.0);
+  if (pb.cam.proj == NI_PERSP) {
+    for (int u = 0; u < W; ++u) {
+      t[u] = ((double)u - pb.cam.cx) / pb.cam.fx;
+      t[W + H + u] = (((double)u + 0.5) - pb.cam.cx) / pb.cam.fx;
+    }
+    for (int v = 0; v < H; ++v) {
+      t[W + v] = ((double)v - pb.cam.cy) / pb.cam.fy;
+      t[2 * W + H + v] = (((double)v + 0.5) - pb.cam.cy) / pb.cam.fy;
+    }
+  }
+  double* tab = ensure<double>(c, c->tab, t.size());
+  check(c, hipMemcpyAsync(tab, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c->stream), "H2D");
+  check(c, hipStreamSynchronize(c->stream), "sync");  // t is pageable and goes out of scope
+  const double th = pb.prm.theta_c_deg;
+  const int use_sim = th > 0 ? 1 : 0;
+  const double cth = use_sim ? cos(th * M_PI / 180.0) : 2.0;
+  check(c, hipMemsetAsync(misc(c) + M_ERR, 0, sizeof(int), c->stream), "memset");
+  check(c,
+        nil::launch_setup(pb.normals, pb.mask, H, W, pb.cam.proj == NI_PERSP, pb.cam.pixel_pitch, tab, cth, use_sim,
+                          ptr<uint8_t>(c->ebits), ptr<float>(c->om_r), ptr<float>(c->om_d), ptr<float>(c->nt),
+                          misc(c) + M_ERR, c->stream),
+        "setup");
+}
+
+// components over similar edges -> labels; returns K
+int stage_label(ni_ctx* c, const Problem& pb, int32_t* labels) {
+  check(c,
+        nil::grid_components(ptr<uint8_t>(c->ebits), pb.H, pb.W, EB_SR, EB_SD, ptr<int>(c->parent),
+                             ptr<int>(c->flag), ptr<int>(c->scanv), labels, misc(c) + M_COUNT,
+                             ptr<int>(c->scan_tmp), c->stream),
+        "label");
+  readback(c, misc(c), 16 * sizeof(int), c->host);
+  if (c->host[M_ERR]) {
+    c->err = "non-finite normal inside the mask";
+    throw Fail{NI_E_NONFINITE};
+  }
+  return c->host[M_COUNT];
+}
+
+struct Seg {
+  int N = 0, K = 0;
+};
+
+}  // namespace
+
+// The segments stage needs the valid count before the compact buffers can be
+// sized, so it is split around one readback.
+namespace {
+
+Seg build_segments(ni_ctx* c, const Problem& pb, const int32_t* labels, int K, bool user_labels) {
+  const int P = pb.P;
+  Seg sg;
+  sg.K = K;
+  int* cntd = misc(c) + M_COUNT;
+  int* bad = misc(c) + M_ERR + 1;
+  if (user_labels) {
+    check(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream), "memset");
+    check(c, nil::check_labels(labels, ptr<uint8_t>(c->ebits), P, K, bad, c->stream), "check labels");
+    readback(c, bad, sizeof(int), c->host);
+    if (c->host[0]) {
+      c->err = "labels must hold ids in [0, K) on the valid pixels and -1 elsewhere";
+      throw Fail{NI_E_ARG};
+    }
+  }
+  // valid count first (flags + scan), then size the compact buffers
+  ensure<uint32_t>(c, c->key, P);
+  ensure<uint32_t>(c, c->val, P);
+  check(c,
+        nil::fill_segments(labels, P, K, ptr<int>(c->flag), ptr<int>(c->scanv), cntd, ptr<uint32_t>(c->key),
+                           ptr<uint32_t>(c->val), nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
+                           ptr<int>(c->scan_tmp), c->stream, 0),
+        "segments/compact");
+  readback(c, cntd, sizeof(int), c->host);
+  const int N = c->host[0];
+  sg.N = N;
+  ensure<uint32_t>(c, c->skey, N);
+  ensure<uint32_t>(c, c->spix, N);
+  ensure<uint32_t>(c, c->ktmp, N);
+  ensure<uint32_t>(c, c->vtmp, N);
+  ensure<int>(c, c->comp_off, (size_t)K + 1);
+  ensure_scan(c, std::max<size_t>(2 * (size_t)P, N));
+  check(c,
+        nil::fill_segments(labels, P, K, nullptr, nullptr, nullptr, ptr<uint32_t>(c->key), ptr<uint32_t>(c->val),
+                           ptr<uint32_t>(c->skey), ptr<uint32_t>(c->spix), ptr<uint32_t>(c->ktmp),
+                           ptr<uint32_t>(c->vtmp), N, ptr<int>(c->comp_off), ptr<int>(c->pos),
+                           ptr<int>(c->scan_tmp), c->stream, 1),
+        "segments/sort");
+  if (N == 0 && K >= 0) check(c, hipMemsetAsync(ptr<int>(c->comp_off), 0, sizeof(int) * (K + 1), c->stream), "memset");
+  if (user_labels) {
+    check(c, nil::check_ids(ptr<uint32_t>(c->skey), N, K, bad, c->stream), "check ids");
+    readback(c, bad, sizeof(int), c->host);
+    if (c->host[0] || (N == 0 && K != 0)) {
+      c->err = "every component id 0..K-1 must label at least one valid pixel";
+      throw Fail{NI_E_ARG};
+    }
+  }
+  return sg;
+}
+
+void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& sg, float* zout,
+                ni_report* rep) {
+  const int P = pb.P, W = pb.W, N = sg.N, K = sg.K;
+  const bool persp = pb.cam.proj == NI_PERSP;
+  const double g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
+  const double g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
+  float* cwr = ensure<float>(c, c->cwr, N);
+  float* cwd = ensure<float>(c, c->cwd, N);
+  float* cwu = ensure<float>(c, c->cwu, N);
+  uint32_t* coff = ensure<uint32_t>(c, c->coff, N);
+  float* rhs = ensure<float>(c, c->rhs, N);
+  float* dinv = ensure<float>(c, c->dinv, N);
+  float* x = ensure<float>(c, c->x, N);
+  float* r = ensure<float>(c, c->r, N);
+  float* z = ensure<float>(c, c->z, N);
+  float* p0 = ensure<float>(c, c->p0, N);
+  float* p1 = ensure<float>(c, c->p1, N);
+  float* q = ensure<float>(c, c->q, N);
+  const uint32_t* cpix = ptr<uint32_t>(c->spix);
+  const int* comp_off = ptr<int>(c->comp_off);
+  mark(c, 3);
+  check(c,
+        nil::fill_assemble(cpix, N, W, P, labels, ptr<uint8_t>(c->ebits), ptr<float>(c->nt), ptr<float>(c->om_r),
+                           ptr<float>(c->om_d), ptr<int>(c->pos), g2fx, g2fy, cwr, cwd, cwu, coff, rhs, dinv,
+                           c->stream),
+        "assemble");
+  size_t K1 = (size_t)K + 1;
+  int* fsmall = ensure<int>(c, c->fsmall, K1);
+  int* flarge = ensure<int>(c, c->flarge, K1);
+  int* nchunk = ensure<int>(c, c->nchunk, K1);
+  int* spos = ensure<int>(c, c->spos, K1);
+  int* lpos = ensure<int>(c, c->lpos, K1);
+  int* cbase = ensure<int>(c, c->cbase, K1);
+  int* small_list = ensure<int>(c, c->small_list, K1);
+  int* large_list = ensure<int>(c, c->large_list, K1);
+  int* cnt = ensure<int>(c, c->cnt, K1);
+  int* done = ensure<int>(c, c->done, K1);
+  int* iters = ensure<int>(c, c->iters, K1);
+  double* rho = ensure<double>(c, c->rho, K1);
+  double* bb = ensure<double>(c, c->bb, K1);
+  double* tol2 = ensure<double>(c, c->tol2, K1);
+  double* alpha = ensure<double>(c, c->alpha, K1);
+  double* beta = ensure<double>(c, c->beta, K1);
+  double* rr = ensure<double>(c, c->rr, K1);
+  double* relres = ensure<double>(c, c->relres, K1);
+  int* cntd = misc(c) + M_COUNT;
+  check(c, nil::fill_classify(comp_off, K, fsmall, flarge, nchunk, spos, lpos, cbase, cntd, ptr<int>(c->scan_tmp),
+                              c->stream),
+        "classify");
+  readback(c, cntd, 4 * sizeof(int), c->host);
+  const int n_small = c->host[0], n_large = c->host[1], n_chunks = c->host[2];
+  int* chunk_comp = ensure<int>(c, c->chunk_comp, n_chunks);
+  int* chunk_start = ensure<int>(c, c->chunk_start, n_chunks);
+  double* part = ensure<double>(c, c->part, 4 * (size_t)std::max(n_chunks, 1));
+  check(c, nil::fill_lists(fsmall, flarge, spos, lpos, nchunk, cbase, comp_off, K, small_list, large_list,
+                           chunk_comp, chunk_start, c->stream),
+        "lists");
+  check(c, hipMemsetAsync(cnt, 0, K1 * sizeof(int), c->stream), "memset");
+  check(c, hipMemsetAsync(iters, 0, K1 * sizeof(int), c->stream), "memset");
+  check(c, hipMemsetAsync(relres, 0, K1 * sizeof(double), c->stream), "memset");
+  check(c, hipMemsetAsync(misc(c) + M_STATS, 0, 8 * sizeof(int), c->stream), "memset");
+  check(c, nil::fill_zero_grid(zout, P, c->stream), "zero");
+  const int warm = pb.prm.warm_start ? 1 : 0;
+  mark(c, 4);
+  const float* xw = nullptr;
+  if (warm) {
+    float* xg = ensure<float>(c, c->xwarm, P);
+    size_t wsb = nil::unet_workspace_bytes(pb.H, pb.W);
+    void* ws = ensure<uint8_t>(c, c->unet_ws, wsb);
+    check(c, nil::unet_predict(c->unet, pb.normals, pb.mask, pb.H, pb.W, &pb.cam, xg, ws, wsb, c->stream), "unet");
+    xw = xg;
+  }
+  check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
+  mark(c, 5);
+  check(c, nil::fill_small(small_list, n_small, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x, cpix, zout,
+                           pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, iters, relres, misc(c) + M_STATS, c->stream),
+        "fill small");
+  mark(c, 6);
+  int launches = 0;
+  if (n_large > 0) {
+    nil::LargeArgs a;
+    a.comp_off = comp_off; a.cbase = cbase; a.nchunk = nchunk; a.chunk_comp = chunk_comp;
+    a.chunk_start = chunk_start; a.cnt = cnt; a.part = part; a.rho = rho; a.bb = bb; a.tol2 = tol2;
+    a.alpha = alpha; a.beta = beta; a.rr = rr; a.done = done; a.iters = iters;
+    a.active = misc(c) + M_ACTIVE; a.stats = misc(c) + M_STATS;
+    a.cwr = cwr; a.cwd = cwd; a.cwu = cwu; a.rhs = rhs; a.dinv = dinv; a.coff = coff;
+    a.x = x; a.r = r; a.z = z; a.p0 = p0; a.p1 = p1; a.q = q;
+    a.rtol = pb.prm.cg_rtol; a.maxit = pb.prm.cg_max_iter;
+    check(c, hipMemsetAsync(a.active, 0, sizeof(int), c->stream), "memset");
+    check(c, hipMemsetAsync(done, 0, K1 * sizeof(int), c->stream), "memset");
+    check(c, nil::large_init(a, n_chunks, warm, c->stream), "large init");
+    bool ran = false;
+    if (pb.prm.persistent) {
+      if (c->persistent_blocks < 0) c->persistent_blocks = nil::large_persistent_blocks(c->device);
+      int nb = std::min(c->persistent_blocks, n_chunks);
+      if (nb > 0) {
+        unsigned* bar = (unsigned*)(misc(c) + M_BAR);
+        check(c, hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), c->stream), "memset");
+        hipError_t e = nil::large_persistent(a, n_chunks, nb, bar, c->stream);
+        if (e == hipSuccess) ran = true;
+        else (void)hipGetLastError();
+      }
+    }
+    if (!ran) {
+      // one launch per CG phase; the host polls the active count in batches
+      const int batch = 16;
+      for (int it = 0;; it += batch) {
+        for (int k = 0; k < batch; ++k) check(c, nil::large_step(a, n_chunks, (it + k) & 1, c->stream), "large step");
+        launches += 2 * batch;
+        readback(c, a.active, sizeof(int), c->host);
+        if (c->host[0] <= 0) break;
+        if (it > pb.prm.cg_max_iter + batch) break;
+      }
+    }
+    check(c, nil::large_finish(a, n_chunks, cpix, zout, c->stream), "large finish");
+  }
+  mark(c, 7);
+  // report
+  readback(c, misc(c) + M_STATS, 4 * sizeof(int), c->host);
+  const int notconv = c->host[0], fallbacks = c->host[1];
+  if (rep) {
+    std::vector<int> it(K), off(K1);
+    std::vector<double> rel(K);
+    if (K > 0) {
+      check(c, hipMemcpyAsync(it.data(), iters, K * sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipMemcpyAsync(off.data(), comp_off, K1 * sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipMemcpyAsync(rel.data(), relres, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
+      // large components: relative residual from rr / bb
+      std::vector<double> hrr(K), hbb(K);
+      check(c, hipMemcpyAsync(hrr.data(), rr, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipMemcpyAsync(hbb.data(), bb, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipStreamSynchronize(c->stream), "sync");
+      int cap = nil::fill_small_cap();
+      long long pxit = 0, lpxit = 0;
+      int itmax = 0;
+      double rmax = 0;
+      for (int k = 0; k < K; ++k) {
+        int n = off[k + 1] - off[k];
+        pxit += (long long)n * it[k];
+        if (n > cap) {
+          lpxit += (long long)n * it[k];
+          rel[k] = hbb[k] > 0 ? sqrt(hrr[k] / hbb[k]) : 0.0;
+        }
+        itmax = std::max(itmax, it[k]);
+        rmax = std::max(rmax, rel[k]);
+      }
+      rep->fill_px_iters = pxit;
+      rep->fill_large_px_iters = lpxit;
+      rep->fill_iters_max = itmax;
+      rep->fill_max_relres = rmax;
+    }
+    rep->n_small = n_small;
+    rep->n_large = n_large;
+    rep->fill_notconv = notconv;
+    rep->fill_large_launches = launches;
+    rep->warm_fallbacks = fallbacks;
+    rep->ms_assemble = ev_ms(c, 3, 4);
+    rep->ms_warm = ev_ms(c, 4, 5);
+    rep->ms_fill_small = ev_ms(c, 5, 6);
+    rep->ms_fill_large = ev_ms(c, 6, 7);
+  }
+  if (notconv > 0) {
+    c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";
+    throw Fail{NI_E_NOTCONV};
+  }
+}
+
+void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& sg, const float* zfill,
+                float* depth, double* log_scale, ni_report* rep) {
+  const int P = pb.P, W = pb.W, K = sg.K;
+  const bool persp = pb.cam.proj == NI_PERSP;
+  int* cntd = misc(c) + M_COUNT;
+  mark(c, 8);
+  // inter-component edges
+  check(c, nil::quot_inter_edges(labels, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
+                                 nullptr, ptr<int>(c->scan_tmp), c->stream, 0),
+        "inter edges");
+  readback(c, cntd, sizeof(int), c->host);
+  const int E = c->host[0];
+  uint32_t* eidx_raw = ensure<uint32_t>(c, c->eidx_raw, E);
+  uint32_t* eidx = ensure<uint32_t>(c, c->eidx, E);
+  check(c, nil::quot_inter_edges(labels, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
+                                 eidx_raw, ptr<int>(c->scan_tmp), c->stream, 1),
+        "inter compact");
+  size_t srt = std::max<size_t>(E, 1);
+  uint32_t* keys = ensure<uint32_t>(c, c->key, std::max<size_t>(srt, P));
+  uint32_t* ktmp = ensure<uint32_t>(c, c->ktmp, srt);
+  uint32_t* vtmp = ensure<uint32_t>(c, c->vtmp, srt);
+  uint32_t* kout2 = ensure<uint32_t>(c, c->kout2, srt);
+  int* pflag = ensure<int>(c, c->pflag, srt);
+  int* ppos = ensure<int>(c, c->ppos, srt);
+  ensure_scan(c, std::max<size_t>(2 * (size_t)P, srt));
+  check(c, nil::quot_sort_edges(eidx_raw, E, W, K, labels, keys, eidx, ktmp, vtmp, kout2, pflag, ppos, cntd,
+                                ptr<int>(c->scan_tmp), c->stream),
+        "sort edges");
+  readback(c, cntd, sizeof(int), c->host);
+  const int Pp = c->host[0];
+  int* pair_start = ensure<int>(c, c->pair_start, (size_t)Pp + 1);
+  int* pair_lo = ensure<int>(c, c->pair_lo, Pp);
+  int* pair_hi = ensure<int>(c, c->pair_hi, Pp);
+  check(c, nil::quot_pairs(eidx, pflag, ppos, E, W, labels, Pp, pair_start, pair_lo, pair_hi, c->stream), "pairs");
+  size_t P2 = std::max<size_t>(2 * (size_t)Pp, 1);
+  uint32_t* ent = ensure<uint32_t>(c, c->ent, P2);
+  uint32_t* ent_tmp = ensure<uint32_t>(c, c->ent_tmp, P2);
+  keys = ensure<uint32_t>(c, c->key, std::max<size_t>({srt, (size_t)P, P2}));
+  ktmp = ensure<uint32_t>(c, c->ktmp, std::max(srt, P2));
+  vtmp = ensure<uint32_t>(c, c->vtmp, std::max(srt, P2));
+  kout2 = ensure<uint32_t>(c, c->kout2, std::max(srt, P2));
+  ensure_scan(c, std::max<size_t>({2 * (size_t)P, srt, P2}));
+  size_t K1 = (size_t)K + 1;
+  int* rowcnt = ensure<int>(c, c->rowcnt, K1);
+  int* row_off = ensure<int>(c, c->row_off, K1);
+  check(c, nil::quot_csr(pair_lo, pair_hi, Pp, K, keys, ent, ktmp, vtmp, kout2, ent_tmp, rowcnt, row_off,
+                         ptr<int>(c->scan_tmp), c->stream),
+        "csr");
+  // per-iteration arrays
+  nil::IrlsArgs a;
+  a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
+  a.nt = ptr<float>(c->nt); a.om_r = ptr<float>(c->om_r); a.om_d = ptr<float>(c->om_d); a.zfill = zfill;
+  a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
+  a.S = ensure<double>(c, c->S, K1);
+  a.ew = ensure<double>(c, c->ew, srt);
+  a.erho = ensure<double>(c, c->erho, srt);
+  a.pW = ensure<double>(c, c->pW, std::max(Pp, 1));
+  a.pB = ensure<double>(c, c->pB, std::max(Pp, 1));
+  a.diag = ensure<double>(c, c->diag, K1);
+  a.rhs = ensure<double>(c, c->qrhs, K1);
+  a.babs = ensure<double>(c, c->babs, K1);
+  a.s = ensure<double>(c, c->qs, K1);
+  a.r = ensure<double>(c, c->qr, K1);
+  a.z = ensure<double>(c, c->qz, K1);
+  a.p0 = ensure<double>(c, c->qp0, K1);
+  a.p1 = ensure<double>(c, c->qp1, K1);
+  a.q = ensure<double>(c, c->qq, K1);
+  a.psum = ensure<double>(c, c->psum, K1);
+  a.pcnt = ensure<int>(c, c->pcnt, K1);
+  a.parent = ensure<int>(c, c->qparent, K1);
+  a.wmax = (unsigned long long*)(misc(c) + M_WMAX);
+  a.bar = (unsigned*)(misc(c) + M_QBAR);
+  a.energy_out = (double*)(misc(c) + M_ENERGY);
+  a.qiters_out = misc(c) + M_QITERS;
+  a.epart = ensure<double>(c, c->epart, (size_t)ni::ceil_div(std::max(Pp, 1), 256));
+  a.g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
+  a.g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
+  a.k = pb.prm.bini_k; a.L = pb.prm.out_L; a.U = pb.prm.out_U; a.cut_rel = pb.prm.w_cut_rel;
+  a.q_rtol = pb.prm.q_rtol; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
+  a.q_maxit = pb.prm.q_max_iter;
+  if (c->qcg_blocks < 0) c->qcg_blocks = nil::qcg_max_blocks(c->device);
+  a.qblocks = K <= 8192 ? 1 : std::max(1, std::min(c->qcg_blocks, std::min(256, ni::ceil_div(K, 2048))));
+  a.part = ensure<double>(c, c->qpart, 3 * 4 * (size_t)std::max(a.qblocks, 1));
+  check(c, hipMemsetAsync(a.S, 0, K1 * sizeof(double), c->stream), "memset");
+  check(c, hipMemsetAsync(a.bar, 0, 2 * sizeof(unsigned), c->stream), "memset");
+  const int T = pb.prm.irls_iters;
+  int ran = 0;
+  std::vector<double> en(NI_MAX_IRLS, 0.0);
+  for (int t = 0; t < T; ++t) {
+    check(c, nil::irls_iteration(a, t, c->stream), "irls");
+    ran = t + 1;
+    if (pb.prm.delta_e_max > 0 && t >= pb.prm.align_iters + 1) {
+      readback(c, a.energy_out, sizeof(double) * (t + 1), en.data());
+      double Ep = en[t - 1], Et = en[t];
+      if (Ep == 0.0 || fabs(Et - Ep) / Ep < pb.prm.delta_e_max) break;
+    }
+  }
+  mark(c, 9);
+  // regions of G_0 and outputs
+  check(c,
+        nil::grid_components(ptr<uint8_t>(c->ebits), pb.H, W, EB_VR, EB_VD, ptr<int>(c->parent), ptr<int>(c->flag),
+                             ptr<int>(c->scanv), nullptr, cntd + 1, ptr<int>(c->scan_tmp), c->stream),
+        "regions");
+  readback(c, cntd + 1, sizeof(int), c->host);
+  const int R = c->host[0];
+  double* csum = ensure<double>(c, c->csum, K1);
+  int* comp_rid = ensure<int>(c, c->comp_rid, K1);
+  double* rsum = ensure<double>(c, c->rsum, std::max(R, 1));
+  double* rcnt = ensure<double>(c, c->rcnt, std::max(R, 1));
+  check(c, nil::final_outputs(labels, zfill, a.S, ptr<int>(c->comp_off), ptr<uint32_t>(c->spix), ptr<int>(c->parent),
+                              ptr<int>(c->scanv), K, R, P, persp ? 1 : 0, csum, comp_rid, rsum, rcnt, depth,
+                              log_scale, c->stream),
+        "finalize");
+  mark(c, 10);
+  check(c, hipStreamSynchronize(c->stream), "sync");
+  if (rep) {
+    rep->n_regions = R;
+    rep->n_inter_edges = E;
+    rep->n_pairs = Pp;
+    rep->irls_iters_run = ran;
+    std::vector<int> qi(NI_MAX_IRLS, 0);
+    check(c, hipMemcpy(en.data(), a.energy_out, sizeof(double) * NI_MAX_IRLS, hipMemcpyDeviceToHost), "D2H");
+    check(c, hipMemcpy(qi.data(), a.qiters_out, sizeof(int) * NI_MAX_IRLS, hipMemcpyDeviceToHost), "D2H");
+    for (int t = 0; t < NI_MAX_IRLS; ++t) {
+      rep->energy[t] = t < ran ? en[t] : 0.0;
+      rep->quot_iters[t] = t < ran ? qi[t] : 0;
+    }
+    rep->ms_irls = ev_ms(c, 8, 9);
+    rep->ms_finalize = ev_ms(c, 9, 10);
+  }
+}
+
+template <class F>
+ni_status guarded(ni_ctx* c, F&& f) {
+  try {
+    f();
+    return NI_OK;
+  } catch (const Fail& e) {
+    return e.s;
+  } catch (...) {
+    c->err = "internal error";
+    return NI_E_DEVICE;
+  }
+}
+
+void begin(ni_ctx* c, ni_report* rep) {
+  check(c, hipSetDevice(c->device), "hipSetDevice");
+  if (rep) memset(rep, 0, sizeof(*rep));
+  mark(c, 0);
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+int32_t ni_abi_version(void) { return NI_ABI_VERSION; }
+
+ni_status ni_params_default(ni_params* p) {
+  if (!p) return NI_E_ARG;
+  memset(p, 0, sizeof(*p));
+  p->theta_c_deg = 2.0;
+  p->connectivity = 4;
+  p->irls_iters = 15;
+  p->align_iters = 2;
+  p->bini_k = 2.0;
+  p->out_L = 1e-5;
+  p->out_U = 1e-3;
+  p->outlier_mode = 1;
+  p->delta_e_max = 0.0;
+  p->w_cut_rel = 1e-8;
+  p->cg_rtol = 1e-6;
+  p->cg_max_iter = 50000;
+  p->q_rtol = 1e-12;
+  p->q_max_iter = 20000;
+  p->warm_start = 0;
+  p->persistent = 1;
+  return NI_OK;
+}
+
+ni_status ni_create(ni_ctx** out, int device) {
+  if (!out) return NI_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NI_E_DEVICE;
+  ni_ctx* c = new (std::nothrow) ni_ctx();
+  if (!c) return NI_E_NOMEM;
+  c->device = device;
+  ni_status s = guarded(c, [&] {
+    check(c, hipSetDevice(device), "hipSetDevice");
+    check(c, hipHostMalloc((void**)&c->host, 64 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+    for (auto& e : c->ev) check(c, hipEventCreate(&e), "hipEventCreate");
+  });
+  if (s != NI_OK) {
+    ni_destroy(c);
+    return s;
+  }
+  *out = c;
+  return NI_OK;
+}
+
+ni_status ni_destroy(ni_ctx* c) {
+  if (!c) return NI_E_ARG;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (Buf* b : c->bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->host) (void)hipHostFree(c->host);
+  if (c->unet) nil::unet_free(c->unet);
+  delete c;
+  return NI_OK;
+}
+
+ni_status ni_set_stream(ni_ctx* c, void* s) {
+  if (!c) return NI_E_ARG;
+  c->stream = (hipStream_t)s;
+  return NI_OK;
+}
+
+ni_status ni_integrate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                       const ni_camera* cam, const ni_params* params, float* depth, int32_t* labels,
+                       double* log_scale, int64_t cap, int32_t* K, ni_report* rep) {
+  Problem pb;
+  ni_status s = validate(c, normals, mask, H, W, cam, params, &pb);
+  if (s != NI_OK) return s;
+  if (!depth || !labels || !K || (cap > 0 && !log_scale) || cap < 0) {
+    c->err = "null output pointer or negative cap";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    begin(c, rep);
+    stage_setup(c, pb);
+    mark(c, 1);
+    int k = stage_label(c, pb, labels);
+    mark(c, 2);
+    *K = k;
+    if (rep) {
+      rep->K = k;
+      rep->ms_setup = ev_ms(c, 0, 1);
+      rep->ms_label = ev_ms(c, 1, 2);
+    }
+    if ((int64_t)k > cap) {
+      c->err = "log_scale capacity smaller than K";
+      throw Fail{NI_E_SHAPE};
+    }
+    Seg sg = build_segments(c, pb, labels, k, false);
+    if (rep) rep->n_valid = sg.N;
+    float* zf = ptr<float>(c->zgrid);
+    ni_status fs = NI_OK;
+    try {
+      stage_fill(c, pb, labels, sg, zf, rep);
+    } catch (const Fail& f) {
+      if (f.s != NI_E_NOTCONV) throw;
+      fs = f.s;
+    }
+    stage_irls(c, pb, labels, sg, zf, depth, log_scale, rep);
+    if (rep) {
+      mark(c, 11);
+      check(c, hipEventSynchronize(c->ev[11]), "sync");
+      rep->ms_segments = ev_ms(c, 2, 3);
+      rep->ms_total = ev_ms(c, 0, 11);
+    }
+    if (fs != NI_OK) throw Fail{fs};
+  });
+}
+
+ni_status ni_label(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                   const ni_camera* cam, const ni_params* params, int32_t* labels, int32_t* K, ni_report* rep) {
+  Problem pb;
+  ni_status s = validate(c, normals, mask, H, W, cam, params, &pb);
+  if (s != NI_OK) return s;
+  if (!labels || !K) {
+    c->err = "null output pointer";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    begin(c, rep);
+    stage_setup(c, pb);
+    mark(c, 1);
+    *K = stage_label(c, pb, labels);
+    mark(c, 2);
+    check(c, hipStreamSynchronize(c->stream), "sync");
+    if (rep) {
+      rep->K = *K;
+      rep->ms_setup = ev_ms(c, 0, 1);
+      rep->ms_label = ev_ms(c, 1, 2);
+    }
+  });
+}
+
+ni_status ni_fill(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W, const ni_camera* cam,
+                  const ni_params* params, const int32_t* labels, int32_t K, float* zfill, ni_report* rep) {
+  Problem pb;
+  ni_status s = validate(c, normals, mask, H, W, cam, params, &pb);
+  if (s != NI_OK) return s;
+  if (!labels || !zfill || K < 0 || (int64_t)K > (int64_t)H * W) {
+    c->err = "null pointer or K out of range";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    begin(c, rep);
+    stage_setup(c, pb);
+    readback(c, misc(c), 16 * sizeof(int), c->host);
+    if (c->host[M_ERR]) {
+      c->err = "non-finite normal inside the mask";
+      throw Fail{NI_E_NONFINITE};
+    }
+    Seg sg = build_segments(c, pb, labels, K, true);
+    if (rep) {
+      rep->K = K;
+      rep->n_valid = sg.N;
+    }
+    stage_fill(c, pb, labels, sg, zfill, rep);
+    check(c, hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+ni_status ni_irls(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W, const ni_camera* cam,
+                  const ni_params* params, const int32_t* labels, int32_t K, const float* zfill, float* depth,
+                  double* log_scale, int64_t cap, ni_report* rep) {
+  Problem pb;
+  ni_status s = validate(c, normals, mask, H, W, cam, params, &pb);
+  if (s != NI_OK) return s;
+  if (!labels || !zfill || !depth || K < 0 || (int64_t)K > (int64_t)H * W || (K > 0 && !log_scale)) {
+    c->err = "null pointer or K out of range";
+    return NI_E_ARG;
+  }
+  if (cap < K) {
+    c->err = "log_scale capacity smaller than K";
+    return NI_E_SHAPE;
+  }
+  return guarded(c, [&] {
+    begin(c, rep);
+    stage_setup(c, pb);
+    readback(c, misc(c), 16 * sizeof(int), c->host);
+    if (c->host[M_ERR]) {
+      c->err = "non-finite normal inside the mask";
+      throw Fail{NI_E_NONFINITE};
+    }
+    Seg sg = build_segments(c, pb, labels, K, true);
+    if (rep) {
+      rep->K = K;
+      rep->n_valid = sg.N;
+    }
+    stage_irls(c, pb, labels, sg, zfill, depth, log_scale, rep);
+  });
+}
+
+ni_status ni_unet_load(ni_ctx* c, const void* blob, size_t nbytes) {
+  if (!c || !blob) return NI_E_ARG;
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    nil::UnetModel* m = nullptr;
+    if (!nil::unet_load(&m, blob, nbytes, &c->err)) throw Fail{NI_E_MODEL};
+    if (c->unet) nil::unet_free(c->unet);
+    c->unet = m;
+  });
+}
+
+const char* ni_status_str(ni_status s) {
+  switch (s) {
+    case NI_OK: return "ok";
+    case NI_E_ARG: return "invalid argument";
+    case NI_E_SHAPE: return "output capacity too small";
+    case NI_E_NONFINITE: return "non-finite normal inside the mask";
+    case NI_E_NOMEM: return "out of device memory";
+    case NI_E_DEVICE: return "HIP runtime error";
+    case NI_E_NOTCONV: return "a CG solve hit its iteration cap";
+    case NI_E_MODEL: return "bad or missing warm-start model";
+  }
+  return "unknown status";
+}
+
+const char* ni_last_error(const ni_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

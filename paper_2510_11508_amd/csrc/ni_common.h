@@ -1,0 +1,103 @@
+// Internal helpers shared by the HIP kernels of libni (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define NI_WAVE 64
+
+// per-pixel edge bits written by the setup kernel
+enum : uint8_t {
+  EB_VR = 1,    // edge to the right neighbour usable
+  EB_VD = 2,    // edge to the lower neighbour usable
+  EB_SR = 4,    // ... and normals similar (theta < theta_c)
+  EB_SD = 8,
+  EB_VALID = 128
+};
+
+namespace ni {
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+  // fixed butterfly order: every lane ends with the same, deterministic sum
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, NI_WAVE);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, NI_WAVE);
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, NI_WAVE);
+  return v;
+}
+
+// Block-wide sum of NV doubles; every thread receives the totals.  `scratch`
+// must hold NV * (blockDim/64) doubles and must not be reused by the caller
+// until a later __syncthreads(); the sum order is fixed (deterministic).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) scratch[k * nw + wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += scratch[k * nw + w];
+    v[k] = s;
+  }
+}
+
+// ------------------------------------------------------------- grid barrier
+// Sense-reversing barrier for a co-resident (cooperatively launched) grid.
+// bar[0] = arrival count, bar[1] = generation.  The fences make every global
+// write issued before the barrier visible to every block after it, across
+// the XCDs' separate L2 caches (agent-scope release / acquire).
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  }
+  __syncthreads();
+}
+
+__host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace ni
+
+// ------------------------------------------------------------- host launchers
+// Each .hip file exposes plain host functions that enqueue its kernels on a
+// stream; they return the HIP error of the launch.
+namespace nil {
+
+hipError_t scan_exclusive_i32(const int* in, int* out, int n, int* total_dev,
+                              int* tmp, hipStream_t st);
+size_t scan_tmp_ints(int n);
+
+// stable LSD radix sort of (key, val) by the low `bits` bits of key.  The
+// result lands in (k_out, v_out); (k_tmp, v_tmp) are scratch of length n.
+hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t* k_out,
+                            uint32_t* v_out, uint32_t* k_tmp, uint32_t* v_tmp, int n,
+                            int bits, int* scan_tmp, hipStream_t st);
+size_t radix_tmp_ints(int n);
+
+}  // namespace nil

@@ -1,0 +1,88 @@
+// Output stage: log-depth z = zfill + S_pi, shifted to zero pixel mean over
+// every connected region of the full pixel graph G_0 (the gauge the method
+// leaves free: depth is recovered up to one scale per region, Sec. 3.1);
+// depth = exp(z) in perspective and z in orthographic mode.
+#include "ni_common.h"
+
+namespace {
+
+// one block per component: FP64 sum of its filled log-depth (fixed order)
+__global__ void __launch_bounds__(256) k_comp_sums(const int* __restrict__ comp_off, const uint32_t* __restrict__ cpix,
+                                                   const float* __restrict__ zfill, double* __restrict__ csum) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double v[1] = {0.0};
+  for (int i = comp_off[c] + threadIdx.x; i < comp_off[c + 1]; i += blockDim.x) v[0] += zfill[cpix[i]];
+  ni::block_sum<1>(v, red);
+  if (threadIdx.x == 0) csum[c] = v[0];
+}
+
+__global__ void k_comp_region(const int* __restrict__ comp_off, const uint32_t* __restrict__ cpix,
+                              const int* __restrict__ parent, const int* __restrict__ cid, int K,
+                              int* __restrict__ comp_rid) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K) comp_rid[c] = cid[parent[cpix[comp_off[c]]]];
+}
+
+__global__ void k_region_zero(double* rsum, double* rcnt, int R) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R) {
+    rsum[i] = 0.0;
+    rcnt[i] = 0.0;
+  }
+}
+
+__global__ void k_region_acc(const int* __restrict__ comp_off, const double* __restrict__ csum,
+                             const double* __restrict__ S, const int* __restrict__ comp_rid, int K,
+                             double* __restrict__ rsum, double* __restrict__ rcnt) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  double n = (double)(comp_off[c + 1] - comp_off[c]);
+  atomicAdd(&rsum[comp_rid[c]], csum[c] + n * S[c]);
+  atomicAdd(&rcnt[comp_rid[c]], n);
+}
+
+__global__ void k_final_out(const int* __restrict__ label, const float* __restrict__ zfill,
+                            const double* __restrict__ S, const int* __restrict__ parent,
+                            const int* __restrict__ cid, const double* __restrict__ rsum,
+                            const double* __restrict__ rcnt, int P, int persp, float* __restrict__ depth) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int c = label[p];
+  float out = __builtin_nanf("");
+  if (c >= 0) {
+    int rid = cid[parent[p]];
+    double z = (double)zfill[p] + S[c] - rsum[rid] / rcnt[rid];
+    out = persp ? (float)exp(z) : (float)z;
+  }
+  depth[p] = out;
+}
+
+__global__ void k_final_scale(const double* __restrict__ S, const int* __restrict__ comp_rid,
+                              const double* __restrict__ rsum, const double* __restrict__ rcnt, int K,
+                              double* __restrict__ log_scale) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K) log_scale[c] = S[c] - rsum[comp_rid[c]] / rcnt[comp_rid[c]];
+}
+
+}  // namespace
+
+namespace nil {
+
+hipError_t final_outputs(const int* label, const float* zfill, const double* S, const int* comp_off,
+                         const uint32_t* cpix, const int* parent, const int* cid, int K, int R, int P, int persp,
+                         double* csum, int* comp_rid, double* rsum, double* rcnt, float* depth, double* log_scale,
+                         hipStream_t st) {
+  if (K > 0) {
+    k_comp_sums<<<K, 256, 0, st>>>(comp_off, cpix, zfill, csum);
+    k_comp_region<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, cpix, parent, cid, K, comp_rid);
+  }
+  if (R > 0) k_region_zero<<<ni::ceil_div(R, 256), 256, 0, st>>>(rsum, rcnt, R);
+  if (K > 0) k_region_acc<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, csum, S, comp_rid, K, rsum, rcnt);
+  k_final_out<<<ni::ceil_div(P, 256), 256, 0, st>>>(label, zfill, S, parent, cid, rsum, rcnt, P, persp, depth);
+  if (K > 0 && log_scale)
+    k_final_scale<<<ni::ceil_div(K, 256), 256, 0, st>>>(S, comp_rid, rsum, rcnt, K, log_scale);
+  return hipGetLastError();
+}
+
+}  // namespace nil

@@ -1,0 +1,223 @@
+// Edge setup (model of continuity, Sec. 3.1 / Eq. 3 and Eq. 7) and
+// union-find connected components on the pixel grid (Sec. 3.3).
+#include "ni_common.h"
+
+namespace {
+
+// FP64 arithmetic whose rounding must match the FP64 reference bit for bit:
+// explicit round-to-nearest intrinsics, never contracted into FMAs.
+__device__ __forceinline__ double mul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double add(double a, double b) { return __dadd_rn(a, b); }
+// (nx*tx + ny*ty) + nz  -- n . tau with tau_z = 1
+__device__ __forceinline__ double ndot(double nx, double ny, double nz, double tx, double ty) {
+  return add(add(mul(nx, tx), mul(ny, ty)), nz);
+}
+__device__ __forceinline__ bool same_sign_nz(double a, double b) {
+  return a != 0.0 && b != 0.0 && ((a > 0.0) == (b > 0.0));
+}
+
+// One thread per pixel a; it owns the edges to its right and lower
+// neighbours b.  Writes:
+//   ebits[a]  EB_VALID | usable/similar bits of its two edges
+//   om_r/om_d omega_{b->a} (FP32), 0 where unusable
+//   nt[a]     n_a . tau_a (perspective) or n_az (orthographic), FP32
+// Perspective: the four dots d_aa, d_am, d_bb, d_bm of Eq. 3; the edge is
+// usable iff (d_aa, d_am) and (d_bb, d_bm) are non-zero pairs of one sign,
+// and omega = log((d_am/d_aa)*(d_bb/d_bm)).  Orthographic: usable iff
+// n_az, n_bz != 0, omega = s*(n_a.d/(2 n_az) + n_b.d/(2 n_bz)).
+// Similar iff usable and (n_ax n_bx + n_ay n_by) + n_az n_bz > cos(theta_c).
+__global__ void __launch_bounds__(256) k_setup(
+    const float* __restrict__ nrm, const uint8_t* __restrict__ mask, int H, int W, int persp,
+    double pitch, const double* __restrict__ tx, const double* __restrict__ ty,
+    const double* __restrict__ txm, const double* __restrict__ tym, double cth, int use_sim,
+    uint8_t* __restrict__ ebits, float* __restrict__ om_r, float* __restrict__ om_d,
+    float* __restrict__ nt, int* __restrict__ err) {
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (long long)H * W) return;
+  const int u = (int)(p % W), v = (int)(p / W);
+  uint8_t eb = 0;
+  float o_r = 0.f, o_d = 0.f, ntp = 0.f;
+  if (mask[p]) {
+    const float ax = nrm[3 * p], ay = nrm[3 * p + 1], az = nrm[3 * p + 2];
+    if (!(isfinite(ax) && isfinite(ay) && isfinite(az))) atomicOr(err, 1);
+    const double nax = ax, nay = ay, naz = az;
+    const double daa = persp ? ndot(nax, nay, naz, tx[u], ty[v]) : naz;
+    ntp = (float)daa;
+    eb = EB_VALID;
+    if (u + 1 < W && mask[p + 1]) {
+      const double nbx = nrm[3 * p + 3], nby = nrm[3 * p + 4], nbz = nrm[3 * p + 5];
+      bool ok;
+      double om = 0.0;
+      if (persp) {
+        const double dam = ndot(nax, nay, naz, txm[u], ty[v]);
+        const double dbb = ndot(nbx, nby, nbz, tx[u + 1], ty[v]);
+        const double dbm = ndot(nbx, nby, nbz, txm[u], ty[v]);
+        ok = same_sign_nz(daa, dam) && same_sign_nz(dbb, dbm);
+        if (ok) om = log((dam / daa) * (dbb / dbm));
+      } else {
+        ok = naz != 0.0 && nbz != 0.0;
+        if (ok) om = pitch * (nax / (2.0 * naz) + nbx / (2.0 * nbz));
+      }
+      if (ok) {
+        eb |= EB_VR;
+        o_r = (float)om;
+        if (use_sim && add(add(mul(nax, nbx), mul(nay, nby)), mul(naz, nbz)) > cth) eb |= EB_SR;
+      }
+    }
+    if (v + 1 < H && mask[p + W]) {
+      const long long q = p + W;
+      const double nbx = nrm[3 * q], nby = nrm[3 * q + 1], nbz = nrm[3 * q + 2];
+      bool ok;
+      double om = 0.0;
+      if (persp) {
+        const double dam = ndot(nax, nay, naz, tx[u], tym[v]);
+        const double dbb = ndot(nbx, nby, nbz, tx[u], ty[v + 1]);
+        const double dbm = ndot(nbx, nby, nbz, tx[u], tym[v]);
+        ok = same_sign_nz(daa, dam) && same_sign_nz(dbb, dbm);
+        if (ok) om = log((dam / daa) * (dbb / dbm));
+      } else {
+        ok = naz != 0.0 && nbz != 0.0;
+        if (ok) om = pitch * (nay / (2.0 * naz) + nby / (2.0 * nbz));
+      }
+      if (ok) {
+        eb |= EB_VD;
+        o_d = (float)om;
+        if (use_sim && add(add(mul(nax, nbx), mul(nay, nby)), mul(naz, nbz)) > cth) eb |= EB_SD;
+      }
+    }
+  }
+  ebits[p] = eb;
+  om_r[p] = o_r;
+  om_d[p] = o_d;
+  nt[p] = ntp;
+}
+
+// ------------------------------------------------------------ union-find
+// parent[x] <= x always holds, so the root of every tree is its smallest
+// index and the final labelling is canonical whatever the order of unions.
+
+__device__ __forceinline__ int uf_find(int* parent, int x) {
+  int cur = parent[x];
+  if (cur != x) {
+    int prev = x, nxt;
+    while (cur > (nxt = parent[cur])) {
+      parent[prev] = nxt;  // path halving; any ancestor is a valid parent
+      prev = cur;
+      cur = nxt;
+    }
+  }
+  return cur;
+}
+
+// hook the larger root under the smaller one; a failed CAS returns the
+// root's new (smaller) parent and the walk resumes from there
+__device__ __forceinline__ void uf_union(int* parent, int a, int b) {
+  int ra = uf_find(parent, a), rb = uf_find(parent, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      int old = atomicCAS(&parent[rb], rb, ra);
+      if (old == rb) break;
+      rb = old;
+    } else {
+      int old = atomicCAS(&parent[ra], ra, rb);
+      if (old == ra) break;
+      ra = old;
+    }
+  }
+}
+
+__global__ void k_uf_init(const uint8_t* __restrict__ ebits, int P, int* __restrict__ parent) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) parent[p] = (ebits[p] & EB_VALID) ? p : -1;
+}
+
+__global__ void k_uf_union_grid(const uint8_t* __restrict__ ebits, int P, int W, uint8_t bit_r,
+                                uint8_t bit_d, int* parent) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  uint8_t e = ebits[p];
+  if (e & bit_r) uf_union(parent, p, p + 1);
+  if (e & bit_d) uf_union(parent, p, p + W);
+}
+
+// union over an explicit edge list (a[i], b[i]) where keep[i] != 0 (keep may be null)
+__global__ void k_uf_union_list(const int* __restrict__ a, const int* __restrict__ b,
+                                const double* __restrict__ keep, int n, int* parent) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (keep && !(keep[i] > 0.0)) return;
+  uf_union(parent, a[i], b[i]);
+}
+
+__global__ void k_uf_flatten(int* parent, int P, int* __restrict__ root_flag) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int r = -1;
+  if (parent[p] >= 0) {
+    r = p;
+    while (parent[r] != r) r = parent[r];
+  }
+  if (r >= 0) parent[p] = r;  // a root is a valid parent for concurrent walkers
+  if (root_flag) root_flag[p] = (r == p) ? 1 : 0;
+}
+
+__global__ void k_uf_label(const int* __restrict__ parent, const int* __restrict__ cid, int P,
+                           int* __restrict__ label) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) label[p] = parent[p] >= 0 ? cid[parent[p]] : -1;
+}
+
+__global__ void k_iota(int* a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+
+}  // namespace
+
+namespace nil {
+
+hipError_t launch_setup(const float* nrm, const uint8_t* mask, int H, int W, int persp, double pitch,
+                        const double* tables, double cth, int use_sim, uint8_t* ebits, float* om_r,
+                        float* om_d, float* nt, int* err, hipStream_t st) {
+  long long P = (long long)H * W;
+  const double* tx = tables;
+  const double* ty = tables + W;
+  const double* txm = tables + W + H;
+  const double* tym = tables + 2 * W + H;
+  k_setup<<<ni::ceil_div(P, 256), 256, 0, st>>>(nrm, mask, H, W, persp, pitch, tx, ty, txm, tym, cth,
+                                                use_sim, ebits, om_r, om_d, nt, err);
+  return hipGetLastError();
+}
+
+// connected components of the valid pixels over the edges flagged by
+// (bit_r, bit_d).  parent[P] ends flattened (root = min index, -1 invalid);
+// flag/cid are scratch of P ints; label (optional) gets compact ids in
+// ascending-root order; *count_dev gets the number of components.
+hipError_t grid_components(const uint8_t* ebits, int H, int W, uint8_t bit_r, uint8_t bit_d,
+                           int* parent, int* flag, int* cid, int* label, int* count_dev,
+                           int* scan_tmp, hipStream_t st) {
+  int P = H * W;
+  int nb = ni::ceil_div(P, 256);
+  k_uf_init<<<nb, 256, 0, st>>>(ebits, P, parent);
+  k_uf_union_grid<<<nb, 256, 0, st>>>(ebits, P, W, bit_r, bit_d, parent);
+  k_uf_flatten<<<nb, 256, 0, st>>>(parent, P, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive_i32(flag, cid, P, count_dev, scan_tmp, st);
+  if (e != hipSuccess) return e;
+  if (label) k_uf_label<<<nb, 256, 0, st>>>(parent, cid, P, label);
+  return hipGetLastError();
+}
+
+// connected components of n nodes over the listed edges with keep > 0;
+// parent[n] ends flattened (root = min index)
+hipError_t list_components(int n, const int* a, const int* b, const double* keep, int m, int* parent,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_iota<<<ni::ceil_div(n, 256), 256, 0, st>>>(parent, n);
+  if (m > 0) k_uf_union_list<<<ni::ceil_div(m, 256), 256, 0, st>>>(a, b, keep, m, parent);
+  k_uf_flatten<<<ni::ceil_div(n, 256), 256, 0, st>>>(parent, n, nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace nil

@@ -1,0 +1,224 @@
+// Device-wide exclusive scan (int32) and stable LSD radix sort of
+// (uint32 key, uint32 value) pairs.  Both are deterministic: the scan is an
+// integer scan and the sort ranks equal digits by their input order using
+// wavefront ballots, so the output never depends on scheduling.
+#include "ni_common.h"
+
+namespace {
+
+constexpr int SC_NT = 256, SC_PPT = 8, SC_TILE = SC_NT * SC_PPT;
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// exclusive scan of one value per thread across the block; returns the
+// exclusive prefix, *total gets the block total (all threads)
+__device__ __forceinline__ int block_excl_scan(int x, int* lds_w, int* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = wave_incl_scan(x);
+  if (lane == 63) lds_w[wid] = inc;
+  __syncthreads();
+  int woff = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    int s = lds_w[w];
+    if (w < wid) woff += s;
+    tot += s;
+  }
+  *total = tot;
+  __syncthreads();
+  return woff + inc - x;
+}
+
+__global__ void __launch_bounds__(SC_NT) k_scan_reduce(const int* __restrict__ in, int n,
+                                                       int* __restrict__ bsum) {
+  __shared__ int lds[SC_NT / 64];
+  long long base = (long long)blockIdx.x * SC_TILE;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SC_PPT; ++k) {
+    long long i = base + k * SC_NT + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  int tot;
+  block_excl_scan(s, lds, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of a tile, offset by boff[block] (or 0)
+__global__ void __launch_bounds__(SC_NT) k_scan_tile(const int* __restrict__ in, int* __restrict__ out,
+                                                     int n, const int* __restrict__ boff,
+                                                     int* __restrict__ total_dev) {
+  __shared__ int tile[SC_TILE];
+  __shared__ int lds[SC_NT / 64];
+  long long base = (long long)blockIdx.x * SC_TILE;
+#pragma unroll
+  for (int k = 0; k < SC_PPT; ++k) {
+    long long i = base + k * SC_NT + threadIdx.x;
+    tile[k * SC_NT + threadIdx.x] = i < n ? in[i] : 0;
+  }
+  __syncthreads();
+  int loc[SC_PPT];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SC_PPT; ++k) {
+    loc[k] = s;
+    s += tile[threadIdx.x * SC_PPT + k];
+  }
+  int tot;
+  int ex = block_excl_scan(s, lds, &tot);
+  int off = (boff ? boff[blockIdx.x] : 0) + ex;
+#pragma unroll
+  for (int k = 0; k < SC_PPT; ++k) tile[threadIdx.x * SC_PPT + k] = off + loc[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SC_PPT; ++k) {
+    long long i = base + k * SC_NT + threadIdx.x;
+    if (i < n) out[i] = tile[k * SC_NT + threadIdx.x];
+  }
+  if (total_dev && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    *total_dev = (boff ? boff[blockIdx.x] : 0) + tot;
+}
+
+// ------------------------------------------------------------------ radix
+constexpr int RS_NT = 256, RS_PPT = 8, RS_TILE = RS_NT * RS_PPT, RS_NW = RS_NT / 64;
+
+__global__ void __launch_bounds__(RS_NT) k_rs_hist(const uint32_t* __restrict__ keys, int n, int shift,
+                                                   int* __restrict__ hist, int nblk) {
+  __shared__ int cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  long long base = (long long)blockIdx.x * RS_TILE;
+#pragma unroll
+  for (int r = 0; r < RS_PPT; ++r) {
+    long long i = base + r * RS_NT + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(RS_NT) k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin, int n, int shift,
+                                                      const int* __restrict__ off, int nblk,
+                                                      uint32_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout) {
+  __shared__ int wcnt[RS_NW][256];
+  __shared__ int running[256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int w = 0; w < RS_NW; ++w) wcnt[w][threadIdx.x] = 0;
+  running[threadIdx.x] = off[threadIdx.x * nblk + blockIdx.x];
+  __syncthreads();
+  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  long long base = (long long)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_PPT; ++r) {
+    long long i = base + r * RS_NT + threadIdx.x;
+    bool valid = i < n;
+    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t val = valid ? vin[i] : 0u;
+    int d = (key >> shift) & 255;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1;
+      unsigned long long bal = __ballot(valid && bit);
+      peers &= bit ? bal : ~bal;
+    }
+    int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = running[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < RS_NW; ++w) {
+      add += wcnt[w][threadIdx.x];
+      wcnt[w][threadIdx.x] = 0;
+    }
+    running[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+namespace nil {
+
+size_t scan_tmp_ints(int n) {
+  size_t s = 0;
+  while (n > SC_TILE) {
+    int nb = ni::ceil_div(n, SC_TILE);
+    s += 2 * (size_t)nb;
+    n = nb;
+  }
+  return s + 4;
+}
+
+hipError_t scan_exclusive_i32(const int* in, int* out, int n, int* total_dev, int* tmp,
+                              hipStream_t st) {
+  if (n <= 0) {
+    if (total_dev) return hipMemsetAsync(total_dev, 0, sizeof(int), st);
+    return hipSuccess;
+  }
+  if (n <= SC_TILE) {
+    k_scan_tile<<<1, SC_NT, 0, st>>>(in, out, n, nullptr, total_dev);
+    return hipGetLastError();
+  }
+  int nb = ni::ceil_div(n, SC_TILE);
+  int* bsum = tmp;
+  int* boff = tmp + nb;
+  k_scan_reduce<<<nb, SC_NT, 0, st>>>(in, n, bsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive_i32(bsum, boff, nb, nullptr, tmp + 2 * nb, st);
+  if (e != hipSuccess) return e;
+  k_scan_tile<<<nb, SC_NT, 0, st>>>(in, out, n, boff, total_dev);
+  return hipGetLastError();
+}
+
+size_t radix_tmp_ints(int n) {
+  int nblk = ni::ceil_div(n > 0 ? n : 1, RS_TILE);
+  return 2 * (size_t)256 * nblk + scan_tmp_ints(256 * nblk);
+}
+
+hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t* k_out,
+                            uint32_t* v_out, uint32_t* k_tmp, uint32_t* v_tmp, int n, int bits,
+                            int* scan_tmp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+  int nblk = ni::ceil_div(n, RS_TILE);
+  int* hist = scan_tmp;
+  int* off = scan_tmp + 256 * nblk;
+  int* stmp = scan_tmp + 2 * 256 * nblk;
+  const uint32_t* ks = k_in;
+  const uint32_t* vs = v_in;
+  for (int p = 0; p < passes; ++p) {
+    // the last pass writes the output buffers
+    bool to_out = ((passes - 1 - p) % 2) == 0;
+    uint32_t* kd = to_out ? k_out : k_tmp;
+    uint32_t* vd = to_out ? v_out : v_tmp;
+    k_rs_hist<<<nblk, RS_NT, 0, st>>>(ks, n, 8 * p, hist, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive_i32(hist, off, 256 * nblk, nullptr, stmp, st);
+    if (e != hipSuccess) return e;
+    k_rs_scatter<<<nblk, RS_NT, 0, st>>>(ks, vs, n, 8 * p, off, nblk, kd, vd);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ks = kd;
+    vs = vd;
+  }
+  return hipSuccess;
+}
+
+}  // namespace nil

@@ -1,0 +1,282 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (stated per output):
+  labels     bit-exact (same canonical ids, same K);
+  depth      |d_gpu - d_oracle| <= 1e-6 + 1e-4 |d_oracle| on every valid pixel;
+  log_scale  |s_gpu - s_oracle| <= 1e-4 (log units);
+  fill       |z_gpu - z_oracle| <= 1e-6 + 1e-4 (log-depth, per-component gauge).
+The 1e-4 relative / 1e-6 absolute depth tolerance comes from the FP32
+vectors of the fill CG (stopped at a 1e-6 relative residual) against an
+exact FP64 solve.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ni_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+RTOL, ATOL = 1e-4, 1e-6
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2510_11508_amd as ni
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ni.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def params(**kw):
+    import paper_2510_11508_amd as ni
+    return ni.ni_params_default(**kw)
+
+
+def oracle_params(p):
+    return dict(theta_c_deg=p.theta_c_deg, irls_iters=p.irls_iters, align_iters=p.align_iters, bini_k=p.bini_k,
+                out_L=p.out_L, out_U=p.out_U, outlier_mode=p.outlier_mode, delta_e_max=p.delta_e_max,
+                w_cut_rel=p.w_cut_rel)
+
+
+def assert_depth_close(d_gpu, d_ref, mask, what="", ortho=False):
+    """Perspective: per-pixel relative bound on depth.  Orthographic depth is
+    an additive height in the per-region zero-mean gauge that crosses zero,
+    so the relative part is taken w.r.t. the map's largest |height|."""
+    v = mask > 0
+    a = d_gpu.astype(np.float64)[v]
+    b = d_ref[v]
+    err = np.abs(a - b)
+    scale = np.max(np.abs(b)) if (ortho and b.size) else np.abs(b)
+    bound = ATOL + RTOL * scale
+    worst = np.argmax(err / bound) if err.size else 0
+    assert np.all(err <= bound), f"{what}: max err {err.max():.3e} at {worst}, ref {b[worst]:.6f}"
+    assert np.all(np.isnan(d_gpu[~v])), f"{what}: off-mask depth must be NaN"
+
+
+SAMPLES = [("c1", 0), ("c1", 1), ("c1", 2), ("c2", 0), ("c2", 1)]
+
+
+def sample(name, seed):
+    if name.startswith("tiny"):
+        proj = name.split("-")[1]
+        return synth.tiny(seed, 9, 11, proj)
+    return synth.make(name, seed)
+
+
+# ----------------------------------------------------------------- labels
+@pytest.mark.parametrize("name,seed", SAMPLES + [("tiny-persp", 0), ("tiny-ortho", 1), ("c3", 0)])
+def test_labels_bit_exact(ctx, name, seed):
+    s = sample(name, seed)
+    p = params(theta_c_deg=2.0)
+    log(f"[labels] {name} seed {seed} {s.mask.shape}")
+    lab, K, _ = ctx.ni_label(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0)
+    ref, Kr = O.labels(e)
+    assert K == Kr
+    assert np.array_equal(lab.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5, 5.0, 180.0])
+def test_labels_thresholds(ctx, theta):
+    s = synth.make("c2", 3)
+    log(f"[labels] c2 seed 3 theta {theta}")
+    lab, K, _ = ctx.ni_label(dev(s.normals), dev(s.mask), s.cam.as_dict(), params(theta_c_deg=theta))
+    ref, Kr = O.labels(O.edges(s.normals, s.mask, s.cam, theta))
+    assert K == Kr and np.array_equal(lab.cpu().numpy(), ref)
+
+
+# ------------------------------------------------------------------- fill
+@pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0), ("tiny-persp", 2), ("tiny-ortho", 3)])
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_fill_matches_oracle(ctx, name, seed, persistent):
+    s = sample(name, seed)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0)
+    lab, K = O.labels(e)
+    zref = O.fill(e, lab, K)
+    log(f"[fill] {name} seed {seed} K {K} persistent {persistent}")
+    z, rep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K, params(persistent=persistent))
+    z = z.cpu().numpy().astype(np.float64)
+    v = s.mask > 0
+    err = np.abs(z[v] - zref[v])
+    assert err.max() <= 1e-6 + 1e-4, (err.max(), rep["fill_iters_max"])
+    assert rep["fill_notconv"] == 0
+
+
+# ------------------------------------------------------------------- IRLS
+@pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0), ("tiny-persp", 1), ("tiny-ortho", 0)])
+@pytest.mark.parametrize("mode", [1, 2, 0])
+def test_irls_matches_oracle_given_fill(ctx, name, seed, mode):
+    s = sample(name, seed)
+    p = params(theta_c_deg=2.0, irls_iters=int(s.params["irls_iters"]), outlier_mode=mode)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0)
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    op = oracle_params(p)
+    S, En, _ = O.irls(e, lab, K, zf, op)
+    depth_ref, ls_ref, _ = O.finalize(e, lab, zf, S)
+    log(f"[irls] {name} seed {seed} mode {mode} K {K}")
+    depth, ls, rep = ctx.ni_irls(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K,
+                                 dev(zf.astype(np.float32)), p)
+    assert_depth_close(depth.cpu().numpy(), depth_ref, s.mask, f"irls {name}", s.cam.proj == "ortho")
+    assert np.max(np.abs(ls.cpu().numpy() - ls_ref)) <= 1e-4
+    assert np.allclose(rep["energy"], En, rtol=1e-3, atol=1e-12)
+
+
+# ------------------------------------------------------------- whole path
+@pytest.mark.parametrize("name,seed", SAMPLES + [("tiny-persp", 4), ("tiny-ortho", 5)])
+def test_integrate_matches_oracle(ctx, name, seed):
+    s = sample(name, seed)
+    p = params(theta_c_deg=2.0, irls_iters=int(s.params["irls_iters"]))
+    log(f"[integrate] {name} seed {seed}")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    ref = O.integrate(s.normals, s.mask, s.cam, oracle_params(p))
+    assert out["K"] == ref.K
+    assert np.array_equal(out["labels"].cpu().numpy(), ref.labels)
+    assert_depth_close(out["depth"].cpu().numpy(), ref.depth, s.mask, f"integrate {name}", s.cam.proj == "ortho")
+    assert np.max(np.abs(out["log_scale"].cpu().numpy() - ref.log_scale)) <= 1e-4
+    rep = out["report"]
+    assert rep["n_inter_edges"] == ref.n_inter_edges and rep["n_regions"] == ref.n_regions
+
+
+def test_deterministic(ctx):
+    s = synth.make("c2", 2)
+    p = params()
+    outs = []
+    for k in range(3):
+        log(f"[determinism] run {k}")
+        o = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+        outs.append((o["labels"].cpu().numpy(), o["depth"].cpu().numpy()))
+    for lab, d in outs[1:]:
+        assert np.array_equal(lab, outs[0][0])
+        v = s.mask > 0
+        assert np.max(np.abs(d[v] - outs[0][1][v])) <= 1e-6 * np.max(np.abs(outs[0][1][v]))
+
+
+# ------------------------------------------------------------- edge cases
+def test_empty_mask(ctx):
+    s = synth.tiny(0)
+    m = np.zeros_like(s.mask)
+    log("[edge] empty mask")
+    out = ctx.ni_integrate(dev(s.normals), dev(m), s.cam.as_dict(), params())
+    assert out["K"] == 0
+    assert np.all(out["labels"].cpu().numpy() == -1)
+    assert np.all(np.isnan(out["depth"].cpu().numpy()))
+
+
+def test_single_pixel_and_thin_maps(ctx):
+    for H, W in [(1, 1), (1, 17), (23, 1), (2, 2)]:
+        s = synth.tiny(1, max(H, 3), max(W, 3), "persp")
+        n = np.ascontiguousarray(s.normals[:H, :W])
+        m = np.ones((H, W), np.uint8)
+        cam = dict(s.cam.as_dict())
+        log(f"[edge] {H}x{W}")
+        out = ctx.ni_integrate(dev(n), dev(m), cam, params(irls_iters=4))
+        ref = O.integrate(n, m, cam, dict(irls_iters=4))
+        assert out["K"] == ref.K and np.array_equal(out["labels"].cpu().numpy(), ref.labels)
+        assert_depth_close(out["depth"].cpu().numpy(), ref.depth, m, f"{H}x{W}", cam["proj"] == "ortho")
+
+
+def test_nonfinite_inside_mask_is_an_error(ctx):
+    import paper_2510_11508_amd as ni
+    s = synth.tiny(2)
+    n = s.normals.copy()
+    v = np.argwhere(s.mask > 0)[3]
+    n[v[0], v[1], 2] = np.inf
+    log("[edge] inf inside mask")
+    with pytest.raises(ni.NIError) as ex:
+        ctx.ni_integrate(dev(n), dev(s.mask), s.cam.as_dict(), params())
+    assert ex.value.status == ni.NI_E_NONFINITE
+    # NaN off the mask is fine
+    m = s.mask.copy()
+    m[v[0], v[1]] = 0
+    n[v[0], v[1], 2] = np.nan
+    log("[edge] nan off mask")
+    out = ctx.ni_integrate(dev(n), dev(m), s.cam.as_dict(), params(irls_iters=3))
+    ref = O.integrate(n, m, s.cam, dict(irls_iters=3))
+    assert out["K"] == ref.K
+
+
+def test_capacity_too_small(ctx):
+    import paper_2510_11508_amd as ni
+    s = synth.tiny(0)
+    log("[edge] cap < K")
+    with pytest.raises(ni.NIError) as ex:
+        ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), params(), cap=2)
+    assert ex.value.status == ni.NI_E_SHAPE
+
+
+def test_bad_arguments(ctx):
+    import paper_2510_11508_amd as ni
+    s = synth.tiny(0)
+    for kw in [dict(connectivity=8), dict(irls_iters=0), dict(outlier_mode=5), dict(out_L=1e-2),
+               dict(warm_start=1)]:
+        log(f"[edge] bad params {kw}")
+        with pytest.raises(ni.NIError) as ex:
+            ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), params(**kw))
+        assert ex.value.status in (ni.NI_E_ARG, ni.NI_E_MODEL)
+
+
+def test_pixel_level_limit(ctx):
+    """theta_c = None: every pixel its own component; the quotient graph is G_0."""
+    s = synth.tiny(3, 10, 12, "persp")
+    p = params(theta_c_deg=0.0, irls_iters=6)
+    log("[edge] pixel level")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    ref = O.integrate(s.normals, s.mask, s.cam, oracle_params(p))
+    assert out["K"] == int(s.mask.sum())
+    assert_depth_close(out["depth"].cpu().numpy(), ref.depth, s.mask, "pixel level")
+
+
+def test_not_converged_is_reported(ctx):
+    import paper_2510_11508_amd as ni
+    s = synth.make("c1", 0)
+    log("[edge] cg_max_iter=1")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), params(cg_max_iter=1),
+                           raise_notconv=False)
+    assert out["status"] == ni.NI_E_NOTCONV and out["report"]["fill_notconv"] > 0
+
+
+# ---------------------------------------------------- full-size properties
+def test_c3_full_size_sampled(ctx):
+    """2048^2: labels bit-exact; the fill of sampled components equals the
+    oracle's exact per-component solve (components are independent)."""
+    s = synth.make("c3", 0)
+    p = params(theta_c_deg=2.0, irls_iters=15)
+    log("[c3] integrate")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0)
+    lab, K = O.labels(e)
+    assert out["K"] == K and np.array_equal(out["labels"].cpu().numpy(), lab)
+    log("[c3] fill")
+    z, rep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K, p)
+    z = z.cpu().numpy()
+    sizes = np.bincount(lab[lab >= 0])
+    rng = np.random.default_rng(0)
+    cand = np.flatnonzero((sizes >= 2) & (sizes <= 30000))
+    pick = list(rng.choice(cand, size=min(12, cand.size), replace=False))
+    pick.append(int(np.argmax(np.where(sizes <= 30000, sizes, 0))))
+    for c in pick:
+        sub = np.where(lab == c, 0, -1).astype(np.int32)
+        zr = O.fill(e, sub, 1)
+        m = lab == c
+        err = np.max(np.abs(z[m] - zr[m]))
+        assert err <= 1e-6 + 1e-4, (c, sizes[c], err)
+    d = out["depth"].cpu().numpy()
+    v = s.mask > 0
+    assert np.all(np.isfinite(d[v])) and np.all(d[v] > 0)
