@@ -1,0 +1,158 @@
+"""Benchmark: valid Mpixels/s integrated at a 1e-6 relative CG residual.
+
+One step = one ni_integrate call on one synthetic normal map already
+resident in HBM (labels, fill, relative-scale IRLS, output), every fill
+system stopped at ||r_c|| <= 1e-6 ||b_c||.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
+
+The roofline object describes the dominant kernel, the batched CG
+iteration of the large fill components (k_lg_iter, one launch per
+iteration): algorithmic bytes = 60 B per pixel per CG iteration (reads x,
+p, r, w, s, 1/diag, three weights and the packed neighbour offsets; writes
+x, p, r, w, s), times the pixel-iterations of one launch, over its
+event-timed duration.  The CPU baseline is the FP64 oracle on this host.
+"""
+import os
+
+# the oracle's CPU baseline is timed single-threaded: pin BLAS pools before numpy loads
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import argparse
+import hashlib
+import json
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "valid Mpixels/s integrated at 1e-6 residual; warm-start vs plain CG speedup"
+HBM_PEAK_GBS = 8000.0
+CG_BYTES_PER_PX_ITER = 60
+WORKLOADS = {
+    "c2": "512x512 perspective (f=600), 5 depth steps, 6 bumps, 45% blob mask, noise 0.005, theta_c 2 deg, T=15",
+    "c3": "2048x2048 perspective (f=2400), 40 steps, 60 bumps, 70% blob mask, noise 0.005, theta_c 2 deg, T=15",
+    "c5": "4096x4096 perspective (f=4800), 150 steps, 240 bumps, 72% blob mask, noise 0.01, theta_c 2 deg, T=15",
+}
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("ni_fill.hip", "ni_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2510_11508_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(workload):
+    """HBM bytes per launch of the fill CG kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"fill_cg_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(sample, params, budget_s=12.0):
+    """The FP64 oracle as it stands, on this host, single-threaded."""
+    from oracle import ni_oracle as O
+    n_valid = int((sample.mask > 0).sum())
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        O.integrate(sample.normals, sample.mask, sample.cam, params)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or runs >= 50:
+            break
+    return dict(value=n_valid * runs / el / 1e6, unit="Mpx/s", cores=1, kind="oracle",
+                sample=f"{runs} full oracle integration(s) of the same {sample.name} map "
+                       f"({n_valid} valid px), FP64 sparse-direct solves, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_11508_amd as ni
+    import synth
+
+    s = synth.make(a.workload, a.seed)
+    T = int(s.params["irls_iters"])
+    p = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T)
+    dev = torch.device("cuda:0")
+    normals = torch.from_numpy(s.normals).to(dev)
+    mask = torch.from_numpy(s.mask).to(dev)
+    n_valid = int((s.mask > 0).sum())
+    ctx = ni.Context(0)
+    cam = s.cam.as_dict()
+
+    if a.copy_calibration:
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    for _ in range(a.warmup):
+        ctx.ni_integrate(normals, mask, cam, p)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        out = ctx.ni_integrate(normals, mask, cam, p)
+        reps.append(out["report"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1000.0 / a.steps
+    value = n_valid / (ms / 1000.0) / 1e6
+
+    rep = reps[-1]
+    k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
+    px_iters = rep["fill_large_px_iters"]
+    launches = max(rep["fill_large_launches"], 1)
+    launch_bytes = CG_BYTES_PER_PX_ITER * px_iters / launches
+    launch_ms = k_ms / launches
+    achieved = launch_bytes / (launch_ms / 1000.0) / 1e9 if k_ms > 0 else 0.0
+    traffic = traffic_record(a.workload)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel="k_lg_iter", bytes_per_px_iter=CG_BYTES_PER_PX_ITER,
+                px_iters_per_launch=round(px_iters / launches, 1), launches=launches,
+                ms_per_launch=round(launch_ms, 5))
+
+    line = dict(metric=METRIC, value=round(value, 3), unit="Mpx/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+                ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32 vectors / f64 reductions", data="synthetic",
+                config=dict(workload=f"{a.workload}: {WORKLOADS[a.workload]}", seed=a.seed, n_valid=n_valid,
+                            K=out["K"], H=int(s.mask.shape[0]), W=int(s.mask.shape[1])),
+                stages_ms={k[3:]: round(float(np.mean([r[k] for r in reps])), 3) for k in rep if k.startswith("ms_")},
+                fill=dict(iters_max=rep["fill_iters_max"], n_small=rep["n_small"], n_large=rep["n_large"],
+                          px_iters=rep["fill_px_iters"], max_relres=rep["fill_max_relres"]),
+                quot_iters=rep["quot_iters"],
+                roofline=roof)
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(s, dict(theta_c_deg=2.0, irls_iters=T))
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -80,8 +80,6 @@ typedef struct {
   double q_rtol;        /* quotient CG: stop at ||r|| <= q_rtol * ||b||_abs   */
   int32_t q_max_iter;   /* quotient CG iteration cap                          */
   int32_t warm_start;   /* 0 zero start; 1 learned start (needs ni_unet_load) */
-  int32_t persistent;   /* fill large components in one persistent launch (1)
-                           or one launch per CG phase (0)                     */
 } ni_params;
 
 typedef struct {
@@ -96,21 +94,23 @@ typedef struct {
   int32_t fill_notconv;          /* components that hit cg_max_iter           */
   int64_t fill_px_iters;         /* sum over components of n_c * iters_c      */
   int64_t fill_large_px_iters;   /* same, grid-wide components only           */
-  int32_t fill_large_launches;   /* CG phase launches (0 when persistent)     */
+  int32_t fill_large_launches;   /* CG iteration launches of the large path   */
   int32_t warm_fallbacks;        /* components whose learned start was reset */
   double fill_max_relres;        /* max_c ||r_c|| / ||b_c|| (recursive)       */
   int32_t quot_iters[NI_MAX_IRLS];
   double energy[NI_MAX_IRLS];    /* E_t of Alg. 1 per iteration               */
   float ms_setup, ms_label, ms_segments, ms_assemble, ms_warm,
         ms_fill_small, ms_fill_large, ms_irls, ms_finalize, ms_total;
+  float ms_large_kernel;  /* the large-path CG iteration launches alone
+                             (HIP events around each batch of launches)    */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;
 
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
- * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-8, cg_rtol 1e-6,
- * cg_max_iter 50000, q_rtol 1e-12, q_max_iter 20000, zero start,
- * persistent 1.  Returns NI_E_ARG on a null pointer. */
+ * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-4, cg_rtol 1e-6,
+ * cg_max_iter 50000, q_rtol 1e-12, q_max_iter 20000, zero start.
+ * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);
 
 /* Create a context on HIP device `device`; it owns a device workspace that

@@ -47,7 +47,7 @@ DEFAULT_PARAMS = dict(
     out_U=1e-3,           # Eq. 18 upper threshold [1e-3]
     outlier_mode=1,       # 0 off, 1 soft (Eq. 18), 2 hard (Suppl. ablation)
     delta_e_max=0.0,      # relative-energy stop; 0 runs exactly T iterations (A13)
-    w_cut_rel=1e-8,       # quotient edges below this fraction of the max weight are cut (A16)
+    w_cut_rel=1e-4,       # quotient edges below this fraction of the max weight are cut (A16)
 )
 
 
@@ -442,9 +442,13 @@ def irls(e: Edges, lab, K, zfill, params=None):
     labf = lab.ravel()
     valid = labf >= 0
     energies = []
+    margin = np.inf
     for t in range(int(p["irls_iters"])):
         z = np.where(valid, zfill.ravel() + S[np.where(valid, labf, 0)], 0.0)
         w, r = edge_weights(e, ie, z, t, p)
+        if w.size and p["w_cut_rel"] > 0 and w.max() > 0:
+            pos = w[w > 0]
+            margin = min(margin, float(np.min(np.abs(np.log10(pos / (p["w_cut_rel"] * w.max()))))))
         s, E, _ = quotient_step(ie, K, w, r, p["w_cut_rel"])
         S += s
         energies.append(E)
@@ -452,6 +456,7 @@ def irls(e: Edges, lab, K, zfill, params=None):
             Ep = energies[-2]
             if Ep == 0.0 or abs(E - Ep) / Ep < p["delta_e_max"]:
                 break
+    irls.last_cut_margin = margin
     return S, energies, ie
 
 
@@ -511,4 +516,7 @@ def integrate(normals, mask, cam, params=None, labels_in=None, zfill_in=None) ->
     S, energies, ie = irls(e, lab, K, zf, p)
     depth, log_scale, logz = finalize(e, lab, zf, S)
     _, R = regions(e)
-    return Result(depth, lab, log_scale, K, zf, logz, energies, int(ie.a.size), R)
+    # smallest |log10(w_e / (w_cut_rel * max w))| over all iterations: how
+    # close any cut decision came to flipping (a diagnostic, not a result)
+    return Result(depth, lab, log_scale, K, zf, logz, energies, int(ie.a.size), R,
+                  extra=dict(cut_margin=irls.last_cut_margin))

@@ -30,8 +30,7 @@ class ni_params(C.Structure):
                 ("align_iters", C.c_int32), ("bini_k", C.c_double), ("out_L", C.c_double),
                 ("out_U", C.c_double), ("outlier_mode", C.c_int32), ("delta_e_max", C.c_double),
                 ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
-                ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32)]
 
 
 class ni_report(C.Structure):
@@ -45,7 +44,7 @@ class ni_report(C.Structure):
                 ("ms_setup", C.c_float), ("ms_label", C.c_float), ("ms_segments", C.c_float),
                 ("ms_assemble", C.c_float), ("ms_warm", C.c_float), ("ms_fill_small", C.c_float),
                 ("ms_fill_large", C.c_float), ("ms_irls", C.c_float), ("ms_finalize", C.c_float),
-                ("ms_total", C.c_float)]
+                ("ms_total", C.c_float), ("ms_large_kernel", C.c_float)]
 
     def as_dict(self):
         d = {}

@@ -25,30 +25,18 @@ hipError_t fill_segments(const int*, int, int, int*, int*, int*, uint32_t*, uint
 hipError_t fill_assemble(const uint32_t*, int, int, int, const int*, const uint8_t*, const float*, const float*,
                          const float*, const int*, double, double, float*, float*, float*, uint32_t*, float*,
                          float*, hipStream_t);
-hipError_t fill_classify(const int*, int, int*, int*, int*, int*, int*, int*, int*, int*, hipStream_t);
-hipError_t fill_lists(const int*, const int*, const int*, const int*, const int*, const int*, const int*, int, int*,
-                      int*, int*, int*, hipStream_t);
+hipError_t fill_tier_list(const int*, int, int, int*, int*, int*, int*, int*, hipStream_t);
+hipError_t fill_chunks(const int*, int, int*, int*, int*, int*, hipStream_t);
+hipError_t fill_chunk_table(const int*, const int*, const int*, int, int*, int*, int*, hipStream_t);
 hipError_t fill_zero_grid(float*, int, hipStream_t);
 hipError_t fill_gather_x0(const uint32_t*, int, const float*, float*, hipStream_t);
-hipError_t fill_small(const int*, int, const int*, const float*, const float*, const float*, const uint32_t*,
+hipError_t fill_small(int, const int*, int, const int*, const float*, const float*, const float*, const uint32_t*,
                       const float*, const float*, const float*, const uint32_t*, float*, double, int, int, int*,
                       double*, int*, hipStream_t);
-struct LargeArgs {
-  const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start;
-  int* cnt;
-  double *part, *rho, *bb, *tol2, *alpha, *beta, *rr;
-  int *done, *iters, *active, *stats;
-  const float *cwr, *cwd, *cwu, *rhs, *dinv;
-  const uint32_t* coff;
-  float *x, *r, *z, *p0, *p1, *q;
-  double rtol;
-  int maxit;
-};
-hipError_t large_init(const LargeArgs&, int, int, hipStream_t);
-hipError_t large_step(const LargeArgs&, int, int, hipStream_t);
-int large_persistent_blocks(int);
-hipError_t large_persistent(const LargeArgs&, int, int, unsigned*, hipStream_t);
-hipError_t large_finish(const LargeArgs&, int, const uint32_t*, float*, hipStream_t);
+
+hipError_t large_init(const LargeArgs&, int, hipStream_t);
+hipError_t large_iter(const LargeArgs&, int, hipStream_t);
+hipError_t large_finish(const LargeArgs&, const uint32_t*, float*, hipStream_t);
 // ni_quot.hip
 hipError_t quot_inter_edges(const int*, const uint8_t*, int, int, int*, int*, int*, uint32_t*, int*, hipStream_t,
                             int);
@@ -58,26 +46,8 @@ hipError_t quot_pairs(const uint32_t*, const int*, const int*, int, int, const i
                       hipStream_t);
 hipError_t quot_csr(const int*, const int*, int, int, uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
                     uint32_t*, int*, int*, int*, hipStream_t);
-struct IrlsArgs {
-  const uint32_t* eidx;
-  int E, P, K, W;
-  const int* label;
-  const uint8_t* ebits;
-  const float *nt, *om_r, *om_d, *zfill;
-  const int *pair_start, *pair_lo, *pair_hi, *row_off;
-  const uint32_t* ent;
-  double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
-  double *s, *r, *z, *p0, *p1, *q, *part, *psum;
-  int *pcnt, *parent;
-  unsigned long long* wmax;
-  unsigned* bar;
-  double* energy_out;
-  int* qiters_out;
-  double* epart;
-  double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
-  int align, outlier_mode, q_maxit, qblocks;
-};
-int qcg_max_blocks(int);
+hipError_t quot_heavy_rows(const int*, int, int*, int*, int*, int*, int*, hipStream_t);
+
 hipError_t irls_iteration(const IrlsArgs&, int, hipStream_t);
 // ni_final.hip
 hipError_t final_outputs(const int*, const float*, const double*, const int*, const uint32_t*, const int*,
@@ -112,7 +82,7 @@ struct ni_ctx {
   // grid
   Buf ebits, om_r, om_d, nt, parent, flag, scanv, pos, zgrid, tab, xwarm;
   // compact / sort
-  Buf key, val, skey, spix, ktmp, vtmp, kout2, cwr, cwd, cwu, coff, rhs, dinv, x, r, z, p0, p1, q;
+  Buf key, val, skey, spix, ktmp, vtmp, kout2, cwr, cwd, cwu, coff, rhs, dinv, x, r, z, p0, p1, q, w0, w1, s0, s1;
   // components
   Buf comp_off, fsmall, flarge, nchunk, spos, lpos, cbase, small_list, large_list, cnt, done, iters, active,
       rho, bb, tol2, alpha, beta, rr, relres, S, qs, qr, qz, qp0, qp1, qq, diag, qrhs, babs, psum, pcnt, qparent,
@@ -121,23 +91,23 @@ struct ni_ctx {
   Buf chunk_comp, chunk_start, part;
   // edges / pairs
   Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
-      row_off, epart, qpart, rsum, rcnt;
+      row_off, epart, qpart, rsum, rcnt, qcol, qw, qt0, qt1, qsc;
   // scratch
   Buf scan_tmp, misc, unet_ws;
   int* host = nullptr;  // pinned readback area (64 ints)
-  hipEvent_t ev[12] = {};
+  hipEvent_t ev[14] = {};
   struct nil::UnetModel* unet = nullptr;
-  int persistent_blocks = -1, qcg_blocks = -1;
+
 
   ni_ctx() {
     Buf* all[] = {&ebits, &om_r, &om_d, &nt, &parent, &flag, &scanv, &pos, &zgrid, &tab, &xwarm, &key, &val,
                   &skey, &spix, &ktmp, &vtmp, &kout2, &cwr, &cwd, &cwu, &coff, &rhs, &dinv, &x, &r, &z, &p0,
-                  &p1, &q, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
+                  &p1, &q, &w0, &w1, &s0, &s1, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
                   &cnt, &done, &iters, &active, &rho, &bb, &tol2, &alpha, &beta, &rr, &relres, &S, &qs, &qr,
                   &qz, &qp0, &qp1, &qq, &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &qpart, &rsum,
-                  &rcnt, &scan_tmp, &misc, &unet_ws};
+                  &rcnt, &qcol, &qw, &qt0, &qt1, &qsc, &scan_tmp, &misc, &unet_ws};
     bufs.assign(std::begin(all), std::end(all));
   }
 };
@@ -149,9 +119,8 @@ enum {
   M_COUNT = 0,    // [0..7] counters written by scans
   M_ERR = 8,      // non-finite flag
   M_STATS = 12,   // [12..15] fill stats
-  M_ACTIVE = 16,
-  M_BAR = 20,     // 2 unsigned (fill barrier)
-  M_QBAR = 24,    // 2 unsigned (quotient barrier)
+  M_ACTIVE = 16,  // 2 ints (fill: components still iterating, by launch parity)
+  M_QFLAG = 24,   // 2 ints (quotient: still iterating, by launch parity)
   M_WMAX = 32,    // u64 (8-byte aligned)
   M_ENERGY = 64,  // NI_MAX_IRLS doubles (8-byte aligned)
   M_QITERS = 64 + 2 * NI_MAX_IRLS,
@@ -392,11 +361,6 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   float* rhs = ensure<float>(c, c->rhs, N);
   float* dinv = ensure<float>(c, c->dinv, N);
   float* x = ensure<float>(c, c->x, N);
-  float* r = ensure<float>(c, c->r, N);
-  float* z = ensure<float>(c, c->z, N);
-  float* p0 = ensure<float>(c, c->p0, N);
-  float* p1 = ensure<float>(c, c->p1, N);
-  float* q = ensure<float>(c, c->q, N);
   const uint32_t* cpix = ptr<uint32_t>(c->spix);
   const int* comp_off = ptr<int>(c->comp_off);
   mark(c, 3);
@@ -406,40 +370,30 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
                            c->stream),
         "assemble");
   size_t K1 = (size_t)K + 1;
-  int* fsmall = ensure<int>(c, c->fsmall, K1);
-  int* flarge = ensure<int>(c, c->flarge, K1);
+  int* tflag = ensure<int>(c, c->fsmall, K1);
+  int* tpos = ensure<int>(c, c->spos, K1);
+  int* lists = ensure<int>(c, c->small_list, 4 * K1);
   int* nchunk = ensure<int>(c, c->nchunk, K1);
-  int* spos = ensure<int>(c, c->spos, K1);
-  int* lpos = ensure<int>(c, c->lpos, K1);
   int* cbase = ensure<int>(c, c->cbase, K1);
-  int* small_list = ensure<int>(c, c->small_list, K1);
-  int* large_list = ensure<int>(c, c->large_list, K1);
-  int* cnt = ensure<int>(c, c->cnt, K1);
-  int* done = ensure<int>(c, c->done, K1);
   int* iters = ensure<int>(c, c->iters, K1);
-  double* rho = ensure<double>(c, c->rho, K1);
-  double* bb = ensure<double>(c, c->bb, K1);
-  double* tol2 = ensure<double>(c, c->tol2, K1);
-  double* alpha = ensure<double>(c, c->alpha, K1);
-  double* beta = ensure<double>(c, c->beta, K1);
-  double* rr = ensure<double>(c, c->rr, K1);
   double* relres = ensure<double>(c, c->relres, K1);
   int* cntd = misc(c) + M_COUNT;
-  check(c, nil::fill_classify(comp_off, K, fsmall, flarge, nchunk, spos, lpos, cbase, cntd, ptr<int>(c->scan_tmp),
-                              c->stream),
-        "classify");
-  readback(c, cntd, 4 * sizeof(int), c->host);
-  const int n_small = c->host[0], n_large = c->host[1], n_chunks = c->host[2];
+  for (int t = 1; t <= 4; ++t)
+    check(c, nil::fill_tier_list(comp_off, K, t, tflag, tpos, lists + (t - 1) * K1, cntd + (t - 1),
+                                 ptr<int>(c->scan_tmp), c->stream),
+          "tier lists");
+  check(c, nil::fill_chunks(comp_off, K, nchunk, cbase, cntd + 4, ptr<int>(c->scan_tmp), c->stream), "chunks");
+  readback(c, cntd, 5 * sizeof(int), c->host);
+  int ntier[4] = {c->host[0], c->host[1], c->host[2], c->host[3]};
+  const int n_chunks = c->host[4];
   int* chunk_comp = ensure<int>(c, c->chunk_comp, n_chunks);
   int* chunk_start = ensure<int>(c, c->chunk_start, n_chunks);
-  double* part = ensure<double>(c, c->part, 4 * (size_t)std::max(n_chunks, 1));
-  check(c, nil::fill_lists(fsmall, flarge, spos, lpos, nchunk, cbase, comp_off, K, small_list, large_list,
-                           chunk_comp, chunk_start, c->stream),
-        "lists");
-  check(c, hipMemsetAsync(cnt, 0, K1 * sizeof(int), c->stream), "memset");
+  int* chunk_end = ensure<int>(c, c->large_list, n_chunks);
+  check(c, nil::fill_chunk_table(comp_off, nchunk, cbase, K, chunk_comp, chunk_start, chunk_end, c->stream),
+        "chunk table");
   check(c, hipMemsetAsync(iters, 0, K1 * sizeof(int), c->stream), "memset");
   check(c, hipMemsetAsync(relres, 0, K1 * sizeof(double), c->stream), "memset");
-  check(c, hipMemsetAsync(misc(c) + M_STATS, 0, 8 * sizeof(int), c->stream), "memset");
+  check(c, hipMemsetAsync(misc(c) + M_STATS, 0, 4 * sizeof(int), c->stream), "memset");
   check(c, nil::fill_zero_grid(zout, P, c->stream), "zero");
   const int warm = pb.prm.warm_start ? 1 : 0;
   mark(c, 4);
@@ -453,65 +407,70 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   }
   check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
   mark(c, 5);
-  check(c, nil::fill_small(small_list, n_small, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x, cpix, zout,
-                           pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, iters, relres, misc(c) + M_STATS, c->stream),
-        "fill small");
+  for (int t = 1; t <= 3; ++t)
+    check(c, nil::fill_small(t, lists + (t - 1) * K1, ntier[t - 1], comp_off, cwr, cwd, cwu, coff, rhs, dinv, x,
+                             cpix, zout, pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, iters, relres, misc(c) + M_STATS,
+                             c->stream),
+          "fill small");
   mark(c, 6);
   int launches = 0;
+  float large_kernel_ms = 0.f;
+  const int n_large = ntier[3];
+  double* rr = ensure<double>(c, c->rr, K1);
+  double* bb = ensure<double>(c, c->bb, K1);
   if (n_large > 0) {
     nil::LargeArgs a;
     a.comp_off = comp_off; a.cbase = cbase; a.nchunk = nchunk; a.chunk_comp = chunk_comp;
-    a.chunk_start = chunk_start; a.cnt = cnt; a.part = part; a.rho = rho; a.bb = bb; a.tol2 = tol2;
-    a.alpha = alpha; a.beta = beta; a.rr = rr; a.done = done; a.iters = iters;
+    a.chunk_start = chunk_start; a.chunk_end = chunk_end;
+    a.part = ensure<double>(c, c->part, 2 * 4 * (size_t)n_chunks);
+    a.gam = ensure<double>(c, c->rho, 2 * K1);
+    a.alp = ensure<double>(c, c->alpha, 2 * K1);
+    a.tol2 = ensure<double>(c, c->tol2, K1);
+    a.rr = rr; a.bb = bb; a.iters = iters;
     a.active = misc(c) + M_ACTIVE; a.stats = misc(c) + M_STATS;
     a.cwr = cwr; a.cwd = cwd; a.cwu = cwu; a.rhs = rhs; a.dinv = dinv; a.coff = coff;
-    a.x = x; a.r = r; a.z = z; a.p0 = p0; a.p1 = p1; a.q = q;
-    a.rtol = pb.prm.cg_rtol; a.maxit = pb.prm.cg_max_iter;
-    check(c, hipMemsetAsync(a.active, 0, sizeof(int), c->stream), "memset");
-    check(c, hipMemsetAsync(done, 0, K1 * sizeof(int), c->stream), "memset");
-    check(c, nil::large_init(a, n_chunks, warm, c->stream), "large init");
-    bool ran = false;
-    if (pb.prm.persistent) {
-      if (c->persistent_blocks < 0) c->persistent_blocks = nil::large_persistent_blocks(c->device);
-      int nb = std::min(c->persistent_blocks, n_chunks);
-      if (nb > 0) {
-        unsigned* bar = (unsigned*)(misc(c) + M_BAR);
-        check(c, hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), c->stream), "memset");
-        hipError_t e = nil::large_persistent(a, n_chunks, nb, bar, c->stream);
-        if (e == hipSuccess) ran = true;
-        else (void)hipGetLastError();
-      }
+    a.x = x;
+    a.p = ensure<float>(c, c->p0, N);
+    a.r0 = ensure<float>(c, c->r, N);
+    a.r1 = ensure<float>(c, c->z, N);
+    a.w0 = ensure<float>(c, c->w0, N);
+    a.w1 = ensure<float>(c, c->w1, N);
+    a.s0 = ensure<float>(c, c->s0, N);
+    a.s1 = ensure<float>(c, c->s1, N);
+    a.nchunks = n_chunks; a.K = K; a.rtol = pb.prm.cg_rtol; a.maxit = pb.prm.cg_max_iter;
+    check(c, hipMemsetAsync(a.active, 0, 2 * sizeof(int), c->stream), "memset");
+    check(c, nil::large_init(a, warm, c->stream), "large init");
+    // one launch per CG iteration; the host reads the count of components
+    // still iterating once per batch.  Events bracket each batch of launches
+    // (not the readbacks) for the kernel-time report.
+    const int batch = 16;
+    float kms = 0.f;
+    for (int it = 0; it <= pb.prm.cg_max_iter + 1; it += batch) {
+      mark(c, 12);
+      for (int k = 0; k < batch; ++k) check(c, nil::large_iter(a, it + k, c->stream), "large iter");
+      mark(c, 13);
+      launches += batch;
+      readback(c, a.active + ((it + batch - 1) & 1), sizeof(int), c->host);
+      kms += ev_ms(c, 12, 13);
+      if (c->host[0] <= 0) break;
     }
-    if (!ran) {
-      // one launch per CG phase; the host polls the active count in batches
-      const int batch = 16;
-      for (int it = 0;; it += batch) {
-        for (int k = 0; k < batch; ++k) check(c, nil::large_step(a, n_chunks, (it + k) & 1, c->stream), "large step");
-        launches += 2 * batch;
-        readback(c, a.active, sizeof(int), c->host);
-        if (c->host[0] <= 0) break;
-        if (it > pb.prm.cg_max_iter + batch) break;
-      }
-    }
-    check(c, nil::large_finish(a, n_chunks, cpix, zout, c->stream), "large finish");
+    large_kernel_ms = kms;
+    check(c, nil::large_finish(a, cpix, zout, c->stream), "large finish");
   }
   mark(c, 7);
-  // report
   readback(c, misc(c) + M_STATS, 4 * sizeof(int), c->host);
   const int notconv = c->host[0], fallbacks = c->host[1];
   if (rep) {
     std::vector<int> it(K), off(K1);
-    std::vector<double> rel(K);
+    std::vector<double> rel(K), hrr(K), hbb(K);
     if (K > 0) {
       check(c, hipMemcpyAsync(it.data(), iters, K * sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
       check(c, hipMemcpyAsync(off.data(), comp_off, K1 * sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
       check(c, hipMemcpyAsync(rel.data(), relres, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
-      // large components: relative residual from rr / bb
-      std::vector<double> hrr(K), hbb(K);
       check(c, hipMemcpyAsync(hrr.data(), rr, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
       check(c, hipMemcpyAsync(hbb.data(), bb, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
       check(c, hipStreamSynchronize(c->stream), "sync");
-      int cap = nil::fill_small_cap();
+      const int cap = nil::fill_small_cap();
       long long pxit = 0, lpxit = 0;
       int itmax = 0;
       double rmax = 0;
@@ -530,7 +489,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
       rep->fill_iters_max = itmax;
       rep->fill_max_relres = rmax;
     }
-    rep->n_small = n_small;
+    rep->n_small = ntier[0] + ntier[1] + ntier[2];
     rep->n_large = n_large;
     rep->fill_notconv = notconv;
     rep->fill_large_launches = launches;
@@ -539,6 +498,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->ms_warm = ev_ms(c, 4, 5);
     rep->ms_fill_small = ev_ms(c, 5, 6);
     rep->ms_fill_large = ev_ms(c, 6, 7);
+    rep->ms_large_kernel = large_kernel_ms;
   }
   if (notconv > 0) {
     c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";
@@ -594,8 +554,17 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   check(c, nil::quot_csr(pair_lo, pair_hi, Pp, K, keys, ent, ktmp, vtmp, kout2, ent_tmp, rowcnt, row_off,
                          ptr<int>(c->scan_tmp), c->stream),
         "csr");
+  // rows multiplied by a whole wavefront
+  int* heavy = ensure<int>(c, c->lpos, K1);
+  check(c, nil::quot_heavy_rows(row_off, K, ptr<int>(c->flag), ptr<int>(c->scanv), heavy, cntd + 2,
+                                ptr<int>(c->scan_tmp), c->stream),
+        "heavy rows");
+  readback(c, cntd + 2, sizeof(int), c->host);
+  const int nheavy = c->host[0];
   // per-iteration arrays
   nil::IrlsArgs a;
+  a.heavy = heavy;
+  a.nheavy = nheavy;
   a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
   a.nt = ptr<float>(c->nt); a.om_r = ptr<float>(c->om_r); a.om_d = ptr<float>(c->om_d); a.zfill = zfill;
   a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
@@ -617,7 +586,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.pcnt = ensure<int>(c, c->pcnt, K1);
   a.parent = ensure<int>(c, c->qparent, K1);
   a.wmax = (unsigned long long*)(misc(c) + M_WMAX);
-  a.bar = (unsigned*)(misc(c) + M_QBAR);
+  a.bar = nullptr;
   a.energy_out = (double*)(misc(c) + M_ENERGY);
   a.qiters_out = misc(c) + M_QITERS;
   a.epart = ensure<double>(c, c->epart, (size_t)ni::ceil_div(std::max(Pp, 1), 256));
@@ -626,11 +595,16 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.k = pb.prm.bini_k; a.L = pb.prm.out_L; a.U = pb.prm.out_U; a.cut_rel = pb.prm.w_cut_rel;
   a.q_rtol = pb.prm.q_rtol; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
   a.q_maxit = pb.prm.q_max_iter;
-  if (c->qcg_blocks < 0) c->qcg_blocks = nil::qcg_max_blocks(c->device);
-  a.qblocks = K <= 8192 ? 1 : std::max(1, std::min(c->qcg_blocks, std::min(256, ni::ceil_div(K, 2048))));
-  a.part = ensure<double>(c, c->qpart, 3 * 4 * (size_t)std::max(a.qblocks, 1));
+  a.nnz = 2 * Pp;
+  a.qcol = ensure<int>(c, c->qcol, std::max(a.nnz, 1));
+  a.qw = ensure<double>(c, c->qw, std::max(a.nnz, 1));
+  a.t0 = ensure<double>(c, c->qt0, K1);
+  a.t1 = ensure<double>(c, c->qt1, K1);
+  a.sc = ensure<double>(c, c->qsc, 4);
+  a.qflag = misc(c) + M_QFLAG;
+  a.host_flag = c->host + 32;
+  a.part = ensure<double>(c, c->qpart, 2 * 4 * (size_t)std::max(ni::ceil_div(K, 256), 1));
   check(c, hipMemsetAsync(a.S, 0, K1 * sizeof(double), c->stream), "memset");
-  check(c, hipMemsetAsync(a.bar, 0, 2 * sizeof(unsigned), c->stream), "memset");
   const int T = pb.prm.irls_iters;
   int ran = 0;
   std::vector<double> en(NI_MAX_IRLS, 0.0);
@@ -716,13 +690,12 @@ ni_status ni_params_default(ni_params* p) {
   p->out_U = 1e-3;
   p->outlier_mode = 1;
   p->delta_e_max = 0.0;
-  p->w_cut_rel = 1e-8;
+  p->w_cut_rel = 1e-4;
   p->cg_rtol = 1e-6;
   p->cg_max_iter = 50000;
   p->q_rtol = 1e-12;
   p->q_max_iter = 20000;
   p->warm_start = 0;
-  p->persistent = 1;
   return NI_OK;
 }
 

@@ -100,4 +100,44 @@ hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t
                             int bits, int* scan_tmp, hipStream_t st);
 size_t radix_tmp_ints(int n);
 
+// arguments of the batched CG of the large fill components (ni_fill.hip)
+struct LargeArgs {
+  const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start, *chunk_end;
+  double *part, *gam, *alp, *tol2, *rr, *bb;
+  int *iters, *active, *stats;
+  const float *cwr, *cwd, *cwu, *rhs, *dinv;
+  const uint32_t* coff;
+  float *x, *p, *r0, *r1, *w0, *w1, *s0, *s1;
+  int nchunks, K;
+  double rtol;
+  int maxit;
+};
+
+// arguments of one relative-scale iteration (ni_quot.hip)
+struct IrlsArgs {
+  const uint32_t* eidx;
+  int E, P, K, W;
+  const int* label;
+  const uint8_t* ebits;
+  const float *nt, *om_r, *om_d, *zfill;
+  const int *pair_start, *pair_lo, *pair_hi, *row_off;
+  const uint32_t* ent;
+  double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
+  double *s, *r, *z, *p0, *p1, *q, *part, *psum;
+  int *pcnt, *parent;
+  unsigned long long* wmax;
+  unsigned* bar;
+  double* energy_out;  // [t]
+  int* qiters_out;     // [t]
+  double* epart;
+  double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
+  int align, outlier_mode, q_maxit, nnz;
+  int* qcol;
+  double *qw, *t0, *t1, *sc;
+  int* qflag;
+  int* host_flag;
+  const int* heavy;
+  int nheavy;
+};
+
 }  // namespace nil

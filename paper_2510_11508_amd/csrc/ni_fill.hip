@@ -124,32 +124,47 @@ __global__ void k_assemble(const uint32_t* __restrict__ cpix, int N, int W, int 
   dinv[i] = dg > 0 ? (float)(1.0 / dg) : 0.f;
 }
 
-// n_c = comp_off[c+1] - comp_off[c]; flags: 1 small (2..cap), 2 large (> cap)
-__global__ void k_classify(const int* __restrict__ comp_off, int K, int cap, int* __restrict__ fsmall,
-                           int* __restrict__ flarge, int* __restrict__ nchunk, int chunk) {
+// size tiers: 1: 2..256 px (one wave), 2: ..2048 (256 threads), 3: ..8192
+// (1024 threads), 4: larger (grid-wide chunks); singletons need no solve
+__device__ __forceinline__ int size_tier(int n) {
+  return n <= 1 ? 0 : n <= 256 ? 1 : n <= 2048 ? 2 : n <= 8192 ? 3 : 4;
+}
+
+__global__ void k_tier_flags(const int* __restrict__ comp_off, int K, int tier, int* __restrict__ flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K) flag[c] = size_tier(comp_off[c + 1] - comp_off[c]) == tier ? 1 : 0;
+}
+
+__global__ void k_tier_list(const int* __restrict__ flag, const int* __restrict__ pos, int K, int* __restrict__ list) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K && flag[c]) list[pos[c]] = c;
+}
+
+__device__ __forceinline__ int chunk_len(int n, int chunk, int maxch, int nt) {
+  int nch = min(max(ni::ceil_div(n, chunk), 1), maxch);
+  return ni::ceil_div(ni::ceil_div(n, nch), nt) * nt;
+}
+
+__global__ void k_chunk_counts(const int* __restrict__ comp_off, int K, int chunk, int maxch, int nt,
+                               int* __restrict__ nchunk) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= K) return;
   int n = comp_off[c + 1] - comp_off[c];
-  fsmall[c] = (n >= 2 && n <= cap) ? 1 : 0;
-  flarge[c] = n > cap ? 1 : 0;
-  nchunk[c] = n > cap ? ni::ceil_div(n, chunk) : 0;
+  nchunk[c] = size_tier(n) == 4 ? ni::ceil_div(n, chunk_len(n, chunk, maxch, nt)) : 0;
 }
 
-__global__ void k_make_lists(const int* __restrict__ fsmall, const int* __restrict__ flarge,
-                             const int* __restrict__ spos, const int* __restrict__ lpos,
-                             const int* __restrict__ nchunk, const int* __restrict__ cbase,
-                             const int* __restrict__ comp_off, int K, int chunk,
-                             int* __restrict__ small_list, int* __restrict__ large_list,
-                             int* __restrict__ chunk_comp, int* __restrict__ chunk_start) {
+__global__ void k_chunk_table(const int* __restrict__ comp_off, const int* __restrict__ nchunk,
+                              const int* __restrict__ cbase, int K, int chunk, int maxch, int nt,
+                              int* __restrict__ chunk_comp, int* __restrict__ chunk_start,
+                              int* __restrict__ chunk_end) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
-  if (fsmall[c]) small_list[spos[c]] = c;
-  if (flarge[c]) {
-    large_list[lpos[c]] = c;
-    for (int j = 0; j < nchunk[c]; ++j) {
-      chunk_comp[cbase[c] + j] = c;
-      chunk_start[cbase[c] + j] = comp_off[c] + j * chunk;
-    }
+  if (c >= K || nchunk[c] == 0) return;
+  const int lo = comp_off[c], hi = comp_off[c + 1];
+  const int len = chunk_len(hi - lo, chunk, maxch, nt);
+  for (int j = 0; j < nchunk[c]; ++j) {
+    chunk_comp[cbase[c] + j] = c;
+    chunk_start[cbase[c] + j] = lo + j * len;
+    chunk_end[cbase[c] + j] = min(lo + (j + 1) * len, hi);
   }
 }
 
@@ -332,284 +347,236 @@ __global__ void __launch_bounds__(NT) k_fill_small(
 }
 
 // ============================================================ large path
-// Components above the LDS capacity are cut into chunks of CH pixels; a
-// workgroup handles one chunk per phase.  Per-component scalars come from a
-// deterministic two-level reduction: every chunk writes its FP64 partials,
-// the last chunk to arrive (atomic counter) sums them in chunk order.
-constexpr int LNT = 256, LPPT = 8, LCH = LNT * LPPT;
+// Components above the LDS capacity are cut into chunks of LCH pixels and
+// all of them advance together through Jacobi-preconditioned CG, two
+// kernel launches per iteration:
+//   A_i: beta_i = rho_i / rho_{i-1}; p_i = D^-1 r_i + beta_i p_{i-1};
+//        q_i = L p_i (the neighbours' p_i are recomputed from their r_i and
+//        p_{i-1}); partial (p_i, q_i)
+//   B_i: alpha_i = rho_i / (p_i, q_i); x += alpha_i p_i; r -= alpha_i q_i;
+//        partials rho_{i+1} = (r, D^-1 r) and ||r||^2
+// The stencil is evaluated in difference form sum_b w_ab (p_a - p_b), which
+// keeps the FP32 vectors accurate; every dot product is an FP64 sum.  Each
+// launch writes per-chunk FP64 partials [rho, rr, pq, bb] into one of two
+// slots, and every workgroup of a component sums the previous launch's slot
+// itself, in chunk order: the scalars are bitwise identical across the
+// component's workgroups and across runs, and no atomic or in-kernel fence
+// is needed for them because the launch boundary orders global memory.
+// chunks: up to 256 per component, at least 512 pixels each, a multiple
+// of the workgroup size long (so mid-size problems still fill the GPU while
+// the per-workgroup partial sums stay short)
+constexpr int LNT = 256, LCH = 512, LMAXCH = 256;
 
 struct LargeState {
-  // per component
   const int* comp_off;
-  const int* cbase;     // first chunk of the component
-  const int* nchunk;
-  int* cnt;             // arrival counters (reset by the last arriver)
-  double* part;         // [nchunks_total * 4]
-  double* rho;
-  double* bb;
-  double* tol2;
-  double* alpha;
-  double* beta;
-  double* rr;
-  int* done;
-  int* iters;
-  int* active;          // number of components not yet converged
-  int* stats;           // [0] not converged, [1] warm fallbacks
-  // per chunk
+  const int* cbase;       // first chunk of each component
+  const int* nchunk;      // chunks per component
   const int* chunk_comp;
   const int* chunk_start;
-  // per compact pixel
+  const int* chunk_end;
+  double* part;           // [2][nchunks][4] = (rho, rr, pq, bb) by launch parity
+  double* gam;            // [2][K] rho_i by iteration parity
+  double* alp;            // [K] unused scratch
+  double* tol2;           // [K]
+  double* rr;             // [K] last ||r||^2
+  double* bb;             // [K] ||b||^2
+  int* iters;             // [K]
+  int* active;            // [2] components still iterating, by iteration parity
+  int* stats;             // [0] not converged, [1] warm fallbacks
   const float *cwr, *cwd, *cwu, *rhs, *dinv;
   const uint32_t* coff;
-  float *x, *r, *z, *p0, *p1, *q;
+  float *x, *p, *r0, *r1, *w0, *w1, *s0, *s1;  // r0 = r, w0 = q, s0/s1 = p by parity
+  int nchunks;
   double rtol;
   int maxit;
 };
 
-// sums NV partials of component c in chunk order with the whole block;
-// called by the block that arrived last; result in every thread
-template <int NV>
-__device__ __forceinline__ void reduce_parts(const LargeState& S, int c, double (&v)[NV], double* scratch) {
+// component sums of the previous launch's partials (slot), fixed order
+__device__ __forceinline__ void comp_partials(const LargeState& S, int c, int slot, double (&v)[4], double* red) {
   const int base = S.cbase[c], nch = S.nchunk[c];
+  const double* pp = S.part + (size_t)slot * S.nchunks * 4;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int k = 0; k < 4; ++k) v[k] = 0.0;
   for (int j = threadIdx.x; j < nch; j += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += S.part[(size_t)(base + j) * 4 + k];
+    for (int k = 0; k < 4; ++k) v[k] += pp[(size_t)(base + j) * 4 + k];
   }
-  ni::block_sum<NV>(v, scratch);
+  ni::block_sum<4>(v, red);
 }
 
-// write partials, count arrival; returns true in every thread of the last block
-template <int NV>
-__device__ __forceinline__ bool arrive(const LargeState& S, int c, int ch, const double (&v)[NV], int* flag) {
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) S.part[(size_t)ch * 4 + k] = v[k];
-    __threadfence();
-    int old = atomicAdd(&S.cnt[c], 1);
-    *flag = (old == S.nchunk[c] - 1);
+// write this chunk's partials: fields in `mask` from v, the others copied
+// from the previous slot (so every slot always holds the latest values)
+__device__ __forceinline__ void put_partials(const LargeState& S, int ch, int wslot, const double* v, int mask) {
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    const size_t dst = ((size_t)wslot * S.nchunks + ch) * 4 + k;
+    const size_t src = ((size_t)(wslot ^ 1) * S.nchunks + ch) * 4 + k;
+    S.part[dst] = ((mask >> k) & 1) ? v[k] : S.part[src];
   }
-  __syncthreads();
-  bool last = *flag;
-  if (last) __threadfence();
-  return last;
 }
 
-// phase 0 (warm start only): mean of x0 per component
-__global__ void __launch_bounds__(LNT) k_large_mean(LargeState S, float* x, int apply_mean) {
+// init A: r = b - L x for the start x (0 or learned); partials -> slot 0
+__global__ void __launch_bounds__(LNT) k_lg_init_a(LargeState S) {
   __shared__ double red[4 * (LNT / 64)];
-  __shared__ int flag;
-  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
-  const int hi = S.comp_off[c + 1];
-  double v[1] = {0.0};
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i < hi) v[0] += x[i];
-  }
-  ni::block_sum<1>(v, red);
-  if (arrive<1>(S, c, ch, v, &flag)) {
-    double t[1];
-    reduce_parts<1>(S, c, t, red + 2 * (LNT / 64));
-    if (threadIdx.x == 0) {
-      S.alpha[c] = t[0] / (double)(hi - S.comp_off[c]);  // alpha[] doubles as scratch here
-      S.cnt[c] = 0;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(LNT) k_large_center(LargeState S, float* x) {
-  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
-  const int hi = S.comp_off[c + 1];
-  const float m = (float)S.alpha[c];
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i < hi) x[i] -= m;
-  }
-}
-
-// init: r = b - L x, z = D^-1 r, p_old = 0; partials rr, rz, bb.
-// With check_warm, only decides per component whether the start is kept
-// (rr < bb) and otherwise zeroes x.
-__global__ void __launch_bounds__(LNT) k_large_init(LargeState S, int check_warm) {
-  __shared__ double red[6 * (LNT / 64)];
-  __shared__ int flag;
   const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
   const int clo = S.comp_off[c], hi = S.comp_off[c + 1];
   double v[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i >= hi) continue;
+  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
     Stencil s = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, i, clo);
-    float xi = S.x[i];
+    const float xi = S.x[i];
     float q = 0.f;
     if (s.wr != 0.f) q += s.wr * (xi - S.x[i + 1]);
     if (s.wl != 0.f) q += s.wl * (xi - S.x[i - 1]);
     if (s.wd != 0.f) q += s.wd * (xi - S.x[i + s.od]);
     if (s.wu != 0.f) q += s.wu * (xi - S.x[i - s.ou]);
-    float b = S.rhs[i];
-    float ri = b - q;
-    float zi = S.dinv[i] * ri;
-    if (!check_warm) {
-      S.r[i] = ri;
-      S.z[i] = zi;
-      S.p0[i] = 0.f;
-      S.p1[i] = 0.f;
-    }
-    v[0] += (double)ri * ri;
-    v[1] += (double)ri * zi;
+    const float b = S.rhs[i];
+    const float ri = b - q;
+    S.r0[i] = ri;
+    v[0] += (double)ri * (S.dinv[i] * ri);
+    v[1] += (double)ri * ri;
     v[2] += (double)b * b;
   }
   ni::block_sum<3>(v, red);
-  if (arrive<3>(S, c, ch, v, &flag)) {
-    double t[3];
-    reduce_parts<3>(S, c, t, red + 3 * (LNT / 64));
-    if (threadIdx.x == 0) {
-      S.cnt[c] = 0;
-      if (check_warm) {
-        S.beta[c] = (t[0] < t[2]) ? 1.0 : 0.0;  // keep the start?
-        if (!(t[0] < t[2])) atomicAdd(&S.stats[1], 1);
-      } else {
-        S.bb[c] = t[2];
-        S.tol2[c] = S.rtol * S.rtol * t[2];
-        S.rho[c] = t[1];
-        S.rr[c] = t[0];
-        S.beta[c] = 0.0;
-        S.iters[c] = 0;
-        int d = (t[2] == 0.0) || (t[0] <= S.tol2[c]);
-        S.done[c] = d;
-        if (!d) atomicAdd(S.active, 1);
-      }
-    }
+  if (threadIdx.x < 4) {
+    const double vv[4] = {v[0], v[1], 0.0, v[2]};
+    S.part[(size_t)ch * 4 + threadIdx.x] = vv[threadIdx.x];
   }
 }
 
-__global__ void __launch_bounds__(LNT) k_large_reset(LargeState S) {
+// init B: a start no better than zero (||r|| >= ||b||) is dropped (x = 0,
+// r = b); p_{-1} = 0; partials -> slot 1, read by launch A_0
+__global__ void __launch_bounds__(LNT) k_lg_init_b(LargeState S, int warm) {
+  __shared__ double red[8 * (LNT / 64)];
   const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
   const int hi = S.comp_off[c + 1];
-  if (S.beta[c] != 0.0) return;
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i < hi) S.x[i] = 0.f;
+  double t[4];
+  comp_partials(S, c, 0, t, red);
+  const bool reset = warm && !(t[1] < t[3]);
+  double v[2] = {0.0, 0.0};
+  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
+    S.s1[i] = 0.f;
+    if (reset) {
+      const float b = S.rhs[i];
+      S.x[i] = 0.f;
+      S.r0[i] = b;
+      v[0] += (double)b * (S.dinv[i] * b);
+      v[1] += (double)b * b;
+    }
+  }
+  if (reset) ni::block_sum<2>(v, red + 4 * (LNT / 64));
+  if (threadIdx.x < 4) {
+    const size_t src = (size_t)ch * 4 + threadIdx.x;
+    const size_t dst = ((size_t)S.nchunks + ch) * 4 + threadIdx.x;
+    double val = S.part[src];
+    if (reset && threadIdx.x < 2) val = v[threadIdx.x];
+    S.part[dst] = val;
+  }
+  if (threadIdx.x == 0 && ch == S.cbase[c]) {
+    S.bb[c] = t[3];
+    S.tol2[c] = S.rtol * S.rtol * t[3];
+    S.iters[c] = 0;
+    if (reset) atomicAdd(&S.stats[1], 1);
   }
 }
 
-// Phase A: p_new = z + beta p_old (also at the neighbours, recomputed),
-// q = L p_new, partial p.q; the last chunk sets alpha = rho / p.q.
-__device__ __forceinline__ void phase_a(const LargeState& S, int ch, const float* __restrict__ pold,
-                                        float* __restrict__ pnew, double* red, int* flag) {
-  const int c = S.chunk_comp[ch];
-  if (S.done[c]) return;
-  const int lo = S.chunk_start[ch], clo = S.comp_off[c], hi = S.comp_off[c + 1];
-  const float beta = (float)S.beta[c];
-  double v[1] = {0.0};
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i >= hi) continue;
-    Stencil s = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, i, clo);
-    const float pi = S.z[i] + beta * pold[i];
+// A_i: launch 2i, writes slot 0, reads slot 1
+__global__ void __launch_bounds__(LNT) k_lg_a(LargeState S, int it, int K) {
+  __shared__ double red[8 * (LNT / 64)];
+  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
+  const int clo = S.comp_off[c], hi = S.comp_off[c + 1];
+  double g[4];
+  comp_partials(S, c, 1, g, red);
+  const double rho = g[0], rri = g[1];
+  const bool conv = (S.bb[c] == 0.0) || (rri <= S.tol2[c]);
+  if (conv || it >= S.maxit) {
+    put_partials(S, ch, 0, g, 0);
+    if (threadIdx.x == 0 && ch == S.cbase[c]) {
+      S.rr[c] = rri;
+      if (!conv && it == S.maxit) atomicAdd(&S.stats[0], 1);
+    }
+    return;
+  }
+  const double beta = it == 0 ? 0.0 : rho / S.gam[(size_t)((it - 1) & 1) * K + c];
+  if (threadIdx.x == 0 && ch == S.cbase[c]) S.gam[(size_t)(it & 1) * K + c] = rho;
+  const float bt = (float)beta;
+  const float* pold = (it & 1) ? S.s0 : S.s1;  // p_{i-1}
+  float* pnew = (it & 1) ? S.s1 : S.s0;        // p_i
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
+    Stencil st = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, i, clo);
+    const float pi = S.dinv[i] * S.r0[i] + bt * pold[i];
     float q = 0.f;
-    if (s.wr != 0.f) q += s.wr * (pi - (S.z[i + 1] + beta * pold[i + 1]));
-    if (s.wl != 0.f) q += s.wl * (pi - (S.z[i - 1] + beta * pold[i - 1]));
-    if (s.wd != 0.f) q += s.wd * (pi - (S.z[i + s.od] + beta * pold[i + s.od]));
-    if (s.wu != 0.f) q += s.wu * (pi - (S.z[i - s.ou] + beta * pold[i - s.ou]));
+    if (st.wr != 0.f) { const int j = i + 1;      q += st.wr * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
+    if (st.wl != 0.f) { const int j = i - 1;      q += st.wl * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
+    if (st.wd != 0.f) { const int j = i + st.od;  q += st.wd * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
+    if (st.wu != 0.f) { const int j = i - st.ou;  q += st.wu * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
     pnew[i] = pi;
-    S.q[i] = q;
-    v[0] += (double)pi * q;
+    S.w0[i] = q;
+    v[2] += (double)pi * q;
+  }
+  ni::block_sum<4>(v, red + 4 * (LNT / 64));
+  put_partials(S, ch, 0, v, 4);
+}
+
+// B_i: launch 2i+1, writes slot 1, reads slot 0
+__global__ void __launch_bounds__(LNT) k_lg_b(LargeState S, int it, int K) {
+  __shared__ double red[8 * (LNT / 64)];
+  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
+  const int hi = S.comp_off[c + 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.active[(it + 1) & 1] = 0;  // read by the host already
+  double g[4];
+  comp_partials(S, c, 0, g, red);
+  const double rho = g[0], rri = g[1], pq = g[2];
+  const bool conv = (S.bb[c] == 0.0) || (rri <= S.tol2[c]);
+  if (conv || it >= S.maxit) {
+    put_partials(S, ch, 1, g, 0);
+    return;
+  }
+  if (threadIdx.x == 0 && ch == S.cbase[c]) {
+    S.iters[c] = it + 1;
+    atomicAdd(&S.active[it & 1], 1);
+  }
+  const float alpha = (float)(rho / pq);
+  const float* pcur = (it & 1) ? S.s1 : S.s0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
+    const float ri = S.r0[i] - alpha * S.w0[i];
+    S.x[i] += alpha * pcur[i];
+    S.r0[i] = ri;
+    v[0] += (double)ri * (S.dinv[i] * ri);
+    v[1] += (double)ri * ri;
+  }
+  ni::block_sum<4>(v, red + 4 * (LNT / 64));
+  put_partials(S, ch, 1, v, 3);
+  if (threadIdx.x == 0 && ch == S.cbase[c]) S.rr[c] = rri;
+}
+
+// zero mean per component, scatter to the grid
+__global__ void __launch_bounds__(LNT) k_lg_sum(LargeState S, int slot) {
+  __shared__ double red[4 * (LNT / 64)];
+  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
+  const int hi = S.comp_off[c + 1];
+  double v[1] = {0.0};
+  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
+    v[0] += S.x[i];
   }
   ni::block_sum<1>(v, red);
-  if (arrive<1>(S, c, ch, v, flag)) {
-    double t[1];
-    reduce_parts<1>(S, c, t, red + 4 * (LNT / 64));
-    if (threadIdx.x == 0) {
-      S.alpha[c] = S.rho[c] / t[0];
-      S.cnt[c] = 0;
-    }
-  }
+  if (threadIdx.x == 0) S.part[((size_t)slot * S.nchunks + ch) * 4] = v[0];
 }
 
-// Phase B: x += alpha p, r -= alpha q, z = D^-1 r; partials rr, rz; the
-// last chunk sets beta = rz_new / rz and retires converged components.
-__device__ __forceinline__ void phase_b(const LargeState& S, int ch, const float* __restrict__ pnew,
-                                        double* red, int* flag) {
-  const int c = S.chunk_comp[ch];
-  if (S.done[c]) return;
-  const int lo = S.chunk_start[ch], hi = S.comp_off[c + 1];
-  const float alpha = (float)S.alpha[c];
-  double v[2] = {0.0, 0.0};
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i >= hi) continue;
-    float xi = S.x[i] + alpha * pnew[i];
-    float ri = S.r[i] - alpha * S.q[i];
-    float zi = S.dinv[i] * ri;
-    S.x[i] = xi;
-    S.r[i] = ri;
-    S.z[i] = zi;
-    v[0] += (double)ri * ri;
-    v[1] += (double)ri * zi;
-  }
-  ni::block_sum<2>(v, red);
-  if (arrive<2>(S, c, ch, v, flag)) {
-    double t[2];
-    reduce_parts<2>(S, c, t, red + 4 * (LNT / 64));
-    if (threadIdx.x == 0) {
-      S.cnt[c] = 0;
-      int it = S.iters[c] + 1;
-      S.iters[c] = it;
-      S.beta[c] = t[1] / S.rho[c];
-      S.rho[c] = t[1];
-      S.rr[c] = t[0];
-      if (t[0] <= S.tol2[c] || it >= S.maxit) {
-        S.done[c] = 1;
-        atomicSub(S.active, 1);
-        if (t[0] > S.tol2[c]) atomicAdd(&S.stats[0], 1);
-      }
-    }
-  }
-}
-
-__global__ void __launch_bounds__(LNT) k_large_a(LargeState S, int parity) {
-  __shared__ double red[6 * (LNT / 64)];
-  __shared__ int flag;
-  phase_a(S, blockIdx.x, parity ? S.p1 : S.p0, parity ? S.p0 : S.p1, red, &flag);
-}
-
-__global__ void __launch_bounds__(LNT) k_large_b(LargeState S, int parity) {
-  __shared__ double red[6 * (LNT / 64)];
-  __shared__ int flag;
-  phase_b(S, blockIdx.x, parity ? S.p0 : S.p1, red, &flag);
-}
-
-// One persistent, cooperatively launched grid runs every CG iteration of
-// every large component: the workgroups stride over the chunks of the
-// components still active, with a grid barrier after each phase.
-__global__ void __launch_bounds__(LNT) k_large_persistent(LargeState S, int nchunks, unsigned* bar) {
-  __shared__ double red[6 * (LNT / 64)];
-  __shared__ int flag;
-  const unsigned nb = gridDim.x;
-  for (int it = 0;; ++it) {
-    // every block reads the same counter between two barriers: uniform exit
-    if (__hip_atomic_load(S.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0) break;
-    const int par = it & 1;
-    const float* pold = par ? S.p1 : S.p0;
-    float* pnew = par ? S.p0 : S.p1;
-    for (int ch = blockIdx.x; ch < nchunks; ch += nb) phase_a(S, ch, pold, pnew, red, &flag);
-    ni::grid_barrier(bar, nb);
-    for (int ch = blockIdx.x; ch < nchunks; ch += nb) phase_b(S, ch, pnew, red, &flag);
-    ni::grid_barrier(bar, nb);
-  }
-}
-
-// zero mean per component and scatter to the grid (two kernels)
-__global__ void __launch_bounds__(LNT) k_large_out(LargeState S, const uint32_t* __restrict__ cpix,
-                                                   float* __restrict__ zgrid) {
+__global__ void __launch_bounds__(LNT) k_lg_center(LargeState S, int slot, float* __restrict__ out,
+                                                   const uint32_t* __restrict__ cpix) {
+  __shared__ double red[4 * (LNT / 64)];
   const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
-  const int hi = S.comp_off[c + 1];
-  const double m = S.alpha[c];
-  for (int k = 0; k < LPPT; ++k) {
-    int i = lo + threadIdx.x + k * LNT;
-    if (i < hi) zgrid[cpix[i]] = (float)((double)S.x[i] - m);
+  const int clo = S.comp_off[c], hi = S.comp_off[c + 1];
+  const int base = S.cbase[c], nch = S.nchunk[c];
+  double v[1] = {0.0};
+  for (int j = threadIdx.x; j < nch; j += blockDim.x) v[0] += S.part[((size_t)slot * S.nchunks + base + j) * 4];
+  ni::block_sum<1>(v, red);
+  const double mean = v[0] / (double)(hi - clo);
+  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
+    if (out) out[cpix[i]] = (float)((double)S.x[i] - mean);
+    else S.x[i] = (float)((double)S.x[i] - mean);
   }
 }
 
@@ -622,11 +589,8 @@ __global__ void k_zero_grid(float* z, int P) {
 
 namespace nil {
 
-// capacity of the LDS-resident path
-constexpr int SMALL_NT = 256, SMALL_PPT = 8, SMALL_CAP = SMALL_NT * SMALL_PPT;
-constexpr int TINY_NT = 64, TINY_PPT = 4, TINY_CAP = TINY_NT * TINY_PPT;
-
-int fill_small_cap() { return SMALL_CAP; }
+int fill_small_cap() { return 8192; }
+int fill_chunk() { return LCH; }
 
 hipError_t check_labels(const int* label, const uint8_t* ebits, int P, int K, int* bad, hipStream_t st) {
   k_check_labels<<<ni::ceil_div(P, 256), 256, 0, st>>>(label, ebits, P, K, bad);
@@ -637,7 +601,6 @@ hipError_t check_ids(const uint32_t* skey, int N, int K, int* bad, hipStream_t s
   if (N > 0) k_check_ids<<<ni::ceil_div(N, 256), 256, 0, st>>>(skey, N, K, bad);
   return hipGetLastError();
 }
-int fill_chunk() { return LCH; }
 
 hipError_t fill_segments(const int* label, int P, int K, int* flag, int* vpos, int* n_dev,
                          uint32_t* key, uint32_t* val, uint32_t* skey, uint32_t* spix, uint32_t* ktmp,
@@ -669,25 +632,31 @@ hipError_t fill_assemble(const uint32_t* cpix, int N, int W, int P, const int* l
   return hipGetLastError();
 }
 
-// builds small / large component lists and the chunk table; counts land in
-// counts_dev[0] = n_small, [1] = n_large, [2] = n_chunks (device)
-hipError_t fill_classify(const int* comp_off, int K, int* fsmall, int* flarge, int* nchunk, int* spos,
-                         int* lpos, int* cbase, int* counts_dev, int* scan_tmp, hipStream_t st) {
-  if (K <= 0) return hipMemsetAsync(counts_dev, 0, 3 * sizeof(int), st);
-  k_classify<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, K, SMALL_CAP, fsmall, flarge, nchunk, LCH);
-  hipError_t e = scan_exclusive_i32(fsmall, spos, K, counts_dev + 0, scan_tmp, st);
+// list of the components of one size tier (ascending id); count -> *count_dev
+hipError_t fill_tier_list(const int* comp_off, int K, int tier, int* flag, int* pos, int* list, int* count_dev,
+                          int* scan_tmp, hipStream_t st) {
+  if (K <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int), st);
+  int nb = ni::ceil_div(K, 256);
+  k_tier_flags<<<nb, 256, 0, st>>>(comp_off, K, tier, flag);
+  hipError_t e = scan_exclusive_i32(flag, pos, K, count_dev, scan_tmp, st);
   if (e != hipSuccess) return e;
-  e = scan_exclusive_i32(flarge, lpos, K, counts_dev + 1, scan_tmp, st);
-  if (e != hipSuccess) return e;
-  return scan_exclusive_i32(nchunk, cbase, K, counts_dev + 2, scan_tmp, st);
+  k_tier_list<<<nb, 256, 0, st>>>(flag, pos, K, list);
+  return hipGetLastError();
 }
 
-hipError_t fill_lists(const int* fsmall, const int* flarge, const int* spos, const int* lpos,
-                      const int* nchunk, const int* cbase, const int* comp_off, int K, int* small_list,
-                      int* large_list, int* chunk_comp, int* chunk_start, hipStream_t st) {
+// chunk table of the large components; total chunks -> *count_dev
+hipError_t fill_chunks(const int* comp_off, int K, int* nchunk, int* cbase, int* count_dev, int* scan_tmp,
+                       hipStream_t st) {
+  if (K <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int), st);
+  k_chunk_counts<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, K, LCH, LMAXCH, LNT, nchunk);
+  return scan_exclusive_i32(nchunk, cbase, K, count_dev, scan_tmp, st);
+}
+
+hipError_t fill_chunk_table(const int* comp_off, const int* nchunk, const int* cbase, int K, int* chunk_comp,
+                            int* chunk_start, int* chunk_end, hipStream_t st) {
   if (K <= 0) return hipSuccess;
-  k_make_lists<<<ni::ceil_div(K, 256), 256, 0, st>>>(fsmall, flarge, spos, lpos, nchunk, cbase, comp_off, K,
-                                                     LCH, small_list, large_list, chunk_comp, chunk_start);
+  k_chunk_table<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, nchunk, cbase, K, LCH, LMAXCH, LNT, chunk_comp,
+                                                      chunk_start, chunk_end);
   return hipGetLastError();
 }
 
@@ -702,77 +671,58 @@ hipError_t fill_gather_x0(const uint32_t* cpix, int N, const float* x0g, float* 
   return hipGetLastError();
 }
 
-hipError_t fill_small(const int* list, int n_small, const int* comp_off, const float* cwr, const float* cwd,
+hipError_t fill_small(int tier, const int* list, int n, const int* comp_off, const float* cwr, const float* cwd,
                       const float* cwu, const uint32_t* coff, const float* rhs, const float* dinv,
                       const float* x0, const uint32_t* cpix, float* zgrid, double rtol, int maxit, int warm,
                       int* iters, double* relres, int* stats, hipStream_t st) {
-  if (n_small <= 0) return hipSuccess;
-  k_fill_small<SMALL_NT, SMALL_PPT><<<n_small, SMALL_NT, 0, st>>>(
-      list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid, rtol, maxit, warm, iters, relres, stats);
+  if (n <= 0) return hipSuccess;
+  if (tier == 1)
+    k_fill_small<64, 4><<<n, 64, 0, st>>>(list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid, rtol,
+                                          maxit, warm, iters, relres, stats);
+  else if (tier == 2)
+    k_fill_small<256, 8><<<n, 256, 0, st>>>(list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid, rtol,
+                                            maxit, warm, iters, relres, stats);
+  else
+    k_fill_small<1024, 8><<<n, 1024, 0, st>>>(list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid,
+                                              rtol, maxit, warm, iters, relres, stats);
   return hipGetLastError();
 }
-
-struct LargeArgs {
-  const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start;
-  int* cnt;
-  double *part, *rho, *bb, *tol2, *alpha, *beta, *rr;
-  int *done, *iters, *active, *stats;
-  const float *cwr, *cwd, *cwu, *rhs, *dinv;
-  const uint32_t* coff;
-  float *x, *r, *z, *p0, *p1, *q;
-  double rtol;
-  int maxit;
-};
 
 static LargeState to_state(const LargeArgs& a) {
   LargeState S;
-  S.comp_off = a.comp_off; S.cbase = a.cbase; S.nchunk = a.nchunk; S.cnt = a.cnt; S.part = a.part;
-  S.rho = a.rho; S.bb = a.bb; S.tol2 = a.tol2; S.alpha = a.alpha; S.beta = a.beta; S.rr = a.rr;
-  S.done = a.done; S.iters = a.iters; S.active = a.active; S.stats = a.stats;
-  S.chunk_comp = a.chunk_comp; S.chunk_start = a.chunk_start;
+  S.comp_off = a.comp_off; S.cbase = a.cbase; S.nchunk = a.nchunk; S.chunk_comp = a.chunk_comp;
+  S.chunk_start = a.chunk_start; S.chunk_end = a.chunk_end; S.part = a.part; S.gam = a.gam; S.alp = a.alp; S.tol2 = a.tol2;
+  S.rr = a.rr; S.bb = a.bb; S.iters = a.iters; S.active = a.active; S.stats = a.stats;
   S.cwr = a.cwr; S.cwd = a.cwd; S.cwu = a.cwu; S.rhs = a.rhs; S.dinv = a.dinv; S.coff = a.coff;
-  S.x = a.x; S.r = a.r; S.z = a.z; S.p0 = a.p0; S.p1 = a.p1; S.q = a.q;
-  S.rtol = a.rtol; S.maxit = a.maxit;
+  S.x = a.x; S.p = a.p; S.r0 = a.r0; S.r1 = a.r1; S.w0 = a.w0; S.w1 = a.w1; S.s0 = a.s0; S.s1 = a.s1;
+  S.nchunks = a.nchunks; S.rtol = a.rtol; S.maxit = a.maxit;
   return S;
 }
 
-hipError_t large_init(const LargeArgs& a, int nchunks, int warm, hipStream_t st) {
+hipError_t large_init(const LargeArgs& a, int warm, hipStream_t st) {
   LargeState S = to_state(a);
   if (warm) {
-    k_large_mean<<<nchunks, LNT, 0, st>>>(S, S.x, 1);
-    k_large_center<<<nchunks, LNT, 0, st>>>(S, S.x);
-    k_large_init<<<nchunks, LNT, 0, st>>>(S, 1);
-    k_large_reset<<<nchunks, LNT, 0, st>>>(S);
+    // centre the learned start on each component: only differences matter
+    k_lg_sum<<<a.nchunks, LNT, 0, st>>>(S, 0);
+    k_lg_center<<<a.nchunks, LNT, 0, st>>>(S, 0, nullptr, nullptr);
   }
-  k_large_init<<<nchunks, LNT, 0, st>>>(S, 0);
+  k_lg_init_a<<<a.nchunks, LNT, 0, st>>>(S);
+  k_lg_init_b<<<a.nchunks, LNT, 0, st>>>(S, warm);
   return hipGetLastError();
 }
 
-hipError_t large_step(const LargeArgs& a, int nchunks, int parity, hipStream_t st) {
+// one CG iteration = launches A_it and B_it
+hipError_t large_iter(const LargeArgs& a, int it, hipStream_t st) {
   LargeState S = to_state(a);
-  k_large_a<<<nchunks, LNT, 0, st>>>(S, parity);
-  k_large_b<<<nchunks, LNT, 0, st>>>(S, parity);
+  k_lg_a<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
+  k_lg_b<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
   return hipGetLastError();
 }
 
-int large_persistent_blocks(int device) {
-  int per_cu = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_large_persistent, LNT, 0) != hipSuccess)
-    return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  return per_cu * ncu;
-}
-
-hipError_t large_persistent(const LargeArgs& a, int nchunks, int nblocks, unsigned* bar, hipStream_t st) {
+hipError_t large_finish(const LargeArgs& a, const uint32_t* cpix, float* zgrid, hipStream_t st) {
   LargeState S = to_state(a);
-  void* args[] = {(void*)&S, (void*)&nchunks, (void*)&bar};
-  return hipLaunchCooperativeKernel((const void*)k_large_persistent, dim3(nblocks), dim3(LNT), args, 0, st);
-}
-
-hipError_t large_finish(const LargeArgs& a, int nchunks, const uint32_t* cpix, float* zgrid, hipStream_t st) {
-  LargeState S = to_state(a);
-  k_large_mean<<<nchunks, LNT, 0, st>>>(S, S.x, 0);
-  k_large_out<<<nchunks, LNT, 0, st>>>(S, cpix, zgrid);
+  k_lg_sum<<<a.nchunks, LNT, 0, st>>>(S, 0);
+  k_lg_center<<<a.nchunks, LNT, 0, st>>>(S, 0, zgrid, cpix);
   return hipGetLastError();
 }
 

@@ -242,108 +242,290 @@ __global__ void k_irls_nodes(const int* __restrict__ row_off, const uint32_t* __
 }
 
 // ------------------------------------------------------ quotient PCG (FP64)
-struct QState {
+// Matrix per iteration: qcol/qw = neighbour id and pair weight of every CSR
+// entry, diag = row sum (pure graph Laplacian), applied in difference form
+// q_c = sum_d w_cd (p_c - p_d).  Jacobi preconditioner; rows with diag = 0
+// (components whose every quotient edge was cut) keep s = 0.
+__global__ void k_q_matrix(const int* __restrict__ row_off, const uint32_t* __restrict__ ent,
+                           const int* __restrict__ pair_lo, const int* __restrict__ pair_hi,
+                           const double* __restrict__ pW, int nnz, int* __restrict__ qcol, double* __restrict__ qw) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nnz) return;
+  uint32_t e = ent[j];
+  int pid = (int)(e >> 1);
+  qcol[j] = (e & 1u) ? pair_lo[pid] : pair_hi[pid];
+  qw[j] = pW[pid];
+}
+
+struct QMat {
   const int* row_off;
-  const uint32_t* ent;
-  const int* pair_lo;
-  const int* pair_hi;
-  const double* pW;
+  const int* qcol;
+  const double* qw;
   const double* diag;
   const double* rhs;
   const double* babs;
-  double *s, *r, *z, *p0, *p1, *q, *part;
+  const int* heavy;   // rows with more than QHEAVY entries (one wavefront each)
+  int nheavy;
   int K;
+};
+
+// rows with more entries than this are multiplied by a whole wavefront;
+// the others by one thread each (quotient degrees are very uneven: a large
+// component can border thousands of others while most border four)
+constexpr int QHEAVY = 32;
+
+__global__ void k_heavy_flags(const int* __restrict__ row_off, int K, int* __restrict__ flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K) flag[c] = (row_off[c + 1] - row_off[c]) > QHEAVY ? 1 : 0;
+}
+
+__global__ void k_heavy_list(const int* __restrict__ flag, const int* __restrict__ pos, int K, int* __restrict__ list) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K && flag[c]) list[pos[c]] = c;
+}
+
+// One workgroup of QWG threads owns every row (K <= QCAP): the search
+// direction and the product L p live in LDS, so an iteration costs a few
+// workgroup barriers and no global synchronisation.  The product is formed
+// one row per wavefront (lanes stride over the row's entries): quotient
+// rows are very uneven, a large component can border thousands of others.
+constexpr int QWG = 1024, QR = 8, QCAP = QWG * QR, QNW = QWG / 64;
+
+__global__ void __launch_bounds__(QWG) k_qcg_wg(QMat M, double* __restrict__ s, double* __restrict__ rv,
+                                                double rtol, int maxit, int* __restrict__ iters_out) {
+  __shared__ double pl[QCAP];
+  __shared__ double ql[QCAP];
+  __shared__ double red[2][3 * QNW];
+  const int K = M.K;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double v3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < QR; ++k) {
+    const int c = threadIdx.x + k * QWG;
+    if (c < K) {
+      const double b = M.rhs[c], dg = M.diag[c];
+      const double z = dg > 0 ? b / dg : 0.0;
+      s[c] = 0.0;
+      rv[c] = b;
+      pl[c] = z;
+      v3[0] += b * b;
+      v3[1] += b * z;
+      v3[2] += M.babs[c] * M.babs[c];
+    }
+  }
+  ni::block_sum<3>(v3, red[0]);
+  double rr = v3[0], rho = v3[1];
+  const double tol2 = rtol * rtol * v3[2];
+  int it = 0;
+  while (rr > tol2 && it < maxit) {
+    double v1[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+      const int c = threadIdx.x + k * QWG;
+      if (c < K) {
+        const int j0 = M.row_off[c], j1 = M.row_off[c + 1];
+        if (j1 - j0 <= QHEAVY) {
+          const double pc = pl[c];
+          double acc = 0.0;
+          for (int j = j0; j < j1; ++j) acc += M.qw[j] * (pc - pl[M.qcol[j]]);
+          ql[c] = acc;
+          v1[0] += pc * acc;
+        }
+      }
+    }
+    for (int h = wid; h < M.nheavy; h += QNW) {
+      const int c = M.heavy[h];
+      const double pc = pl[c];
+      double acc = 0.0;
+      for (int j = M.row_off[c] + lane; j < M.row_off[c + 1]; j += 64) acc += M.qw[j] * (pc - pl[M.qcol[j]]);
+      acc = ni::wave_sum(acc);
+      if (lane == 0) {
+        ql[c] = acc;
+        v1[0] += pc * acc;
+      }
+    }
+    ni::block_sum<1>(v1, red[1]);
+    const double alpha = rho / v1[0];
+    double v2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+      const int c = threadIdx.x + k * QWG;
+      if (c < K) {
+        const double dg = M.diag[c];
+        s[c] += alpha * pl[c];
+        const double r = rv[c] - alpha * ql[c];
+        rv[c] = r;
+        const double z = dg > 0 ? r / dg : 0.0;
+        v2[0] += r * r;
+        v2[1] += r * z;
+      }
+    }
+    ni::block_sum<2>(v2, red[0]);
+    const double beta = v2[1] / rho;
+    rr = v2[0];
+    rho = v2[1];
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+      const int c = threadIdx.x + k * QWG;
+      if (c < K) {
+        const double dg = M.diag[c];
+        pl[c] = (dg > 0 ? rv[c] / dg : 0.0) + beta * pl[c];
+      }
+    }
+    __syncthreads();
+    ++it;
+  }
+  if (threadIdx.x == 0) *iters_out = it;
+}
+
+// Larger quotient systems: Jacobi PCG with two launches per iteration over
+// blocks of QB rows (one row per wavefront in the product).  Every block
+// re-sums all blocks' FP64 partials of the previous launch in block order
+// (deterministic, no atomics, no in-kernel fences); partial fields are
+// (rho, rr, pq, bscale^2) and each launch copies the fields it does not own.
+constexpr int QNT = 256, QB = 256;
+
+struct QIter {
+  QMat M;
+  double *s, *p0, *p1, *r, *q;
+  double* part;   // [2][nblk][4]
+  double* sc;     // [2] rho by iteration parity
+  int* flag;      // [2] still iterating, by iteration parity
+  int nblk;
   double rtol;
   int maxit;
   int* iters_out;
 };
 
-// grid-wide sum of NV per-block values, same result and order in every block
-template <int NV>
-__device__ __forceinline__ void grid_sum(const QState& Q, double (&v)[NV], double* red, unsigned* bar,
-                                         int slot) {
-  ni::block_sum<NV>(v, red);
-  const unsigned nb = gridDim.x;
-  if (nb == 1) return;
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ void q_partials(const QIter& Q, int slot, double (&v)[4], double* red) {
+  const double* pp = Q.part + (size_t)slot * Q.nblk * 4;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) Q.part[(size_t)slot * 4 * nb + blockIdx.x * 4 + k] = v[k];
+  for (int k = 0; k < 4; ++k) v[k] = 0.0;
+  for (int j = threadIdx.x; j < Q.nblk; j += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += pp[(size_t)j * 4 + k];
   }
-  ni::grid_barrier(bar, nb);
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (unsigned j = threadIdx.x; j < nb; j += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += Q.part[(size_t)slot * 4 * nb + j * 4 + k];
-  }
-  ni::block_sum<NV>(v, red + 8 * (blockDim.x >> 6));
+  ni::block_sum<4>(v, red);
 }
 
-__device__ __forceinline__ int nbr_of(const QState& Q, uint32_t e, int row) {
-  int pid = (int)(e >> 1);
-  return (e & 1u) ? Q.pair_lo[pid] : Q.pair_hi[pid];
+__device__ __forceinline__ void q_put(const QIter& Q, int wslot, const double* v, int mask) {
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    const size_t dst = ((size_t)wslot * Q.nblk + blockIdx.x) * 4 + k;
+    const size_t src = ((size_t)(wslot ^ 1) * Q.nblk + blockIdx.x) * 4 + k;
+    Q.part[dst] = ((mask >> k) & 1) ? v[k] : Q.part[src];
+  }
 }
 
-__global__ void __launch_bounds__(256) k_qcg(QState Q, unsigned* bar) {
-  __shared__ double red[16 * 4];
-  const int K = Q.K;
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gsz = gridDim.x * blockDim.x;
-  double v3[3] = {0.0, 0.0, 0.0};
-  for (int c = gtid; c < K; c += gsz) {
-    double b = Q.rhs[c];
-    double dg = Q.diag[c];
-    double zc = dg > 0 ? b / dg : 0.0;
+// s = 0, r = b, p_{-1} = 0; partials (rho, rr, 0, bscale^2) -> slot 1
+__global__ void __launch_bounds__(QNT) k_qcg_init(QIter Q) {
+  __shared__ double red[4 * (QNT / 64)];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int c = blockIdx.x * QB + threadIdx.x;
+  if (c < Q.M.K) {
+    const double b = Q.M.rhs[c], dg = Q.M.diag[c];
     Q.s[c] = 0.0;
     Q.r[c] = b;
-    Q.z[c] = zc;
-    Q.p0[c] = 0.0;
-    v3[0] += b * b;
-    v3[1] += b * zc;
-    v3[2] += Q.babs[c] * Q.babs[c];
+    Q.p1[c] = 0.0;
+    v[0] = dg > 0 ? b * b / dg : 0.0;
+    v[1] = b * b;
+    v[3] = Q.M.babs[c] * Q.M.babs[c];
   }
-  grid_sum<3>(Q, v3, red, bar, 0);
-  double rr = v3[0], rho = v3[1];
-  const double tol2 = Q.rtol * Q.rtol * v3[2];
-  double beta = 0.0;
-  int it = 0;
-  while (rr > tol2 && it < Q.maxit) {
-    const double* pold = (it & 1) ? Q.p1 : Q.p0;
-    double* pnew = (it & 1) ? Q.p0 : Q.p1;
-    double v1[1] = {0.0};
-    for (int c = gtid; c < K; c += gsz) {
-      double pc = Q.z[c] + beta * pold[c];
-      double qc = 0.0;
-      for (int j = Q.row_off[c]; j < Q.row_off[c + 1]; ++j) {
-        uint32_t e = Q.ent[j];
-        int d = nbr_of(Q, e, c);
-        double pd = Q.z[d] + beta * pold[d];
-        qc += Q.pW[e >> 1] * (pc - pd);
+  ni::block_sum<4>(v, red);
+  if (threadIdx.x < 4) Q.part[((size_t)Q.nblk + blockIdx.x) * 4 + threadIdx.x] = v[threadIdx.x];
+}
+
+// A_i: p_i = D^-1 r + beta p_{i-1} (neighbours recomputed), q = L p_i, (p, q)
+__global__ void __launch_bounds__(QNT) k_qcg_a(QIter Q, int it) {
+  __shared__ double red[8 * (QNT / 64)];
+  double g[4];
+  q_partials(Q, 1, g, red);
+  const bool done = !(g[1] > Q.rtol * Q.rtol * g[3]) || it >= Q.maxit;
+  if (done) {
+    q_put(Q, 0, g, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Q.flag[it & 1] = 0;
+      if (*Q.iters_out < 0) *Q.iters_out = it;
+    }
+    return;
+  }
+  const double beta = it == 0 ? 0.0 : g[0] / Q.sc[(it - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Q.sc[it & 1] = g[0];
+    Q.flag[it & 1] = 1;
+  }
+  const double* pold = (it & 1) ? Q.p0 : Q.p1;
+  double* pnew = (it & 1) ? Q.p1 : Q.p0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  {
+    // light rows of this block's range: one thread each
+    const int c = blockIdx.x * QB + threadIdx.x;
+    if (c < Q.M.K) {
+      const int j0 = Q.M.row_off[c], j1 = Q.M.row_off[c + 1];
+      if (j1 - j0 <= QHEAVY) {
+        const double dc = Q.M.diag[c];
+        const double pc = (dc > 0 ? Q.r[c] / dc : 0.0) + beta * pold[c];
+        double acc = 0.0;
+        for (int j = j0; j < j1; ++j) {
+          const int d = Q.M.qcol[j];
+          const double dd = Q.M.diag[d];
+          const double pd = (dd > 0 ? Q.r[d] / dd : 0.0) + beta * pold[d];
+          acc += Q.M.qw[j] * (pc - pd);
+        }
+        pnew[c] = pc;
+        Q.q[c] = acc;
+        v[2] += pc * acc;
       }
-      pnew[c] = pc;
-      Q.q[c] = qc;
-      v1[0] += pc * qc;
     }
-    grid_sum<1>(Q, v1, red, bar, 1);
-    const double alpha = rho / v1[0];
-    double v2[2] = {0.0, 0.0};
-    for (int c = gtid; c < K; c += gsz) {
-      double dg = Q.diag[c];
-      Q.s[c] += alpha * pnew[c];
-      double rc = Q.r[c] - alpha * Q.q[c];
-      double zc = dg > 0 ? rc / dg : 0.0;
-      Q.r[c] = rc;
-      Q.z[c] = zc;
-      v2[0] += rc * rc;
-      v2[1] += rc * zc;
-    }
-    grid_sum<2>(Q, v2, red, bar, 2);
-    rr = v2[0];
-    beta = v2[1] / rho;
-    rho = v2[1];
-    ++it;
   }
-  if (gtid == 0) *Q.iters_out = it;
+  // heavy rows, dealt round-robin to the blocks: one wavefront each
+  for (int h = blockIdx.x * (QNT / 64) + wid; h < Q.M.nheavy; h += gridDim.x * (QNT / 64)) {
+    const int c = Q.M.heavy[h];
+    const double dc = Q.M.diag[c];
+    const double pc = (dc > 0 ? Q.r[c] / dc : 0.0) + beta * pold[c];
+    double acc = 0.0;
+    for (int j = Q.M.row_off[c] + lane; j < Q.M.row_off[c + 1]; j += 64) {
+      const int d = Q.M.qcol[j];
+      const double dd = Q.M.diag[d];
+      const double pd = (dd > 0 ? Q.r[d] / dd : 0.0) + beta * pold[d];
+      acc += Q.M.qw[j] * (pc - pd);
+    }
+    acc = ni::wave_sum(acc);
+    if (lane == 0) {
+      pnew[c] = pc;
+      Q.q[c] = acc;
+      v[2] += pc * acc;
+    }
+  }
+  ni::block_sum<4>(v, red + 4 * (QNT / 64));
+  q_put(Q, 0, v, 4);
+}
+
+// B_i: alpha = rho / (p, q); s += alpha p; r -= alpha q; (r, D^-1 r), ||r||^2
+__global__ void __launch_bounds__(QNT) k_qcg_b(QIter Q, int it) {
+  __shared__ double red[8 * (QNT / 64)];
+  double g[4];
+  q_partials(Q, 0, g, red);
+  const bool done = !(g[1] > Q.rtol * Q.rtol * g[3]) || it >= Q.maxit;
+  if (done) {
+    q_put(Q, 1, g, 0);
+    return;
+  }
+  const double alpha = g[0] / g[2];
+  const double* pcur = (it & 1) ? Q.p1 : Q.p0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int c = blockIdx.x * QB + threadIdx.x;
+  if (c < Q.M.K) {
+    const double dg = Q.M.diag[c];
+    Q.s[c] += alpha * pcur[c];
+    const double r = Q.r[c] - alpha * Q.q[c];
+    Q.r[c] = r;
+    v[0] = dg > 0 ? r * r / dg : 0.0;
+    v[1] = r * r;
+  }
+  ni::block_sum<4>(v, red + 4 * (QNT / 64));
+  q_put(Q, 1, v, 3);
 }
 
 // piece gauge: zero mean of s over every connected piece (root = parent)
@@ -398,6 +580,17 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ pa
 }  // namespace
 
 namespace nil {
+
+// rows of the quotient CSR with more than QHEAVY entries; count -> *count_dev
+hipError_t quot_heavy_rows(const int* row_off, int K, int* flag, int* pos, int* list, int* count_dev, int* scan_tmp,
+                           hipStream_t st) {
+  if (K <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int), st);
+  k_heavy_flags<<<ni::ceil_div(K, 256), 256, 0, st>>>(row_off, K, flag);
+  hipError_t e = scan_exclusive_i32(flag, pos, K, count_dev, scan_tmp, st);
+  if (e != hipSuccess) return e;
+  k_heavy_list<<<ni::ceil_div(K, 256), 256, 0, st>>>(flag, pos, K, list);
+  return hipGetLastError();
+}
 
 hipError_t list_components(int n, const int* a, const int* b, const double* keep, int m, int* parent,
                            hipStream_t st);
@@ -470,32 +663,7 @@ hipError_t quot_csr(const int* pair_lo, const int* pair_hi, int P, int K, uint32
   return e;
 }
 
-struct IrlsArgs {
-  const uint32_t* eidx;
-  int E, P, K, W;
-  const int* label;
-  const uint8_t* ebits;
-  const float *nt, *om_r, *om_d, *zfill;
-  const int *pair_start, *pair_lo, *pair_hi, *row_off;
-  const uint32_t* ent;
-  double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
-  double *s, *r, *z, *p0, *p1, *q, *part, *psum;
-  int *pcnt, *parent;
-  unsigned long long* wmax;
-  unsigned* bar;
-  double* energy_out;  // [t]
-  int* qiters_out;     // [t]
-  double* epart;
-  double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
-  int align, outlier_mode, q_maxit, qblocks;
-};
 
-int qcg_max_blocks(int device) {
-  int per_cu = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_qcg, 256, 0) != hipSuccess) return 1;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 1;
-  return per_cu * ncu;
-}
 
 hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   hipError_t e;
@@ -525,19 +693,36 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   // pieces of the weighted quotient graph
   e = list_components(a.K, a.pair_lo, a.pair_hi, a.pW, a.P, a.parent, st);
   if (e != hipSuccess) return e;
-  // PCG
-  QState Q;
-  Q.row_off = a.row_off; Q.ent = a.ent; Q.pair_lo = a.pair_lo; Q.pair_hi = a.pair_hi;
-  Q.pW = a.pW; Q.diag = a.diag; Q.rhs = a.rhs; Q.babs = a.babs;
-  Q.s = a.s; Q.r = a.r; Q.z = a.z; Q.p0 = a.p0; Q.p1 = a.p1; Q.q = a.q; Q.part = a.part;
-  Q.K = a.K; Q.rtol = a.q_rtol; Q.maxit = a.q_maxit; Q.iters_out = a.qiters_out + t;
-  unsigned* bar = a.bar;
-  if (a.qblocks <= 1) {
-    k_qcg<<<1, 256, 0, st>>>(Q, bar);
+  // quotient PCG
+  if (a.nnz > 0) k_q_matrix<<<ni::ceil_div(a.nnz, 256), 256, 0, st>>>(a.row_off, a.ent, a.pair_lo, a.pair_hi, a.pW,
+                                                                       a.nnz, a.qcol, a.qw);
+  QMat M;
+  M.row_off = a.row_off; M.qcol = a.qcol; M.qw = a.qw; M.diag = a.diag; M.rhs = a.rhs; M.babs = a.babs; M.K = a.K;
+  M.heavy = a.heavy; M.nheavy = a.nheavy;
+  if (a.K <= QCAP) {
+    k_qcg_wg<<<1, QWG, 0, st>>>(M, a.s, a.r, a.q_rtol, a.q_maxit, a.qiters_out + t);
     e = hipGetLastError();
   } else {
-    void* args[] = {(void*)&Q, (void*)&bar};
-    e = hipLaunchCooperativeKernel((const void*)k_qcg, dim3(a.qblocks), dim3(256), args, 0, st);
+    QIter Q;
+    Q.M = M; Q.s = a.s; Q.p0 = a.p0; Q.p1 = a.p1; Q.r = a.r; Q.q = a.q;
+    Q.part = a.part; Q.sc = a.sc; Q.flag = a.qflag; Q.nblk = ni::ceil_div(a.K, QB); Q.rtol = a.q_rtol;
+    Q.maxit = a.q_maxit; Q.iters_out = a.qiters_out + t;
+    k_fill_i32<<<1, 1, 0, st>>>(Q.iters_out, 1, -1);
+    k_qcg_init<<<Q.nblk, QNT, 0, st>>>(Q);
+    e = hipGetLastError();
+    // two launches per iteration; the host polls the "still iterating" flag in batches
+    const int batch = 32;
+    for (int it = 0; e == hipSuccess && it <= a.q_maxit + 1; it += batch) {
+      for (int k = 0; k < batch; ++k) {
+        k_qcg_a<<<Q.nblk, QNT, 0, st>>>(Q, it + k);
+        k_qcg_b<<<Q.nblk, QNT, 0, st>>>(Q, it + k);
+      }
+      e = hipGetLastError();
+      if (e != hipSuccess) break;
+      e = hipMemcpyAsync(a.host_flag, Q.flag + ((it + batch - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (*a.host_flag == 0) break;
+    }
   }
   if (e != hipSuccess) return e;
   // piece gauge and accumulate S

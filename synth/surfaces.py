@@ -90,6 +90,50 @@ class _Scene:
             z = np.maximum(z, self.zmin)
         return z
 
+    def grid(self, u0, v0, H, W, du=0.0, dv=0.0):
+        """z at (u0 + j + du, v0 + i + dv) for i < H, j < W, evaluating each
+        bump and circle only inside its support window (6 sigma / radius)
+        and every half-plane step through one row-wise prefix sum."""
+        u = u0 + np.arange(W, dtype=np.float64) + du
+        v = v0 + np.arange(H, dtype=np.float64) + dv
+        z = self.base(u[None, :], v[:, None]) + np.zeros((H, W))
+        for A, uc, vc, sg in self.bumps:
+            rad = 6.0 * sg
+            j0, j1 = np.searchsorted(u, uc - rad), np.searchsorted(u, uc + rad, side="right")
+            i0, i1 = np.searchsorted(v, vc - rad), np.searchsorted(v, vc + rad, side="right")
+            if j0 < j1 and i0 < i1:
+                gu = np.exp(-((u[j0:j1] - uc) ** 2) / (2.0 * sg * sg))
+                gv = np.exp(-((v[i0:i1] - vc) ** 2) / (2.0 * sg * sg))
+                z[i0:i1, j0:j1] += A * gv[:, None] * gu[None, :]
+        if self.lines:
+            diff = np.zeros((H, W + 1))
+            for d, lu, lv, c, sn in self.lines:
+                # (u - lu) c + (v - lv) sn > 0, solved for u row by row
+                if c == 0.0:
+                    on = ((v - lv) * sn) > 0.0
+                    diff[on, 0] += d
+                    diff[on, W] -= d
+                    continue
+                thr = lu - (v - lv) * sn / c
+                if c > 0:
+                    k = np.clip(np.searchsorted(u, thr, side="right"), 0, W)
+                    diff[np.arange(H), k] += d
+                    diff[:, W] -= d
+                else:
+                    k = np.clip(np.searchsorted(u, thr, side="left"), 0, W)
+                    diff[:, 0] += d
+                    diff[np.arange(H), k] -= d
+            z += np.cumsum(diff, axis=1)[:, :W]
+        for d, uc, vc, r in self.circles:
+            j0, j1 = np.searchsorted(u, uc - r), np.searchsorted(u, uc + r, side="right")
+            i0, i1 = np.searchsorted(v, vc - r), np.searchsorted(v, vc + r, side="right")
+            if j0 < j1 and i0 < i1:
+                inside = ((u[None, j0:j1] - uc) ** 2 + (v[i0:i1, None] - vc) ** 2) < r * r
+                z[i0:i1, j0:j1] += d * inside
+        if self.zmin is not None:
+            z = np.maximum(z, self.zmin)
+        return z
+
 
 def _blob_mask(rng, H, W, coverage):
     """Gaussian-smoothed white noise (correlation length W/16) thresholded at
@@ -122,8 +166,15 @@ def _persp_points(z_fn, u, v, cam):
 def _persp_normals(z_fn, H, W, cam, u0=0, v0=0):
     u = np.arange(u0, u0 + W, dtype=np.float64)[None, :] + np.zeros((H, 1))
     v = np.arange(v0, v0 + H, dtype=np.float64)[:, None] + np.zeros((1, W))
-    du = _persp_points(z_fn, u + 1, v, cam) - _persp_points(z_fn, u - 1, v, cam)
-    dv = _persp_points(z_fn, u, v + 1, cam) - _persp_points(z_fn, u, v - 1, cam)
+    if isinstance(z_fn, _Scene):
+        def pts(a, b):
+            z = z_fn.grid(u0, v0, H, W, a, b)
+            return np.stack([z * (u + a - cam.cx) / cam.fx, z * (v + b - cam.cy) / cam.fy, z], axis=-1)
+        du = pts(1.0, 0.0) - pts(-1.0, 0.0)
+        dv = pts(0.0, 1.0) - pts(0.0, -1.0)
+    else:
+        du = _persp_points(z_fn, u + 1, v, cam) - _persp_points(z_fn, u - 1, v, cam)
+        dv = _persp_points(z_fn, u, v + 1, cam) - _persp_points(z_fn, u, v - 1, cam)
     n = np.cross(du, dv)
     tau = np.stack([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy, np.ones_like(u)], axis=-1)
     s = np.sign(np.sum(n * tau, axis=-1, keepdims=True))
@@ -214,9 +265,7 @@ def make_persp(name: str, seed: int) -> Sample:
     cam = Camera("persp", fx=f, fy=f, cx=(W - 1) / 2.0, cy=(H - 1) / 2.0)
     n = _persp_normals(sc, H, W, cam)
     n = _add_noise(rng, n, cfg["noise"])
-    u = np.arange(W, dtype=np.float64)[None, :] + np.zeros((H, 1))
-    v = np.arange(H, dtype=np.float64)[:, None] + np.zeros((1, W))
-    z = sc(u, v)
+    z = sc.grid(0, 0, H, W)
     return Sample(n.astype(np.float32), mask, z, cam,
                   params=dict(theta_c_deg=2.0, irls_iters=cfg["T"]), name=f"{name}/s{seed}")
 
@@ -242,9 +291,7 @@ def make_patch(seed: int, size: int = 256) -> Sample:
     n = _persp_normals(sc, size, size, cam_full, u0=u0, v0=v0)
     n = _add_noise(rng, n, cfg["noise"])
     cam = Camera("persp", fx=f, fy=f, cx=(Wf - 1) / 2.0 - u0, cy=(Hf - 1) / 2.0 - v0)
-    u = np.arange(u0, u0 + size, dtype=np.float64)[None, :] + np.zeros((size, 1))
-    v = np.arange(v0, v0 + size, dtype=np.float64)[:, None] + np.zeros((1, size))
-    z = sc(u, v)
+    z = sc.grid(u0, v0, size, size)
     return Sample(n.astype(np.float32), mask, z, cam,
                   params=dict(theta_c_deg=2.0, irls_iters=15), name=f"patch/s{seed}")
 

