@@ -166,9 +166,43 @@ ni_status ni_irls(ni_ctx* ctx, const float* normals, const uint8_t* mask,
                   const float* zfill, float* depth, double* log_scale,
                   int64_t cap, ni_report* rep);
 
-/* Learned warm start: load the U-Net weight blob (host memory, format
- * "NIUNET01", see ni_unet_blob_size) used when params->warm_start = 1. */
+/* ---------------------------------------------------------------------
+ * Learned warm start (not in the paper): a 4-level U-Net (16-32-64-128
+ * channels, 3x3 convolutions, BF16 activations and weights, FP32
+ * accumulation on MFMA) maps (normal, mask, ray direction) to a log-depth
+ * estimate; with params->warm_start = 1 the fill CG of every component
+ * starts from it (centred per component; a start no better than zero is
+ * dropped).  Weight blob format: "NIUNET01", int32 n, n FP32 parameters.
+ * All model calls use the context's device and stream.
+ * ------------------------------------------------------------------- */
+int32_t ni_unet_param_count(void);
+size_t ni_unet_blob_size(void);
+/* fresh model, He-normal initialisation from a 64-bit seed */
+ni_status ni_unet_init(ni_ctx* ctx, uint64_t seed);
+/* load / save a weight blob (host memory of ni_unet_blob_size() bytes) */
 ni_status ni_unet_load(ni_ctx* ctx, const void* blob, size_t nbytes);
+ni_status ni_unet_save(ni_ctx* ctx, void* blob, size_t nbytes);
+/* FP32 master parameters, host arrays of ni_unet_param_count() floats */
+ni_status ni_unet_get_params(ni_ctx* ctx, float* host, int32_t n);
+ni_status ni_unet_set_params(ni_ctx* ctx, const float* host, int32_t n);
+/* log-depth estimate of a whole map: normals / mask as in ni_integrate,
+ * out device f32 [H][W] */
+ni_status ni_unet_predict(ni_ctx* ctx, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                          const ni_camera* cam, float* out);
+/* forward on raw features: feat device f32 [B][H][W][6] (n, mask, tau_x,
+ * tau_y), H and W multiples of 8; out device f32 [B][H][W] */
+ni_status ni_unet_forward(ni_ctx* ctx, const float* feat, int32_t B, int32_t H, int32_t W, float* out);
+/* after ni_unet_forward: gradient of sum(dout * out) w.r.t. the master
+ * parameters; dout device f32 [B][H][W], grad device f32 [param_count] */
+ni_status ni_unet_backward(ni_ctx* ctx, const float* dout, float* grad);
+/* one Adam step (lr, beta 0.9 / 0.999) on B patches of S x S (S multiple
+ * of 8): normals device f32 [B][S][S][3], mask device u8 [B][S][S], cams
+ * host [B], target device f32 [B][S][S] (fill log-depth), labels device
+ * i32 [B][S][S] with component ids unique across the batch in [0, ncomp)
+ * (-1 off the mask); loss host out: per-component centred MSE */
+ni_status ni_unet_train_step(ni_ctx* ctx, const float* normals, const uint8_t* mask, const ni_camera* cams,
+                             const float* target, const int32_t* labels, int32_t ncomp, int32_t B, int32_t S,
+                             float lr, double* loss);
 
 const char* ni_status_str(ni_status s);
 const char* ni_last_error(const ni_ctx* ctx);

@@ -17,7 +17,9 @@ NI_OK, NI_E_ARG, NI_E_SHAPE, NI_E_NONFINITE, NI_E_NOMEM, NI_E_DEVICE, NI_E_NOTCO
 NI_ORTHO, NI_PERSP = 0, 1
 
 EXPORTED = ["ni_params_default", "ni_create", "ni_destroy", "ni_set_stream", "ni_integrate", "ni_label",
-            "ni_fill", "ni_irls", "ni_unet_load", "ni_status_str", "ni_last_error", "ni_abi_version"]
+            "ni_fill", "ni_irls", "ni_unet_load", "ni_status_str", "ni_last_error", "ni_abi_version",
+            "ni_unet_param_count", "ni_unet_blob_size", "ni_unet_init", "ni_unet_save", "ni_unet_get_params",
+            "ni_unet_set_params", "ni_unet_predict", "ni_unet_forward", "ni_unet_backward", "ni_unet_train_step"]
 
 
 class ni_camera(C.Structure):
@@ -79,13 +81,24 @@ def lib():
         L.ni_irls.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, vp, vp, i64,
                               P(ni_report)]
         L.ni_unet_load.argtypes = [vp, vp, C.c_size_t]
+        L.ni_unet_param_count.restype = i32
+        L.ni_unet_blob_size.restype = C.c_size_t
+        L.ni_unet_init.argtypes = [vp, C.c_uint64]
+        L.ni_unet_save.argtypes = [vp, vp, C.c_size_t]
+        L.ni_unet_get_params.argtypes = [vp, vp, i32]
+        L.ni_unet_set_params.argtypes = [vp, vp, i32]
+        L.ni_unet_predict.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), vp]
+        L.ni_unet_forward.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.ni_unet_backward.argtypes = [vp, vp, vp]
+        L.ni_unet_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, C.c_float, P(C.c_double)]
         L.ni_status_str.argtypes = [C.c_int]
         L.ni_status_str.restype = C.c_char_p
         L.ni_last_error.argtypes = [vp]
         L.ni_last_error.restype = C.c_char_p
         L.ni_abi_version.restype = C.c_int32
         for name in EXPORTED:
-            if name not in ("ni_status_str", "ni_last_error", "ni_abi_version"):
+            if name not in ("ni_status_str", "ni_last_error", "ni_abi_version", "ni_unet_param_count",
+                            "ni_unet_blob_size"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -228,3 +241,62 @@ class Context:
     def ni_unet_load(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         self._raise(lib().ni_unet_load(self.h, C.cast(buf, C.c_void_p), len(blob)))
+
+    def ni_unet_init(self, seed: int):
+        self._raise(lib().ni_unet_init(self.h, C.c_uint64(seed)))
+
+    def ni_unet_save(self) -> bytes:
+        n = lib().ni_unet_blob_size()
+        buf = C.create_string_buffer(n)
+        self._raise(lib().ni_unet_save(self.h, C.cast(buf, C.c_void_p), n))
+        return buf.raw
+
+    def ni_unet_get_params(self):
+        import numpy as np
+        n = lib().ni_unet_param_count()
+        out = np.empty(n, np.float32)
+        self._raise(lib().ni_unet_get_params(self.h, C.c_void_p(out.ctypes.data), n))
+        return out
+
+    def ni_unet_set_params(self, prm):
+        import numpy as np
+        prm = np.ascontiguousarray(prm, dtype=np.float32)
+        self._stream()
+        self._raise(lib().ni_unet_set_params(self.h, C.c_void_p(prm.ctypes.data), prm.size))
+
+    def ni_unet_predict(self, normals, mask, cam):
+        import torch
+        H, W = _check_inputs(normals, mask)
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        out = torch.empty((H, W), dtype=torch.float32, device=normals.device)
+        self._stream()
+        self._raise(lib().ni_unet_predict(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), _ptr(out)))
+        return out
+
+    def ni_unet_forward(self, feat):
+        import torch
+        B, H, W, c6 = feat.shape
+        assert c6 == 6 and feat.dtype == torch.float32 and feat.is_contiguous()
+        out = torch.empty((B, H, W), dtype=torch.float32, device=feat.device)
+        self._stream()
+        self._raise(lib().ni_unet_forward(self.h, _ptr(feat), B, H, W, _ptr(out)))
+        return out
+
+    def ni_unet_backward(self, dout):
+        import torch
+        g = torch.empty((lib().ni_unet_param_count(),), dtype=torch.float32, device=dout.device)
+        self._stream()
+        self._raise(lib().ni_unet_backward(self.h, _ptr(dout.contiguous()), _ptr(g)))
+        return g
+
+    def ni_unet_train_step(self, normals, mask, cams, target, labels, ncomp, lr):
+        """normals [B,S,S,3] f32, mask [B,S,S] u8, cams list of camera dicts,
+        target [B,S,S] f32, labels [B,S,S] i32 (unique ids across the batch)."""
+        B, S = normals.shape[0], normals.shape[1]
+        arr = (ni_camera * B)(*[make_camera(c) for c in cams])
+        loss = C.c_double(0.0)
+        self._stream()
+        self._raise(lib().ni_unet_train_step(self.h, _ptr(normals), _ptr(mask), C.cast(arr, C.c_void_p),
+                                             _ptr(target), _ptr(labels), int(ncomp), B, S, float(lr),
+                                             C.byref(loss)))
+        return loss.value

@@ -58,7 +58,17 @@ hipError_t unet_predict(struct UnetModel*, const float*, const uint8_t*, int, in
                         void*, size_t, hipStream_t);
 size_t unet_workspace_bytes(int, int);
 int unet_load(struct UnetModel**, const void*, size_t, std::string*);
+int unet_new(struct UnetModel**, uint64_t, std::string*);
 void unet_free(struct UnetModel*);
+int unet_param_count();
+size_t unet_blob_size();
+hipError_t unet_save(struct UnetModel*, void*);
+hipError_t unet_get_params(struct UnetModel*, float*);
+hipError_t unet_set_params(struct UnetModel*, const float*, hipStream_t);
+hipError_t unet_forward_raw(struct UnetModel*, const float*, int, int, int, float*, hipStream_t);
+hipError_t unet_backward_raw(struct UnetModel*, const float*, float*, hipStream_t);
+hipError_t unet_train_step(struct UnetModel*, const float*, const uint8_t*, const ni_camera*, const float*,
+                           const int*, int, int, int, float, double*, hipStream_t);
 }  // namespace nil
 
 namespace {
@@ -870,6 +880,20 @@ ni_status ni_irls(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t 
   });
 }
 
+int32_t ni_unet_param_count(void) { return nil::unet_param_count(); }
+size_t ni_unet_blob_size(void) { return nil::unet_blob_size(); }
+
+ni_status ni_unet_init(ni_ctx* c, uint64_t seed) {
+  if (!c) return NI_E_ARG;
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    nil::UnetModel* m = nullptr;
+    if (!nil::unet_new(&m, seed, &c->err)) throw Fail{NI_E_NOMEM};
+    if (c->unet) nil::unet_free(c->unet);
+    c->unet = m;
+  });
+}
+
 ni_status ni_unet_load(ni_ctx* c, const void* blob, size_t nbytes) {
   if (!c || !blob) return NI_E_ARG;
   return guarded(c, [&] {
@@ -878,6 +902,113 @@ ni_status ni_unet_load(ni_ctx* c, const void* blob, size_t nbytes) {
     if (!nil::unet_load(&m, blob, nbytes, &c->err)) throw Fail{NI_E_MODEL};
     if (c->unet) nil::unet_free(c->unet);
     c->unet = m;
+  });
+}
+
+static ni_status need_model(ni_ctx* c) {
+  if (!c) return NI_E_ARG;
+  if (!c->unet) {
+    c->err = "no U-Net model (ni_unet_init or ni_unet_load first)";
+    return NI_E_MODEL;
+  }
+  c->err.clear();
+  return NI_OK;
+}
+
+ni_status ni_unet_save(ni_ctx* c, void* blob, size_t nbytes) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!blob || nbytes != nil::unet_blob_size()) {
+    c->err = "blob must be ni_unet_blob_size() bytes";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    check(c, nil::unet_save(c->unet, blob), "save");
+  });
+}
+
+ni_status ni_unet_get_params(ni_ctx* c, float* host, int32_t n) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!host || n != nil::unet_param_count()) {
+    c->err = "need ni_unet_param_count() floats";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] { check(c, nil::unet_get_params(c->unet, host), "get params"); });
+}
+
+ni_status ni_unet_set_params(ni_ctx* c, const float* host, int32_t n) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!host || n != nil::unet_param_count()) {
+    c->err = "need ni_unet_param_count() floats";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    check(c, nil::unet_set_params(c->unet, host, c->stream), "set params");
+    check(c, hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+ni_status ni_unet_predict(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                          const ni_camera* cam, float* out) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!normals || !mask || !cam || !out || H < 1 || W < 1 || (long long)H * W > (1ll << 28)) {
+    c->err = "bad argument";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    check(c, nil::unet_predict(c->unet, normals, mask, H, W, cam, out, nullptr, 0, c->stream), "predict");
+    check(c, hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+ni_status ni_unet_forward(ni_ctx* c, const float* feat, int32_t B, int32_t H, int32_t W, float* out) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!feat || !out || B < 1 || H < 8 || W < 8 || H % 8 || W % 8 || (long long)B * H * W > (1ll << 28)) {
+    c->err = "need B >= 1 and H, W multiples of 8";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    check(c, nil::unet_forward_raw(c->unet, feat, B, H, W, out, c->stream), "forward");
+    check(c, hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+ni_status ni_unet_backward(ni_ctx* c, const float* dout, float* grad) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!dout || !grad) {
+    c->err = "bad argument";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    check(c, nil::unet_backward_raw(c->unet, dout, grad, c->stream), "backward");
+    check(c, hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+ni_status ni_unet_train_step(ni_ctx* c, const float* normals, const uint8_t* mask, const ni_camera* cams,
+                             const float* target, const int32_t* labels, int32_t ncomp, int32_t B, int32_t S,
+                             float lr, double* loss) {
+  ni_status s = need_model(c);
+  if (s != NI_OK) return s;
+  if (!normals || !mask || !cams || !target || !labels || !loss || B < 1 || S < 8 || S % 8 || ncomp < 1 ||
+      (long long)B * S * S > (1ll << 28)) {
+    c->err = "bad argument";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    check(c, nil::unet_train_step(c->unet, normals, mask, cams, target, labels, ncomp, B, S, lr, loss, c->stream),
+          "train step");
+    check(c, hipStreamSynchronize(c->stream), "sync");
   });
 }
 
