@@ -6,12 +6,18 @@ system stopped at ||r_c|| <= 1e-6 ||b_c||.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
 
-The roofline object describes the dominant kernel, the batched CG
-iteration of the large fill components (k_lg_iter, one launch per
-iteration): algorithmic bytes = 60 B per pixel per CG iteration (reads x,
-p, r, w, s, 1/diag, three weights and the packed neighbour offsets; writes
-x, p, r, w, s), times the pixel-iterations of one launch, over its
-event-timed duration.  The CPU baseline is the FP64 oracle on this host.
+The roofline object describes the batched CG iteration of the large fill
+components, two launches per iteration (k_lg_a, k_lg_b): algorithmic bytes
+= 64 B per active pixel per CG iteration (k_lg_a reads r, 1/diag, p_{i-1},
+three weights and the packed neighbour offsets and writes p_i and q;
+k_lg_b reads r, q, x, p_i, 1/diag and writes x and r), times the active
+pixel-iterations of one iteration, over the event-timed duration of one
+iteration's two launches.  The CPU baseline is the FP64 oracle on this host.
+
+With a trained warm-start model (paper_2510_11508_amd/weights/, or
+--model) the same map is also integrated with warm_start = 1 and the
+report compares the two at the same 1e-6 residual (relative to ||b||):
+speedup = wall(zero start) / wall(warm start incl. network inference).
 """
 import os
 
@@ -30,7 +36,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "valid Mpixels/s integrated at 1e-6 residual; warm-start vs plain CG speedup"
 HBM_PEAK_GBS = 8000.0
-CG_BYTES_PER_PX_ITER = 60
+CG_BYTES_PER_PX_ITER = 64
+DEFAULT_MODEL = os.path.join(ROOT, "paper_2510_11508_amd", "weights", "unet_warmstart.niunet")
 WORKLOADS = {
     "c2": "512x512 perspective (f=600), 5 depth steps, 6 bumps, 45% blob mask, noise 0.005, theta_c 2 deg, T=15",
     "c3": "2048x2048 perspective (f=2400), 40 steps, 60 bumps, 70% blob mask, noise 0.005, theta_c 2 deg, T=15",
@@ -81,6 +88,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--model", default=DEFAULT_MODEL, help="warm-start weights (skipped if absent)")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     a = ap.parse_args()
@@ -111,18 +120,44 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    for _ in range(a.warmup):
-        ctx.ni_integrate(normals, mask, cam, p)
-    torch.cuda.synchronize()
-    reps = []
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        out = ctx.ni_integrate(normals, mask, cam, p)
-        reps.append(out["report"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1000.0 / a.steps
+    def timed(prm):
+        for _ in range(a.warmup):
+            ctx.ni_integrate(normals, mask, cam, prm)
+        torch.cuda.synchronize()
+        reps = []
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            out = ctx.ni_integrate(normals, mask, cam, prm)
+            reps.append(out["report"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / a.steps
+        return ms, reps, out
+
+    ms, reps, out = timed(p)
     value = n_valid / (ms / 1000.0) / 1e6
+
+    def stage_ms(rs):
+        return {k[3:]: round(float(np.mean([r[k] for r in rs])), 3) for k in rs[-1] if k.startswith("ms_")}
+
+    warm = None
+    if not a.no_warm and os.path.exists(a.model):
+        ctx.ni_unet_load(open(a.model, "rb").read())
+        pw = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T, warm_start=1)
+        ms_w, reps_w, out_w = timed(pw)
+        rw = reps_w[-1]
+        z_ref, z_w = out["depth"], out_w["depth"]
+        v = torch.isfinite(z_ref)
+        dz = float(((z_w[v] - z_ref[v]).abs() / z_ref[v].abs().clamp_min(1e-30)).max()) if bool(v.any()) else 0.0
+        warm = dict(model=os.path.relpath(a.model, ROOT), ms_per_step=round(ms_w, 3),
+                    value=round(n_valid / (ms_w / 1000.0) / 1e6, 3),
+                    speedup=round(ms / ms_w, 3),
+                    fill_speedup=round((reps[-1]["ms_fill_small"] + reps[-1]["ms_fill_large"]) /
+                                       max(rw["ms_warm"] + rw["ms_fill_small"] + rw["ms_fill_large"], 1e-9), 3),
+                    stages_ms=stage_ms(reps_w),
+                    fill_iters_max=dict(zero=reps[-1]["fill_iters_max"], warm=rw["fill_iters_max"]),
+                    fill_px_iters=dict(zero=reps[-1]["fill_px_iters"], warm=rw["fill_px_iters"]),
+                    fallbacks=rw["warm_fallbacks"], max_relres=rw["fill_max_relres"],
+                    max_rel_depth_diff_vs_zero_start=dz)
 
     rep = reps[-1]
     k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
@@ -134,20 +169,23 @@ def main():
     traffic = traffic_record(a.workload)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_lg_iter", bytes_per_px_iter=CG_BYTES_PER_PX_ITER,
-                px_iters_per_launch=round(px_iters / launches, 1), launches=launches,
-                ms_per_launch=round(launch_ms, 5))
+                kernel="k_lg_a + k_lg_b (one CG iteration of the large components)",
+                bytes_per_px_iter=CG_BYTES_PER_PX_ITER,
+                px_iters_per_iteration=round(px_iters / launches, 1), iterations=launches,
+                ms_per_iteration=round(launch_ms, 5))
 
     line = dict(metric=METRIC, value=round(value, 3), unit="Mpx/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
                 ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype="f32 vectors / f64 reductions", data="synthetic",
                 config=dict(workload=f"{a.workload}: {WORKLOADS[a.workload]}", seed=a.seed, n_valid=n_valid,
                             K=out["K"], H=int(s.mask.shape[0]), W=int(s.mask.shape[1])),
-                stages_ms={k[3:]: round(float(np.mean([r[k] for r in reps])), 3) for k in rep if k.startswith("ms_")},
+                stages_ms=stage_ms(reps),
                 fill=dict(iters_max=rep["fill_iters_max"], n_small=rep["n_small"], n_large=rep["n_large"],
                           px_iters=rep["fill_px_iters"], max_relres=rep["fill_max_relres"]),
                 quot_iters=rep["quot_iters"],
                 roofline=roof)
+    if warm is not None:
+        line["warm_start"] = warm
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, dict(theta_c_deg=2.0, irls_iters=T))
     ctx.close()

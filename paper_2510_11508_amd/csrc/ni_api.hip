@@ -101,7 +101,7 @@ struct ni_ctx {
   Buf chunk_comp, chunk_start, part;
   // edges / pairs
   Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
-      row_off, epart, qpart, rsum, rcnt, qcol, qw, qt0, qt1, qsc;
+      row_off, epart, qpart, rsum, rcnt, qcol, qw, qt0, qt1, qsc, qpv, qst, qecol, qew;
   // scratch
   Buf scan_tmp, misc, unet_ws;
   int* host = nullptr;  // pinned readback area (64 ints)
@@ -117,7 +117,7 @@ struct ni_ctx {
                   &qz, &qp0, &qp1, &qq, &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &qpart, &rsum,
-                  &rcnt, &qcol, &qw, &qt0, &qt1, &qsc, &scan_tmp, &misc, &unet_ws};
+                  &rcnt, &qcol, &qw, &qt0, &qt1, &qsc, &qpv, &qst, &qecol, &qew, &scan_tmp, &misc, &unet_ws};
     bufs.assign(std::begin(all), std::end(all));
   }
 };
@@ -569,12 +569,13 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   check(c, nil::quot_heavy_rows(row_off, K, ptr<int>(c->flag), ptr<int>(c->scanv), heavy, cntd + 2,
                                 ptr<int>(c->scan_tmp), c->stream),
         "heavy rows");
-  readback(c, cntd + 2, sizeof(int), c->host);
-  const int nheavy = c->host[0];
+  readback(c, cntd + 2, 2 * sizeof(int), c->host);
+  const int nbig = c->host[0], nheavy = c->host[0] + c->host[1];
   // per-iteration arrays
   nil::IrlsArgs a;
   a.heavy = heavy;
   a.nheavy = nheavy;
+  a.nbig = nbig;
   a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
   a.nt = ptr<float>(c->nt); a.om_r = ptr<float>(c->om_r); a.om_d = ptr<float>(c->om_d); a.zfill = zfill;
   a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
@@ -610,10 +611,14 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.qw = ensure<double>(c, c->qw, std::max(a.nnz, 1));
   a.t0 = ensure<double>(c, c->qt0, K1);
   a.t1 = ensure<double>(c, c->qt1, K1);
+  a.pv = ensure<double>(c, c->qpv, K1);
+  a.qst = ensure<double>(c, c->qst, 8 * (size_t)K1);
+  a.ell_col = ensure<int>(c, c->qecol, 8 * (size_t)K1);
+  a.ell_w = ensure<double>(c, c->qew, 8 * (size_t)K1);
   a.sc = ensure<double>(c, c->qsc, 4);
   a.qflag = misc(c) + M_QFLAG;
   a.host_flag = c->host + 32;
-  a.part = ensure<double>(c, c->qpart, 2 * 4 * (size_t)std::max(ni::ceil_div(K, 256), 1));
+  a.part = ensure<double>(c, c->qpart, 2 * 4 * ((size_t)std::max(ni::ceil_div(K, 256), 1) + nheavy));
   check(c, hipMemsetAsync(a.S, 0, K1 * sizeof(double), c->stream), "memset");
   const int T = pb.prm.irls_iters;
   int ran = 0;

@@ -133,11 +133,13 @@ struct IrlsArgs {
   double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
   int align, outlier_mode, q_maxit, nnz;
   int* qcol;
-  double *qw, *t0, *t1, *sc;
+  double *qw, *t0, *t1, *sc, *pv, *qst;
   int* qflag;
   int* host_flag;
   const int* heavy;
-  int nheavy;
+  int nheavy, nbig;
+  int* ell_col;   // [8][K] ELL copy of the light quotient rows
+  double* ell_w;
 };
 
 }  // namespace nil

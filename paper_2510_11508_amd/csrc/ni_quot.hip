@@ -257,275 +257,446 @@ __global__ void k_q_matrix(const int* __restrict__ row_off, const uint32_t* __re
   qw[j] = pW[pid];
 }
 
+// Row classes of the quotient matrix.  Most rows have at most QELL entries
+// (a component borders a handful of others); they are also stored in an
+// ELL layout ecol/ew [QELL][K] (padding: column = the row, weight 0) so that
+// a thread loads all its entries with coalesced, independent loads.  Rows
+// with more entries ("heavy") are listed big first (> QBIG entries: one
+// workgroup each) then mid (one wavefront each); a large component can
+// border a thousand others.
+constexpr int QELL = 8, QBIG = 512;
+constexpr int QUNR = 8;  // entries per lane loaded ahead in a heavy row
+
 struct QMat {
   const int* row_off;
   const int* qcol;
   const double* qw;
+  const int* ecol;
+  const double* ew;
   const double* diag;
   const double* rhs;
   const double* babs;
-  const int* heavy;   // rows with more than QHEAVY entries (one wavefront each)
-  int nheavy;
+  const int* heavy;  // nbig big rows, then the mid rows
+  int nheavy, nbig;
   int K;
 };
 
-// rows with more entries than this are multiplied by a whole wavefront;
-// the others by one thread each (quotient degrees are very uneven: a large
-// component can border thousands of others while most border four)
-constexpr int QHEAVY = 32;
-
-__global__ void k_heavy_flags(const int* __restrict__ row_off, int K, int* __restrict__ flag) {
+__global__ void k_heavy_flags(const int* __restrict__ row_off, int K, int lo, int hi, int* __restrict__ flag) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < K) flag[c] = (row_off[c + 1] - row_off[c]) > QHEAVY ? 1 : 0;
+  if (c < K) {
+    const int n = row_off[c + 1] - row_off[c];
+    flag[c] = (n > lo && n <= hi) ? 1 : 0;
+  }
 }
 
-__global__ void k_heavy_list(const int* __restrict__ flag, const int* __restrict__ pos, int K, int* __restrict__ list) {
+__global__ void k_heavy_list(const int* __restrict__ flag, const int* __restrict__ pos, int K, int base,
+                             int* __restrict__ list) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < K && flag[c]) list[pos[c]] = c;
+  if (c < K && flag[c]) list[base + pos[c]] = c;
 }
 
-// One workgroup of QWG threads owns every row (K <= QCAP): the search
-// direction and the product L p live in LDS, so an iteration costs a few
-// workgroup barriers and no global synchronisation.  The product is formed
-// one row per wavefront (lanes stride over the row's entries): quotient
-// rows are very uneven, a large component can border thousands of others.
-constexpr int QWG = 1024, QR = 8, QCAP = QWG * QR, QNW = QWG / 64;
+// ELL copy of the rows with at most QELL entries (heavy rows: padding only)
+__global__ void k_q_ell(const int* __restrict__ row_off, const int* __restrict__ qcol, const double* __restrict__ qw,
+                        int K, int* __restrict__ ecol, double* __restrict__ ew) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  const int j0 = row_off[c], n = row_off[c + 1] - j0;
+  const bool light = n <= QELL;
+#pragma unroll
+  for (int k = 0; k < QELL; ++k) {
+    const bool use = light && k < n;
+    ecol[(size_t)k * K + c] = use ? qcol[j0 + k] : c;
+    ew[(size_t)k * K + c] = use ? qw[j0 + k] : 0.0;
+  }
+}
 
-__global__ void __launch_bounds__(QWG) k_qcg_wg(QMat M, double* __restrict__ s, double* __restrict__ rv,
-                                                double rtol, int maxit, int* __restrict__ iters_out) {
-  __shared__ double pl[QCAP];
-  __shared__ double ql[QCAP];
-  __shared__ double red[2][3 * QNW];
+// sum over the ELL entries of row c of q (X_c - X_d), X = one LDS vector
+__device__ __forceinline__ double ell_lds(const QMat& M, int c, const double* __restrict__ xl, double xc) {
+  int d[QELL];
+  double q[QELL];
+#pragma unroll
+  for (int k = 0; k < QELL; ++k) {
+    d[k] = M.ecol[(size_t)k * M.K + c];
+    q[k] = M.ew[(size_t)k * M.K + c];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < QELL; ++k) acc += q[k] * (xc - xl[d[k]]);
+  return acc;
+}
+
+// Quotient systems are solved by Jacobi-preconditioned CG in the
+// single-reduction form of Chronopoulos and Gear.  With u = D^-1 r and
+// w = L u carried along, an iteration needs the three sums (r,u), (w,u) and
+// (r,r) of the same vectors, so one reduction instead of two:
+//   p_i = u_i + b_i p_{i-1},   h_i = w_i + b_i h_{i-1}        (h_i = L p_i)
+//   s  += a_i p_i,   r_{i+1} = r_i - a_i h_i,   u_{i+1} = D^-1 r_{i+1},   w_{i+1} = L u_{i+1}
+//   g_{i+1} = (r_{i+1}, u_{i+1}),   d_{i+1} = (w_{i+1}, u_{i+1})
+//   b_{i+1} = g_{i+1} / g_i,   a_{i+1} = g_{i+1} / (d_{i+1} - b_{i+1} g_{i+1} / a_i)
+// from s = 0, r_0 = b, b_0 = 0, a_0 = g_0 / d_0.  In exact arithmetic these
+// are the iterates of standard PCG.  The products are applied in difference
+// form (L v)_c = sum_d w_cd (v_c - v_d); rows whose every quotient edge was
+// cut (diag = 0) keep s = 0.  Iteration stops at ||r|| <= rtol ||b_abs||,
+// b_abs = the row-wise sums of |w_e r_e| (a scale of the right-hand side
+// that does not cancel).
+//
+// One workgroup of QWG threads owns every row (K <= QCAP): u and L u live
+// in LDS, and an iteration costs one block reduction and two or three
+// barriers.  QR rows per thread; r, p, h, 1/diag of the rows stay in
+// registers (with more rows per thread they would spill), the solution
+// accumulates in place in s (each thread its own rows).
+constexpr int QWG = 1024, QNW = QWG / 64, QR = 4, QCAP = QWG * QR;
+
+__global__ void __launch_bounds__(QWG) k_qcg_wg(QMat M, double* __restrict__ s, double rtol, int maxit,
+                                                int* __restrict__ iters_out) {
+  __shared__ double ul[QCAP];  // u = D^-1 r of every row
+  __shared__ double wl[QCAP];  // L u of every row
+  __shared__ double red0[QNW];
+  __shared__ double red[3 * QNW];
   const int K = M.K;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double v3[3] = {0.0, 0.0, 0.0};
+  double r[QR], p[QR], h[QR], di[QR];
+  int lmask = 0;  // bit k: row k of this thread is light
+  double v0[1] = {0.0};
 #pragma unroll
   for (int k = 0; k < QR; ++k) {
     const int c = threadIdx.x + k * QWG;
+    r[k] = p[k] = h[k] = di[k] = 0.0;
     if (c < K) {
-      const double b = M.rhs[c], dg = M.diag[c];
-      const double z = dg > 0 ? b / dg : 0.0;
+      if (M.row_off[c + 1] - M.row_off[c] <= QELL) lmask |= 1 << k;
+      const double dg = M.diag[c];
+      di[k] = dg > 0 ? 1.0 / dg : 0.0;
+      r[k] = M.rhs[c];
+      ul[c] = r[k] * di[k];
       s[c] = 0.0;
-      rv[c] = b;
-      pl[c] = z;
-      v3[0] += b * b;
-      v3[1] += b * z;
-      v3[2] += M.babs[c] * M.babs[c];
+      v0[0] += M.babs[c] * M.babs[c];
     }
   }
-  ni::block_sum<3>(v3, red[0]);
-  double rr = v3[0], rho = v3[1];
-  const double tol2 = rtol * rtol * v3[2];
+  ni::block_sum<1>(v0, red0);  // its barrier also publishes ul
+  const double tol2 = rtol * rtol * v0[0];
+  double gam_old = 1.0, alp_old = 1.0;
   int it = 0;
-  while (rr > tol2 && it < maxit) {
-    double v1[1] = {0.0};
-#pragma unroll
+  for (;;) {
+    // one row at a time: the loads of all rows at once would not fit in registers
+#pragma unroll 1
     for (int k = 0; k < QR; ++k) {
       const int c = threadIdx.x + k * QWG;
-      if (c < K) {
-        const int j0 = M.row_off[c], j1 = M.row_off[c + 1];
-        if (j1 - j0 <= QHEAVY) {
-          const double pc = pl[c];
-          double acc = 0.0;
-          for (int j = j0; j < j1; ++j) acc += M.qw[j] * (pc - pl[M.qcol[j]]);
-          ql[c] = acc;
-          v1[0] += pc * acc;
-        }
-      }
+      if (c < K && ((lmask >> k) & 1)) wl[c] = ell_lds(M, c, ul, ul[c]);
     }
-    for (int h = wid; h < M.nheavy; h += QNW) {
-      const int c = M.heavy[h];
-      const double pc = pl[c];
+    for (int hh = wid; hh < M.nheavy; hh += QNW) {
+      const int c = M.heavy[hh];
+      const double uc = ul[c];
+      const int j1 = M.row_off[c + 1];
       double acc = 0.0;
-      for (int j = M.row_off[c] + lane; j < M.row_off[c + 1]; j += 64) acc += M.qw[j] * (pc - pl[M.qcol[j]]);
+      for (int base = M.row_off[c]; base < j1; base += 64 * QUNR) {
+        int d[QUNR];
+        double q[QUNR];
+#pragma unroll
+        for (int u = 0; u < QUNR; ++u) {
+          const int j = base + u * 64 + lane;
+          d[u] = j < j1 ? M.qcol[j] : c;
+          q[u] = j < j1 ? M.qw[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < QUNR; ++u) acc += q[u] * (uc - ul[d[u]]);
+      }
       acc = ni::wave_sum(acc);
-      if (lane == 0) {
-        ql[c] = acc;
-        v1[0] += pc * acc;
-      }
+      if (lane == 0) wl[c] = acc;
     }
-    ni::block_sum<1>(v1, red[1]);
-    const double alpha = rho / v1[0];
-    double v2[2] = {0.0, 0.0};
+    if (M.nheavy > 0) __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
       const int c = threadIdx.x + k * QWG;
       if (c < K) {
-        const double dg = M.diag[c];
-        s[c] += alpha * pl[c];
-        const double r = rv[c] - alpha * ql[c];
-        rv[c] = r;
-        const double z = dg > 0 ? r / dg : 0.0;
-        v2[0] += r * r;
-        v2[1] += r * z;
+        const double uc = r[k] * di[k];
+        v[0] += r[k] * uc;
+        v[1] += wl[c] * uc;
+        v[2] += r[k] * r[k];
       }
     }
-    ni::block_sum<2>(v2, red[0]);
-    const double beta = v2[1] / rho;
-    rr = v2[0];
-    rho = v2[1];
+    ni::block_sum<3>(v, red);
+    if (!(v[2] > tol2) || it >= maxit) break;
+    const double gam = v[0], del = v[1];
+    const double beta = it == 0 ? 0.0 : gam / gam_old;
+    const double alpha = it == 0 ? gam / del : gam / (del - beta * gam / alp_old);
+    gam_old = gam;
+    alp_old = alpha;
 #pragma unroll
     for (int k = 0; k < QR; ++k) {
       const int c = threadIdx.x + k * QWG;
       if (c < K) {
-        const double dg = M.diag[c];
-        pl[c] = (dg > 0 ? rv[c] / dg : 0.0) + beta * pl[c];
+        p[k] = r[k] * di[k] + beta * p[k];
+        h[k] = wl[c] + beta * h[k];
+        s[c] += alpha * p[k];
+        r[k] -= alpha * h[k];
+        ul[c] = r[k] * di[k];
       }
     }
-    __syncthreads();
+    __syncthreads();  // u complete before the next product; red and wl free again
     ++it;
   }
   if (threadIdx.x == 0) *iters_out = it;
 }
 
-// Larger quotient systems: Jacobi PCG with two launches per iteration over
-// blocks of QB rows (one row per wavefront in the product).  Every block
-// re-sums all blocks' FP64 partials of the previous launch in block order
-// (deterministic, no atomics, no in-kernel fences); partial fields are
-// (rho, rr, pq, bscale^2) and each launch copies the fields it does not own.
-constexpr int QNT = 256, QB = 256;
+// Larger quotient systems: the same iteration, one launch per iteration.
+// Blocks [0, nblk) own QB consecutive rows each (light rows through the ELL
+// copy); the next nbig blocks form L u for one big row each, all QNT
+// threads striding over its entries; the last blocks give one mid row to
+// each wavefront.
+//
+// Per row and parity slot one 32-byte record {r, w, h, 1/diag}: launch i
+// reads r_i, w_i, h_{i-1} from slot i&1 and writes r_{i+1}, w_{i+1}, h_i to
+// the other slot, so a neighbour costs one record load, and the neighbours'
+// u_{i+1} are recomputed from their slot-i values (no block waits for
+// another).  Every block re-sums all blocks' FP64 partials (g, d, rr, |b|^2)
+// of the previous launch in block order (deterministic, no atomics, no
+// in-kernel fences); the gathers that do not depend on a_i, b_i are issued
+// first, so the two latencies overlap.
+constexpr int QNT = 256, QB = 256, QNWB = QNT / 64;
 
 struct QIter {
   QMat M;
-  double *s, *p0, *p1, *r, *q;
-  double* part;   // [2][nblk][4]
-  double* sc;     // [2] rho by iteration parity
-  int* flag;      // [2] still iterating, by iteration parity
-  int nblk;
+  double *x, *p;
+  double4* st;     // [2][K] records {r, w, h, 1/diag}
+  double* part;    // [2][nparts][4]: g, d, rr, |b|^2
+  double* sc;      // [2][2]: g_i, a_i by iteration parity
+  int* flag;       // [2] still iterating, by iteration parity
+  int nblk, nparts;
   double rtol;
   int maxit;
   int* iters_out;
 };
 
-__device__ __forceinline__ void q_partials(const QIter& Q, int slot, double (&v)[4], double* red) {
-  const double* pp = Q.part + (size_t)slot * Q.nblk * 4;
+__host__ __device__ inline int q_nparts(int nblk, int nbig, int nmid) { return nblk + nbig + (nmid + QNWB - 1) / QNWB; }
+
+// terms q (X_e - X_d), X = r, w, h scaled by 1/diag, over entries
+// [j0 + t0, j1) with stride `stride`; QUNR entries are loaded before use
+__device__ __forceinline__ void row_terms(const QMat& M, const double4* __restrict__ sA, int e, int j0, int j1,
+                                          int t0, int stride, double Re, double We, double He, double& sR,
+                                          double& sW, double& sH) {
+  sR = sW = sH = 0.0;
+  for (int base = j0 + t0; base < j1; base += stride * QUNR) {
+    int d[QUNR];
+    double q[QUNR];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = 0.0;
-  for (int j = threadIdx.x; j < Q.nblk; j += blockDim.x) {
+    for (int u = 0; u < QUNR; ++u) {
+      const int j = base + u * stride;
+      d[u] = j < j1 ? M.qcol[j] : e;
+      q[u] = j < j1 ? M.qw[j] : 0.0;
+    }
+    double4 n[QUNR];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] += pp[(size_t)j * 4 + k];
+    for (int u = 0; u < QUNR; ++u) n[u] = sA[d[u]];
+#pragma unroll
+    for (int u = 0; u < QUNR; ++u) {
+      sR += q[u] * (Re - n[u].x * n[u].w);
+      sW += q[u] * (We - n[u].y * n[u].w);
+      sH += q[u] * (He - n[u].z * n[u].w);
+    }
   }
-  ni::block_sum<4>(v, red);
 }
 
-__device__ __forceinline__ void q_put(const QIter& Q, int wslot, const double* v, int mask) {
-  if (threadIdx.x < 4) {
-    const int k = threadIdx.x;
-    const size_t dst = ((size_t)wslot * Q.nblk + blockIdx.x) * 4 + k;
-    const size_t src = ((size_t)(wslot ^ 1) * Q.nblk + blockIdx.x) * 4 + k;
-    Q.part[dst] = ((mask >> k) & 1) ? v[k] : Q.part[src];
-  }
-}
-
-// s = 0, r = b, p_{-1} = 0; partials (rho, rr, 0, bscale^2) -> slot 1
+// s = 0, p = 0, slot 0 = {b, L D^-1 b, 0, 1/diag}; partials -> slot 0.
+// Same block layout as the iteration.
 __global__ void __launch_bounds__(QNT) k_qcg_init(QIter Q) {
-  __shared__ double red[4 * (QNT / 64)];
+  __shared__ double red[4 * QNWB];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int big0 = Q.nblk, mid0 = Q.nblk + Q.M.nbig;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const int c = blockIdx.x * QB + threadIdx.x;
-  if (c < Q.M.K) {
-    const double b = Q.M.rhs[c], dg = Q.M.diag[c];
-    Q.s[c] = 0.0;
-    Q.r[c] = b;
-    Q.p1[c] = 0.0;
-    v[0] = dg > 0 ? b * b / dg : 0.0;
-    v[1] = b * b;
-    v[3] = Q.M.babs[c] * Q.M.babs[c];
+  if (blockIdx.x < big0) {
+    const int c = blockIdx.x * QB + threadIdx.x;
+    if (c < Q.M.K) {
+      const double dg = Q.M.diag[c];
+      const double dc = dg > 0 ? 1.0 / dg : 0.0;
+      const double b = Q.M.rhs[c], uc = b * dc;
+      Q.x[c] = 0.0;
+      Q.p[c] = 0.0;
+      const int j0 = Q.M.row_off[c], j1 = Q.M.row_off[c + 1];
+      if (j1 - j0 <= QELL) {
+        double acc = 0.0;
+        for (int j = j0; j < j1; ++j) {
+          const int d = Q.M.qcol[j];
+          const double dd = Q.M.diag[d];
+          acc += Q.M.qw[j] * (uc - (dd > 0 ? Q.M.rhs[d] / dd : 0.0));
+        }
+        v[1] = acc * uc;
+        Q.st[c] = make_double4(b, acc, 0.0, dc);
+      } else {  // w of a heavy row is stored by the block or wavefront that forms it
+        double* rec = reinterpret_cast<double*>(Q.st + c);
+        rec[0] = b;
+        rec[2] = 0.0;
+        rec[3] = dc;
+      }
+      v[0] = b * uc;
+      v[2] = b * b;
+      v[3] = Q.M.babs[c] * Q.M.babs[c];
+    }
+  } else {
+    // heavy row: a whole block (big) or one wavefront (mid)
+    const bool big = blockIdx.x < mid0;
+    const int hi = big ? blockIdx.x - big0 : Q.M.nbig + (blockIdx.x - mid0) * QNWB + wid;
+    const bool have = big || hi < Q.M.nheavy;
+    double acc = 0.0, ue = 0.0;
+    int e = 0;
+    if (have) {
+      e = Q.M.heavy[hi];
+      const double de = Q.M.diag[e];
+      ue = de > 0 ? Q.M.rhs[e] / de : 0.0;
+      const int t0 = big ? threadIdx.x : lane, stride = big ? QNT : 64;
+      for (int j = Q.M.row_off[e] + t0; j < Q.M.row_off[e + 1]; j += stride) {
+        const int d = Q.M.qcol[j];
+        const double dd = Q.M.diag[d];
+        acc += Q.M.qw[j] * (ue - (dd > 0 ? Q.M.rhs[d] / dd : 0.0));
+      }
+    }
+    if (big) {
+      double a1[1] = {acc};
+      ni::block_sum<1>(a1, red);
+      acc = a1[0];
+      __syncthreads();
+    } else {
+      acc = ni::wave_sum(acc);
+    }
+    const bool writer = have && (big ? threadIdx.x == 0 : lane == 0);
+    if (writer) {
+      reinterpret_cast<double*>(Q.st + e)[1] = acc;
+      v[1] = acc * ue;
+    }
   }
   ni::block_sum<4>(v, red);
-  if (threadIdx.x < 4) Q.part[((size_t)Q.nblk + blockIdx.x) * 4 + threadIdx.x] = v[threadIdx.x];
+  if (threadIdx.x < 4) Q.part[(size_t)blockIdx.x * 4 + threadIdx.x] = v[threadIdx.x];
 }
 
-// A_i: p_i = D^-1 r + beta p_{i-1} (neighbours recomputed), q = L p_i, (p, q)
-__global__ void __launch_bounds__(QNT) k_qcg_a(QIter Q, int it) {
-  __shared__ double red[8 * (QNT / 64)];
-  double g[4];
-  q_partials(Q, 1, g, red);
-  const bool done = !(g[1] > Q.rtol * Q.rtol * g[3]) || it >= Q.maxit;
+__global__ void __launch_bounds__(QNT) k_qcg_it(QIter Q, int it) {
+  __shared__ double red[4 * QNWB];
+  __shared__ double gsh[4];
+  const int A = it & 1;
+  const double4* sA = Q.st + (size_t)A * Q.M.K;
+  double4* sB = Q.st + (size_t)(A ^ 1) * Q.M.K;
+  const double* pin = Q.part + (size_t)A * Q.nparts * 4;
+  double* pout = Q.part + (size_t)(A ^ 1) * Q.nparts * 4;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int big0 = Q.nblk, mid0 = Q.nblk + Q.M.nbig;
+  const int kind = blockIdx.x < big0 ? 0 : (blockIdx.x < mid0 ? 1 : 2);  // rows / big row / mid rows
+  // 1. gathers that do not depend on a_i, b_i
+  int c = -1;
+  if (kind == 0) {
+    c = blockIdx.x * QB + threadIdx.x;
+    if (c >= Q.M.K) c = -1;
+  } else if (kind == 1) {
+    c = Q.M.heavy[blockIdx.x - big0];
+  } else {
+    const int hi = Q.M.nbig + (blockIdx.x - mid0) * QNWB + wid;
+    c = hi < Q.M.nheavy ? Q.M.heavy[hi] : -1;
+  }
+  bool light = false;
+  double4 s4 = make_double4(0.0, 0.0, 0.0, 0.0);
+  double aR = 0.0, aW = 0.0, aH = 0.0;
+  if (c >= 0) {
+    s4 = sA[c];
+    const double Rc = s4.x * s4.w, Wc = s4.y * s4.w, Hc = s4.z * s4.w;
+    const int j0 = Q.M.row_off[c], j1 = Q.M.row_off[c + 1];
+    if (kind == 0) {
+      light = j1 - j0 <= QELL;
+      int d[QELL];
+      double q[QELL];
+#pragma unroll
+      for (int k = 0; k < QELL; ++k) {
+        d[k] = Q.M.ecol[(size_t)k * Q.M.K + c];
+        q[k] = Q.M.ew[(size_t)k * Q.M.K + c];
+      }
+      double4 n[QELL];
+#pragma unroll
+      for (int k = 0; k < QELL; ++k) n[k] = sA[d[k]];
+#pragma unroll
+      for (int k = 0; k < QELL; ++k) {
+        aR += q[k] * (Rc - n[k].x * n[k].w);
+        aW += q[k] * (Wc - n[k].y * n[k].w);
+        aH += q[k] * (Hc - n[k].z * n[k].w);
+      }
+    } else if (kind == 1) {
+      row_terms(Q.M, sA, c, j0, j1, threadIdx.x, QNT, Rc, Wc, Hc, aR, aW, aH);
+    } else {
+      row_terms(Q.M, sA, c, j0, j1, lane, 64, Rc, Wc, Hc, aR, aW, aH);
+    }
+  }
+  // 2. partials of the previous launch, summed by the first wavefront
+  if (wid == 0) {
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = lane; j < Q.nparts; j += 64) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] += pin[(size_t)j * 4 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = ni::wave_sum(g[k]);
+    if (lane < 4) gsh[lane] = g[lane];
+  }
+  if (kind == 1) {
+    double t3[3] = {aR, aW, aH};
+    ni::block_sum<3>(t3, red);
+    aR = t3[0];
+    aW = t3[1];
+    aH = t3[2];
+  } else if (kind == 2) {
+    aR = ni::wave_sum(aR);
+    aW = ni::wave_sum(aW);
+    aH = ni::wave_sum(aH);
+  }
+  __syncthreads();  // gsh ready; red free again
+  const double gam = gsh[0], del = gsh[1], rr = gsh[2], bs = gsh[3];
+  const bool done = !(rr > Q.rtol * Q.rtol * bs) || it >= Q.maxit;
   if (done) {
-    q_put(Q, 0, g, 0);
+    if (threadIdx.x < 4) pout[(size_t)blockIdx.x * 4 + threadIdx.x] = pin[(size_t)blockIdx.x * 4 + threadIdx.x];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       Q.flag[it & 1] = 0;
       if (*Q.iters_out < 0) *Q.iters_out = it;
     }
     return;
   }
-  const double beta = it == 0 ? 0.0 : g[0] / Q.sc[(it - 1) & 1];
+  double beta = 0.0, alpha = gam / del;
+  if (it > 0) {
+    const double gp = Q.sc[((it - 1) & 1) * 2], ap = Q.sc[((it - 1) & 1) * 2 + 1];
+    beta = gam / gp;
+    alpha = gam / (del - beta * gam / ap);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Q.sc[it & 1] = g[0];
+    Q.sc[(it & 1) * 2] = gam;
+    Q.sc[(it & 1) * 2 + 1] = alpha;
     Q.flag[it & 1] = 1;
   }
-  const double* pold = (it & 1) ? Q.p0 : Q.p1;
-  double* pnew = (it & 1) ? Q.p1 : Q.p0;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  {
-    // light rows of this block's range: one thread each
-    const int c = blockIdx.x * QB + threadIdx.x;
-    if (c < Q.M.K) {
-      const int j0 = Q.M.row_off[c], j1 = Q.M.row_off[c + 1];
-      if (j1 - j0 <= QHEAVY) {
-        const double dc = Q.M.diag[c];
-        const double pc = (dc > 0 ? Q.r[c] / dc : 0.0) + beta * pold[c];
-        double acc = 0.0;
-        for (int j = j0; j < j1; ++j) {
-          const int d = Q.M.qcol[j];
-          const double dd = Q.M.diag[d];
-          const double pd = (dd > 0 ? Q.r[d] / dd : 0.0) + beta * pold[d];
-          acc += Q.M.qw[j] * (pc - pd);
-        }
-        pnew[c] = pc;
-        Q.q[c] = acc;
-        v[2] += pc * acc;
+  // 3. updates: row blocks own r, h, p, x of their rows (and w of the light
+  // ones); the block or wavefront of a heavy row stores its w
+  double v[3] = {0.0, 0.0, 0.0};
+  const double dc = s4.w;
+  const double hn = s4.y + beta * s4.z;
+  const double rn = s4.x - alpha * hn;
+  const double un = rn * dc;
+  const double wn = aR - alpha * (aW + beta * aH);
+  if (kind == 0) {
+    if (c >= 0) {
+      const double pn = s4.x * dc + beta * Q.p[c];
+      Q.x[c] += alpha * pn;
+      Q.p[c] = pn;
+      v[0] = rn * un;
+      v[2] = rn * rn;
+      if (light) {
+        sB[c] = make_double4(rn, wn, hn, dc);
+        v[1] = wn * un;
+      } else {
+        double* rec = reinterpret_cast<double*>(sB + c);
+        rec[0] = rn;
+        rec[2] = hn;
+        rec[3] = dc;
       }
     }
+  } else if (c >= 0 && (kind == 1 ? threadIdx.x == 0 : lane == 0)) {
+    reinterpret_cast<double*>(sB + c)[1] = wn;
+    v[1] = wn * un;
   }
-  // heavy rows, dealt round-robin to the blocks: one wavefront each
-  for (int h = blockIdx.x * (QNT / 64) + wid; h < Q.M.nheavy; h += gridDim.x * (QNT / 64)) {
-    const int c = Q.M.heavy[h];
-    const double dc = Q.M.diag[c];
-    const double pc = (dc > 0 ? Q.r[c] / dc : 0.0) + beta * pold[c];
-    double acc = 0.0;
-    for (int j = Q.M.row_off[c] + lane; j < Q.M.row_off[c + 1]; j += 64) {
-      const int d = Q.M.qcol[j];
-      const double dd = Q.M.diag[d];
-      const double pd = (dd > 0 ? Q.r[d] / dd : 0.0) + beta * pold[d];
-      acc += Q.M.qw[j] * (pc - pd);
-    }
-    acc = ni::wave_sum(acc);
-    if (lane == 0) {
-      pnew[c] = pc;
-      Q.q[c] = acc;
-      v[2] += pc * acc;
-    }
-  }
-  ni::block_sum<4>(v, red + 4 * (QNT / 64));
-  q_put(Q, 0, v, 4);
-}
-
-// B_i: alpha = rho / (p, q); s += alpha p; r -= alpha q; (r, D^-1 r), ||r||^2
-__global__ void __launch_bounds__(QNT) k_qcg_b(QIter Q, int it) {
-  __shared__ double red[8 * (QNT / 64)];
-  double g[4];
-  q_partials(Q, 0, g, red);
-  const bool done = !(g[1] > Q.rtol * Q.rtol * g[3]) || it >= Q.maxit;
-  if (done) {
-    q_put(Q, 1, g, 0);
-    return;
-  }
-  const double alpha = g[0] / g[2];
-  const double* pcur = (it & 1) ? Q.p1 : Q.p0;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const int c = blockIdx.x * QB + threadIdx.x;
-  if (c < Q.M.K) {
-    const double dg = Q.M.diag[c];
-    Q.s[c] += alpha * pcur[c];
-    const double r = Q.r[c] - alpha * Q.q[c];
-    Q.r[c] = r;
-    v[0] = dg > 0 ? r * r / dg : 0.0;
-    v[1] = r * r;
-  }
-  ni::block_sum<4>(v, red + 4 * (QNT / 64));
-  q_put(Q, 1, v, 3);
+  ni::block_sum<3>(v, red);
+  if (threadIdx.x < 3) pout[(size_t)blockIdx.x * 4 + threadIdx.x] = v[threadIdx.x];
+  if (threadIdx.x == 3) pout[(size_t)blockIdx.x * 4 + 3] = pin[(size_t)blockIdx.x * 4 + 3];
 }
 
 // piece gauge: zero mean of s over every connected piece (root = parent)
@@ -581,14 +752,24 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ pa
 
 namespace nil {
 
-// rows of the quotient CSR with more than QHEAVY entries; count -> *count_dev
+// rows of the quotient CSR with more than QELL entries: the big ones
+// (> QBIG entries) first, then the mid ones; counts -> count_dev[0..1]
 hipError_t quot_heavy_rows(const int* row_off, int K, int* flag, int* pos, int* list, int* count_dev, int* scan_tmp,
                            hipStream_t st) {
-  if (K <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int), st);
-  k_heavy_flags<<<ni::ceil_div(K, 256), 256, 0, st>>>(row_off, K, flag);
+  if (K <= 0) return hipMemsetAsync(count_dev, 0, 2 * sizeof(int), st);
+  const int nb = ni::ceil_div(K, 256);
+  k_heavy_flags<<<nb, 256, 0, st>>>(row_off, K, QBIG, 1 << 30, flag);
   hipError_t e = scan_exclusive_i32(flag, pos, K, count_dev, scan_tmp, st);
   if (e != hipSuccess) return e;
-  k_heavy_list<<<ni::ceil_div(K, 256), 256, 0, st>>>(flag, pos, K, list);
+  k_heavy_list<<<nb, 256, 0, st>>>(flag, pos, K, 0, list);
+  int nbig = 0;
+  e = hipMemcpyAsync(&nbig, count_dev, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  k_heavy_flags<<<nb, 256, 0, st>>>(row_off, K, QELL, QBIG, flag);
+  e = scan_exclusive_i32(flag, pos, K, count_dev + 1, scan_tmp, st);
+  if (e != hipSuccess) return e;
+  k_heavy_list<<<nb, 256, 0, st>>>(flag, pos, K, nbig, list);
   return hipGetLastError();
 }
 
@@ -696,27 +877,27 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   // quotient PCG
   if (a.nnz > 0) k_q_matrix<<<ni::ceil_div(a.nnz, 256), 256, 0, st>>>(a.row_off, a.ent, a.pair_lo, a.pair_hi, a.pW,
                                                                        a.nnz, a.qcol, a.qw);
+  if (a.K > 0) k_q_ell<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.row_off, a.qcol, a.qw, a.K, a.ell_col, a.ell_w);
   QMat M;
-  M.row_off = a.row_off; M.qcol = a.qcol; M.qw = a.qw; M.diag = a.diag; M.rhs = a.rhs; M.babs = a.babs; M.K = a.K;
-  M.heavy = a.heavy; M.nheavy = a.nheavy;
+  M.row_off = a.row_off; M.qcol = a.qcol; M.qw = a.qw; M.ecol = a.ell_col; M.ew = a.ell_w;
+  M.diag = a.diag; M.rhs = a.rhs; M.babs = a.babs; M.K = a.K;
+  M.heavy = a.heavy; M.nheavy = a.nheavy; M.nbig = a.nbig;
   if (a.K <= QCAP) {
-    k_qcg_wg<<<1, QWG, 0, st>>>(M, a.s, a.r, a.q_rtol, a.q_maxit, a.qiters_out + t);
+    k_qcg_wg<<<1, QWG, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
     e = hipGetLastError();
   } else {
     QIter Q;
-    Q.M = M; Q.s = a.s; Q.p0 = a.p0; Q.p1 = a.p1; Q.r = a.r; Q.q = a.q;
-    Q.part = a.part; Q.sc = a.sc; Q.flag = a.qflag; Q.nblk = ni::ceil_div(a.K, QB); Q.rtol = a.q_rtol;
+    Q.M = M; Q.x = a.s; Q.p = a.pv; Q.st = reinterpret_cast<double4*>(a.qst);
+    Q.part = a.part; Q.sc = a.sc; Q.flag = a.qflag; Q.nblk = ni::ceil_div(a.K, QB);
+    Q.nparts = q_nparts(Q.nblk, a.nbig, a.nheavy - a.nbig); Q.rtol = a.q_rtol;
     Q.maxit = a.q_maxit; Q.iters_out = a.qiters_out + t;
     k_fill_i32<<<1, 1, 0, st>>>(Q.iters_out, 1, -1);
-    k_qcg_init<<<Q.nblk, QNT, 0, st>>>(Q);
+    k_qcg_init<<<Q.nparts, QNT, 0, st>>>(Q);
     e = hipGetLastError();
-    // two launches per iteration; the host polls the "still iterating" flag in batches
+    // one launch per iteration; the host polls the "still iterating" flag in batches
     const int batch = 32;
     for (int it = 0; e == hipSuccess && it <= a.q_maxit + 1; it += batch) {
-      for (int k = 0; k < batch; ++k) {
-        k_qcg_a<<<Q.nblk, QNT, 0, st>>>(Q, it + k);
-        k_qcg_b<<<Q.nblk, QNT, 0, st>>>(Q, it + k);
-      }
+      for (int k = 0; k < batch; ++k) k_qcg_it<<<Q.nparts, QNT, 0, st>>>(Q, it + k);
       e = hipGetLastError();
       if (e != hipSuccess) break;
       e = hipMemcpyAsync(a.host_flag, Q.flag + ((it + batch - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, st);

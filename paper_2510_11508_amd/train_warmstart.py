@@ -35,7 +35,7 @@ def _gen(seed):
     return s.normals, s.mask, s.cam.as_dict()
 
 
-def make_dataset(ctx, n, seed0, workers, log):
+def make_dataset(ctx, pool, n, seed0, log):
     """Patches plus their plain-method fills (targets) and labels."""
     import torch
 
@@ -48,24 +48,26 @@ def make_dataset(ctx, n, seed0, workers, log):
     K = np.empty(n, np.int32)
     cams = []
     t0 = time.time()
-    with Pool(workers) as pool:
-        for i, (nn, mm, cam) in enumerate(pool.imap(_gen, range(seed0, seed0 + n), chunksize=16)):
-            dn, dm = torch.from_numpy(nn).cuda(), torch.from_numpy(mm).cuda()
-            lab, k, _ = ctx.ni_label(dn, dm, cam, p)
-            z, _ = ctx.ni_fill(dn, dm, cam, lab, k, p)
-            N[i], M[i], T[i], L[i], K[i] = nn, mm, z.cpu().numpy(), lab.cpu().numpy(), k
-            cams.append(cam)
-            if (i + 1) % 1000 == 0:
-                log(f"data {i + 1}/{n} patches ({time.time() - t0:.0f} s)")
+    for i, (nn, mm, cam) in enumerate(pool.imap(_gen, range(seed0, seed0 + n), chunksize=16)):
+        dn, dm = torch.from_numpy(nn).cuda(), torch.from_numpy(mm).cuda()
+        lab, k, _ = ctx.ni_label(dn, dm, cam, p)
+        z, _ = ctx.ni_fill(dn, dm, cam, lab, k, p)
+        N[i], M[i], T[i], L[i], K[i] = nn, mm, z.cpu().numpy(), lab.cpu().numpy(), k
+        cams.append(cam)
+        if (i + 1) % 1000 == 0:
+            log(f"data {i + 1}/{n} patches ({time.time() - t0:.0f} s)")
     return N, M, T, L, K, cams
 
 
 def train(args, log=print):
     import torch
 
-    import paper_2510_11508_amd as ni
-    ctx = ni.Context(0)
-    N, M, T, L, K, cams = make_dataset(ctx, args.patches, args.seed, args.workers, log)
+    # the generator workers are forked before this process loads the library
+    # or touches the GPU
+    with Pool(args.workers) as pool:
+        import paper_2510_11508_amd as ni
+        ctx = ni.Context(0)
+        N, M, T, L, K, cams = make_dataset(ctx, pool, args.patches, args.seed, log)
     ctx.ni_unet_init(args.seed)
     rng = np.random.default_rng(args.seed)
     B = args.batch
