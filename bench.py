@@ -47,8 +47,7 @@ WORKLOADS = {
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("ni_fill.hip", "ni_common.h"):
-        h.update(open(os.path.join(ROOT, "paper_2510_11508_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2510_11508_amd", "csrc", "ni_fill.hip"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -94,7 +93,7 @@ def main():
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); there is no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
@@ -115,10 +114,14 @@ def main():
     cam = s.cam.as_dict()
 
     if a.copy_calibration:
-        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        # a plain 1 GiB device copy: the same counters read on it give the
+        # bytes-per-count factor of the fill kernels' counter readings
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
 
     def timed(prm):
         for _ in range(a.warmup):
