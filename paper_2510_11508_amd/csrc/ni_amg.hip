@@ -1,0 +1,1046 @@
+// Aggregation multigrid preconditioner for the quotient relative-scale
+// systems (Sec. 3.4, Eq. 16-17) of large component graphs.
+//
+// The quotient Laplacian of a large map is badly conditioned: after the
+// weight cut it splits into many pieces, and regions where every pixel is
+// its own component form grid-like sub-graphs.  Jacobi PCG then needs
+// thousands of iterations per IRLS step.  Here the CG is preconditioned by
+// one V-cycle of an aggregation hierarchy:
+//
+//   aggregation   pairwise handshakes (each free node proposes its strongest
+//                 free neighbour; mutual proposals pair up; three rounds),
+//                 then every node left over joins the aggregate of its
+//                 strongest aggregated neighbour; nodes without a weighted
+//                 edge take no part.  Aggregate ids follow the smallest
+//                 member, so the hierarchy is deterministic.
+//   coarse graph  Galerkin product with piecewise-constant prolongation: a
+//                 coarse pair's weight is the sum of the fine pair weights
+//                 between the two aggregates (again a weighted graph
+//                 Laplacian), summed in a fixed order.
+//   cycle         V(1,1) with damped Jacobi (omega = 2/3) on every level
+//                 and an exact solve on the coarsest (<= AMAXC nodes): one
+//                 node per connected piece is pinned to zero and the
+//                 remaining SPD matrix is inverted once per IRLS step.
+//
+// The pre- and post-smoothers are the same and restriction is the
+// transpose of prolongation, so the cycle is a symmetric positive operator
+// and plain PCG applies.  The hierarchy is rebuilt from every IRLS step's
+// weights: a hierarchy kept from one step loses most of its effect a few
+// steps later, once the weight cut has moved.
+//
+// All reductions are block partials summed in block order by a one-block
+// kernel, so results are reproducible run to run.
+#include <vector>
+
+#include "ni_common.h"
+
+namespace {
+
+constexpr int ANT = 256;      // threads per block, one row per thread
+constexpr int AH = 16;        // rows with more entries are heavy: one block each
+constexpr int AMAXC = 256;    // largest coarsest level solved exactly
+constexpr int AMAXL = 24;     // levels at most
+constexpr double AOMEGA = 2.0 / 3.0;
+
+// scalars of the PCG, one double each
+enum { S_RHO = 0, S_RHOP, S_BETA, S_ALPHA, S_RR, S_BS, S_PQ, S_N };
+
+// device view of one level
+struct ALev {
+  int n, nblk, nheavy;
+  const int* row_off;  // [n+1]
+  const int* col;      // neighbour of every entry
+  const double* w;     // weight of every entry
+  const double* diag;  // row sums
+  const int* heavy;    // rows with more than AH entries
+  const int* cid;      // node -> node of the next level (-1: none); null on the coarsest
+  double *b, *x, *r, *y;
+};
+
+__device__ __forceinline__ bool is_done(const int* done) { return *reinterpret_cast<const volatile int*>(done) != 0; }
+
+// row index handled by this thread: regular blocks skip heavy rows; heavy
+// blocks (index >= nblk) take one heavy row with all threads
+struct RowSel {
+  int c;      // row, or -1
+  bool big;   // block-wide row
+};
+
+__device__ __forceinline__ RowSel row_sel(const ALev& L) {
+  RowSel s;
+  if ((int)blockIdx.x < L.nblk) {
+    const int c = blockIdx.x * ANT + threadIdx.x;
+    s.big = false;
+    s.c = (c < L.n && L.row_off[c + 1] - L.row_off[c] <= AH) ? c : -1;
+  } else {
+    s.big = true;
+    s.c = L.heavy[blockIdx.x - L.nblk];
+  }
+  return s;
+}
+
+// sum over the entries of row c of w_j * (vc - val(col_j)); a heavy row is
+// split over the block's threads (then summed by the caller)
+template <class V>
+__device__ __forceinline__ double row_diff_sum(const ALev& L, const RowSel& s, double vc, V val) {
+  const int j0 = L.row_off[s.c], j1 = L.row_off[s.c + 1];
+  const int t0 = s.big ? threadIdx.x : 0, st = s.big ? ANT : 1;
+  double acc = 0.0;
+  for (int base = j0 + t0; base < j1; base += 8 * st) {
+    int d[8];
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = base + u * st;
+      d[u] = j < j1 ? L.col[j] : s.c;
+      q[u] = j < j1 ? L.w[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += q[u] * (vc - val(d[u]));
+  }
+  return acc;
+}
+
+template <int NV>
+__device__ __forceinline__ void put_parts(double (&v)[NV], double* red, double* parts, int stride) {
+  ni::block_sum<NV>(v, red);
+  if (threadIdx.x < NV) parts[(size_t)threadIdx.x * stride + blockIdx.x] = v[threadIdx.x];
+}
+
+// ------------------------------------------------------------------ cycle
+// pre-smoothing from zero and the residual: x = w D^-1 b, r = b - A x
+__global__ void __launch_bounds__(ANT) k_cy_down(ALev L, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const RowSel s = row_sel(L);
+  const double* b = L.b;
+  const double* dg = L.diag;
+  auto xv = [&](int d) { const double e = dg[d]; return e > 0 ? AOMEGA * b[d] / e : 0.0; };
+  double acc = 0.0, xc = 0.0;
+  if (s.c >= 0) {
+    xc = xv(s.c);
+    acc = row_diff_sum(L, s, xc, xv);
+  }
+  if (s.big) {
+    double t[1] = {acc};
+    ni::block_sum<1>(t, red);
+    acc = t[0];
+  }
+  if (s.c >= 0 && (!s.big || threadIdx.x == 0)) {
+    L.x[s.c] = xc;
+    L.r[s.c] = b[s.c] - acc;
+  }
+}
+
+// restriction b' = P^T r: each coarse node sums its members' residuals
+// (members of big aggregates are summed by a whole block)
+__global__ void __launch_bounds__(ANT) k_cy_restrict(int n, int nblk, const int* __restrict__ mem_off,
+                                                     const int* __restrict__ mem, const int* __restrict__ mheavy,
+                                                     const double* __restrict__ r, double* __restrict__ bc,
+                                                     const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  int C;
+  bool big;
+  if ((int)blockIdx.x < nblk) {
+    C = blockIdx.x * ANT + threadIdx.x;
+    big = false;
+    if (C >= n || mem_off[C + 1] - mem_off[C] > AH) C = -1;
+  } else {
+    C = mheavy[blockIdx.x - nblk];
+    big = true;
+  }
+  double acc = 0.0;
+  if (C >= 0) {
+    const int i0 = mem_off[C], i1 = mem_off[C + 1];
+    for (int i = i0 + (big ? threadIdx.x : 0); i < i1; i += big ? ANT : 1) acc += r[mem[i]];
+  }
+  if (big) {
+    double t[1] = {acc};
+    ni::block_sum<1>(t, red);
+    acc = t[0];
+  }
+  if (C >= 0 && (!big || threadIdx.x == 0)) bc[C] = acc;
+}
+
+// exact coarsest solve y = A^+ b with the pinned inverse (one block)
+__global__ void __launch_bounds__(AMAXC) k_cy_coarsest(int n, const double* __restrict__ ainv,
+                                                       const uint8_t* __restrict__ pin, const double* __restrict__ b,
+                                                       double* __restrict__ y, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double bl[AMAXC];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) bl[i] = pin[i] ? 0.0 : b[i];
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += ainv[(size_t)j * n + c] * bl[j];  // symmetric: column c = row c
+    y[c] = acc;
+  }
+}
+
+// prolongation and post-smoothing: x += P y', y = x + w D^-1 (b - A x)
+// (yn = null: no coarser level, smoothing only).  On the finest level the
+// block partials of (b, y) are written to parts.
+__global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict__ yn, double* __restrict__ parts,
+                                               int pstride, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const RowSel s = row_sel(L);
+  const double* x = L.x;
+  const int* cid = L.cid;
+  auto xv = [&](int d) {
+    double v = x[d];
+    if (yn) {
+      const int k = cid[d];
+      if (k >= 0) v += yn[k];
+    }
+    return v;
+  };
+  double acc = 0.0, xc = 0.0;
+  if (s.c >= 0) {
+    xc = xv(s.c);
+    acc = row_diff_sum(L, s, xc, xv);
+  }
+  if (s.big) {
+    double t[1] = {acc};
+    ni::block_sum<1>(t, red);
+    acc = t[0];
+  }
+  double v[1] = {0.0};
+  if (s.c >= 0 && (!s.big || threadIdx.x == 0)) {
+    const double e = L.diag[s.c];
+    const double yc = e > 0 ? xc + AOMEGA * (L.b[s.c] - acc) / e : 0.0;
+    L.y[s.c] = yc;
+    v[0] = L.b[s.c] * yc;
+  }
+  if (parts) {
+    __syncthreads();
+    put_parts<1>(v, red, parts, pstride);
+  }
+}
+
+// -------------------------------------------------------------------- PCG
+// x = 0, r = b, p = q = 0; partials of (r, r) and |b_abs|^2
+__global__ void __launch_bounds__(ANT) k_cg_init(int n, const double* __restrict__ rhs, const double* __restrict__ babs,
+                                                 double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+                                                 double* __restrict__ q, double* __restrict__ parts, int pstride) {
+  __shared__ double red[2 * (ANT / 64)];
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (c < n) {
+    const double b = rhs[c];
+    x[c] = 0.0;
+    r[c] = b;
+    p[c] = 0.0;
+    q[c] = 0.0;
+    v[0] = b * b;
+    v[1] = babs[c] * babs[c];
+  }
+  put_parts<2>(v, red, parts, pstride);
+}
+
+// p = z + beta p, q = A z + beta q (= A p), block partials of (p, q)
+__global__ void __launch_bounds__(ANT) k_cg_pq(ALev L, double* __restrict__ p, double* __restrict__ q,
+                                               const double* __restrict__ sc, double* __restrict__ parts,
+                                               int pstride, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const RowSel s = row_sel(L);
+  const double* z = L.y;
+  auto zv = [&](int d) { return z[d]; };
+  double acc = 0.0;
+  if (s.c >= 0) acc = row_diff_sum(L, s, z[s.c], zv);
+  if (s.big) {
+    double t[1] = {acc};
+    ni::block_sum<1>(t, red);
+    acc = t[0];
+  }
+  double v[1] = {0.0};
+  if (s.c >= 0 && (!s.big || threadIdx.x == 0)) {
+    const double beta = sc[S_BETA];
+    const double pn = z[s.c] + beta * p[s.c];
+    const double qn = acc + beta * q[s.c];
+    p[s.c] = pn;
+    q[s.c] = qn;
+    v[0] = pn * qn;
+  }
+  __syncthreads();
+  put_parts<1>(v, red, parts, pstride);
+}
+
+// x += alpha p, r -= alpha q, block partials of (r, r)
+__global__ void __launch_bounds__(ANT) k_cg_xr(int n, double* __restrict__ x, double* __restrict__ r,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               const double* __restrict__ sc, double* __restrict__ parts,
+                                               const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  double v[1] = {0.0};
+  if (c < n) {
+    const double a = sc[S_ALPHA];
+    x[c] += a * p[c];
+    const double rn = r[c] - a * q[c];
+    r[c] = rn;
+    v[0] = rn * rn;
+  }
+  put_parts<1>(v, red, parts, gridDim.x);
+}
+
+// one-block scalar steps; partial arrays are summed in block order
+__device__ __forceinline__ double sum_parts(const double* parts, int n, double* red) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += parts[i];
+  ni::block_sum<1>(v, red);
+  return v[0];
+}
+
+// mode 0: after init (rr, |b|^2); mode 1: after the cycle (rho -> beta,
+// convergence test on rr); mode 2: after (p, q) (alpha); mode 3: after the
+// update (rr)
+__global__ void __launch_bounds__(ANT) k_cg_scal(int mode, const double* __restrict__ parts, int np, int pstride,
+                                                 double* __restrict__ sc, int* __restrict__ done, int* it_ctr,
+                                                 double rtol, int maxit, int* __restrict__ iters_out,
+                                                 int* __restrict__ flag) {
+  __shared__ double red[ANT / 64];
+  if (mode != 0 && is_done(done)) return;
+  if (mode == 0) {
+    const double rr = sum_parts(parts, np, red);
+    __syncthreads();
+    const double bs = sum_parts(parts + pstride, np, red);
+    if (threadIdx.x == 0) {
+      sc[S_RR] = rr;
+      sc[S_BS] = bs;
+      sc[S_RHOP] = 1.0;
+      *done = 0;
+      *it_ctr = 0;
+      *flag = 1;
+    }
+  } else if (mode == 1) {
+    const double rho = sum_parts(parts, np, red);
+    if (threadIdx.x == 0) {
+      const int it = *it_ctr;
+      if (!(sc[S_RR] > rtol * rtol * sc[S_BS]) || it >= maxit) {
+        *done = 1;
+        *flag = 0;
+        *iters_out = it;
+      } else {
+        sc[S_BETA] = it == 0 ? 0.0 : rho / sc[S_RHOP];
+        sc[S_RHO] = rho;
+        sc[S_RHOP] = rho;
+      }
+    }
+  } else if (mode == 2) {
+    const double pq = sum_parts(parts, np, red);
+    if (threadIdx.x == 0) {
+      sc[S_PQ] = pq;
+      sc[S_ALPHA] = pq != 0.0 ? sc[S_RHO] / pq : 0.0;
+    }
+  } else {
+    const double rr = sum_parts(parts, np, red);
+    if (threadIdx.x == 0) {
+      sc[S_RR] = rr;
+      *it_ctr += 1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ setup
+__global__ void k_am_fill(int* a, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// a node takes part when it has an edge of positive weight
+__global__ void k_am_active(int n, const int* __restrict__ row_off, const double* __restrict__ w, int* __restrict__ agg,
+                            uint8_t* __restrict__ act) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  bool a = false;
+  for (int j = row_off[c]; j < row_off[c + 1]; ++j) a |= w[j] > 0.0;
+  act[c] = a ? 1 : 0;
+  agg[c] = -1;
+}
+
+// strongest neighbour with agg == -1 (want_free) or agg >= 0; ties -> smaller index
+__device__ __forceinline__ int strongest(int c, const int* row_off, const int* col, const double* w, const int* agg,
+                                         const uint8_t* act, bool want_free) {
+  int best = -1;
+  double bw = 0.0;
+  for (int j = row_off[c]; j < row_off[c + 1]; ++j) {
+    const int d = col[j];
+    const double v = w[j];
+    if (v <= 0.0 || d == c || !act[d] || ((agg[d] < 0) != want_free)) continue;
+    if (v > bw || (v == bw && d < best)) {
+      bw = v;
+      best = d;
+    }
+  }
+  return best;
+}
+
+__global__ void k_am_pick(int n, const int* __restrict__ row_off, const int* __restrict__ col,
+                          const double* __restrict__ w, const int* __restrict__ agg, const uint8_t* __restrict__ act,
+                          int* __restrict__ best) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  best[c] = (act[c] && agg[c] < 0) ? strongest(c, row_off, col, w, agg, act, true) : -1;
+}
+
+__global__ void k_am_match(int n, const int* __restrict__ best, int* __restrict__ agg) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int b = best[c];
+  if (agg[c] < 0 && b >= 0 && best[b] == c) agg[c] = min(c, b);
+}
+
+// leftover active nodes join their strongest aggregated neighbour's
+// aggregate, or stay alone; leaders (agg == self) are flagged
+__global__ void k_am_attach(int n, const int* __restrict__ row_off, const int* __restrict__ col,
+                            const double* __restrict__ w, const int* __restrict__ agg,
+                            const uint8_t* __restrict__ act, int* __restrict__ agg2, int* __restrict__ lead) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int a = agg[c];
+  if (act[c] && a < 0) {
+    const int d = strongest(c, row_off, col, w, agg, act, false);
+    a = d >= 0 ? agg[d] : c;
+  }
+  if (!act[c]) a = -1;
+  agg2[c] = a;
+  lead[c] = (a == c) ? 1 : 0;
+}
+
+__global__ void k_am_cid(int n, const int* __restrict__ agg2, const int* __restrict__ pos, int* __restrict__ cid,
+                         int* __restrict__ flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int a = agg2[c];
+  cid[c] = a >= 0 ? pos[a] : -1;
+  flag[c] = a >= 0 ? 1 : 0;
+}
+
+// compact (key, value) of the flagged entries
+__global__ void k_am_compact(int n, const int* __restrict__ flag, const int* __restrict__ pos,
+                             const int* __restrict__ key, uint32_t* __restrict__ ko, uint32_t* __restrict__ vo) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) {
+    ko[pos[i]] = (uint32_t)key[i];
+    vo[pos[i]] = (uint32_t)i;
+  }
+}
+
+// offsets of runs of a sorted key array: off[k] = first index of key k
+// (every key 0..nk-1 present), off[nk] = m
+__global__ void k_am_offsets(int m, const uint32_t* __restrict__ keys, int nk, int* __restrict__ off) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  if (i == 0 || keys[i] != keys[i - 1]) off[keys[i]] = i;
+  if (i == m - 1) off[nk] = m;
+}
+
+// offsets when some keys may be absent: counts per key (then scanned)
+__global__ void k_am_count(int m, const uint32_t* __restrict__ keys, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) atomicAdd(&cnt[keys[i]], 1);
+}
+
+__global__ void k_am_u32(const uint32_t* __restrict__ a, int n, int* __restrict__ o) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = (int)a[i];
+}
+
+// coarse pair keys of the fine pairs whose ends lie in two different aggregates
+__global__ void k_am_pflag(int np, const int* __restrict__ plo, const int* __restrict__ phi,
+                           const int* __restrict__ cid, int* __restrict__ flag) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int a = cid[plo[p]], b = cid[phi[p]];
+  flag[p] = (a >= 0 && b >= 0 && a != b) ? 1 : 0;
+}
+
+__global__ void k_am_pcompact(int np, const int* __restrict__ flag, const int* __restrict__ pos,
+                              const int* __restrict__ plo, const int* __restrict__ phi, const int* __restrict__ cid,
+                              uint32_t* __restrict__ klo, uint32_t* __restrict__ khi, uint32_t* __restrict__ fp,
+                              uint32_t* __restrict__ idx) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np || !flag[p]) return;
+  const int a = cid[plo[p]], b = cid[phi[p]];
+  const int i = pos[p];
+  klo[i] = (uint32_t)min(a, b);
+  khi[i] = (uint32_t)max(a, b);
+  fp[i] = (uint32_t)p;
+  idx[i] = (uint32_t)i;
+}
+
+__global__ void k_am_gather(int m, const uint32_t* __restrict__ a, const uint32_t* __restrict__ idx,
+                            uint32_t* __restrict__ o) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) o[i] = a[idx[i]];
+}
+
+// runs of equal (lo, hi) in sorted order -> coarse pairs
+__global__ void k_am_runs(int m, const uint32_t* __restrict__ ord, const uint32_t* __restrict__ klo,
+                          const uint32_t* __restrict__ khi, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t k = ord[i];
+  flag[i] = (i == 0 || klo[k] != klo[ord[i - 1]] || khi[k] != khi[ord[i - 1]]) ? 1 : 0;
+}
+
+__global__ void k_am_pairs_out(int m, const uint32_t* __restrict__ ord, const uint32_t* __restrict__ klo,
+                               const uint32_t* __restrict__ khi, const int* __restrict__ flag,
+                               const int* __restrict__ pos, const uint32_t* __restrict__ fsrc, int* __restrict__ plo,
+                               int* __restrict__ phi, int* __restrict__ gal_off, int* __restrict__ gal_src,
+                               int npn) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t k = ord[i];
+  gal_src[i] = (int)fsrc[k];
+  if (flag[i]) {
+    const int q = pos[i];
+    plo[q] = (int)klo[k];
+    phi[q] = (int)khi[k];
+    gal_off[q] = i;
+  }
+  if (i == m - 1) gal_off[npn] = m;
+}
+
+// CSR entries of a pair list: entry e = 2 p + side; row = side ? hi : lo
+__global__ void k_am_ekeys(int np, const int* __restrict__ plo, const int* __restrict__ phi,
+                           uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * np) return;
+  key[e] = (uint32_t)((e & 1) ? phi[e >> 1] : plo[e >> 1]);
+  val[e] = (uint32_t)e;
+}
+
+__global__ void k_am_ecol(int ne, const uint32_t* __restrict__ ent, const int* __restrict__ plo,
+                          const int* __restrict__ phi, int* __restrict__ ento, int* __restrict__ col) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ne) return;
+  const int e = (int)ent[j];
+  ento[j] = e;
+  col[j] = (e & 1) ? plo[e >> 1] : phi[e >> 1];
+}
+
+__global__ void k_am_heavy_flag(int n, const int* __restrict__ off, int* __restrict__ flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) flag[c] = off[c + 1] - off[c] > AH ? 1 : 0;
+}
+
+__global__ void k_am_list(int n, const int* __restrict__ flag, const int* __restrict__ pos, int* __restrict__ list) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && flag[c]) list[pos[c]] = c;
+}
+
+// ------------------------------------------------------- per-step values
+// coarse pair weight = sum of its fine pairs' weights (fixed order)
+__global__ void k_am_gal(int np, const int* __restrict__ gal_off, const int* __restrict__ gal_src,
+                         const double* __restrict__ pwf, double* __restrict__ pw) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  double s = 0.0;
+  for (int i = gal_off[q]; i < gal_off[q + 1]; ++i) s += pwf[gal_src[i]];
+  pw[q] = s;
+}
+
+__global__ void k_am_ew(int ne, const int* __restrict__ ent, const double* __restrict__ pw, double* __restrict__ w) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < ne) w[j] = pw[ent[j] >> 1];
+}
+
+__global__ void k_am_diag(int n, const int* __restrict__ row_off, const double* __restrict__ w,
+                          double* __restrict__ diag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double s = 0.0;
+  for (int j = row_off[c]; j < row_off[c + 1]; ++j) s += w[j];
+  diag[c] = s;
+}
+
+// Coarsest level (n <= AMAXC): dense Laplacian, pieces by label
+// propagation, the smallest node of every piece (and every node without
+// edges) pinned, then an in-place Gauss-Jordan inverse of the SPD rest.
+__global__ void __launch_bounds__(1024) k_am_invert(int n, const int* __restrict__ row_off, const int* __restrict__ col,
+                                                    const double* __restrict__ w, const double* __restrict__ diag,
+                                                    double* __restrict__ A, uint8_t* __restrict__ pin) {
+  __shared__ int lab[AMAXC];
+  __shared__ int changed;
+  __shared__ double colk[AMAXC];
+  __shared__ double rowk[AMAXC];
+  const int T = blockDim.x;
+  for (int i = threadIdx.x; i < n * n; i += T) A[i] = 0.0;
+  for (int c = threadIdx.x; c < n; c += T) lab[c] = c;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += T) {
+    A[(size_t)c * n + c] = diag[c];
+    for (int j = row_off[c]; j < row_off[c + 1]; ++j)
+      if (w[j] > 0.0) A[(size_t)c * n + col[j]] -= w[j];
+  }
+  // pieces: minimum label over edges of positive weight, until stable
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) changed = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += T) {
+      int m = lab[c];
+      for (int j = row_off[c]; j < row_off[c + 1]; ++j)
+        if (w[j] > 0.0) m = min(m, lab[col[j]]);
+      if (m < lab[c]) {
+        atomicMin(&lab[c], m);
+        changed = 1;
+      }
+    }
+    __syncthreads();
+    if (!changed) break;
+  }
+  for (int c = threadIdx.x; c < n; c += T) pin[c] = (lab[c] == c || !(diag[c] > 0.0)) ? 1 : 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * n; i += T) {
+    const int r = i / n, c = i % n;
+    if (pin[r] || pin[c]) A[i] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    for (int i = threadIdx.x; i < n; i += T) {
+      colk[i] = A[(size_t)i * n + k];
+      rowk[i] = A[(size_t)k * n + i];
+    }
+    __syncthreads();
+    const double piv = 1.0 / colk[k];
+    for (int idx = threadIdx.x; idx < n * n; idx += T) {
+      const int i = idx / n, j = idx % n;
+      double v;
+      if (i == k) v = (j == k) ? piv : rowk[j] * piv;
+      else if (j == k) v = -colk[i] * piv;
+      else v = A[idx] - colk[i] * rowk[j] * piv;
+      A[idx] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ host side
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+template <class T>
+T* grow(DBuf& b, size_t count, hipError_t& err) {
+  const size_t bytes = ((std::max<size_t>(count, 1) * sizeof(T)) + 255) & ~size_t(255);
+  if (b.cap < bytes) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      err = e;
+      return nullptr;
+    }
+    b.cap = bytes;
+  }
+  return static_cast<T*>(b.p);
+}
+
+inline int nb256(long long n) { return (int)std::max<long long>((n + 255) / 256, 1); }
+
+}  // namespace
+
+namespace nil {
+
+struct AmgLevel {
+  int n = 0, np = 0, nheavy = 0, nmheavy = 0;
+  // levels >= 1: members of every node, Galerkin lists (fine pairs per pair)
+  DBuf mem_off_b, mem_b, mheavy_b, gal_off_b, gal_src_b;
+  // map of this level's nodes to the next level
+  DBuf cid_b;
+  // pairs and CSR (level 0: views of the quotient arrays)
+  DBuf plo_b, phi_b, row_off_b, ent_b, col_b, heavy_b;
+  // per step
+  DBuf pw_b, w_b, diag_b;
+  // cycle vectors
+  DBuf bv_b, x_b, r_b, y_b;
+  const int *row_off = nullptr, *col = nullptr, *ent = nullptr, *plo = nullptr, *phi = nullptr;
+  const double *w = nullptr, *diag = nullptr, *pw = nullptr;
+  const int *mem_off = nullptr, *mem = nullptr, *mheavy = nullptr, *gal_off = nullptr, *gal_src = nullptr;
+  const int* heavy = nullptr;
+  int* cid = nullptr;
+  double *bv = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;
+  DBuf* all() { return &mem_off_b; }
+};
+
+constexpr int NSCR = 16;
+
+struct Amg {
+  std::vector<AmgLevel*> lv;
+  int nlev = 0;        // levels in use (0 .. nlev-1); the last is the coarsest
+  bool dense = false;  // coarsest solved exactly
+  DBuf s[NSCR];
+  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr;
+  ~Amg() {
+    for (AmgLevel* L : lv) {
+      DBuf* b[] = {&L->mem_off_b, &L->mem_b, &L->mheavy_b, &L->gal_off_b, &L->gal_src_b, &L->cid_b, &L->plo_b,
+                   &L->phi_b, &L->row_off_b, &L->ent_b, &L->col_b, &L->heavy_b, &L->pw_b, &L->w_b, &L->diag_b,
+                   &L->bv_b, &L->x_b, &L->r_b, &L->y_b};
+      for (DBuf* d : b)
+        if (d->p) (void)hipFree(d->p);
+      delete L;
+    }
+    for (DBuf& d : s)
+      if (d.p) (void)hipFree(d.p);
+    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr};
+    for (DBuf* d : own)
+      if (d->p) (void)hipFree(d->p);
+  }
+};
+
+Amg* amg_new() { return new Amg(); }
+void amg_free(Amg* a) { delete a; }
+int amg_levels(const Amg* a) { return a ? a->nlev : 0; }
+
+static hipError_t read_int(const int* dev, int* host, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(host, dev, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+static int bits_for(int n) {
+  int b = 0;
+  while ((1ll << b) < (long long)n) ++b;
+  return b;
+}
+
+#define AMG_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+// rows (or members) with more than AH entries of an offset array
+static hipError_t heavy_list(Amg* A, int n, const int* off, DBuf& out, int* count, const int*& view,
+                             hipStream_t st) {
+  hipError_t err = hipSuccess;
+  int* flag = grow<int>(A->s[14], n, err);
+  int* pos = grow<int>(A->s[15], n + 1, err);
+  int* list = grow<int>(out, n, err);
+  int* tot = grow<int>(A->ctr, 8, err);
+  int* scan = grow<int>(A->scan, scan_tmp_ints(n + 1), err);
+  AMG_TRY(err);
+  k_am_heavy_flag<<<nb256(n), 256, 0, st>>>(n, off, flag);
+  AMG_TRY(scan_exclusive_i32(flag, pos, n, tot, scan, st));
+  k_am_list<<<nb256(n), 256, 0, st>>>(n, flag, pos, list);
+  view = list;
+  return read_int(tot, count, st);
+}
+
+// CSR (row_off, ent, col) of a level's pair list, and its heavy rows
+static hipError_t build_csr(Amg* A, AmgLevel* L, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  const int n = L->n, np = L->np, ne = 2 * np;
+  int* row_off = grow<int>(L->row_off_b, n + 1, err);
+  int* ent = grow<int>(L->ent_b, ne, err);
+  int* col = grow<int>(L->col_b, ne, err);
+  uint32_t* k0 = grow<uint32_t>(A->s[0], ne, err);
+  uint32_t* v0 = grow<uint32_t>(A->s[1], ne, err);
+  uint32_t* k1 = grow<uint32_t>(A->s[2], ne, err);
+  uint32_t* v1 = grow<uint32_t>(A->s[3], ne, err);
+  uint32_t* kt = grow<uint32_t>(A->s[4], ne, err);
+  uint32_t* vt = grow<uint32_t>(A->s[5], ne, err);
+  int* cnt = grow<int>(A->s[6], n + 1, err);
+  int* scan = grow<int>(A->scan, std::max(radix_tmp_ints(std::max(ne, 1)), scan_tmp_ints(n + 1)), err);
+  AMG_TRY(err);
+  k_am_fill<<<nb256(n + 1), 256, 0, st>>>(cnt, n + 1, 0);
+  if (ne > 0) {
+    k_am_ekeys<<<nb256(ne), 256, 0, st>>>(np, L->plo, L->phi, k0, v0);
+    AMG_TRY(radix_sort_pairs(k0, v0, k1, v1, kt, vt, ne, bits_for(n), scan, st));
+    k_am_ecol<<<nb256(ne), 256, 0, st>>>(ne, v1, L->plo, L->phi, ent, col);
+    k_am_count<<<nb256(ne), 256, 0, st>>>(ne, k1, cnt);
+  }
+  AMG_TRY(scan_exclusive_i32(cnt, row_off, n + 1, nullptr, scan, st));
+  L->row_off = row_off;
+  L->ent = ent;
+  L->col = col;
+  return heavy_list(A, n, row_off, L->heavy_b, &L->nheavy, L->heavy, st);
+}
+
+// per-step values of a coarse level from the finer level's pair weights
+static void level_values(AmgLevel* L, const double* pwf, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  double* pw = grow<double>(L->pw_b, L->np, err);
+  double* w = grow<double>(L->w_b, 2 * (size_t)L->np, err);
+  double* diag = grow<double>(L->diag_b, L->n, err);
+  if (err != hipSuccess) return;
+  if (L->np > 0) {
+    k_am_gal<<<nb256(L->np), 256, 0, st>>>(L->np, L->gal_off, L->gal_src, pwf, pw);
+    k_am_ew<<<nb256(2 * (long long)L->np), 256, 0, st>>>(2 * L->np, L->ent, pw, w);
+  }
+  k_am_diag<<<nb256(L->n), 256, 0, st>>>(L->n, L->row_off, w, diag);
+  L->pw = pw;
+  L->w = w;
+  L->diag = diag;
+}
+
+// Build the hierarchy from the quotient graph of this step: K nodes, P
+// pairs (pair_lo < pair_hi, weights pW), CSR row_off / qcol / qw.
+hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, const double* qw,
+                     const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  if (A->lv.empty()) A->lv.push_back(new AmgLevel());
+  AmgLevel* L0 = A->lv[0];
+  L0->n = K;
+  L0->np = P;
+  L0->row_off = row_off;
+  L0->col = qcol;
+  L0->w = qw;
+  L0->plo = pair_lo;
+  L0->phi = pair_hi;
+  L0->pw = pW;
+  // every scratch array at its largest size up front: nothing is freed and
+  // reallocated while kernels that use it may still be queued
+  {
+    const size_t big = (size_t)std::max(2 * (size_t)P, (size_t)K) + 2;
+    for (int i = 0; i < NSCR; ++i) grow<uint32_t>(A->s[i], big, err);
+    grow<int>(A->scan, std::max(radix_tmp_ints((int)big), scan_tmp_ints((int)big)), err);
+    grow<int>(A->ctr, 8, err);
+    AMG_TRY(err);
+  }
+  AMG_TRY(heavy_list(A, K, row_off, L0->heavy_b, &L0->nheavy, L0->heavy, st));
+  int* tot = static_cast<int*>(A->ctr.p);
+  int l = 0;
+  A->dense = false;
+  for (;;) {
+    AmgLevel* F = A->lv[l];
+    const int n = F->n;
+    if (n <= AMAXC) {
+      A->dense = true;
+      break;
+    }
+    if (l + 1 >= AMAXL) break;
+    // ---- aggregation of level l
+    int* agg = grow<int>(A->s[7], n, err);
+    int* best = grow<int>(A->s[8], n, err);
+    int* agg2 = grow<int>(A->s[9], n, err);
+    int* lead = grow<int>(A->s[10], n, err);
+    int* pos = grow<int>(A->s[11], n + 1, err);
+    uint8_t* act = grow<uint8_t>(A->s[12], n, err);
+    int* cid = grow<int>(F->cid_b, n, err);
+    int* flag = grow<int>(A->s[13], n, err);
+    int* scan = grow<int>(A->scan, std::max(radix_tmp_ints(std::max(std::max(2 * F->np, n), 1)),
+                                            scan_tmp_ints(std::max(F->np, n) + 1)), err);
+    AMG_TRY(err);
+    k_am_active<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->w, agg, act);
+    for (int round = 0; round < 3; ++round) {
+      k_am_pick<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, best);
+      k_am_match<<<nb256(n), 256, 0, st>>>(n, best, agg);
+    }
+    k_am_attach<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, agg2, lead);
+    AMG_TRY(scan_exclusive_i32(lead, pos, n, tot, scan, st));
+    int nc = 0;
+    AMG_TRY(read_int(tot, &nc, st));
+    if (nc <= 0 || nc > (int)(0.9 * n)) break;  // no edges left, or coarsening stalled
+    k_am_cid<<<nb256(n), 256, 0, st>>>(n, agg2, pos, cid, flag);
+    F->cid = cid;
+    if (l + 1 >= (int)A->lv.size()) A->lv.push_back(new AmgLevel());
+    AmgLevel* C = A->lv[l + 1];
+    C->n = nc;
+    // ---- members of every coarse node: the fine nodes sorted on cid
+    {
+      int* fpos = grow<int>(A->s[11], n + 1, err);
+      uint32_t* ko = grow<uint32_t>(A->s[0], n, err);
+      uint32_t* vo = grow<uint32_t>(A->s[1], n, err);
+      uint32_t* ks = grow<uint32_t>(A->s[2], n, err);
+      uint32_t* vs = grow<uint32_t>(A->s[3], n, err);
+      uint32_t* kt = grow<uint32_t>(A->s[4], n, err);
+      uint32_t* vt = grow<uint32_t>(A->s[5], n, err);
+      int* mem_off = grow<int>(C->mem_off_b, nc + 1, err);
+      int* mem = grow<int>(C->mem_b, n, err);
+      AMG_TRY(err);
+      AMG_TRY(scan_exclusive_i32(flag, fpos, n, tot, scan, st));
+      int m = 0;
+      AMG_TRY(read_int(tot, &m, st));
+      k_am_compact<<<nb256(n), 256, 0, st>>>(n, flag, fpos, cid, ko, vo);
+      AMG_TRY(radix_sort_pairs(ko, vo, ks, vs, kt, vt, m, bits_for(nc), scan, st));
+      k_am_u32<<<nb256(m), 256, 0, st>>>(vs, m, mem);
+      k_am_offsets<<<nb256(m), 256, 0, st>>>(m, ks, nc, mem_off);
+      C->mem_off = mem_off;
+      C->mem = mem;
+      AMG_TRY(heavy_list(A, nc, mem_off, C->mheavy_b, &C->nmheavy, C->mheavy, st));
+    }
+    // ---- coarse pairs: fine pairs between two aggregates, grouped by (lo, hi)
+    {
+      const int npf = F->np;
+      int* pflag = grow<int>(A->s[13], std::max(npf, n), err);
+      int* ppos = grow<int>(A->s[11], npf + 1, err);
+      uint32_t* klo = grow<uint32_t>(A->s[0], npf, err);
+      uint32_t* khi = grow<uint32_t>(A->s[1], npf, err);
+      uint32_t* fp = grow<uint32_t>(A->s[2], npf, err);
+      uint32_t* idx = grow<uint32_t>(A->s[3], npf, err);
+      uint32_t* k1 = grow<uint32_t>(A->s[4], npf, err);
+      uint32_t* o1 = grow<uint32_t>(A->s[5], npf, err);
+      uint32_t* k2 = grow<uint32_t>(A->s[6], npf, err);
+      uint32_t* k3 = grow<uint32_t>(A->s[7], npf, err);  // agg no longer needed
+      uint32_t* ord = grow<uint32_t>(A->s[8], npf, err);
+      uint32_t* tk = grow<uint32_t>(A->s[9], npf, err);
+      uint32_t* tv = grow<uint32_t>(A->s[10], npf, err);
+      int* rflag = grow<int>(A->s[12], npf, err);
+      int* rpos = grow<int>(A->s[14], npf + 1, err);
+      AMG_TRY(err);
+      int mp = 0;
+      if (npf > 0) {
+        k_am_pflag<<<nb256(npf), 256, 0, st>>>(npf, F->plo, F->phi, cid, pflag);
+        AMG_TRY(scan_exclusive_i32(pflag, ppos, npf, tot, scan, st));
+        AMG_TRY(read_int(tot, &mp, st));
+      }
+      int npc = 0;
+      if (mp > 0) {
+        k_am_pcompact<<<nb256(npf), 256, 0, st>>>(npf, pflag, ppos, F->plo, F->phi, cid, klo, khi, fp, idx);
+        const int bc = bits_for(nc);
+        AMG_TRY(radix_sort_pairs(khi, idx, k1, o1, tk, tv, mp, bc, scan, st));   // by hi
+        k_am_gather<<<nb256(mp), 256, 0, st>>>(mp, klo, o1, k2);                 // lo in that order
+        AMG_TRY(radix_sort_pairs(k2, o1, k3, ord, tk, tv, mp, bc, scan, st));     // stably by lo
+        k_am_runs<<<nb256(mp), 256, 0, st>>>(mp, ord, klo, khi, rflag);
+        AMG_TRY(scan_exclusive_i32(rflag, rpos, mp, tot, scan, st));
+        AMG_TRY(read_int(tot, &npc, st));
+      }
+      int* plo = grow<int>(C->plo_b, npc, err);
+      int* phi = grow<int>(C->phi_b, npc, err);
+      int* gal_off = grow<int>(C->gal_off_b, npc + 1, err);
+      int* gal_src = grow<int>(C->gal_src_b, mp, err);
+      AMG_TRY(err);
+      if (mp > 0)
+        k_am_pairs_out<<<nb256(mp), 256, 0, st>>>(mp, ord, klo, khi, rflag, rpos, fp, plo, phi, gal_off, gal_src,
+                                                  npc);
+      else
+        k_am_fill<<<1, 1, 0, st>>>(gal_off, 1, 0);
+      C->np = npc;
+      C->plo = plo;
+      C->phi = phi;
+      C->gal_off = gal_off;
+      C->gal_src = gal_src;
+    }
+    AMG_TRY(build_csr(A, C, st));
+    // this step's weights on the new level (the next aggregation uses them)
+    level_values(C, F->pw, st);
+    AMG_TRY(hipGetLastError());
+    ++l;
+  }
+  A->nlev = l + 1;
+  AmgLevel* Lc = A->lv[l];
+  Lc->cid = nullptr;
+  // cycle vectors
+  for (int k = 0; k < A->nlev; ++k) {
+    AmgLevel* L = A->lv[k];
+    L->bv = grow<double>(L->bv_b, L->n, err);
+    L->x = grow<double>(L->x_b, L->n, err);
+    L->r = grow<double>(L->r_b, L->n, err);
+    L->y = grow<double>(L->y_b, L->n, err);
+  }
+  AMG_TRY(err);
+  return hipGetLastError();
+}
+
+// per IRLS step: the finest level's values (quotient CSR weights and row
+// sums, pair weights) and the Galerkin sums of every coarser level; the
+// coarsest pinned inverse
+hipError_t amg_update(Amg* A, const double* qw, const double* diag, const double* pW, hipStream_t st) {
+  if (A->nlev <= 0) return hipErrorInvalidValue;
+  AmgLevel* L0 = A->lv[0];
+  L0->w = qw;
+  L0->diag = diag;
+  L0->pw = pW;
+  for (int k = 1; k < A->nlev; ++k) level_values(A->lv[k], A->lv[k - 1]->pw, st);
+  AmgLevel* Lc = A->lv[A->nlev - 1];
+  if (A->dense && Lc->n > 0) {
+    hipError_t err = hipSuccess;
+    double* ainv = grow<double>(A->ainv, (size_t)Lc->n * Lc->n, err);
+    uint8_t* pin = grow<uint8_t>(A->pin, Lc->n, err);
+    AMG_TRY(err);
+    k_am_invert<<<1, 1024, 0, st>>>(Lc->n, Lc->row_off, Lc->col, Lc->w, Lc->diag, ainv, pin);
+  }
+  return hipGetLastError();
+}
+
+static ALev view(const AmgLevel* L, double* b) {
+  ALev v;
+  v.n = L->n;
+  v.nblk = nb256(L->n);
+  v.nheavy = L->nheavy;
+  v.row_off = L->row_off;
+  v.col = L->col;
+  v.w = L->w;
+  v.diag = L->diag;
+  v.heavy = L->heavy;
+  v.cid = L->cid;
+  v.b = b;
+  v.x = L->x;
+  v.r = L->r;
+  v.y = L->y;
+  return v;
+}
+
+// PCG on the finest level, preconditioned by one V-cycle.  rhs / babs as
+// in the Jacobi solver; the solution goes to s.  Iterations -> *iters_out
+// (device).  The host polls the "still iterating" flag every `batch`
+// iterations.
+hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, double rtol, int maxit,
+                     int* iters_out, int* host_flag, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  AmgLevel* L0 = A->lv[0];
+  const int n = L0->n;
+  const int nblk = nb256(n);
+  double* p = grow<double>(A->p, n, err);
+  double* q = grow<double>(A->q, n, err);
+  double* r = grow<double>(A->r, n, err);
+  const int pstride = nblk + L0->nheavy;
+  double* parts = grow<double>(A->parts, 2 * (size_t)pstride, err);
+  double* sc = grow<double>(A->sc, S_N, err);
+  int* ctr = grow<int>(A->ctr, 8, err);  // [0] done, [1] iteration, [2] flag
+  AMG_TRY(err);
+  int* done = ctr;
+  int* itc = ctr + 1;
+  int* flag = ctr + 2;
+  k_cg_init<<<nblk, ANT, 0, st>>>(n, rhs, babs, s, r, p, q, parts, pstride);
+  k_cg_scal<<<1, ANT, 0, st>>>(0, parts, nblk, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+  std::vector<ALev> V(A->nlev);
+  for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
+  const int batch = 8;
+  for (int it = 0; it <= maxit + 1; it += batch) {
+    for (int k = 0; k < batch; ++k) {
+      // V-cycle on r -> z (= y of level 0)
+      for (int l = 0; l + 1 < A->nlev; ++l) {
+        const ALev& L = V[l];
+        k_cy_down<<<L.nblk + L.nheavy, ANT, 0, st>>>(L, done);
+        const AmgLevel* C = A->lv[l + 1];
+        k_cy_restrict<<<nb256(C->n) + C->nmheavy, ANT, 0, st>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy,
+                                                                L.r, V[l + 1].b, done);
+      }
+      const ALev& Lc = V[A->nlev - 1];
+      if (A->dense) {
+        k_cy_coarsest<<<1, AMAXC, 0, st>>>(Lc.n, static_cast<const double*>(A->ainv.p),
+                                           static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
+      } else {  // no exact coarsest: smoothing only
+        k_cy_down<<<Lc.nblk + Lc.nheavy, ANT, 0, st>>>(Lc, done);
+        k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, st>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, done);
+      }
+      for (int l = A->nlev - 2; l >= 0; --l) {
+        const ALev& L = V[l];
+        k_cy_up<<<L.nblk + L.nheavy, ANT, 0, st>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, done);
+      }
+      // rho = (r, z) -> beta; convergence on the last ||r||
+      k_cg_scal<<<1, ANT, 0, st>>>(1, parts, pstride, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+      k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
+      k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+      k_cg_xr<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts, done);
+      k_cg_scal<<<1, ANT, 0, st>>>(3, parts, nblk, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+    }
+    AMG_TRY(hipGetLastError());
+    AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    AMG_TRY(hipStreamSynchronize(st));
+    if (*host_flag == 0) break;
+  }
+  return hipSuccess;
+}
+
+}  // namespace nil

@@ -107,6 +107,7 @@ struct ni_ctx {
   int* host = nullptr;  // pinned readback area (64 ints)
   hipEvent_t ev[14] = {};
   struct nil::UnetModel* unet = nullptr;
+  nil::Amg* amg = nullptr;
 
 
   ni_ctx() {
@@ -576,6 +577,8 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.heavy = heavy;
   a.nheavy = nheavy;
   a.nbig = nbig;
+  if (!c->amg) c->amg = nil::amg_new();
+  a.amg = c->amg;
   a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
   a.nt = ptr<float>(c->nt); a.om_r = ptr<float>(c->om_r); a.om_d = ptr<float>(c->om_d); a.zfill = zfill;
   a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
@@ -746,6 +749,7 @@ ni_status ni_destroy(ni_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   if (c->host) (void)hipHostFree(c->host);
   if (c->unet) nil::unet_free(c->unet);
+  if (c->amg) nil::amg_free(c->amg);
   delete c;
   return NI_OK;
 }

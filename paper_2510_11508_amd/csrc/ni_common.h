@@ -113,6 +113,17 @@ struct LargeArgs {
   int maxit;
 };
 
+// aggregation multigrid for the quotient systems (ni_amg.hip)
+struct Amg;
+Amg* amg_new();
+void amg_free(Amg*);
+int amg_levels(const Amg*);
+hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, const double* qw, const int* pair_lo,
+                     const int* pair_hi, const double* pW, hipStream_t st);
+hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
+hipError_t amg_solve(Amg*, const double* rhs, const double* babs, double* s, double rtol, int maxit, int* iters_out,
+                     int* host_flag, hipStream_t st);
+
 // arguments of one relative-scale iteration (ni_quot.hip)
 struct IrlsArgs {
   const uint32_t* eidx;
@@ -140,6 +151,7 @@ struct IrlsArgs {
   int nheavy, nbig;
   int* ell_col;   // [8][K] ELL copy of the light quotient rows
   double* ell_w;
+  Amg* amg;       // multigrid for K above the one-workgroup solver (null: Jacobi)
 };
 
 }  // namespace nil

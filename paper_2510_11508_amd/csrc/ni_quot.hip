@@ -885,6 +885,14 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (a.K <= QCAP) {
     k_qcg_wg<<<1, QWG, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
     e = hipGetLastError();
+  } else if (a.amg) {
+    // multigrid-preconditioned CG on a hierarchy built from this step's
+    // weights (the cut set and the weights change from step to step)
+    e = hipGetLastError();
+    if (e == hipSuccess) e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.pair_lo, a.pair_hi, a.pW, st);
+    if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
+    if (e == hipSuccess)
+      e = amg_solve(a.amg, a.rhs, a.babs, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag, st);
   } else {
     QIter Q;
     Q.M = M; Q.x = a.s; Q.p = a.pv; Q.st = reinterpret_cast<double4*>(a.qst);
