@@ -38,7 +38,7 @@ namespace {
 
 constexpr int ANT = 256;      // threads per block, one row per thread
 constexpr int AH = 16;        // rows with more entries are heavy: one block each
-constexpr int AMAXC = 256;    // largest coarsest level solved exactly
+constexpr int AMAXC = 128;    // largest coarsest level solved exactly (its matrix fits in LDS)
 constexpr int AMAXL = 24;     // levels at most
 constexpr double AOMEGA = 2.0 / 3.0;
 
@@ -108,7 +108,8 @@ __device__ __forceinline__ void put_parts(double (&v)[NV], double* red, double* 
 }
 
 // ------------------------------------------------------------------ cycle
-// pre-smoothing from zero and the residual: x = w D^-1 b, r = b - A x
+// pre-smoothing from zero and the residual: r = b - A x with x = w D^-1 b
+// (x itself is recomputed where it is needed)
 __global__ void __launch_bounds__(ANT) k_cy_down(ALev L, const int* done) {
   if (is_done(done)) return;
   __shared__ double red[ANT / 64];
@@ -116,24 +117,18 @@ __global__ void __launch_bounds__(ANT) k_cy_down(ALev L, const int* done) {
   const double* b = L.b;
   const double* dg = L.diag;
   auto xv = [&](int d) { const double e = dg[d]; return e > 0 ? AOMEGA * b[d] / e : 0.0; };
-  double acc = 0.0, xc = 0.0;
-  if (s.c >= 0) {
-    xc = xv(s.c);
-    acc = row_diff_sum(L, s, xc, xv);
-  }
+  double acc = 0.0;
+  if (s.c >= 0) acc = row_diff_sum(L, s, xv(s.c), xv);
   if (s.big) {
     double t[1] = {acc};
     ni::block_sum<1>(t, red);
     acc = t[0];
   }
-  if (s.c >= 0 && (!s.big || threadIdx.x == 0)) {
-    L.x[s.c] = xc;
-    L.r[s.c] = b[s.c] - acc;
-  }
+  if (s.c >= 0 && (!s.big || threadIdx.x == 0)) L.r[s.c] = b[s.c] - acc;
 }
 
 // restriction b' = P^T r: each coarse node sums its members' residuals
-// (members of big aggregates are summed by a whole block)
+// (aggregates with more than AH members are summed by a whole block)
 __global__ void __launch_bounds__(ANT) k_cy_restrict(int n, int nblk, const int* __restrict__ mem_off,
                                                      const int* __restrict__ mem, const int* __restrict__ mheavy,
                                                      const double* __restrict__ r, double* __restrict__ bc,
@@ -178,18 +173,21 @@ __global__ void __launch_bounds__(AMAXC) k_cy_coarsest(int n, const double* __re
   }
 }
 
-// prolongation and post-smoothing: x += P y', y = x + w D^-1 (b - A x)
-// (yn = null: no coarser level, smoothing only).  On the finest level the
+// prolongation and post-smoothing: x = w D^-1 b + P y',
+// y = x + w D^-1 (b - A x) (yn = null: no coarser level, the two Jacobi
+// sweeps only).  On the finest level the
 // block partials of (b, y) are written to parts.
 __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict__ yn, double* __restrict__ parts,
                                                int pstride, const int* done) {
   if (is_done(done)) return;
   __shared__ double red[ANT / 64];
   const RowSel s = row_sel(L);
-  const double* x = L.x;
+  const double* b = L.b;
+  const double* dg = L.diag;
   const int* cid = L.cid;
   auto xv = [&](int d) {
-    double v = x[d];
+    const double e = dg[d];
+    double v = e > 0 ? AOMEGA * b[d] / e : 0.0;
     if (yn) {
       const int k = cid[d];
       if (k >= 0) v += yn[k];
@@ -295,19 +293,21 @@ __device__ __forceinline__ double sum_parts(const double* parts, int n, double* 
   return v[0];
 }
 
-// mode 0: after init (rr, |b|^2); mode 1: after the cycle (rho -> beta,
-// convergence test on rr); mode 2: after (p, q) (alpha); mode 3: after the
-// update (rr)
+// mode 0 (after init): rr and |b|^2 from nrr partials at parts and
+// parts + pstride.  mode 1 (after the cycle): rho from np partials at
+// parts; rr of the last update from nrr partials at parts + pstride (none
+// before the first update); convergence test, beta.  mode 2 (after (p, q)):
+// alpha.
 __global__ void __launch_bounds__(ANT) k_cg_scal(int mode, const double* __restrict__ parts, int np, int pstride,
-                                                 double* __restrict__ sc, int* __restrict__ done, int* it_ctr,
-                                                 double rtol, int maxit, int* __restrict__ iters_out,
+                                                 int nrr, double* __restrict__ sc, int* __restrict__ done,
+                                                 int* it_ctr, double rtol, int maxit, int* __restrict__ iters_out,
                                                  int* __restrict__ flag) {
   __shared__ double red[ANT / 64];
   if (mode != 0 && is_done(done)) return;
   if (mode == 0) {
-    const double rr = sum_parts(parts, np, red);
+    const double rr = sum_parts(parts, nrr, red);
     __syncthreads();
-    const double bs = sum_parts(parts + pstride, np, red);
+    const double bs = sum_parts(parts + pstride, nrr, red);
     if (threadIdx.x == 0) {
       sc[S_RR] = rr;
       sc[S_BS] = bs;
@@ -317,9 +317,15 @@ __global__ void __launch_bounds__(ANT) k_cg_scal(int mode, const double* __restr
       *flag = 1;
     }
   } else if (mode == 1) {
+    const int it = *it_ctr;
     const double rho = sum_parts(parts, np, red);
+    double rr = 0.0;
+    if (it > 0) {
+      __syncthreads();
+      rr = sum_parts(parts + pstride, nrr, red);
+    }
     if (threadIdx.x == 0) {
-      const int it = *it_ctr;
+      if (it > 0) sc[S_RR] = rr;
       if (!(sc[S_RR] > rtol * rtol * sc[S_BS]) || it >= maxit) {
         *done = 1;
         *flag = 0;
@@ -328,19 +334,14 @@ __global__ void __launch_bounds__(ANT) k_cg_scal(int mode, const double* __restr
         sc[S_BETA] = it == 0 ? 0.0 : rho / sc[S_RHOP];
         sc[S_RHO] = rho;
         sc[S_RHOP] = rho;
+        *it_ctr = it + 1;
       }
     }
-  } else if (mode == 2) {
+  } else {
     const double pq = sum_parts(parts, np, red);
     if (threadIdx.x == 0) {
       sc[S_PQ] = pq;
       sc[S_ALPHA] = pq != 0.0 ? sc[S_RHO] / pq : 0.0;
-    }
-  } else {
-    const double rr = sum_parts(parts, np, red);
-    if (threadIdx.x == 0) {
-      sc[S_RR] = rr;
-      *it_ctr += 1;
     }
   }
 }
@@ -351,15 +352,16 @@ __global__ void k_am_fill(int* a, int n, int v) {
   if (i < n) a[i] = v;
 }
 
-// a node takes part when it has an edge of positive weight
-__global__ void k_am_active(int n, const int* __restrict__ row_off, const double* __restrict__ w, int* __restrict__ agg,
-                            uint8_t* __restrict__ act) {
+// a node takes part when it has an edge of positive weight (row sum > 0);
+// nodes with more than AH entries start as aggregates of their own (their
+// neighbours may attach to them; scanning their rows would be slow)
+__global__ void k_am_active(int n, const int* __restrict__ row_off, const double* __restrict__ diag,
+                            int* __restrict__ agg, uint8_t* __restrict__ act) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  bool a = false;
-  for (int j = row_off[c]; j < row_off[c + 1]; ++j) a |= w[j] > 0.0;
+  const bool a = diag[c] > 0.0;
   act[c] = a ? 1 : 0;
-  agg[c] = -1;
+  agg[c] = (a && row_off[c + 1] - row_off[c] > AH) ? c : -1;
 }
 
 // strongest neighbour with agg == -1 (want_free) or agg >= 0; ties -> smaller index
@@ -559,24 +561,27 @@ __global__ void k_am_diag(int n, const int* __restrict__ row_off, const double* 
   diag[c] = s;
 }
 
-// Coarsest level (n <= AMAXC): dense Laplacian, pieces by label
+// Coarsest level (n <= AMAXC): dense Laplacian in LDS, pieces by label
 // propagation, the smallest node of every piece (and every node without
-// edges) pinned, then an in-place Gauss-Jordan inverse of the SPD rest.
+// edges) pinned, then an in-place Gauss-Jordan inverse of the SPD rest;
+// the inverse goes to A.
 __global__ void __launch_bounds__(1024) k_am_invert(int n, const int* __restrict__ row_off, const int* __restrict__ col,
                                                     const double* __restrict__ w, const double* __restrict__ diag,
                                                     double* __restrict__ A, uint8_t* __restrict__ pin) {
+  __shared__ double M[AMAXC * AMAXC];
   __shared__ int lab[AMAXC];
+  __shared__ uint8_t pn[AMAXC];
   __shared__ int changed;
   __shared__ double colk[AMAXC];
   __shared__ double rowk[AMAXC];
   const int T = blockDim.x;
-  for (int i = threadIdx.x; i < n * n; i += T) A[i] = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += T) M[i] = 0.0;
   for (int c = threadIdx.x; c < n; c += T) lab[c] = c;
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += T) {
-    A[(size_t)c * n + c] = diag[c];
+    M[c * n + c] = diag[c];
     for (int j = row_off[c]; j < row_off[c + 1]; ++j)
-      if (w[j] > 0.0) A[(size_t)c * n + col[j]] -= w[j];
+      if (w[j] > 0.0) M[c * n + col[j]] -= w[j];
   }
   // pieces: minimum label over edges of positive weight, until stable
   for (;;) {
@@ -595,17 +600,20 @@ __global__ void __launch_bounds__(1024) k_am_invert(int n, const int* __restrict
     __syncthreads();
     if (!changed) break;
   }
-  for (int c = threadIdx.x; c < n; c += T) pin[c] = (lab[c] == c || !(diag[c] > 0.0)) ? 1 : 0;
+  for (int c = threadIdx.x; c < n; c += T) {
+    pn[c] = (lab[c] == c || !(diag[c] > 0.0)) ? 1 : 0;
+    pin[c] = pn[c];
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < n * n; i += T) {
     const int r = i / n, c = i % n;
-    if (pin[r] || pin[c]) A[i] = (r == c) ? 1.0 : 0.0;
+    if (pn[r] || pn[c]) M[i] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
     for (int i = threadIdx.x; i < n; i += T) {
-      colk[i] = A[(size_t)i * n + k];
-      rowk[i] = A[(size_t)k * n + i];
+      colk[i] = M[i * n + k];
+      rowk[i] = M[k * n + i];
     }
     __syncthreads();
     const double piv = 1.0 / colk[k];
@@ -614,11 +622,12 @@ __global__ void __launch_bounds__(1024) k_am_invert(int n, const int* __restrict
       double v;
       if (i == k) v = (j == k) ? piv : rowk[j] * piv;
       else if (j == k) v = -colk[i] * piv;
-      else v = A[idx] - colk[i] * rowk[j] * piv;
-      A[idx] = v;
+      else v = M[idx] - colk[i] * rowk[j] * piv;
+      M[idx] = v;
     }
     __syncthreads();
   }
+  for (int i = threadIdx.x; i < n * n; i += T) A[i] = M[i];
 }
 
 // ------------------------------------------------------------ host side
@@ -783,9 +792,10 @@ static void level_values(AmgLevel* L, const double* pwf, hipStream_t st) {
 }
 
 // Build the hierarchy from the quotient graph of this step: K nodes, P
-// pairs (pair_lo < pair_hi, weights pW), CSR row_off / qcol / qw.
+// pairs (pair_lo < pair_hi, weights pW), CSR row_off / qcol / qw, row sums
+// diag.
 hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, const double* qw,
-                     const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st) {
+                     const double* diag, const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st) {
   hipError_t err = hipSuccess;
   if (A->lv.empty()) A->lv.push_back(new AmgLevel());
   AmgLevel* L0 = A->lv[0];
@@ -794,6 +804,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
   L0->row_off = row_off;
   L0->col = qcol;
   L0->w = qw;
+  L0->diag = diag;
   L0->plo = pair_lo;
   L0->phi = pair_hi;
   L0->pw = pW;
@@ -830,7 +841,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
     int* scan = grow<int>(A->scan, std::max(radix_tmp_ints(std::max(std::max(2 * F->np, n), 1)),
                                             scan_tmp_ints(std::max(F->np, n) + 1)), err);
     AMG_TRY(err);
-    k_am_active<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->w, agg, act);
+    k_am_active<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->diag, agg, act);
     for (int round = 0; round < 3; ++round) {
       k_am_pick<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, best);
       k_am_match<<<nb256(n), 256, 0, st>>>(n, best, agg);
@@ -866,7 +877,16 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
       k_am_offsets<<<nb256(m), 256, 0, st>>>(m, ks, nc, mem_off);
       C->mem_off = mem_off;
       C->mem = mem;
-      AMG_TRY(heavy_list(A, nc, mem_off, C->mheavy_b, &C->nmheavy, C->mheavy, st));
+      // aggregates with more than AH members: a block each in the restriction
+      int* hf = grow<int>(A->s[14], nc, err);
+      int* hp = grow<int>(A->s[15], nc + 1, err);
+      int* hl = grow<int>(C->mheavy_b, nc, err);
+      AMG_TRY(err);
+      k_am_heavy_flag<<<nb256(nc), 256, 0, st>>>(nc, mem_off, hf);
+      AMG_TRY(scan_exclusive_i32(hf, hp, nc, tot, scan, st));
+      k_am_list<<<nb256(nc), 256, 0, st>>>(nc, hf, hp, hl);
+      C->mheavy = hl;
+      AMG_TRY(read_int(tot, &C->nmheavy, st));
     }
     // ---- coarse pairs: fine pairs between two aggregates, grouped by (lo, hi)
     {
@@ -1002,7 +1022,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   int* itc = ctr + 1;
   int* flag = ctr + 2;
   k_cg_init<<<nblk, ANT, 0, st>>>(n, rhs, babs, s, r, p, q, parts, pstride);
-  k_cg_scal<<<1, ANT, 0, st>>>(0, parts, nblk, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+  k_cg_scal<<<1, ANT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
   const int batch = 8;
@@ -1021,19 +1041,17 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
         k_cy_coarsest<<<1, AMAXC, 0, st>>>(Lc.n, static_cast<const double*>(A->ainv.p),
                                            static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
       } else {  // no exact coarsest: smoothing only
-        k_cy_down<<<Lc.nblk + Lc.nheavy, ANT, 0, st>>>(Lc, done);
         k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, st>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, done);
       }
       for (int l = A->nlev - 2; l >= 0; --l) {
         const ALev& L = V[l];
         k_cy_up<<<L.nblk + L.nheavy, ANT, 0, st>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, done);
       }
-      // rho = (r, z) -> beta; convergence on the last ||r||
-      k_cg_scal<<<1, ANT, 0, st>>>(1, parts, pstride, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+      // rho = (r, z) -> beta; convergence on ||r||
+      k_cg_scal<<<1, ANT, 0, st>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
       k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
-      k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
-      k_cg_xr<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts, done);
-      k_cg_scal<<<1, ANT, 0, st>>>(3, parts, nblk, pstride, sc, done, itc, rtol, maxit, iters_out, flag);
+      k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+      k_cg_xr<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts + pstride, done);
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

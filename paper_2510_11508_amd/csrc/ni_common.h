@@ -118,8 +118,8 @@ struct Amg;
 Amg* amg_new();
 void amg_free(Amg*);
 int amg_levels(const Amg*);
-hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, const double* qw, const int* pair_lo,
-                     const int* pair_hi, const double* pW, hipStream_t st);
+hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, const double* qw, const double* diag,
+                     const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st);
 hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
 hipError_t amg_solve(Amg*, const double* rhs, const double* babs, double* s, double rtol, int maxit, int* iters_out,
                      int* host_flag, hipStream_t st);

@@ -889,7 +889,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
     // multigrid-preconditioned CG on a hierarchy built from this step's
     // weights (the cut set and the weights change from step to step)
     e = hipGetLastError();
-    if (e == hipSuccess) e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.pair_lo, a.pair_hi, a.pW, st);
+    if (e == hipSuccess) e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
     if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
     if (e == hipSuccess)
       e = amg_solve(a.amg, a.rhs, a.babs, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag, st);
