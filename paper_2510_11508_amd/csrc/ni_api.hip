@@ -26,8 +26,8 @@ hipError_t fill_assemble(const uint32_t*, int, int, int, const int*, const uint8
                          const float*, const int*, double, double, float*, float*, float*, uint32_t*, float*,
                          float*, hipStream_t);
 hipError_t fill_tier_list(const int*, int, int, int*, int*, int*, int*, int*, hipStream_t);
-hipError_t fill_chunks(const int*, int, int*, int*, int*, int*, hipStream_t);
-hipError_t fill_chunk_table(const int*, const int*, const int*, int, int*, int*, int*, hipStream_t);
+hipError_t fill_chunks(const int*, int, int, int*, int*, int*, int*, hipStream_t);
+hipError_t fill_chunk_table(const int*, const int*, const int*, int, int, int*, int*, int*, hipStream_t);
 hipError_t fill_zero_grid(float*, int, hipStream_t);
 hipError_t fill_gather_x0(const uint32_t*, int, const float*, float*, hipStream_t);
 hipError_t fill_small(int, const int*, int, const int*, const float*, const float*, const float*, const uint32_t*,
@@ -108,6 +108,10 @@ struct ni_ctx {
   hipEvent_t ev[14] = {};
   struct nil::UnetModel* unet = nullptr;
   nil::Amg* amg = nullptr;
+  // autotuned schedule of the large fill path: shortest chunk per block,
+  // and the map size class it was tuned for
+  int fill_chunk = 0, fill_chunk_key = -1;
+  float tune_ms[4] = {};
 
 
   ni_ctx() {
@@ -393,15 +397,79 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     check(c, nil::fill_tier_list(comp_off, K, t, tflag, tpos, lists + (t - 1) * K1, cntd + (t - 1),
                                  ptr<int>(c->scan_tmp), c->stream),
           "tier lists");
-  check(c, nil::fill_chunks(comp_off, K, nchunk, cbase, cntd + 4, ptr<int>(c->scan_tmp), c->stream), "chunks");
-  readback(c, cntd, 5 * sizeof(int), c->host);
+  readback(c, cntd, 4 * sizeof(int), c->host);
   int ntier[4] = {c->host[0], c->host[1], c->host[2], c->host[3]};
-  const int n_chunks = c->host[4];
-  int* chunk_comp = ensure<int>(c, c->chunk_comp, n_chunks);
-  int* chunk_start = ensure<int>(c, c->chunk_start, n_chunks);
-  int* chunk_end = ensure<int>(c, c->large_list, n_chunks);
-  check(c, nil::fill_chunk_table(comp_off, nchunk, cbase, K, chunk_comp, chunk_start, chunk_end, c->stream),
-        "chunk table");
+  const int n_large = ntier[3];
+  double* rr = ensure<double>(c, c->rr, K1);
+  double* bb = ensure<double>(c, c->bb, K1);
+  // chunk table of the large components for chunk length `len`
+  int n_chunks = 0;
+  int *chunk_comp = nullptr, *chunk_start = nullptr, *chunk_end = nullptr;
+  auto chunks = [&](int len) {
+    check(c, nil::fill_chunks(comp_off, K, len, nchunk, cbase, cntd + 4, ptr<int>(c->scan_tmp), c->stream),
+          "chunks");
+    readback(c, cntd + 4, sizeof(int), c->host);
+    n_chunks = c->host[0];
+    chunk_comp = ensure<int>(c, c->chunk_comp, n_chunks);
+    chunk_start = ensure<int>(c, c->chunk_start, n_chunks);
+    chunk_end = ensure<int>(c, c->large_list, n_chunks);
+    check(c, nil::fill_chunk_table(comp_off, nchunk, cbase, K, len, chunk_comp, chunk_start, chunk_end, c->stream),
+          "chunk table");
+  };
+  auto large_args = [&]() {
+    nil::LargeArgs a;
+    a.comp_off = comp_off; a.cbase = cbase; a.nchunk = nchunk; a.chunk_comp = chunk_comp;
+    a.chunk_start = chunk_start; a.chunk_end = chunk_end;
+    a.part = ensure<double>(c, c->part, 2 * 4 * (size_t)n_chunks);
+    a.gam = ensure<double>(c, c->rho, 2 * K1);
+    a.alp = ensure<double>(c, c->alpha, 2 * K1);
+    a.tol2 = ensure<double>(c, c->tol2, K1);
+    a.rr = rr; a.bb = bb; a.iters = iters;
+    a.active = misc(c) + M_ACTIVE; a.stats = misc(c) + M_STATS;
+    a.cwr = cwr; a.cwd = cwd; a.cwu = cwu; a.rhs = rhs; a.dinv = dinv; a.coff = coff;
+    a.x = x;
+    a.p = ensure<float>(c, c->p0, N);
+    a.r0 = ensure<float>(c, c->r, N);
+    a.r1 = ensure<float>(c, c->z, N);
+    a.w0 = ensure<float>(c, c->w0, N);
+    a.w1 = ensure<float>(c, c->w1, N);
+    a.s0 = ensure<float>(c, c->s0, N);
+    a.s1 = ensure<float>(c, c->s1, N);
+    a.nchunks = n_chunks; a.K = K; a.rtol = pb.prm.cg_rtol; a.maxit = pb.prm.cg_max_iter;
+    return a;
+  };
+  // Autotuner: the first time a map of this size class reaches the large
+  // path, every candidate chunk length runs a few CG iterations from a zero
+  // start and the fastest per iteration is kept for the context.  The
+  // probe's vectors are reset before the real solve.
+  int key = 0;
+  while ((1ll << key) < (long long)N) ++key;
+  if (n_large > 0 && c->fill_chunk_key != key) {
+    const int cand[4] = {512, 1024, 2048, 4096};
+    const int probe = 8;
+    float best = 1e30f;
+    int pick = cand[2];
+    for (int k = 0; k < 4; ++k) {
+      chunks(cand[k]);
+      nil::LargeArgs a = large_args();
+      check(c, nil::fill_gather_x0(cpix, N, nullptr, x, c->stream), "gather");
+      check(c, hipMemsetAsync(a.active, 0, 2 * sizeof(int), c->stream), "memset");
+      check(c, nil::large_init(a, 0, c->stream), "large init");
+      mark(c, 12);
+      for (int it = 0; it < probe; ++it) check(c, nil::large_iter(a, it, c->stream), "large iter");
+      mark(c, 13);
+      check(c, hipStreamSynchronize(c->stream), "sync");
+      const float ms = ev_ms(c, 12, 13);
+      c->tune_ms[k] = ms;
+      if (ms < best) {
+        best = ms;
+        pick = cand[k];
+      }
+    }
+    c->fill_chunk = pick;
+    c->fill_chunk_key = key;
+  }
+  chunks(c->fill_chunk);
   check(c, hipMemsetAsync(iters, 0, K1 * sizeof(int), c->stream), "memset");
   check(c, hipMemsetAsync(relres, 0, K1 * sizeof(double), c->stream), "memset");
   check(c, hipMemsetAsync(misc(c) + M_STATS, 0, 4 * sizeof(int), c->stream), "memset");
@@ -426,29 +494,8 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   mark(c, 6);
   int launches = 0;
   float large_kernel_ms = 0.f;
-  const int n_large = ntier[3];
-  double* rr = ensure<double>(c, c->rr, K1);
-  double* bb = ensure<double>(c, c->bb, K1);
   if (n_large > 0) {
-    nil::LargeArgs a;
-    a.comp_off = comp_off; a.cbase = cbase; a.nchunk = nchunk; a.chunk_comp = chunk_comp;
-    a.chunk_start = chunk_start; a.chunk_end = chunk_end;
-    a.part = ensure<double>(c, c->part, 2 * 4 * (size_t)n_chunks);
-    a.gam = ensure<double>(c, c->rho, 2 * K1);
-    a.alp = ensure<double>(c, c->alpha, 2 * K1);
-    a.tol2 = ensure<double>(c, c->tol2, K1);
-    a.rr = rr; a.bb = bb; a.iters = iters;
-    a.active = misc(c) + M_ACTIVE; a.stats = misc(c) + M_STATS;
-    a.cwr = cwr; a.cwd = cwd; a.cwu = cwu; a.rhs = rhs; a.dinv = dinv; a.coff = coff;
-    a.x = x;
-    a.p = ensure<float>(c, c->p0, N);
-    a.r0 = ensure<float>(c, c->r, N);
-    a.r1 = ensure<float>(c, c->z, N);
-    a.w0 = ensure<float>(c, c->w0, N);
-    a.w1 = ensure<float>(c, c->w1, N);
-    a.s0 = ensure<float>(c, c->s0, N);
-    a.s1 = ensure<float>(c, c->s1, N);
-    a.nchunks = n_chunks; a.K = K; a.rtol = pb.prm.cg_rtol; a.maxit = pb.prm.cg_max_iter;
+    nil::LargeArgs a = large_args();
     check(c, hipMemsetAsync(a.active, 0, 2 * sizeof(int), c->stream), "memset");
     check(c, nil::large_init(a, warm, c->stream), "large init");
     // one launch per CG iteration; the host reads the count of components

@@ -366,6 +366,7 @@ __global__ void __launch_bounds__(NT) k_fill_small(
 // of the workgroup size long (so mid-size problems still fill the GPU while
 // the per-workgroup partial sums stay short)
 constexpr int LNT = 256, LCH = 512, LMAXCH = 256;
+constexpr int LU = 4;  // pixels per thread whose loads are issued together
 
 struct LargeState {
   const int* comp_off;
@@ -411,7 +412,9 @@ __device__ __forceinline__ void put_partials(const LargeState& S, int ch, int ws
     const int k = threadIdx.x;
     const size_t dst = ((size_t)wslot * S.nchunks + ch) * 4 + k;
     const size_t src = ((size_t)(wslot ^ 1) * S.nchunks + ch) * 4 + k;
-    S.part[dst] = ((mask >> k) & 1) ? v[k] : S.part[src];
+    // select without indexing v by the thread (that would put v in scratch)
+    const double vk = k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
+    S.part[dst] = ((mask >> k) & 1) ? vk : S.part[src];
   }
 }
 
@@ -502,17 +505,42 @@ __global__ void __launch_bounds__(LNT) k_lg_a(LargeState S, int it, int K) {
   const float* pold = (it & 1) ? S.s0 : S.s1;  // p_{i-1}
   float* pnew = (it & 1) ? S.s1 : S.s0;        // p_i
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
-    Stencil st = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, i, clo);
-    const float pi = S.dinv[i] * S.r0[i] + bt * pold[i];
-    float q = 0.f;
-    if (st.wr != 0.f) { const int j = i + 1;      q += st.wr * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
-    if (st.wl != 0.f) { const int j = i - 1;      q += st.wl * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
-    if (st.wd != 0.f) { const int j = i + st.od;  q += st.wd * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
-    if (st.wu != 0.f) { const int j = i - st.ou;  q += st.wu * (pi - (S.dinv[j] * S.r0[j] + bt * pold[j])); }
-    pnew[i] = pi;
-    S.w0[i] = q;
-    v[2] += (double)pi * q;
+  const int end = S.chunk_end[ch];
+  auto P = [&](int j) { return S.dinv[j] * S.r0[j] + bt * pold[j]; };
+  // LU pixels per thread and round, every load issued before any use; a
+  // missing neighbour (weight 0) reads the pixel itself
+  for (int i0 = lo + threadIdx.x; i0 < end; i0 += LNT * LU) {
+    int ix[LU];
+    Stencil st[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      ix[u] = i0 + u * LNT < end ? i0 + u * LNT : lo;
+      st[u] = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, ix[u], clo);
+    }
+    float pc[LU], pr[LU], pl[LU], pd[LU], pu[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int i = ix[u];
+      pc[u] = P(i);
+      pr[u] = P(st[u].wr != 0.f ? i + 1 : i);
+      pl[u] = P(st[u].wl != 0.f ? i - 1 : i);
+      pd[u] = P(st[u].wd != 0.f ? i + st[u].od : i);
+      pu[u] = P(st[u].wu != 0.f ? i - st[u].ou : i);
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      if (i0 + u * LNT < end) {
+        const int i = ix[u];
+        float q = 0.f;
+        q += st[u].wr * (pc[u] - pr[u]);
+        q += st[u].wl * (pc[u] - pl[u]);
+        q += st[u].wd * (pc[u] - pd[u]);
+        q += st[u].wu * (pc[u] - pu[u]);
+        pnew[i] = pc[u];
+        S.w0[i] = q;
+        v[2] += (double)pc[u] * q;
+      }
+    }
   }
   ni::block_sum<4>(v, red + 4 * (LNT / 64));
   put_partials(S, ch, 0, v, 4);
@@ -539,12 +567,29 @@ __global__ void __launch_bounds__(LNT) k_lg_b(LargeState S, int it, int K) {
   const float alpha = (float)(rho / pq);
   const float* pcur = (it & 1) ? S.s1 : S.s0;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
-    const float ri = S.r0[i] - alpha * S.w0[i];
-    S.x[i] += alpha * pcur[i];
-    S.r0[i] = ri;
-    v[0] += (double)ri * (S.dinv[i] * ri);
-    v[1] += (double)ri * ri;
+  const int end = S.chunk_end[ch];
+  for (int i0 = lo + threadIdx.x; i0 < end; i0 += LNT * LU) {
+    float r[LU], w[LU], x[LU], pp[LU], d[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int i = i0 + u * LNT < end ? i0 + u * LNT : lo;
+      r[u] = S.r0[i];
+      w[u] = S.w0[i];
+      x[u] = S.x[i];
+      pp[u] = pcur[i];
+      d[u] = S.dinv[i];
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int i = i0 + u * LNT;
+      if (i < end) {
+        const float ri = r[u] - alpha * w[u];
+        S.x[i] = x[u] + alpha * pp[u];
+        S.r0[i] = ri;
+        v[0] += (double)ri * (d[u] * ri);
+        v[1] += (double)ri * ri;
+      }
+    }
   }
   ni::block_sum<4>(v, red + 4 * (LNT / 64));
   put_partials(S, ch, 1, v, 3);
@@ -645,17 +690,18 @@ hipError_t fill_tier_list(const int* comp_off, int K, int tier, int* flag, int* 
 }
 
 // chunk table of the large components; total chunks -> *count_dev
-hipError_t fill_chunks(const int* comp_off, int K, int* nchunk, int* cbase, int* count_dev, int* scan_tmp,
+hipError_t fill_chunks(const int* comp_off, int K, int chunk, int* nchunk, int* cbase, int* count_dev, int* scan_tmp,
                        hipStream_t st) {
   if (K <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int), st);
-  k_chunk_counts<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, K, LCH, LMAXCH, LNT, nchunk);
+  k_chunk_counts<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, K, chunk > 0 ? chunk : LCH, LMAXCH, LNT, nchunk);
   return scan_exclusive_i32(nchunk, cbase, K, count_dev, scan_tmp, st);
 }
 
-hipError_t fill_chunk_table(const int* comp_off, const int* nchunk, const int* cbase, int K, int* chunk_comp,
+hipError_t fill_chunk_table(const int* comp_off, const int* nchunk, const int* cbase, int K, int chunk, int* chunk_comp,
                             int* chunk_start, int* chunk_end, hipStream_t st) {
   if (K <= 0) return hipSuccess;
-  k_chunk_table<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, nchunk, cbase, K, LCH, LMAXCH, LNT, chunk_comp,
+  k_chunk_table<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, nchunk, cbase, K, chunk > 0 ? chunk : LCH, LMAXCH,
+                                                      LNT, chunk_comp,
                                                       chunk_start, chunk_end);
   return hipGetLastError();
 }
