@@ -80,6 +80,9 @@ typedef struct {
   double q_rtol;        /* quotient CG: stop at ||r|| <= q_rtol * ||b||_abs   */
   int32_t q_max_iter;   /* quotient CG iteration cap                          */
   int32_t warm_start;   /* 0 zero start; 1 learned start (needs ni_unet_load) */
+  int32_t graphs;       /* 1: the multigrid quotient CG replays each iteration's
+                           launches from a HIP graph; 0: plain stream launches
+                           (same kernels, same results) */
 } ni_params;
 
 typedef struct {
@@ -109,7 +112,8 @@ typedef struct ni_ctx ni_ctx;
 
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
  * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-4, cg_rtol 1e-6,
- * cg_max_iter 50000, q_rtol 1e-12, q_max_iter 20000, zero start.
+ * cg_max_iter 50000, q_rtol 1e-12, q_max_iter 20000, zero start, no
+ * graphs.
  * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);
 

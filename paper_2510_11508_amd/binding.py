@@ -32,7 +32,8 @@ class ni_params(C.Structure):
                 ("align_iters", C.c_int32), ("bini_k", C.c_double), ("out_L", C.c_double),
                 ("out_U", C.c_double), ("outlier_mode", C.c_int32), ("delta_e_max", C.c_double),
                 ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
-                ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32)]
+                ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 class ni_report(C.Structure):

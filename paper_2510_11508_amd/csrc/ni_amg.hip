@@ -688,7 +688,9 @@ struct Amg {
   bool dense = false;  // coarsest solved exactly
   DBuf s[NSCR];
   DBuf scan, ainv, pin, p, q, r, parts, sc, ctr;
+  hipStream_t cap = nullptr;  // capture stream of the iteration graph
   ~Amg() {
+    if (cap) (void)hipStreamDestroy(cap);
     for (AmgLevel* L : lv) {
       DBuf* b[] = {&L->mem_off_b, &L->mem_b, &L->mheavy_b, &L->gal_off_b, &L->gal_src_b, &L->cid_b, &L->plo_b,
                    &L->phi_b, &L->row_off_b, &L->ent_b, &L->col_b, &L->heavy_b, &L->pw_b, &L->w_b, &L->diag_b,
@@ -1005,7 +1007,7 @@ static ALev view(const AmgLevel* L, double* b) {
 // (device).  The host polls the "still iterating" flag every `batch`
 // iterations.
 hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, double rtol, int maxit,
-                     int* iters_out, int* host_flag, hipStream_t st) {
+                     int* iters_out, int* host_flag, bool graph, hipStream_t st) {
   hipError_t err = hipSuccess;
   AmgLevel* L0 = A->lv[0];
   const int n = L0->n;
@@ -1025,33 +1027,60 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   k_cg_scal<<<1, ANT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
+  // one PCG iteration: V-cycle on r -> z (= y of level 0), then the CG
+  // update; every kernel returns at once after convergence
+  auto iteration = [&](hipStream_t q_) {
+    for (int l = 0; l + 1 < A->nlev; ++l) {
+      const ALev& L = V[l];
+      k_cy_down<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
+      const AmgLevel* C = A->lv[l + 1];
+      k_cy_restrict<<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy,
+                                                              L.r, V[l + 1].b, done);
+    }
+    const ALev& Lc = V[A->nlev - 1];
+    if (A->dense) {
+      k_cy_coarsest<<<1, AMAXC, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
+                                         static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
+    } else {  // no exact coarsest: smoothing only
+      k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, done);
+    }
+    for (int l = A->nlev - 2; l >= 0; --l) {
+      const ALev& L = V[l];
+      k_cy_up<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, done);
+    }
+    // rho = (r, z) -> beta; convergence on ||r||
+    k_cg_scal<<<1, ANT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+    k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, q_>>>(V[0], p, q, sc, parts, pstride, done);
+    k_cg_scal<<<1, ANT, 0, q_>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+    k_cg_xr<<<nblk, ANT, 0, q_>>>(n, s, r, p, q, sc, parts + pstride, done);
+  };
+  // optionally the iteration's ~3 launches per level are captured once per
+  // solve into a graph (on a private stream: the caller's may be the legacy
+  // default stream, which cannot be captured) and replayed on the caller's
+  // stream.  On gfx950 this did not shorten an iteration (the time between
+  // dependent kernels is spent on the device, not in the launch calls).
+  hipGraphExec_t ge = nullptr;
+  if (graph) {
+    if (!A->cap) AMG_TRY(hipStreamCreateWithFlags(&A->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    AMG_TRY(hipStreamBeginCapture(A->cap, hipStreamCaptureModeThreadLocal));
+    iteration(A->cap);
+    hipError_t ce = hipStreamEndCapture(A->cap, &g);
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    AMG_TRY(ce);
+  }
+  struct ExecGuard {
+    hipGraphExec_t e;
+    ~ExecGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } guard{ge};
   const int batch = 8;
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
-      // V-cycle on r -> z (= y of level 0)
-      for (int l = 0; l + 1 < A->nlev; ++l) {
-        const ALev& L = V[l];
-        k_cy_down<<<L.nblk + L.nheavy, ANT, 0, st>>>(L, done);
-        const AmgLevel* C = A->lv[l + 1];
-        k_cy_restrict<<<nb256(C->n) + C->nmheavy, ANT, 0, st>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy,
-                                                                L.r, V[l + 1].b, done);
-      }
-      const ALev& Lc = V[A->nlev - 1];
-      if (A->dense) {
-        k_cy_coarsest<<<1, AMAXC, 0, st>>>(Lc.n, static_cast<const double*>(A->ainv.p),
-                                           static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
-      } else {  // no exact coarsest: smoothing only
-        k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, st>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, done);
-      }
-      for (int l = A->nlev - 2; l >= 0; --l) {
-        const ALev& L = V[l];
-        k_cy_up<<<L.nblk + L.nheavy, ANT, 0, st>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, done);
-      }
-      // rho = (r, z) -> beta; convergence on ||r||
-      k_cg_scal<<<1, ANT, 0, st>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
-      k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
-      k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
-      k_cg_xr<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts + pstride, done);
+      if (ge) AMG_TRY(hipGraphLaunch(ge, st));
+      else iteration(st);
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

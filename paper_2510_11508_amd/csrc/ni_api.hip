@@ -626,6 +626,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.nbig = nbig;
   if (!c->amg) c->amg = nil::amg_new();
   a.amg = c->amg;
+  a.graphs = pb.prm.graphs ? 1 : 0;
   a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
   a.nt = ptr<float>(c->nt); a.om_r = ptr<float>(c->om_r); a.om_d = ptr<float>(c->om_d); a.zfill = zfill;
   a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
@@ -761,6 +762,7 @@ ni_status ni_params_default(ni_params* p) {
   p->q_rtol = 1e-12;
   p->q_max_iter = 20000;
   p->warm_start = 0;
+  p->graphs = 0;
   return NI_OK;
 }
 

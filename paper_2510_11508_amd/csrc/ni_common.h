@@ -122,7 +122,7 @@ hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, co
                      const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st);
 hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
 hipError_t amg_solve(Amg*, const double* rhs, const double* babs, double* s, double rtol, int maxit, int* iters_out,
-                     int* host_flag, hipStream_t st);
+                     int* host_flag, bool graph, hipStream_t st);
 
 // arguments of one relative-scale iteration (ni_quot.hip)
 struct IrlsArgs {
@@ -152,6 +152,7 @@ struct IrlsArgs {
   int* ell_col;   // [8][K] ELL copy of the light quotient rows
   double* ell_w;
   Amg* amg;       // multigrid for K above the one-workgroup solver (null: Jacobi)
+  int graphs;     // replay the multigrid iteration from a HIP graph
 };
 
 }  // namespace nil

@@ -892,7 +892,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
     if (e == hipSuccess) e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
     if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
     if (e == hipSuccess)
-      e = amg_solve(a.amg, a.rhs, a.babs, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag, st);
+      e = amg_solve(a.amg, a.rhs, a.babs, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag, a.graphs != 0, st);
   } else {
     QIter Q;
     Q.M = M; Q.x = a.s; Q.p = a.pv; Q.st = reinterpret_cast<double4*>(a.qst);

@@ -206,6 +206,27 @@ def test_integrate_large_quotient(ctx, theta):
     assert out["report"]["n_inter_edges"] == ref.n_inter_edges
 
 
+def test_graph_replay_equals_stream_launches(ctx):
+    """The multigrid quotient CG replayed from a HIP graph gives the output
+    of the same kernels launched one by one, call after call (the graph is
+    captured per solve and replayed many times per call)."""
+    s = synth.make("c2", 1)
+    outs = []
+    for g in (0, 1, 0, 1):
+        p = params(theta_c_deg=0.8, graphs=g)
+        log(f"[graph replay] graphs={g}")
+        o = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+        assert o["K"] > 4096
+        outs.append((o["depth"].cpu().numpy(), o["log_scale"].cpu().numpy(), list(o["report"]["quot_iters"])))
+    # the piece and region means use FP64 atomics (summation order varies
+    # between runs), so the comparison is at rounding level, not bitwise
+    v = s.mask > 0
+    for d, ls, qi in outs[1:]:
+        assert np.max(np.abs(d[v] - outs[0][0][v]) / np.abs(outs[0][0][v])) <= 1e-6
+        assert np.max(np.abs(ls - outs[0][1])) <= 1e-10
+        assert all(abs(a - b) <= 2 for a, b in zip(qi, outs[0][2]))
+
+
 @pytest.mark.parametrize("theta", [2.0, 0.8])
 def test_deterministic(ctx, theta):
     s = synth.make("c2", 2)
