@@ -38,6 +38,13 @@ METRIC = "valid Mpixels/s integrated at 1e-6 residual; warm-start vs plain CG sp
 HBM_PEAK_GBS = 8000.0
 CG_BYTES_PER_PX_ITER = 64
 DEFAULT_MODEL = os.path.join(ROOT, "paper_2510_11508_amd", "weights", "unet_warmstart.niunet")
+# forward multiply-adds per input pixel of the warm-start U-Net: 3x3
+# convolutions (cin -> cout) at full, 1/4, 1/16 and 1/64 resolution, plus
+# the 1x1 head
+UNET_LEVELS = [(1, [(6, 16), (16, 16), (48, 16), (16, 16)]), (4, [(16, 32), (32, 32), (96, 32), (32, 32)]),
+               (16, [(32, 64), (64, 64), (192, 64), (64, 64)]), (64, [(64, 128), (128, 128)])]
+UNET_FLOP_PER_PX = 2 * (sum(9 * ci * co / div for div, convs in UNET_LEVELS for ci, co in convs) + 16)
+BF16_PEAK_TFLOPS = 2500.0
 WORKLOADS = {
     "c2": "512x512 perspective (f=600), 5 depth steps, 6 bumps, 45% blob mask, noise 0.005, theta_c 2 deg, T=15",
     "c3": "2048x2048 perspective (f=2400), 40 steps, 60 bumps, 70% blob mask, noise 0.005, theta_c 2 deg, T=15",
@@ -161,6 +168,20 @@ def main():
                     fill_px_iters=dict(zero=reps[-1]["fill_px_iters"], warm=rw["fill_px_iters"]),
                     fallbacks=rw["warm_fallbacks"], max_relres=rw["fill_max_relres"],
                     max_rel_depth_diff_vs_zero_start=dz)
+        # network inference alone (features, forward, crop) on this map
+        hw = int(s.mask.shape[0]) * int(s.mask.shape[1])
+        for _ in range(2):
+            ctx.ni_unet_predict(normals, mask, cam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.ni_unet_predict(normals, mask, cam)
+        torch.cuda.synchronize()
+        ms_u = (time.perf_counter() - t0) * 1000.0 / 5
+        tfl = UNET_FLOP_PER_PX * hw / (ms_u / 1000.0) / 1e12
+        warm["unet_forward"] = dict(ms_per_map=round(ms_u, 3), flop_per_px=round(UNET_FLOP_PER_PX),
+                                    tflops=round(tfl, 2), peak_tflops=BF16_PEAK_TFLOPS,
+                                    frac=round(tfl / BF16_PEAK_TFLOPS, 4), dtype="bf16 mfma, fp32 accumulate")
 
     rep = reps[-1]
     k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
