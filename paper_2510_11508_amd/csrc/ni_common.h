@@ -36,6 +36,32 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
+// Atomic accumulation of (a, b) into (da[key], db[key]).  When every valid
+// lane of the wavefront has the same key (the common case: one giant piece
+// or region), the wavefront sums first and issues one pair of atomics
+// instead of 64.  Every lane of the wavefront must call it.
+template <class TB>
+__device__ __forceinline__ void acc_by_key(bool valid, int key, double a, TB b, double* da, TB* db) {
+  const int lead = __shfl(key, 0, NI_WAVE);
+  const bool lead_valid = __shfl(valid ? 1 : 0, 0, NI_WAVE) != 0;
+  if (lead_valid && __all(!valid || key == lead)) {
+    double sa = valid ? a : 0.0;
+    TB sb = valid ? b : TB(0);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sa += __shfl_xor(sa, o, NI_WAVE);
+      sb += __shfl_xor(sb, o, NI_WAVE);
+    }
+    if ((threadIdx.x & (NI_WAVE - 1)) == 0) {
+      atomicAdd(&da[lead], sa);
+      atomicAdd(&db[lead], sb);
+    }
+  } else if (valid) {
+    atomicAdd(&da[key], a);
+    atomicAdd(&db[key], b);
+  }
+}
+
 // Block-wide sum of NV doubles; every thread receives the totals.  `scratch`
 // must hold NV * (blockDim/64) doubles and must not be reused by the caller
 // until a later __syncthreads(); the sum order is fixed (deterministic).

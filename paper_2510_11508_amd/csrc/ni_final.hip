@@ -35,11 +35,10 @@ __global__ void k_region_zero(double* rsum, double* rcnt, int R) {
 __global__ void k_region_acc(const int* __restrict__ comp_off, const double* __restrict__ csum,
                              const double* __restrict__ S, const int* __restrict__ comp_rid, int K,
                              double* __restrict__ rsum, double* __restrict__ rcnt) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
-  double n = (double)(comp_off[c + 1] - comp_off[c]);
-  atomicAdd(&rsum[comp_rid[c]], csum[c] + n * S[c]);
-  atomicAdd(&rcnt[comp_rid[c]], n);
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool v = c < K;
+  const double n = v ? (double)(comp_off[c + 1] - comp_off[c]) : 0.0;
+  ni::acc_by_key<double>(v, v ? comp_rid[c] : 0, v ? csum[c] + n * S[c] : 0.0, n, rsum, rcnt);
 }
 
 __global__ void k_final_out(const int* __restrict__ label, const float* __restrict__ zfill,

@@ -18,6 +18,9 @@
 
 namespace {
 
+// quotient rows with more entries than QELL are "heavy" (see the row classes below)
+constexpr int QELL = 8, QBIG = 512;
+
 __global__ void k_inter_flags(const int* __restrict__ label, const uint8_t* __restrict__ ebits, int P, int W,
                               int* __restrict__ flag) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -226,7 +229,7 @@ __global__ void k_irls_nodes(const int* __restrict__ row_off, const uint32_t* __
                              const double* __restrict__ pW, const double* __restrict__ pB,
                              double* __restrict__ diag, double* __restrict__ rhs, double* __restrict__ babs) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
+  if (c >= K || row_off[c + 1] - row_off[c] > QELL) return;  // long rows: k_irls_nodes_heavy
   double dg = 0.0, b = 0.0, ba = 0.0;
   for (int j = row_off[c]; j < row_off[c + 1]; ++j) {
     uint32_t e = ent[j];
@@ -239,6 +242,33 @@ __global__ void k_irls_nodes(const int* __restrict__ row_off, const uint32_t* __
   diag[c] = dg;
   rhs[c] = b;
   babs[c] = ba;
+}
+
+// the same for the rows with more than QELL entries, one wavefront each
+__global__ void k_irls_nodes_heavy(const int* __restrict__ row_off, const uint32_t* __restrict__ ent,
+                                   const int* __restrict__ heavy, int nheavy, const double* __restrict__ pW,
+                                   const double* __restrict__ pB, double* __restrict__ diag,
+                                   double* __restrict__ rhs, double* __restrict__ babs) {
+  const int h = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (h >= nheavy) return;
+  const int c = heavy[h];
+  double dg = 0.0, b = 0.0, ba = 0.0;
+  for (int j = row_off[c] + lane; j < row_off[c + 1]; j += 64) {
+    uint32_t e = ent[j];
+    int pid = (int)(e >> 1);
+    dg += pW[pid];
+    double v = (e & 1u) ? pB[pid] : -pB[pid];
+    b += v;
+    ba += fabs(v);
+  }
+  dg = ni::wave_sum(dg);
+  b = ni::wave_sum(b);
+  ba = ni::wave_sum(ba);
+  if (lane == 0) {
+    diag[c] = dg;
+    rhs[c] = b;
+    babs[c] = ba;
+  }
 }
 
 // ------------------------------------------------------ quotient PCG (FP64)
@@ -264,7 +294,6 @@ __global__ void k_q_matrix(const int* __restrict__ row_off, const uint32_t* __re
 // with more entries ("heavy") are listed big first (> QBIG entries: one
 // workgroup each) then mid (one wavefront each); a large component can
 // border a thousand others.
-constexpr int QELL = 8, QBIG = 512;
 constexpr int QUNR = 8;  // entries per lane loaded ahead in a heavy row
 
 struct QMat {
@@ -702,11 +731,9 @@ __global__ void __launch_bounds__(QNT) k_qcg_it(QIter Q, int it) {
 // piece gauge: zero mean of s over every connected piece (root = parent)
 __global__ void k_piece_acc(const int* __restrict__ parent, const double* __restrict__ s, int K,
                             double* __restrict__ psum, int* __restrict__ pcnt) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
-  int r = parent[c];
-  atomicAdd(&psum[r], s[c]);
-  atomicAdd(&pcnt[r], 1);
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool v = c < K;
+  ni::acc_by_key<int>(v, v ? parent[c] : 0, v ? s[c] : 0.0, 1, psum, pcnt);
 }
 
 __global__ void k_piece_apply(const int* __restrict__ parent, double* __restrict__ s, int K,
@@ -869,6 +896,9 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
                                                         a.pB);
   }
   k_irls_nodes<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.row_off, a.ent, a.K, a.pW, a.pB, a.diag, a.rhs, a.babs);
+  if (a.nheavy > 0)
+    k_irls_nodes_heavy<<<ni::ceil_div(a.nheavy, 4), 256, 0, st>>>(a.row_off, a.ent, a.heavy, a.nheavy, a.pW, a.pB,
+                                                                   a.diag, a.rhs, a.babs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // pieces of the weighted quotient graph
