@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--model", default=DEFAULT_MODEL, help="warm-start weights (skipped if absent)")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start comparison")
+    ap.add_argument("--no-pixel-level", action="store_true",
+                    help="skip the pixel-level comparison (theta_c = 0: every pixel its own component)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     a = ap.parse_args()
@@ -183,6 +185,20 @@ def main():
                                     tflops=round(tfl, 2), peak_tflops=BF16_PEAK_TFLOPS,
                                     frac=round(tfl / BF16_PEAK_TFLOPS, 4), dtype="bf16 mfma, fp32 accumulate")
 
+    pixel = None
+    if not a.no_pixel_level:
+        # the paper's plain form: no continuous components, the relative
+        # scales of all pixels by the same IRLS (one warm-up, one timed call)
+        pp = ni.ni_params_default(theta_c_deg=0.0, irls_iters=T)
+        ctx.ni_integrate(normals, mask, cam, pp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = ctx.ni_integrate(normals, mask, cam, pp)
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t0) * 1000.0
+        pixel = dict(ms_per_step=round(ms_p, 3), value=round(n_valid / (ms_p / 1000.0) / 1e6, 3), K=op["K"],
+                     component_speedup=round(ms_p / ms, 2), quot_iters=op["report"]["quot_iters"])
+
     rep = reps[-1]
     k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
     px_iters = rep["fill_large_px_iters"]
@@ -210,6 +226,8 @@ def main():
                 roofline=roof)
     if warm is not None:
         line["warm_start"] = warm
+    if pixel is not None:
+        line["pixel_level"] = pixel
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, dict(theta_c_deg=2.0, irls_iters=T))
     ctx.close()

@@ -8,7 +8,8 @@
 // one V-cycle of an aggregation hierarchy:
 //
 //   aggregation   pairwise handshakes (each free node proposes its strongest
-//                 free neighbour; mutual proposals pair up; three rounds),
+//                 free neighbour, equal weights ordered by a hash of the
+//                 edge; mutual proposals pair up; three rounds),
 //                 then every node left over joins the aggregate of its
 //                 strongest aggregated neighbour; nodes without a weighted
 //                 edge take no part.  Aggregate ids follow the smallest
@@ -364,17 +365,35 @@ __global__ void k_am_active(int n, const int* __restrict__ row_off, const double
   agg[c] = (a && row_off[c + 1] - row_off[c] > AH) ? c : -1;
 }
 
-// strongest neighbour with agg == -1 (want_free) or agg >= 0; ties -> smaller index
+// A symmetric hash of an edge, used to break ties between equal weights.
+// (With ties broken by the smaller index, the uniform weights of a pixel
+// grid make every node propose to the same side and no proposal is ever
+// mutual; a hash of the edge pairs them up like a random matching.)
+__device__ __forceinline__ uint32_t edge_hash(int c, int d) {
+  uint64_t k = ((uint64_t)(uint32_t)min(c, d) << 32) | (uint32_t)max(c, d);
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+
+// strongest neighbour with agg == -1 (want_free) or agg >= 0; ties ->
+// larger edge hash, then smaller index
 __device__ __forceinline__ int strongest(int c, const int* row_off, const int* col, const double* w, const int* agg,
                                          const uint8_t* act, bool want_free) {
   int best = -1;
   double bw = 0.0;
+  uint32_t bh = 0;
   for (int j = row_off[c]; j < row_off[c + 1]; ++j) {
     const int d = col[j];
     const double v = w[j];
     if (v <= 0.0 || d == c || !act[d] || ((agg[d] < 0) != want_free)) continue;
-    if (v > bw || (v == bw && d < best)) {
+    const uint32_t h = edge_hash(c, d);
+    if (v > bw || (v == bw && (h > bh || (h == bh && d < best)))) {
       bw = v;
+      bh = h;
       best = d;
     }
   }
