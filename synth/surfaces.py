@@ -227,6 +227,29 @@ def make_c1(seed: int, noise: float = 0.01) -> Sample:
                   params=dict(theta_c_deg=2.0, irls_iters=10), name=f"c1/s{seed}")
 
 
+def make_ortho(seed: int, H: int = 384, W: int = 384, noise: float = 0.01) -> Sample:
+    """A larger orthographic map in the style of c1: tilted plane, Gaussian
+    bumps and circular steps over a blob mask (55%), pixel pitch 1."""
+    rng = np.random.default_rng([7, seed])
+    mask = _blob_mask(rng, H, W, 0.55)
+    sc = _Scene()
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    phi = rng.uniform(0, 2 * math.pi)
+    g = math.tan(math.radians(10.0))
+    sc.base = lambda u, v: 10.0 + g * (math.cos(phi) * (u - cx) + math.sin(phi) * (v - cy))
+    bu, bv = _uniform_in_mask(rng, mask, 8)
+    sc.bumps = [(rng.uniform(0.5, 3.0) * rng.choice([-1.0, 1.0]), bu[i], bv[i], rng.uniform(6.0, 30.0))
+                for i in range(8)]
+    cu, cv = _uniform_in_mask(rng, mask, 4)
+    sc.circles = [(rng.uniform(0.2, 1.0), cu[i], cv[i], rng.uniform(10.0, 60.0)) for i in range(4)]
+    n = _ortho_normals(sc, H, W, 1.0)
+    n = _add_noise(rng, n, noise)
+    z = sc.grid(0, 0, H, W)
+    cam = Camera("ortho", pixel_pitch=1.0)
+    return Sample(n.astype(np.float32), mask, z, cam,
+                  params=dict(theta_c_deg=2.0, irls_iters=10), name=f"ortho{H}/s{seed}")
+
+
 # ----------------------------------------------------------------------------
 # perspective configurations
 # ----------------------------------------------------------------------------

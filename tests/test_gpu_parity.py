@@ -162,6 +162,26 @@ def knife_edge(s, p, ref):
     return False
 
 
+def fill_sensitive(s, p, ref, seed=0):
+    """True when the oracle's own output moves beyond the parity bound once
+    its exact fill is perturbed, pixel by pixel, by seeded Gaussian noise of
+    standard deviation 1e-6 x max |fill| (the order of an FP32 fill that
+    meets the 1e-6 residual): the relative-scale step then hangs on
+    differences the fill tolerance allows, and the input is not comparable
+    at 1e-4.  Only the oracle runs here."""
+    op = oracle_params(p)
+    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"])
+    lab, K = ref.labels, ref.K
+    zf = O.fill(e, lab, K)
+    v = s.mask > 0
+    amp = 1e-6 * np.max(np.abs(zf[v])) if np.any(v) else 0.0
+    z = zf + amp * np.random.default_rng(seed).standard_normal(zf.shape)
+    S, _, _ = O.irls(e, lab, K, z, op)
+    depth, _, _ = O.finalize(e, lab, z, S)
+    scale = np.max(np.abs(ref.depth[v])) if s.cam.proj == "ortho" else np.abs(ref.depth[v])
+    return bool(np.any(np.abs(depth[v] - ref.depth[v]) > ATOL + RTOL * scale))
+
+
 @pytest.mark.parametrize("name,seed", SAMPLES + [("tiny-persp", 4), ("tiny-ortho", 5), ("tiny-ortho", 6),
                                                  ("tiny-persp", 7)])
 def test_integrate_matches_oracle(ctx, name, seed):
@@ -204,6 +224,30 @@ def test_integrate_large_quotient(ctx, theta):
                         "changes by 0.1%")
         raise
     assert out["report"]["n_inter_edges"] == ref.n_inter_edges
+
+
+@pytest.mark.parametrize("seed,theta", [(0, 2.0), (1, 0.8)])
+def test_integrate_ortho_384(ctx, seed, theta):
+    """A 384^2 orthographic map (additive depth, reading A1); at 0.8 deg
+    its ~25k components take the multigrid quotient path."""
+    s = synth.make_ortho(seed)
+    p = params(theta_c_deg=theta, irls_iters=10)
+    log(f"[integrate ortho 384] seed {seed} theta {theta}")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    ref = O.integrate(s.normals, s.mask, s.cam, oracle_params(p))
+    assert out["K"] == ref.K
+    assert np.array_equal(out["labels"].cpu().numpy(), ref.labels)
+    try:
+        assert_depth_close(out["depth"].cpu().numpy(), ref.depth, s.mask, f"ortho 384 {seed}", True)
+        assert_scale_close(out["log_scale"].cpu().numpy(), ref.log_scale, True)
+    except AssertionError:
+        if knife_edge(s, p, ref):
+            pytest.skip("knife-edge weight cut: the oracle's own output moves beyond 1e-4 when w_cut_rel "
+                        "changes by 0.1%")
+        if fill_sensitive(s, p, ref):
+            pytest.skip("fill-sensitive: the oracle's own output moves beyond 1e-4 when its exact fill is "
+                        "perturbed at the 1e-6 level the fill tolerance allows")
+        raise
 
 
 def test_graph_replay_equals_stream_launches(ctx):
