@@ -23,16 +23,14 @@ hipError_t check_ids(const uint32_t*, int, int, int*, hipStream_t);
 hipError_t fill_segments(const int*, int, int, int*, int*, int*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
                          uint32_t*, uint32_t*, int, int*, int*, int*, hipStream_t, int);
 hipError_t fill_assemble(const uint32_t*, int, int, int, const int*, const uint8_t*, const float*, const float*,
-                         const float*, const int*, double, double, float*, float*, float*, uint32_t*, float*,
-                         float*, hipStream_t);
+                         const float*, const int*, double, double, float4*, float*, float*, hipStream_t);
 hipError_t fill_tier_list(const int*, int, int, int*, int*, int*, int*, int*, hipStream_t);
 hipError_t fill_chunks(const int*, int, int, int*, int*, int*, int*, hipStream_t);
 hipError_t fill_chunk_table(const int*, const int*, const int*, int, int, int*, int*, int*, hipStream_t);
 hipError_t fill_zero_grid(float*, int, hipStream_t);
 hipError_t fill_gather_x0(const uint32_t*, int, const float*, float*, hipStream_t);
-hipError_t fill_small(int, const int*, int, const int*, const float*, const float*, const float*, const uint32_t*,
-                      const float*, const float*, const float*, const uint32_t*, float*, double, int, int, int*,
-                      double*, int*, hipStream_t);
+hipError_t fill_small(int, const int*, int, const int*, const float4*, const float*, const float*, const float*,
+                      const uint32_t*, float*, double, int, int, int*, double*, int*, hipStream_t);
 
 hipError_t large_init(const LargeArgs&, int, hipStream_t);
 hipError_t large_iter(const LargeArgs&, int, hipStream_t);
@@ -92,7 +90,7 @@ struct ni_ctx {
   // grid
   Buf ebits, om_r, om_d, nt, parent, flag, scanv, pos, zgrid, tab, xwarm;
   // compact / sort
-  Buf key, val, skey, spix, ktmp, vtmp, kout2, cwr, cwd, cwu, coff, rhs, dinv, x, r, z, p0, p1, q, w0, w1, s0, s1;
+  Buf key, val, skey, spix, ktmp, vtmp, kout2, cst, rhs, dinv, x, r, z, p0, p1, q, w0, w1, s0, s1;
   // components
   Buf comp_off, fsmall, flarge, nchunk, spos, lpos, cbase, small_list, large_list, cnt, done, iters, active,
       rho, bb, tol2, alpha, beta, rr, relres, S, qs, qr, qz, qp0, qp1, qq, diag, qrhs, babs, psum, pcnt, qparent,
@@ -116,7 +114,7 @@ struct ni_ctx {
 
   ni_ctx() {
     Buf* all[] = {&ebits, &om_r, &om_d, &nt, &parent, &flag, &scanv, &pos, &zgrid, &tab, &xwarm, &key, &val,
-                  &skey, &spix, &ktmp, &vtmp, &kout2, &cwr, &cwd, &cwu, &coff, &rhs, &dinv, &x, &r, &z, &p0,
+                  &skey, &spix, &ktmp, &vtmp, &kout2, &cst, &rhs, &dinv, &x, &r, &z, &p0,
                   &p1, &q, &w0, &w1, &s0, &s1, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
                   &cnt, &done, &iters, &active, &rho, &bb, &tol2, &alpha, &beta, &rr, &relres, &S, &qs, &qr,
                   &qz, &qp0, &qp1, &qq, &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
@@ -369,10 +367,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   const bool persp = pb.cam.proj == NI_PERSP;
   const double g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
   const double g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
-  float* cwr = ensure<float>(c, c->cwr, N);
-  float* cwd = ensure<float>(c, c->cwd, N);
-  float* cwu = ensure<float>(c, c->cwu, N);
-  uint32_t* coff = ensure<uint32_t>(c, c->coff, N);
+  float4* cst = ensure<float4>(c, c->cst, N);  // stencil: w_right, w_down, w_up, packed offsets
   float* rhs = ensure<float>(c, c->rhs, N);
   float* dinv = ensure<float>(c, c->dinv, N);
   float* x = ensure<float>(c, c->x, N);
@@ -381,8 +376,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   mark(c, 3);
   check(c,
         nil::fill_assemble(cpix, N, W, P, labels, ptr<uint8_t>(c->ebits), ptr<float>(c->nt), ptr<float>(c->om_r),
-                           ptr<float>(c->om_d), ptr<int>(c->pos), g2fx, g2fy, cwr, cwd, cwu, coff, rhs, dinv,
-                           c->stream),
+                           ptr<float>(c->om_d), ptr<int>(c->pos), g2fx, g2fy, cst, rhs, dinv, c->stream),
         "assemble");
   size_t K1 = (size_t)K + 1;
   int* tflag = ensure<int>(c, c->fsmall, K1);
@@ -426,7 +420,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     a.tol2 = ensure<double>(c, c->tol2, K1);
     a.rr = rr; a.bb = bb; a.iters = iters;
     a.active = misc(c) + M_ACTIVE; a.stats = misc(c) + M_STATS;
-    a.cwr = cwr; a.cwd = cwd; a.cwu = cwu; a.rhs = rhs; a.dinv = dinv; a.coff = coff;
+    a.cst = cst; a.rhs = rhs; a.dinv = dinv;
     a.x = x;
     a.p = ensure<float>(c, c->p0, N);
     a.r0 = ensure<float>(c, c->r, N);
@@ -487,7 +481,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
   mark(c, 5);
   for (int t = 1; t <= 3; ++t)
-    check(c, nil::fill_small(t, lists + (t - 1) * K1, ntier[t - 1], comp_off, cwr, cwd, cwu, coff, rhs, dinv, x,
+    check(c, nil::fill_small(t, lists + (t - 1) * K1, ntier[t - 1], comp_off, cst, rhs, dinv, x,
                              cpix, zout, pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, iters, relres, misc(c) + M_STATS,
                              c->stream),
           "fill small");

@@ -131,8 +131,8 @@ struct LargeArgs {
   const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start, *chunk_end;
   double *part, *gam, *alp, *tol2, *rr, *bb;
   int *iters, *active, *stats;
-  const float *cwr, *cwd, *cwu, *rhs, *dinv;
-  const uint32_t* coff;
+  const float4* cst;  // per pixel (w_right, w_down, w_up, packed offsets)
+  const float *rhs, *dinv;
   float *x, *p, *r0, *r1, *w0, *w1, *s0, *s1;
   int nchunks, K;
   double rtol;

@@ -77,8 +77,7 @@ __global__ void k_assemble(const uint32_t* __restrict__ cpix, int N, int W, int 
                            const int* __restrict__ label, const uint8_t* __restrict__ ebits,
                            const float* __restrict__ nt, const float* __restrict__ om_r,
                            const float* __restrict__ om_d, const int* __restrict__ pos, double g2fx,
-                           double g2fy, float* __restrict__ cwr, float* __restrict__ cwd,
-                           float* __restrict__ cwu, uint32_t* __restrict__ coff,
+                           double g2fy, float4* __restrict__ cst,
                            float* __restrict__ rhs, float* __restrict__ dinv) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -115,10 +114,7 @@ __global__ void k_assemble(const uint32_t* __restrict__ cpix, int N, int W, int 
   // weights are rounded to FP32 first so that the stored matrix is exactly
   // symmetric (w_l of pixel i is bitwise the w_r of pixel i-1)
   const float fr = (float)wr, fl = (float)wl, fd = (float)wd, fu = (float)wu;
-  cwr[i] = fr;
-  cwd[i] = fd;
-  cwu[i] = fu;
-  coff[i] = ou | (od << 16);
+  cst[i] = make_float4(fr, fd, fu, __uint_as_float(ou | (od << 16)));
   rhs[i] = (float)b;
   double dg = (double)fr + (double)fl + (double)fd + (double)fu;
   dinv[i] = dg > 0 ? (float)(1.0 / dg) : 0.f;
@@ -181,15 +177,14 @@ struct Stencil {
   int od, ou;
 };
 
-__device__ __forceinline__ Stencil load_stencil(const float* __restrict__ cwr, const float* __restrict__ cwd,
-                                                const float* __restrict__ cwu,
-                                                const uint32_t* __restrict__ coff, int i, int lo) {
+__device__ __forceinline__ Stencil load_stencil(const float4* __restrict__ cst, int i, int lo) {
   Stencil s;
-  s.wr = cwr[i];
-  s.wl = i > lo ? cwr[i - 1] : 0.f;
-  s.wd = cwd[i];
-  s.wu = cwu[i];
-  uint32_t o = coff[i];
+  const float4 v = cst[i];
+  s.wr = v.x;
+  s.wl = i > lo ? cst[i - 1].x : 0.f;
+  s.wd = v.y;
+  s.wu = v.z;
+  uint32_t o = __float_as_uint(v.w);
   s.ou = (int)(o & OFF_MASK);
   s.od = (int)(o >> 16);
   return s;
@@ -201,8 +196,7 @@ __device__ __forceinline__ Stencil load_stencil(const float* __restrict__ cwr, c
 // global traffic inside the iteration loop.
 template <int NT, int PPT>
 __global__ void __launch_bounds__(NT) k_fill_small(
-    const int* __restrict__ list, const int* __restrict__ comp_off, const float* __restrict__ cwr,
-    const float* __restrict__ cwd, const float* __restrict__ cwu, const uint32_t* __restrict__ coff,
+    const int* __restrict__ list, const int* __restrict__ comp_off, const float4* __restrict__ cst,
     const float* __restrict__ rhs, const float* __restrict__ dinv, const float* __restrict__ x0,
     const uint32_t* __restrict__ cpix, float* __restrict__ zgrid, double rtol, int maxit, int warm,
     int* __restrict__ iters, double* __restrict__ relres, int* __restrict__ stats) {
@@ -219,7 +213,7 @@ __global__ void __launch_bounds__(NT) k_fill_small(
   for (int k = 0; k < PPT; ++k) {
     const int j = threadIdx.x + k * NT;
     if (j < n) {
-      Stencil s = load_stencil(cwr, cwd, cwu, coff, lo + j, lo);
+      Stencil s = load_stencil(cst, lo + j, lo);
       wr[k] = s.wr; wl[k] = s.wl; wd[k] = s.wd; wu[k] = s.wu; od[k] = s.od; ou[k] = s.ou;
       di[k] = dinv[lo + j];
       r[k] = rhs[lo + j];
@@ -384,8 +378,8 @@ struct LargeState {
   int* iters;             // [K]
   int* active;            // [2] components still iterating, by iteration parity
   int* stats;             // [0] not converged, [1] warm fallbacks
-  const float *cwr, *cwd, *cwu, *rhs, *dinv;
-  const uint32_t* coff;
+  const float4* cst;  // per pixel (w_right, w_down, w_up, packed offsets)
+  const float *rhs, *dinv;
   float *x, *p, *r0, *r1, *w0, *w1, *s0, *s1;  // r0 = r, w0 = q, s0/s1 = p by parity
   int nchunks;
   double rtol;
@@ -425,7 +419,7 @@ __global__ void __launch_bounds__(LNT) k_lg_init_a(LargeState S) {
   const int clo = S.comp_off[c], hi = S.comp_off[c + 1];
   double v[3] = {0.0, 0.0, 0.0};
   for (int i = lo + threadIdx.x; i < S.chunk_end[ch]; i += LNT) {
-    Stencil s = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, i, clo);
+    Stencil s = load_stencil(S.cst, i, clo);
     const float xi = S.x[i];
     float q = 0.f;
     if (s.wr != 0.f) q += s.wr * (xi - S.x[i + 1]);
@@ -515,7 +509,7 @@ __global__ void __launch_bounds__(LNT) k_lg_a(LargeState S, int it, int K) {
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
       ix[u] = i0 + u * LNT < end ? i0 + u * LNT : lo;
-      st[u] = load_stencil(S.cwr, S.cwd, S.cwu, S.coff, ix[u], clo);
+      st[u] = load_stencil(S.cst, ix[u], clo);
     }
     float pc[LU], pr[LU], pl[LU], pd[LU], pu[LU];
 #pragma unroll
@@ -669,11 +663,11 @@ hipError_t fill_segments(const int* label, int P, int K, int* flag, int* vpos, i
 
 hipError_t fill_assemble(const uint32_t* cpix, int N, int W, int P, const int* label,
                          const uint8_t* ebits, const float* nt, const float* om_r, const float* om_d,
-                         const int* pos, double g2fx, double g2fy, float* cwr, float* cwd, float* cwu,
-                         uint32_t* coff, float* rhs, float* dinv, hipStream_t st) {
+                         const int* pos, double g2fx, double g2fy, float4* cst, float* rhs, float* dinv,
+                         hipStream_t st) {
   if (N <= 0) return hipSuccess;
   k_assemble<<<ni::ceil_div(N, 256), 256, 0, st>>>(cpix, N, W, P, label, ebits, nt, om_r, om_d, pos, g2fx,
-                                                   g2fy, cwr, cwd, cwu, coff, rhs, dinv);
+                                                   g2fy, cst, rhs, dinv);
   return hipGetLastError();
 }
 
@@ -717,19 +711,19 @@ hipError_t fill_gather_x0(const uint32_t* cpix, int N, const float* x0g, float* 
   return hipGetLastError();
 }
 
-hipError_t fill_small(int tier, const int* list, int n, const int* comp_off, const float* cwr, const float* cwd,
-                      const float* cwu, const uint32_t* coff, const float* rhs, const float* dinv,
+hipError_t fill_small(int tier, const int* list, int n, const int* comp_off, const float4* cst, const float* rhs,
+                      const float* dinv,
                       const float* x0, const uint32_t* cpix, float* zgrid, double rtol, int maxit, int warm,
                       int* iters, double* relres, int* stats, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (tier == 1)
-    k_fill_small<64, 4><<<n, 64, 0, st>>>(list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid, rtol,
+    k_fill_small<64, 4><<<n, 64, 0, st>>>(list, comp_off, cst, rhs, dinv, x0, cpix, zgrid, rtol,
                                           maxit, warm, iters, relres, stats);
   else if (tier == 2)
-    k_fill_small<256, 8><<<n, 256, 0, st>>>(list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid, rtol,
+    k_fill_small<256, 8><<<n, 256, 0, st>>>(list, comp_off, cst, rhs, dinv, x0, cpix, zgrid, rtol,
                                             maxit, warm, iters, relres, stats);
   else
-    k_fill_small<1024, 8><<<n, 1024, 0, st>>>(list, comp_off, cwr, cwd, cwu, coff, rhs, dinv, x0, cpix, zgrid,
+    k_fill_small<1024, 8><<<n, 1024, 0, st>>>(list, comp_off, cst, rhs, dinv, x0, cpix, zgrid,
                                               rtol, maxit, warm, iters, relres, stats);
   return hipGetLastError();
 }
@@ -739,7 +733,7 @@ static LargeState to_state(const LargeArgs& a) {
   S.comp_off = a.comp_off; S.cbase = a.cbase; S.nchunk = a.nchunk; S.chunk_comp = a.chunk_comp;
   S.chunk_start = a.chunk_start; S.chunk_end = a.chunk_end; S.part = a.part; S.gam = a.gam; S.alp = a.alp; S.tol2 = a.tol2;
   S.rr = a.rr; S.bb = a.bb; S.iters = a.iters; S.active = a.active; S.stats = a.stats;
-  S.cwr = a.cwr; S.cwd = a.cwd; S.cwu = a.cwu; S.rhs = a.rhs; S.dinv = a.dinv; S.coff = a.coff;
+  S.cst = a.cst; S.rhs = a.rhs; S.dinv = a.dinv;
   S.x = a.x; S.p = a.p; S.r0 = a.r0; S.r1 = a.r1; S.w0 = a.w0; S.w1 = a.w1; S.s0 = a.s0; S.s1 = a.s1;
   S.nchunks = a.nchunks; S.rtol = a.rtol; S.maxit = a.maxit;
   return S;

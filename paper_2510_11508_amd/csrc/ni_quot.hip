@@ -919,7 +919,11 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
     // multigrid-preconditioned CG on a hierarchy built from this step's
     // weights (the cut set and the weights change from step to step)
     e = hipGetLastError();
-    if (e == hipSuccess) e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
+    // the uniform-weight steps (t < align) share one matrix: the hierarchy of
+    // step 0 serves them all
+    const bool same_as_previous = t > 0 && t < a.align;
+    if (e == hipSuccess && !same_as_previous)
+      e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
     if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
     if (e == hipSuccess)
       e = amg_solve(a.amg, a.rhs, a.babs, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag, a.graphs != 0, st);
