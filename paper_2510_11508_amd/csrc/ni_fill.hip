@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(NT) k_fill_small(
 // chunks: up to 256 per component, at least 512 pixels each, a multiple
 // of the workgroup size long (so mid-size problems still fill the GPU while
 // the per-workgroup partial sums stay short)
-constexpr int LNT = 256, LCH = 512, LMAXCH = 256;
+constexpr int LNT = 256, LCH = 512, LMAXCH = 512;
 constexpr int LU = 4;  // pixels per thread whose loads are issued together
 
 struct LargeState {
