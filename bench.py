@@ -209,7 +209,8 @@ def main():
     traffic = traffic_record(a.workload)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_lg_a + k_lg_b (one CG iteration of the large components)",
+                kernel=("k_lg_p + k_lg_q + k_lg_b" if rep["fill_split"] else "k_lg_a + k_lg_b")
+                + " (one CG iteration of the large components)",
                 bytes_per_px_iter=CG_BYTES_PER_PX_ITER,
                 px_iters_per_iteration=round(px_iters / launches, 1), iterations=launches,
                 ms_per_iteration=round(launch_ms, 5))
@@ -221,7 +222,9 @@ def main():
                             K=out["K"], H=int(s.mask.shape[0]), W=int(s.mask.shape[1])),
                 stages_ms=stage_ms(reps),
                 fill=dict(iters_max=rep["fill_iters_max"], n_small=rep["n_small"], n_large=rep["n_large"],
-                          px_iters=rep["fill_px_iters"], max_relres=rep["fill_max_relres"]),
+                          px_iters=rep["fill_px_iters"], max_relres=rep["fill_max_relres"],
+                          tuned_schedule=dict(chunk_px=rep["fill_chunk"],
+                                              launches_per_iteration=3 if rep["fill_split"] else 2)),
                 quot_iters=rep["quot_iters"],
                 roofline=roof)
     if warm is not None:

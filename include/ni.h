@@ -106,6 +106,9 @@ typedef struct {
         ms_fill_small, ms_fill_large, ms_irls, ms_finalize, ms_total;
   float ms_large_kernel;  /* the large-path CG iteration launches alone
                              (HIP events around each batch of launches)    */
+  int32_t fill_chunk;     /* autotuned schedule of the large path: shortest */
+  int32_t fill_split;     /* chunk (px), and 1 if p is materialised (three
+                             launches per iteration) instead of recomputed */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;

@@ -47,7 +47,8 @@ class ni_report(C.Structure):
                 ("ms_setup", C.c_float), ("ms_label", C.c_float), ("ms_segments", C.c_float),
                 ("ms_assemble", C.c_float), ("ms_warm", C.c_float), ("ms_fill_small", C.c_float),
                 ("ms_fill_large", C.c_float), ("ms_irls", C.c_float), ("ms_finalize", C.c_float),
-                ("ms_total", C.c_float), ("ms_large_kernel", C.c_float)]
+                ("ms_total", C.c_float), ("ms_large_kernel", C.c_float), ("fill_chunk", C.c_int32),
+                ("fill_split", C.c_int32)]
 
     def as_dict(self):
         d = {}

@@ -108,8 +108,8 @@ struct ni_ctx {
   nil::Amg* amg = nullptr;
   // autotuned schedule of the large fill path: shortest chunk per block,
   // and the map size class it was tuned for
-  int fill_chunk = 0, fill_chunk_key = -1;
-  float tune_ms[4] = {};
+  int fill_chunk = 0, fill_split = 0, fill_chunk_key = -1;
+  float tune_ms[8] = {};
 
 
   ni_ctx() {
@@ -430,21 +430,24 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     a.s0 = ensure<float>(c, c->s0, N);
     a.s1 = ensure<float>(c, c->s1, N);
     a.nchunks = n_chunks; a.K = K; a.rtol = pb.prm.cg_rtol; a.maxit = pb.prm.cg_max_iter;
+    a.split = c->fill_split;
     return a;
   };
   // Autotuner: the first time a map of this size class reaches the large
-  // path, every candidate chunk length runs a few CG iterations from a zero
-  // start and the fastest per iteration is kept for the context.  The
-  // probe's vectors are reset before the real solve.
+  // path, every candidate schedule (chunk length x two- or three-launch
+  // iteration) runs a few CG iterations from a zero start and the fastest
+  // per iteration is kept for the context.  The probe's vectors are reset
+  // before the real solve.
   int key = 0;
   while ((1ll << key) < (long long)N) ++key;
   if (n_large > 0 && c->fill_chunk_key != key) {
     const int cand[4] = {512, 1024, 2048, 4096};
     const int probe = 8;
     float best = 1e30f;
-    int pick = cand[2];
-    for (int k = 0; k < 4; ++k) {
-      chunks(cand[k]);
+    int pick = cand[2], pick_split = 0;
+    for (int k = 0; k < 8; ++k) {
+      chunks(cand[k & 3]);
+      c->fill_split = k >> 2;
       nil::LargeArgs a = large_args();
       check(c, nil::fill_gather_x0(cpix, N, nullptr, x, c->stream), "gather");
       check(c, hipMemsetAsync(a.active, 0, 2 * sizeof(int), c->stream), "memset");
@@ -457,10 +460,12 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
       c->tune_ms[k] = ms;
       if (ms < best) {
         best = ms;
-        pick = cand[k];
+        pick = cand[k & 3];
+        pick_split = k >> 2;
       }
     }
     c->fill_chunk = pick;
+    c->fill_split = pick_split;
     c->fill_chunk_key = key;
   }
   chunks(c->fill_chunk);
@@ -551,6 +556,8 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->ms_fill_small = ev_ms(c, 5, 6);
     rep->ms_fill_large = ev_ms(c, 6, 7);
     rep->ms_large_kernel = large_kernel_ms;
+    rep->fill_chunk = n_large > 0 ? c->fill_chunk : 0;
+    rep->fill_split = n_large > 0 ? c->fill_split : 0;
   }
   if (notconv > 0) {
     c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";

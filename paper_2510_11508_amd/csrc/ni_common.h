@@ -137,6 +137,7 @@ struct LargeArgs {
   int nchunks, K;
   double rtol;
   int maxit;
+  int split;  // 0: two launches per CG iteration; 1: three (p materialised)
 };
 
 // aggregation multigrid for the quotient systems (ni_amg.hip)

@@ -540,6 +540,95 @@ __global__ void __launch_bounds__(LNT) k_lg_a(LargeState S, int it, int K) {
   put_partials(S, ch, 0, v, 4);
 }
 
+// Three-launch form of the same iteration (chosen by the autotuner where it
+// is faster, on the largest maps): P_i materialises p_i, then Q_i applies
+// the stencil to p_i alone, so a neighbour costs one load instead of three
+// at the price of one more launch and 4 more bytes per pixel.
+// P_i: p_i = D^-1 r + beta p_{i-1}, elementwise (reads slot 1)
+__global__ void __launch_bounds__(LNT) k_lg_p(LargeState S, int it, int K) {
+  __shared__ double red[8 * (LNT / 64)];
+  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
+  double g[4];
+  comp_partials(S, c, 1, g, red);
+  const double rho = g[0], rri = g[1];
+  const bool conv = (S.bb[c] == 0.0) || (rri <= S.tol2[c]);
+  if (conv || it >= S.maxit) return;
+  const double beta = it == 0 ? 0.0 : rho / S.gam[(size_t)((it - 1) & 1) * K + c];
+  if (threadIdx.x == 0 && ch == S.cbase[c]) S.gam[(size_t)(it & 1) * K + c] = rho;
+  const float bt = (float)beta;
+  const float* pold = (it & 1) ? S.s0 : S.s1;
+  float* pnew = (it & 1) ? S.s1 : S.s0;
+  const int end = S.chunk_end[ch];
+  for (int i0 = lo + threadIdx.x; i0 < end; i0 += LNT * LU) {
+    float d[LU], r[LU], po[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int i = i0 + u * LNT < end ? i0 + u * LNT : lo;
+      d[u] = S.dinv[i];
+      r[u] = S.r0[i];
+      po[u] = pold[i];
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u)
+      if (i0 + u * LNT < end) pnew[i0 + u * LNT] = d[u] * r[u] + bt * po[u];
+  }
+}
+
+// Q_i: q = L p_i and (p, q) -> slot 0 (reads slot 1 for the convergence test)
+__global__ void __launch_bounds__(LNT) k_lg_q(LargeState S, int it, int K) {
+  __shared__ double red[8 * (LNT / 64)];
+  const int ch = blockIdx.x, c = S.chunk_comp[ch], lo = S.chunk_start[ch];
+  const int clo = S.comp_off[c];
+  double g[4];
+  comp_partials(S, c, 1, g, red);
+  const double rri = g[1];
+  const bool conv = (S.bb[c] == 0.0) || (rri <= S.tol2[c]);
+  if (conv || it >= S.maxit) {
+    put_partials(S, ch, 0, g, 0);
+    if (threadIdx.x == 0 && ch == S.cbase[c]) {
+      S.rr[c] = rri;
+      if (!conv && it == S.maxit) atomicAdd(&S.stats[0], 1);
+    }
+    return;
+  }
+  const float* pp = (it & 1) ? S.s1 : S.s0;  // p_i
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int end = S.chunk_end[ch];
+  for (int i0 = lo + threadIdx.x; i0 < end; i0 += LNT * LU) {
+    int ix[LU];
+    Stencil st[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      ix[u] = i0 + u * LNT < end ? i0 + u * LNT : lo;
+      st[u] = load_stencil(S.cst, ix[u], clo);
+    }
+    float pc[LU], pr[LU], pl[LU], pd[LU], pu[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int i = ix[u];
+      pc[u] = pp[i];
+      pr[u] = pp[st[u].wr != 0.f ? i + 1 : i];
+      pl[u] = pp[st[u].wl != 0.f ? i - 1 : i];
+      pd[u] = pp[st[u].wd != 0.f ? i + st[u].od : i];
+      pu[u] = pp[st[u].wu != 0.f ? i - st[u].ou : i];
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      if (i0 + u * LNT < end) {
+        float q = 0.f;
+        q += st[u].wr * (pc[u] - pr[u]);
+        q += st[u].wl * (pc[u] - pl[u]);
+        q += st[u].wd * (pc[u] - pd[u]);
+        q += st[u].wu * (pc[u] - pu[u]);
+        S.w0[ix[u]] = q;
+        v[2] += (double)pc[u] * q;
+      }
+    }
+  }
+  ni::block_sum<4>(v, red + 4 * (LNT / 64));
+  put_partials(S, ch, 0, v, 4);
+}
+
 // B_i: launch 2i+1, writes slot 1, reads slot 0
 __global__ void __launch_bounds__(LNT) k_lg_b(LargeState S, int it, int K) {
   __shared__ double red[8 * (LNT / 64)];
@@ -754,7 +843,12 @@ hipError_t large_init(const LargeArgs& a, int warm, hipStream_t st) {
 // one CG iteration = launches A_it and B_it
 hipError_t large_iter(const LargeArgs& a, int it, hipStream_t st) {
   LargeState S = to_state(a);
-  k_lg_a<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
+  if (a.split) {
+    k_lg_p<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
+    k_lg_q<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
+  } else {
+    k_lg_a<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
+  }
   k_lg_b<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
   return hipGetLastError();
 }
