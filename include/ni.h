@@ -115,7 +115,7 @@ typedef struct ni_ctx ni_ctx;
 
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
  * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-4, cg_rtol 1e-6,
- * cg_max_iter 50000, q_rtol 1e-12, q_max_iter 20000, zero start, no
+ * cg_max_iter 50000, q_rtol 1e-10, q_max_iter 20000, zero start, no
  * graphs.
  * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);

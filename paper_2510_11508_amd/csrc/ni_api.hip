@@ -760,7 +760,7 @@ ni_status ni_params_default(ni_params* p) {
   p->w_cut_rel = 1e-4;
   p->cg_rtol = 1e-6;
   p->cg_max_iter = 50000;
-  p->q_rtol = 1e-12;
+  p->q_rtol = 1e-10;
   p->q_max_iter = 20000;
   p->warm_start = 0;
   p->graphs = 0;
