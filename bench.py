@@ -7,12 +7,18 @@ system stopped at ||r_c|| <= 1e-6 ||b_c||.  Prints ONE JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
 
 The roofline object describes the batched CG iteration of the large fill
-components, two launches per iteration (k_lg_a, k_lg_b): algorithmic bytes
-= 64 B per active pixel per CG iteration (k_lg_a reads r, 1/diag, p_{i-1},
-three weights and the packed neighbour offsets and writes p_i and q;
-k_lg_b reads r, q, x, p_i, 1/diag and writes x and r), times the active
-pixel-iterations of one iteration, over the event-timed duration of one
-iteration's two launches.  The CPU baseline is the FP64 oracle on this host.
+components.  The library's autotuner runs it either as two launches
+(k_lg_a: p_i = D^-1 r + beta p_{i-1} recomputed at the pixel and its
+neighbours, q = L p_i; k_lg_b: x and r updates) or as three (k_lg_p
+materialises p_i, k_lg_q applies the stencil, k_lg_b).  Algorithmic bytes
+= 64 B per active pixel per CG iteration: the two-launch form reads r,
+1/diag, p_{i-1} and the packed stencil (16 B) and writes p_i and q, then
+reads r, q, x, p_i, 1/diag and writes x and r (the three-launch form moves
+4 B more, not counted).  achieved = 64 B x the active pixel-iterations of
+one iteration / the event-timed duration of that iteration's launches.
+traffic = calibrated FETCH_SIZE + WRITE_SIZE per iteration from committed
+counter runs (profiles/fill_cg_traffic_<workload>.json), while they match
+the kernel source.  The CPU baseline is the FP64 oracle on this host.
 
 With a trained warm-start model (paper_2510_11508_amd/weights/, or
 --model) the same map is also integrated with warm_start = 1 and the
