@@ -64,16 +64,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_record(workload):
+def traffic_record(workload, chunk, split):
     """HBM bytes per launch of the fill CG kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
+    counter runs, if they were taken on the current kernel source with the
+    schedule this run uses."""
     path = os.path.join(ROOT, "profiles", f"fill_cg_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_hash") != kernel_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("schedules", {}).get(f"{chunk}:{split}", {}).get("bytes_per_launch")
 
 
 def cpu_baseline(sample, params, budget_s=12.0):
@@ -104,6 +105,8 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start comparison")
     ap.add_argument("--no-pixel-level", action="store_true",
                     help="skip the pixel-level comparison (theta_c = 0: every pixel its own component)")
+    ap.add_argument("--fill-schedule", default=None, metavar="CHUNK:SPLIT",
+                    help="fix the large-path fill schedule (e.g. 4096:1) instead of autotuning it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     a = ap.parse_args()
@@ -120,7 +123,11 @@ def main():
 
     s = synth.make(a.workload, a.seed)
     T = int(s.params["irls_iters"])
-    p = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T)
+    sched = {}
+    if a.fill_schedule:
+        ch, sp = a.fill_schedule.split(":")
+        sched = dict(fill_chunk=int(ch), fill_split=int(sp))
+    p = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T, **sched)
     dev = torch.device("cuda:0")
     normals = torch.from_numpy(s.normals).to(dev)
     mask = torch.from_numpy(s.mask).to(dev)
@@ -212,7 +219,7 @@ def main():
     launch_bytes = CG_BYTES_PER_PX_ITER * px_iters / launches
     launch_ms = k_ms / launches
     achieved = launch_bytes / (launch_ms / 1000.0) / 1e9 if k_ms > 0 else 0.0
-    traffic = traffic_record(a.workload)
+    traffic = traffic_record(a.workload, rep["fill_chunk"], rep["fill_split"])
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel=("k_lg_p + k_lg_q + k_lg_b" if rep["fill_split"] else "k_lg_a + k_lg_b")

@@ -83,6 +83,12 @@ typedef struct {
   int32_t graphs;       /* 1: the multigrid quotient CG replays each iteration's
                            launches from a HIP graph; 0: plain stream launches
                            (same kernels, same results) */
+  int32_t fill_chunk;   /* large-path schedule: 0 autotunes it per map size
+                           class; 512, 1024, 2048 or 4096 fixes the shortest
+                           chunk (px) per block ...                          */
+  int32_t fill_split;   /* ... and, with fill_chunk set, 1 materialises p
+                           (three launches per CG iteration), 0 recomputes it
+                           (two launches)                                    */
 } ni_params;
 
 typedef struct {
@@ -116,7 +122,7 @@ typedef struct ni_ctx ni_ctx;
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
  * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-4, cg_rtol 1e-6,
  * cg_max_iter 50000, q_rtol 1e-10, q_max_iter 20000, zero start, no
- * graphs.
+ * graphs, autotuned fill schedule.
  * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);
 

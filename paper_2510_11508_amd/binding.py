@@ -33,7 +33,7 @@ class ni_params(C.Structure):
                 ("out_U", C.c_double), ("outlier_mode", C.c_int32), ("delta_e_max", C.c_double),
                 ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("fill_chunk", C.c_int32), ("fill_split", C.c_int32)]
 
 
 class ni_report(C.Structure):

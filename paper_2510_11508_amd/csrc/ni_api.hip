@@ -218,6 +218,10 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
   if (prm->outlier_mode < 0 || prm->outlier_mode > 2) return bad("outlier_mode must be 0, 1 or 2");
   if (!(prm->w_cut_rel >= 0 && prm->w_cut_rel < 1)) return bad("w_cut_rel must be in [0, 1)");
   if (!(prm->bini_k > 0)) return bad("bini_k must be > 0");
+  if (prm->fill_chunk != 0 && prm->fill_chunk != 512 && prm->fill_chunk != 1024 && prm->fill_chunk != 2048 &&
+      prm->fill_chunk != 4096)
+    return bad("fill_chunk must be 0, 512, 1024, 2048 or 4096");
+  if (prm->fill_split != 0 && prm->fill_split != 1) return bad("fill_split must be 0 or 1");
   if (prm->warm_start && !c->unet) {
     c->err = "warm_start needs a model (ni_unet_load)";
     return NI_E_MODEL;
@@ -440,7 +444,12 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   // before the real solve.
   int key = 0;
   while ((1ll << key) < (long long)N) ++key;
-  if (n_large > 0 && c->fill_chunk_key != key) {
+  if (n_large > 0 && pb.prm.fill_chunk > 0) {
+    // a fixed schedule; the next autotuned call tunes afresh
+    c->fill_chunk = pb.prm.fill_chunk;
+    c->fill_split = pb.prm.fill_split;
+    c->fill_chunk_key = -1;
+  } else if (n_large > 0 && c->fill_chunk_key != key) {
     const int cand[4] = {512, 1024, 2048, 4096};
     const int probe = 8;
     float best = 1e30f;
@@ -764,6 +773,8 @@ ni_status ni_params_default(ni_params* p) {
   p->q_max_iter = 20000;
   p->warm_start = 0;
   p->graphs = 0;
+  p->fill_chunk = 0;
+  p->fill_split = 0;
   return NI_OK;
 }
 

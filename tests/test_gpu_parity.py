@@ -125,6 +125,26 @@ def test_fill_matches_oracle(ctx, name, seed):
     assert rep["fill_notconv"] == 0
 
 
+@pytest.mark.parametrize("chunk", [512, 1024, 2048, 4096])
+@pytest.mark.parametrize("split", [0, 1])
+def test_fill_fixed_schedules(ctx, chunk, split):
+    """Every schedule the autotuner chooses between, fixed by the caller,
+    solves the large components to the same bound."""
+    s = sample("c2", 0)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0)
+    lab, K = O.labels(e)
+    zref = O.fill(e, lab, K)
+    log(f"[fill schedule] c2 seed 0 chunk {chunk} split {split}")
+    z, rep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K,
+                         params(fill_chunk=chunk, fill_split=split))
+    assert rep["n_large"] > 0
+    assert (rep["fill_chunk"], rep["fill_split"]) == (chunk, split)
+    z = z.cpu().numpy().astype(np.float64)
+    v = s.mask > 0
+    assert np.abs(z[v] - zref[v]).max() <= 1e-6 + 1e-4
+    assert rep["fill_notconv"] == 0
+
+
 # ------------------------------------------------------------------- IRLS
 @pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0), ("tiny-persp", 1), ("tiny-ortho", 0)])
 @pytest.mark.parametrize("mode", [1, 2, 0])
@@ -343,7 +363,7 @@ def test_bad_arguments(ctx):
     import paper_2510_11508_amd as ni
     s = synth.tiny(0)
     for kw in [dict(connectivity=8), dict(irls_iters=0), dict(outlier_mode=5), dict(out_L=1e-2),
-               dict(warm_start=1)]:
+               dict(warm_start=1), dict(fill_chunk=300), dict(fill_chunk=1024, fill_split=2)]:
         log(f"[edge] bad params {kw}")
         with pytest.raises(ni.NIError) as ex:
             ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), params(**kw))
