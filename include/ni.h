@@ -89,6 +89,10 @@ typedef struct {
   int32_t fill_split;   /* ... and, with fill_chunk set, 1 materialises p
                            (three launches per CG iteration), 0 recomputes it
                            (two launches)                                    */
+  int32_t fill_precond; /* preconditioner of the large components' CG:
+                           1 multigrid (aggregates of 2x2 pixel blocks per
+                           component, V(1,1) cycle), 0 Jacobi (the chunked
+                           schedule above)                                   */
 } ni_params;
 
 typedef struct {
@@ -115,6 +119,8 @@ typedef struct {
   int32_t fill_chunk;     /* autotuned schedule of the large path: shortest */
   int32_t fill_split;     /* chunk (px), and 1 if p is materialised (three
                              launches per iteration) instead of recomputed */
+  int32_t fill_mg_levels; /* levels of the fill multigrid (0: Jacobi path)  */
+  float ms_fill_mg_build; /* its level-0 system and hierarchy build         */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;
@@ -122,7 +128,7 @@ typedef struct ni_ctx ni_ctx;
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
  * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-4, cg_rtol 1e-6,
  * cg_max_iter 50000, q_rtol 1e-10, q_max_iter 20000, zero start, no
- * graphs, autotuned fill schedule.
+ * graphs, autotuned fill schedule, multigrid fill preconditioner.
  * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);
 

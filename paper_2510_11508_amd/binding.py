@@ -33,7 +33,8 @@ class ni_params(C.Structure):
                 ("out_U", C.c_double), ("outlier_mode", C.c_int32), ("delta_e_max", C.c_double),
                 ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
-                ("graphs", C.c_int32), ("fill_chunk", C.c_int32), ("fill_split", C.c_int32)]
+                ("graphs", C.c_int32), ("fill_chunk", C.c_int32), ("fill_split", C.c_int32),
+                ("fill_precond", C.c_int32)]
 
 
 class ni_report(C.Structure):
@@ -48,7 +49,7 @@ class ni_report(C.Structure):
                 ("ms_assemble", C.c_float), ("ms_warm", C.c_float), ("ms_fill_small", C.c_float),
                 ("ms_fill_large", C.c_float), ("ms_irls", C.c_float), ("ms_finalize", C.c_float),
                 ("ms_total", C.c_float), ("ms_large_kernel", C.c_float), ("fill_chunk", C.c_int32),
-                ("fill_split", C.c_int32)]
+                ("fill_split", C.c_int32), ("fill_mg_levels", C.c_int32), ("ms_fill_mg_build", C.c_float)]
 
     def as_dict(self):
         d = {}

@@ -174,12 +174,14 @@ __global__ void __launch_bounds__(AMAXC) k_cy_coarsest(int n, const double* __re
   }
 }
 
-// prolongation and post-smoothing: x = w D^-1 b + P y',
+// prolongation and post-smoothing: x = w D^-1 b + corr P y',
 // y = x + w D^-1 (b - A x) (yn = null: no coarser level, the two Jacobi
-// sweeps only).  On the finest level the
-// block partials of (b, y) are written to parts.
+// sweeps only).  corr > 1 over-corrects: piecewise-constant prolongation
+// over 4:1 aggregates undershoots smooth errors, and a constant factor
+// below 2 keeps the cycle symmetric positive definite.  On the finest level
+// the block partials of (b, y) are written to parts.
 __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict__ yn, double* __restrict__ parts,
-                                               int pstride, const int* done) {
+                                               int pstride, double corr, const int* done) {
   if (is_done(done)) return;
   __shared__ double red[ANT / 64];
   const RowSel s = row_sel(L);
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict_
     double v = e > 0 ? AOMEGA * b[d] / e : 0.0;
     if (yn) {
       const int k = cid[d];
-      if (k >= 0) v += yn[k];
+      if (k >= 0) v += corr * yn[k];
     }
     return v;
   };
@@ -649,6 +651,191 @@ __global__ void __launch_bounds__(1024) k_am_invert(int n, const int* __restrict
   for (int i = threadIdx.x; i < n * n; i += T) A[i] = M[i];
 }
 
+// ------------------------------------------- geometric aggregation (fill)
+// Pixel graphs carry coordinates: a node of level l stands for the pixels
+// of one component inside a 2^l x 2^l block.  Its aggregate on level l+1 is
+// the set of nodes of the same component in the same 2x2 block of level-l
+// cells (at most four).  Keys: the cell of the aggregate (y>>1, x>>1, 14
+// bits each) and the component.
+__global__ void k_gm_keys(int n, const double* __restrict__ diag, const int* __restrict__ gy,
+                          const int* __restrict__ gx, const int* __restrict__ gc, int* __restrict__ kcell,
+                          uint32_t* __restrict__ kcomp, int* __restrict__ flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const bool a = diag[c] > 0.0 && gc[c] >= 0;
+  flag[c] = a ? 1 : 0;
+  kcell[c] = ((gy[c] >> 1) << 14) | (gx[c] >> 1);
+  kcomp[c] = a ? (uint32_t)gc[c] : 0u;
+}
+
+// first position of every run of equal keys (runs sorted by key, members by
+// node index: the first member is the smallest)
+__global__ void k_gm_starts(int m, const int* __restrict__ rflag, const int* __restrict__ rpos, int* __restrict__ rs) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m && rflag[j]) rs[rpos[j]] = j;
+}
+
+// every member joins the aggregate led by its run's smallest node
+__global__ void k_gm_agg(int m, const uint32_t* __restrict__ node, const int* __restrict__ rflag,
+                         const int* __restrict__ rpos, const int* __restrict__ rs, int* __restrict__ agg2,
+                         int* __restrict__ lead) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int run = rpos[j] - 1 + rflag[j];
+  const int ld = (int)node[rs[run]];
+  const int me = (int)node[j];
+  agg2[me] = ld;
+  lead[me] = ld == me ? 1 : 0;
+}
+
+// coordinates of the coarse nodes from their leaders
+__global__ void k_gm_coarse(int n, const int* __restrict__ agg2, const int* __restrict__ pos,
+                            const int* __restrict__ gy, const int* __restrict__ gx, const int* __restrict__ gc,
+                            int* __restrict__ cy, int* __restrict__ cx, int* __restrict__ cc) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || agg2[c] != c) return;
+  const int k = pos[c];
+  cy[k] = gy[c] >> 1;
+  cx[k] = gx[c] >> 1;
+  cc[k] = gc[c];
+}
+
+// ------------------------------------------------- batched fill PCG
+// Many independent component systems on one level-0 graph (block
+// diagonal); one global alpha and beta, and a stop when every component
+// meets its own test ||r_c|| <= rtol ||b_c||.  comp[c] < 0: a node of no
+// system (its row is empty and its right-hand side zero).
+
+// r = b - A x for the start x; p = q = 0; per component |r|^2 and |b|^2
+__global__ void __launch_bounds__(ANT) k_fs_init(ALev L, const int* __restrict__ comp, const double* __restrict__ x,
+                                                 const double* __restrict__ b, double* __restrict__ r,
+                                                 double* __restrict__ p, double* __restrict__ q,
+                                                 double* __restrict__ rrc, double* __restrict__ bbc) {
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  const bool in = c < L.n;
+  const int k = in ? comp[c] : -1;
+  double rv = 0.0, bv = 0.0;
+  if (in) {
+    const double xc = x[c];
+    double acc = 0.0;
+    for (int j = L.row_off[c]; j < L.row_off[c + 1]; ++j) acc += L.w[j] * (xc - x[L.col[j]]);
+    bv = b[c];
+    rv = bv - acc;
+    r[c] = rv;
+    p[c] = 0.0;
+    q[c] = 0.0;
+  }
+  ni::acc_by_key<double>(k >= 0, k, rv * rv, bv * bv, rrc, bbc);
+}
+
+// one block: a learned start no better than zero is dropped (flag per
+// component; its |r|^2 becomes |b|^2); iteration counts start at -1
+__global__ void __launch_bounds__(ANT) k_fs_scal0(const int* __restrict__ list, int nl, double* __restrict__ rrc,
+                                                  const double* __restrict__ bbc, int* __restrict__ reset, int warm,
+                                                  int* __restrict__ iters, int* __restrict__ stats,
+                                                  double* __restrict__ sc, int* __restrict__ done,
+                                                  int* __restrict__ itc, int* __restrict__ flag) {
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    const int c = list[i];
+    const bool rs = warm && !(rrc[c] < bbc[c]);
+    reset[c] = rs ? 1 : 0;
+    if (rs) {
+      rrc[c] = bbc[c];
+      atomicAdd(&stats[1], 1);
+    }
+    iters[c] = -1;
+  }
+  if (threadIdx.x == 0) {
+    sc[S_RHOP] = 1.0;
+    *done = 0;
+    *itc = 0;
+    *flag = 1;
+  }
+}
+
+__global__ void k_fs_reset(int n, const int* __restrict__ comp, const int* __restrict__ reset,
+                           const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k = comp[c];
+  if (k >= 0 && reset[k]) {
+    x[c] = 0.0;
+    r[c] = b[c];
+  }
+}
+
+// one block, after the cycle: rho = (r, z); per-component test on the
+// residual of the last update (the start's before the first); a component
+// records the iteration it first passes; beta, or stop
+__global__ void __launch_bounds__(ANT) k_fs_scal1(const double* __restrict__ parts, int np,
+                                                  const int* __restrict__ list, int nl, double* __restrict__ rrc,
+                                                  double* __restrict__ rr, const double* __restrict__ bbc,
+                                                  int* __restrict__ iters, int* __restrict__ stats,
+                                                  double* __restrict__ sc, int* __restrict__ done,
+                                                  int* __restrict__ itc, double rtol, int maxit,
+                                                  int* __restrict__ flag) {
+  __shared__ double red[ANT / 64];
+  __shared__ int open_s;
+  if (is_done(done)) return;
+  const int it = *itc;
+  const double rho = sum_parts(parts, np, red);
+  if (threadIdx.x == 0) open_s = 0;
+  __syncthreads();
+  const double t2 = rtol * rtol;
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    const int c = list[i];
+    const double v = rrc[c];
+    rr[c] = v;
+    rrc[c] = 0.0;
+    if (!(v > t2 * bbc[c])) {
+      if (iters[c] < 0) iters[c] = it;
+    } else {
+      atomicAdd(&open_s, 1);
+    }
+  }
+  __syncthreads();
+  const bool stop = open_s == 0 || it >= maxit;
+  if (stop) {
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+      const int c = list[i];
+      if (iters[c] < 0) {
+        iters[c] = it;
+        atomicAdd(&stats[0], 1);
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (stop) {
+      *done = 1;
+      *flag = 0;
+    } else {
+      sc[S_BETA] = it == 0 ? 0.0 : rho / sc[S_RHOP];
+      sc[S_RHO] = rho;
+      sc[S_RHOP] = rho;
+      *itc = it + 1;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q, per-component |r|^2
+__global__ void __launch_bounds__(ANT) k_fs_xr(int n, const int* __restrict__ comp, double* __restrict__ x,
+                                               double* __restrict__ r, const double* __restrict__ p,
+                                               const double* __restrict__ q, const double* __restrict__ sc,
+                                               double* __restrict__ rrc, const int* done) {
+  if (is_done(done)) return;
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  const bool in = c < n;
+  const int k = in ? comp[c] : -1;
+  double rv = 0.0;
+  if (in) {
+    const double a = sc[S_ALPHA];
+    x[c] += a * p[c];
+    rv = r[c] - a * q[c];
+    r[c] = rv;
+  }
+  ni::acc1_by_key(k >= 0, k, rv * rv, rrc);
+}
+
 // ------------------------------------------------------------ host side
 struct DBuf {
   void* p = nullptr;
@@ -690,6 +877,9 @@ struct AmgLevel {
   DBuf pw_b, w_b, diag_b;
   // cycle vectors
   DBuf bv_b, x_b, r_b, y_b;
+  // pixel coordinates and component of every node (geometric aggregation)
+  DBuf gy_b, gx_b, gc_b;
+  const int *gy = nullptr, *gx = nullptr, *gc = nullptr;
   const int *row_off = nullptr, *col = nullptr, *ent = nullptr, *plo = nullptr, *phi = nullptr;
   const double *w = nullptr, *diag = nullptr, *pw = nullptr;
   const int *mem_off = nullptr, *mem = nullptr, *mheavy = nullptr, *gal_off = nullptr, *gal_src = nullptr;
@@ -705,22 +895,23 @@ struct Amg {
   std::vector<AmgLevel*> lv;
   int nlev = 0;        // levels in use (0 .. nlev-1); the last is the coarsest
   bool dense = false;  // coarsest solved exactly
+  double corr = 1.0;   // coarse-correction factor
   DBuf s[NSCR];
-  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr;
+  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst;
   hipStream_t cap = nullptr;  // capture stream of the iteration graph
   ~Amg() {
     if (cap) (void)hipStreamDestroy(cap);
     for (AmgLevel* L : lv) {
       DBuf* b[] = {&L->mem_off_b, &L->mem_b, &L->mheavy_b, &L->gal_off_b, &L->gal_src_b, &L->cid_b, &L->plo_b,
                    &L->phi_b, &L->row_off_b, &L->ent_b, &L->col_b, &L->heavy_b, &L->pw_b, &L->w_b, &L->diag_b,
-                   &L->bv_b, &L->x_b, &L->r_b, &L->y_b};
+                   &L->bv_b, &L->x_b, &L->r_b, &L->y_b, &L->gy_b, &L->gx_b, &L->gc_b};
       for (DBuf* d : b)
         if (d->p) (void)hipFree(d->p);
       delete L;
     }
     for (DBuf& d : s)
       if (d.p) (void)hipFree(d.p);
-    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr};
+    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst};
     for (DBuf* d : own)
       if (d->p) (void)hipFree(d->p);
   }
@@ -729,6 +920,9 @@ struct Amg {
 Amg* amg_new() { return new Amg(); }
 void amg_free(Amg* a) { delete a; }
 int amg_levels(const Amg* a) { return a ? a->nlev : 0; }
+void amg_set_corr(Amg* a, double corr) {
+  if (a) a->corr = corr;
+}
 
 static hipError_t read_int(const int* dev, int* host, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(host, dev, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -812,11 +1006,57 @@ static void level_values(AmgLevel* L, const double* pwf, hipStream_t st) {
   L->diag = diag;
 }
 
+// 2x2-block aggregation of a pixel-graph level: every active node (row
+// sum > 0) is sorted on (component, aggregate cell) with its index as the
+// value (stable sorts keep equal keys in index order), and joins the
+// aggregate led by the first node of its run.  Inactive nodes: agg2 = -1.
+static hipError_t geo_aggregate(Amg* A, const AmgLevel* F, int ncomp, int* agg2, int* lead, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  const int n = F->n;
+  int* kcell = grow<int>(A->s[14], n, err);
+  uint32_t* kcomp = grow<uint32_t>(A->s[15], n, err);
+  int* flag = grow<int>(A->s[13], n, err);
+  int* fpos = grow<int>(A->s[11], n + 1, err);
+  uint32_t* ko = grow<uint32_t>(A->s[0], n, err);
+  uint32_t* vo = grow<uint32_t>(A->s[1], n, err);
+  uint32_t* k1 = grow<uint32_t>(A->s[2], n, err);
+  uint32_t* v1 = grow<uint32_t>(A->s[3], n, err);
+  uint32_t* tk = grow<uint32_t>(A->s[4], n, err);
+  uint32_t* tv = grow<uint32_t>(A->s[5], n, err);
+  uint32_t* k2 = grow<uint32_t>(A->s[6], n, err);
+  uint32_t* k3 = grow<uint32_t>(A->s[7], n, err);
+  uint32_t* v3 = grow<uint32_t>(A->s[8], n, err);
+  int* rflag = grow<int>(A->s[12], n, err);
+  int* scan = grow<int>(A->scan, std::max(radix_tmp_ints(std::max(n, 1)), scan_tmp_ints(n + 1)), err);
+  int* tot = grow<int>(A->ctr, 8, err);
+  AMG_TRY(err);
+  k_am_fill<<<nb256(n), 256, 0, st>>>(agg2, n, -1);
+  k_am_fill<<<nb256(n), 256, 0, st>>>(lead, n, 0);
+  k_gm_keys<<<nb256(n), 256, 0, st>>>(n, F->diag, F->gy, F->gx, F->gc, kcell, kcomp, flag);
+  AMG_TRY(scan_exclusive_i32(flag, fpos, n, tot, scan, st));
+  int m = 0;
+  AMG_TRY(read_int(tot, &m, st));
+  if (m <= 0) return hipGetLastError();
+  k_am_compact<<<nb256(n), 256, 0, st>>>(n, flag, fpos, kcell, ko, vo);
+  AMG_TRY(radix_sort_pairs(ko, vo, k1, v1, tk, tv, m, 28, scan, st));
+  k_am_gather<<<nb256(m), 256, 0, st>>>(m, kcomp, v1, k2);
+  AMG_TRY(radix_sort_pairs(k2, v1, k3, v3, tk, tv, m, std::max(bits_for(ncomp), 1), scan, st));
+  k_am_runs<<<nb256(m), 256, 0, st>>>(m, v3, kcomp, reinterpret_cast<const uint32_t*>(kcell), rflag);
+  int* rpos = reinterpret_cast<int*>(ko);
+  int* rs = reinterpret_cast<int*>(vo);
+  AMG_TRY(scan_exclusive_i32(rflag, rpos, m, nullptr, scan, st));
+  k_gm_starts<<<nb256(m), 256, 0, st>>>(m, rflag, rpos, rs);
+  k_gm_agg<<<nb256(m), 256, 0, st>>>(m, v3, rflag, rpos, rs, agg2, lead);
+  return hipGetLastError();
+}
+
 // Build the hierarchy from the quotient graph of this step: K nodes, P
 // pairs (pair_lo < pair_hi, weights pW), CSR row_off / qcol / qw, row sums
 // diag.
 hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, const double* qw,
-                     const double* diag, const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st) {
+                     const double* diag, const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st,
+                     const int* gy, const int* gx, const int* gc, int ncomp) {
+  const bool geo = gy && gx && gc;
   hipError_t err = hipSuccess;
   if (A->lv.empty()) A->lv.push_back(new AmgLevel());
   AmgLevel* L0 = A->lv[0];
@@ -829,6 +1069,9 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
   L0->plo = pair_lo;
   L0->phi = pair_hi;
   L0->pw = pW;
+  L0->gy = geo ? gy : nullptr;
+  L0->gx = geo ? gx : nullptr;
+  L0->gc = geo ? gc : nullptr;
   // every scratch array at its largest size up front: nothing is freed and
   // reallocated while kernels that use it may still be queued
   {
@@ -862,12 +1105,16 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
     int* scan = grow<int>(A->scan, std::max(radix_tmp_ints(std::max(std::max(2 * F->np, n), 1)),
                                             scan_tmp_ints(std::max(F->np, n) + 1)), err);
     AMG_TRY(err);
-    k_am_active<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->diag, agg, act);
-    for (int round = 0; round < 3; ++round) {
-      k_am_pick<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, best);
-      k_am_match<<<nb256(n), 256, 0, st>>>(n, best, agg);
+    if (geo) {
+      AMG_TRY(geo_aggregate(A, F, ncomp, agg2, lead, st));
+    } else {
+      k_am_active<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->diag, agg, act);
+      for (int round = 0; round < 3; ++round) {
+        k_am_pick<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, best);
+        k_am_match<<<nb256(n), 256, 0, st>>>(n, best, agg);
+      }
+      k_am_attach<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, agg2, lead);
     }
-    k_am_attach<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->col, F->w, agg, act, agg2, lead);
     AMG_TRY(scan_exclusive_i32(lead, pos, n, tot, scan, st));
     int nc = 0;
     AMG_TRY(read_int(tot, &nc, st));
@@ -877,6 +1124,18 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
     if (l + 1 >= (int)A->lv.size()) A->lv.push_back(new AmgLevel());
     AmgLevel* C = A->lv[l + 1];
     C->n = nc;
+    if (geo) {
+      int* cy = grow<int>(C->gy_b, nc, err);
+      int* cx = grow<int>(C->gx_b, nc, err);
+      int* cc = grow<int>(C->gc_b, nc, err);
+      AMG_TRY(err);
+      k_gm_coarse<<<nb256(n), 256, 0, st>>>(n, agg2, pos, F->gy, F->gx, F->gc, cy, cx, cc);
+      C->gy = cy;
+      C->gx = cx;
+      C->gc = cc;
+    } else {
+      C->gy = C->gx = C->gc = nullptr;
+    }
     // ---- members of every coarse node: the fine nodes sorted on cid
     {
       int* fpos = grow<int>(A->s[11], n + 1, err);
@@ -1021,6 +1280,31 @@ static ALev view(const AmgLevel* L, double* b) {
   return v;
 }
 
+// one V-cycle on V[0].b -> V[0].y; the finest level writes the block
+// partials of (b, y) to parts
+static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts, int pstride, const int* done,
+                         hipStream_t q_) {
+  for (int l = 0; l + 1 < A->nlev; ++l) {
+    const ALev& L = V[l];
+    k_cy_down<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
+    const AmgLevel* C = A->lv[l + 1];
+    k_cy_restrict<<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy, L.r,
+                                                            V[l + 1].b, done);
+  }
+  const ALev& Lc = V[A->nlev - 1];
+  if (A->dense) {
+    k_cy_coarsest<<<1, AMAXC, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
+                                       static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
+  } else {  // no exact coarsest: smoothing only
+    k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, A->corr,
+                                                 done);
+  }
+  for (int l = A->nlev - 2; l >= 0; --l) {
+    const ALev& L = V[l];
+    k_cy_up<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, A->corr, done);
+  }
+}
+
 // PCG on the finest level, preconditioned by one V-cycle.  rhs / babs as
 // in the Jacobi solver; the solution goes to s.  Iterations -> *iters_out
 // (device).  The host polls the "still iterating" flag every `batch`
@@ -1049,24 +1333,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   // one PCG iteration: V-cycle on r -> z (= y of level 0), then the CG
   // update; every kernel returns at once after convergence
   auto iteration = [&](hipStream_t q_) {
-    for (int l = 0; l + 1 < A->nlev; ++l) {
-      const ALev& L = V[l];
-      k_cy_down<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
-      const AmgLevel* C = A->lv[l + 1];
-      k_cy_restrict<<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy,
-                                                              L.r, V[l + 1].b, done);
-    }
-    const ALev& Lc = V[A->nlev - 1];
-    if (A->dense) {
-      k_cy_coarsest<<<1, AMAXC, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
-                                         static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
-    } else {  // no exact coarsest: smoothing only
-      k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, done);
-    }
-    for (int l = A->nlev - 2; l >= 0; --l) {
-      const ALev& L = V[l];
-      k_cy_up<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, done);
-    }
+    launch_cycle(A, V, parts, pstride, done, q_);
     // rho = (r, z) -> beta; convergence on ||r||
     k_cg_scal<<<1, ANT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
     k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, q_>>>(V[0], p, q, sc, parts, pstride, done);
@@ -1106,6 +1373,58 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
     AMG_TRY(hipStreamSynchronize(st));
     if (*host_flag == 0) break;
   }
+  return hipSuccess;
+}
+
+hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int K, const double* b, double* x,
+                          double rtol, int maxit, int warm, double* rr, double* bb, int* iters, int* stats,
+                          int* host_flag, int* its, hipStream_t st) {
+  *its = 0;
+  if (A->nlev <= 0 || nl <= 0) return hipSuccess;
+  hipError_t err = hipSuccess;
+  AmgLevel* L0 = A->lv[0];
+  if (L0->nheavy != 0) return hipErrorInvalidValue;  // pixel rows have at most four entries
+  const int n = L0->n;
+  const int nblk = nb256(n);
+  double* p = grow<double>(A->p, n, err);
+  double* q = grow<double>(A->q, n, err);
+  double* r = grow<double>(A->r, n, err);
+  const int pstride = nblk;
+  double* parts = grow<double>(A->parts, 2 * (size_t)pstride, err);
+  double* sc = grow<double>(A->sc, S_N, err);
+  int* ctr = grow<int>(A->ctr, 8, err);  // [0] done, [1] iteration, [2] flag, [3] unused
+  double* rrc = grow<double>(A->rrc, (size_t)std::max(K, 1), err);
+  int* rst = grow<int>(A->rst, (size_t)std::max(K, 1), err);
+  AMG_TRY(err);
+  int* done = ctr;
+  int* itc = ctr + 1;
+  int* flag = ctr + 2;
+  std::vector<ALev> V(A->nlev);
+  for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
+  AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * std::max(K, 1), st));
+  AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * std::max(K, 1), st));
+  k_fs_init<<<nblk, ANT, 0, st>>>(V[0], comp, x, b, r, p, q, rrc, bb);
+  k_fs_scal0<<<1, ANT, 0, st>>>(list, nl, rrc, bb, rst, warm, iters, stats, sc, done, itc, flag);
+  if (warm) k_fs_reset<<<nblk, ANT, 0, st>>>(n, comp, rst, b, x, r);
+  AMG_TRY(hipGetLastError());
+  const int batch = 8;
+  for (int it = 0; it <= maxit + 1; it += batch) {
+    for (int k = 0; k < batch; ++k) {
+      launch_cycle(A, V, parts, pstride, done, st);
+      k_fs_scal1<<<1, ANT, 0, st>>>(parts, pstride, list, nl, rrc, rr, bb, iters, stats, sc, done, itc, rtol, maxit,
+                                    flag);
+      k_cg_pq<<<nblk, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
+      k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
+      k_fs_xr<<<nblk, ANT, 0, st>>>(n, comp, x, r, p, q, sc, rrc, done);
+    }
+    AMG_TRY(hipGetLastError());
+    AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    AMG_TRY(hipStreamSynchronize(st));
+    if (*host_flag == 0) break;
+  }
+  AMG_TRY(hipMemcpyAsync(host_flag, itc, sizeof(int), hipMemcpyDeviceToHost, st));
+  AMG_TRY(hipStreamSynchronize(st));
+  *its = *host_flag;
   return hipSuccess;
 }
 

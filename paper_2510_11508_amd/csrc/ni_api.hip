@@ -35,6 +35,12 @@ hipError_t fill_small(int, const int*, int, const int*, const float4*, const flo
 hipError_t large_init(const LargeArgs&, int, hipStream_t);
 hipError_t large_iter(const LargeArgs&, int, hipStream_t);
 hipError_t large_finish(const LargeArgs&, const uint32_t*, float*, hipStream_t);
+hipError_t large_center(const LargeArgs&, hipStream_t);
+hipError_t mg_count(int, const float4*, const uint32_t*, const int*, int*, int*, hipStream_t);
+hipError_t mg_build(int, int, const float4*, const float*, const float*, const uint32_t*, const uint32_t*, const int*,
+                    const int*, const int*, int*, double*, double*, int*, int*, double*, int*, int*, int*, double*,
+                    double*, hipStream_t);
+hipError_t mg_out(int, const uint32_t*, const int*, const double*, float*, hipStream_t);
 // ni_quot.hip
 hipError_t quot_inter_edges(const int*, const uint8_t*, int, int, int*, int*, int*, uint32_t*, int*, hipStream_t,
                             int);
@@ -100,12 +106,15 @@ struct ni_ctx {
   // edges / pairs
   Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
       row_off, epart, qpart, rsum, rcnt, qcol, qw, qt0, qt1, qsc, qpv, qst, qecol, qew;
+  // fill multigrid: level-0 system of the large components
+  Buf mg_deg, mg_pc, mg_row, mg_poff, mg_col, mg_w, mg_diag, mg_plo, mg_phi, mg_pw, mg_gy, mg_gx, mg_gc, mg_b, mg_x;
   // scratch
   Buf scan_tmp, misc, unet_ws;
   int* host = nullptr;  // pinned readback area (64 ints)
-  hipEvent_t ev[14] = {};
+  hipEvent_t ev[16] = {};
   struct nil::UnetModel* unet = nullptr;
-  nil::Amg* amg = nullptr;
+  nil::Amg* amg = nullptr;       // quotient systems
+  nil::Amg* amg_fill = nullptr;  // fill of the large components
   // autotuned schedule of the large fill path: shortest chunk per block,
   // and the map size class it was tuned for
   int fill_chunk = 0, fill_split = 0, fill_chunk_key = -1;
@@ -120,7 +129,9 @@ struct ni_ctx {
                   &qz, &qp0, &qp1, &qq, &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &qpart, &rsum,
-                  &rcnt, &qcol, &qw, &qt0, &qt1, &qsc, &qpv, &qst, &qecol, &qew, &scan_tmp, &misc, &unet_ws};
+                  &rcnt, &qcol, &qw, &qt0, &qt1, &qsc, &qpv, &qst, &qecol, &qew, &mg_deg, &mg_pc, &mg_row,
+                  &mg_poff, &mg_col, &mg_w, &mg_diag, &mg_plo, &mg_phi, &mg_pw, &mg_gy, &mg_gx, &mg_gc, &mg_b,
+                  &mg_x, &scan_tmp, &misc, &unet_ws};
     bufs.assign(std::begin(all), std::end(all));
   }
 };
@@ -222,6 +233,7 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
       prm->fill_chunk != 4096)
     return bad("fill_chunk must be 0, 512, 1024, 2048 or 4096");
   if (prm->fill_split != 0 && prm->fill_split != 1) return bad("fill_split must be 0 or 1");
+  if (prm->fill_precond != 0 && prm->fill_precond != 1) return bad("fill_precond must be 0 or 1");
   if (prm->warm_start && !c->unet) {
     c->err = "warm_start needs a model (ni_unet_load)";
     return NI_E_MODEL;
@@ -444,7 +456,11 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   // before the real solve.
   int key = 0;
   while ((1ll << key) < (long long)N) ++key;
-  if (n_large > 0 && pb.prm.fill_chunk > 0) {
+  const bool mg = n_large > 0 && pb.prm.fill_precond == 1;
+  if (mg) {
+    // the multigrid path does not use the chunked schedule (the chunk table
+    // only serves the final centring)
+  } else if (n_large > 0 && pb.prm.fill_chunk > 0) {
     // a fixed schedule; the next autotuned call tunes afresh
     c->fill_chunk = pb.prm.fill_chunk;
     c->fill_split = pb.prm.fill_split;
@@ -500,9 +516,63 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
                              c->stream),
           "fill small");
   mark(c, 6);
-  int launches = 0;
-  float large_kernel_ms = 0.f;
-  if (n_large > 0) {
+  int launches = 0, mg_levels = 0;
+  float large_kernel_ms = 0.f, mg_build_ms = 0.f;
+  if (mg) {
+    // one multigrid-preconditioned CG over all large components together
+    nil::LargeArgs a = large_args();
+    if (warm) check(c, nil::large_center(a, c->stream), "centre start");
+    mark(c, 14);
+    int* deg = ensure<int>(c, c->mg_deg, N);
+    int* npair = ensure<int>(c, c->mg_pc, N);
+    int* row_off = ensure<int>(c, c->mg_row, (size_t)N + 1);
+    int* poff = ensure<int>(c, c->mg_poff, (size_t)N + 1);
+    check(c, nil::mg_count(N, cst, ptr<uint32_t>(c->skey), comp_off, deg, npair, c->stream), "mg count");
+    check(c, nil::scan_exclusive_i32(deg, row_off, N, row_off + N, ptr<int>(c->scan_tmp), c->stream), "scan");
+    check(c, nil::scan_exclusive_i32(npair, poff, N, poff + N, ptr<int>(c->scan_tmp), c->stream), "scan");
+    readback(c, row_off + N, sizeof(int), c->host);
+    const int nnz = c->host[0];
+    readback(c, poff + N, sizeof(int), c->host);
+    const int npr = c->host[0];
+    if (nnz != 2 * npr) {
+      c->err = "fill multigrid: inconsistent level-0 graph";
+      throw Fail{NI_E_DEVICE};
+    }
+    int* col = ensure<int>(c, c->mg_col, nnz);
+    double* w = ensure<double>(c, c->mg_w, nnz);
+    double* dg = ensure<double>(c, c->mg_diag, N);
+    int* plo = ensure<int>(c, c->mg_plo, npr);
+    int* phi = ensure<int>(c, c->mg_phi, npr);
+    double* pw = ensure<double>(c, c->mg_pw, npr);
+    int* gy = ensure<int>(c, c->mg_gy, N);
+    int* gx = ensure<int>(c, c->mg_gx, N);
+    int* gc = ensure<int>(c, c->mg_gc, N);
+    double* b64 = ensure<double>(c, c->mg_b, N);
+    double* x64 = ensure<double>(c, c->mg_x, N);
+    check(c,
+          nil::mg_build(N, W, cst, rhs, x, cpix, ptr<uint32_t>(c->skey), comp_off, row_off, poff, col, w, dg, plo,
+                        phi, pw, gy, gx, gc, b64, x64, c->stream),
+          "mg build");
+    if (!c->amg_fill) c->amg_fill = nil::amg_new();
+    check(c, nil::amg_build(c->amg_fill, N, npr, row_off, col, w, dg, plo, phi, pw, c->stream, gy, gx, gc, K),
+          "mg hierarchy");
+    nil::amg_set_corr(c->amg_fill, 1.8);
+    check(c, nil::amg_update(c->amg_fill, w, dg, pw, c->stream), "mg values");
+    mark(c, 12);
+    int its = 0;
+    check(c,
+          nil::amg_fill_solve(c->amg_fill, gc, lists + 3 * K1, n_large, K, b64, x64, pb.prm.cg_rtol,
+                              pb.prm.cg_max_iter, warm, rr, bb, iters, misc(c) + M_STATS, c->host, &its, c->stream),
+          "mg solve");
+    mark(c, 13);
+    check(c, nil::mg_out(N, ptr<uint32_t>(c->skey), comp_off, x64, x, c->stream), "mg out");
+    check(c, nil::large_finish(a, cpix, zout, c->stream), "large finish");
+    check(c, hipStreamSynchronize(c->stream), "sync");
+    launches = its;
+    large_kernel_ms = ev_ms(c, 12, 13);
+    mg_build_ms = ev_ms(c, 14, 12);
+    mg_levels = nil::amg_levels(c->amg_fill);
+  } else if (n_large > 0) {
     nil::LargeArgs a = large_args();
     check(c, hipMemsetAsync(a.active, 0, 2 * sizeof(int), c->stream), "memset");
     check(c, nil::large_init(a, warm, c->stream), "large init");
@@ -565,8 +635,10 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->ms_fill_small = ev_ms(c, 5, 6);
     rep->ms_fill_large = ev_ms(c, 6, 7);
     rep->ms_large_kernel = large_kernel_ms;
-    rep->fill_chunk = n_large > 0 ? c->fill_chunk : 0;
-    rep->fill_split = n_large > 0 ? c->fill_split : 0;
+    rep->fill_chunk = n_large > 0 && !mg ? c->fill_chunk : 0;
+    rep->fill_split = n_large > 0 && !mg ? c->fill_split : 0;
+    rep->fill_mg_levels = mg_levels;
+    rep->ms_fill_mg_build = mg_build_ms;
   }
   if (notconv > 0) {
     c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";
@@ -775,6 +847,7 @@ ni_status ni_params_default(ni_params* p) {
   p->graphs = 0;
   p->fill_chunk = 0;
   p->fill_split = 0;
+  p->fill_precond = 1;
   return NI_OK;
 }
 
@@ -811,6 +884,7 @@ ni_status ni_destroy(ni_ctx* c) {
   if (c->host) (void)hipHostFree(c->host);
   if (c->unet) nil::unet_free(c->unet);
   if (c->amg) nil::amg_free(c->amg);
+  if (c->amg_fill) nil::amg_free(c->amg_fill);
   delete c;
   return NI_OK;
 }

@@ -62,6 +62,20 @@ __device__ __forceinline__ void acc_by_key(bool valid, int key, double a, TB b, 
   }
 }
 
+// One-value form of acc_by_key.
+__device__ __forceinline__ void acc1_by_key(bool valid, int key, double a, double* da) {
+  const int lead = __shfl(key, 0, NI_WAVE);
+  const bool lead_valid = __shfl(valid ? 1 : 0, 0, NI_WAVE) != 0;
+  if (lead_valid && __all(!valid || key == lead)) {
+    double sa = valid ? a : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sa += __shfl_xor(sa, o, NI_WAVE);
+    if ((threadIdx.x & (NI_WAVE - 1)) == 0) atomicAdd(&da[lead], sa);
+  } else if (valid) {
+    atomicAdd(&da[key], a);
+  }
+}
+
 // Block-wide sum of NV doubles; every thread receives the totals.  `scratch`
 // must hold NV * (blockDim/64) doubles and must not be reused by the caller
 // until a later __syncthreads(); the sum order is fixed (deterministic).
@@ -145,8 +159,24 @@ struct Amg;
 Amg* amg_new();
 void amg_free(Amg*);
 int amg_levels(const Amg*);
+// gy / gx / gc (optional): pixel coordinates and component of every node;
+// when given, aggregates are 2x2 blocks of one component (pixel graphs),
+// otherwise pairwise handshakes (general graphs).  gc < ncomp.
 hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, const double* qw, const double* diag,
-                     const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st);
+                     const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st,
+                     const int* gy = nullptr, const int* gx = nullptr, const int* gc = nullptr, int ncomp = 0);
+// coarse-correction factor of the cycle (1 unless set)
+void amg_set_corr(Amg*, double corr);
+// Batched PCG of independent component systems on level 0 (block
+// diagonal): comp[node] (-1: no system), list[nl] the components; x holds
+// the start (warm != 0: a start no better than zero is dropped per
+// component) and receives the solution.  Per component: rr = |r|^2 at the
+// end, bb = |b|^2, iters = iterations to ||r_c|| <= rtol ||b_c||; stats[0]
+// counts components that hit maxit, stats[1] dropped starts.  rrc / reset
+// are K-sized scratch.  *its = iterations run.
+hipError_t amg_fill_solve(Amg*, const int* comp, const int* list, int nl, int K, const double* b, double* x,
+                          double rtol, int maxit, int warm, double* rr, double* bb, int* iters, int* stats,
+                          int* host_flag, int* its, hipStream_t st);
 hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
 hipError_t amg_solve(Amg*, const double* rhs, const double* babs, double* s, double rtol, int maxit, int* iters_out,
                      int* host_flag, bool graph, hipStream_t st);

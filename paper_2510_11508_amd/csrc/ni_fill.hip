@@ -708,6 +708,90 @@ __global__ void __launch_bounds__(LNT) k_lg_center(LargeState S, int slot, float
   }
 }
 
+// ====================================================== multigrid path
+// The large components' systems as one weighted graph Laplacian for the
+// multigrid PCG: level-0 nodes are the compacted pixels (a node of a small
+// component has an empty row and takes no part), entries in FP64 from the
+// same FP32 weights as the stencil, pairs (i < j) for the right and down
+// edges, the pixel coordinates and component of every node.
+__device__ __forceinline__ bool is_large(const uint32_t* skey, const int* comp_off, int i, int cap, int& k) {
+  k = (int)skey[i];
+  return comp_off[k + 1] - comp_off[k] > cap;
+}
+
+__global__ void k_mg_count(int N, const float4* __restrict__ cst, const uint32_t* __restrict__ skey,
+                           const int* __restrict__ comp_off, int cap, int* __restrict__ deg, int* __restrict__ npair) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int k;
+  int d = 0, pr = 0;
+  if (is_large(skey, comp_off, i, cap, k)) {
+    const Stencil s = load_stencil(cst, i, comp_off[k]);
+    d = (s.wr != 0.f) + (s.wl != 0.f) + (s.wd != 0.f) + (s.wu != 0.f);
+    pr = (s.wr != 0.f) + (s.wd != 0.f);
+  }
+  deg[i] = d;
+  npair[i] = pr;
+}
+
+__global__ void k_mg_build(int N, int W, const float4* __restrict__ cst, const float* __restrict__ rhs,
+                           const float* __restrict__ x32, const uint32_t* __restrict__ cpix,
+                           const uint32_t* __restrict__ skey, const int* __restrict__ comp_off, int cap,
+                           const int* __restrict__ row_off, const int* __restrict__ pair_off, int* __restrict__ col,
+                           double* __restrict__ w, double* __restrict__ diag, int* __restrict__ plo,
+                           int* __restrict__ phi, double* __restrict__ pw, int* __restrict__ gy, int* __restrict__ gx,
+                           int* __restrict__ gc, double* __restrict__ b64, double* __restrict__ x64) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int k;
+  const int p = (int)cpix[i];
+  gy[i] = p / W;
+  gx[i] = p % W;
+  if (!is_large(skey, comp_off, i, cap, k)) {
+    diag[i] = 0.0;
+    gc[i] = -1;
+    b64[i] = 0.0;
+    x64[i] = 0.0;
+    return;
+  }
+  const Stencil s = load_stencil(cst, i, comp_off[k]);
+  int j = row_off[i];
+  double dg = 0.0;
+  auto put = [&](int c, float v) {
+    col[j] = c;
+    w[j] = (double)v;
+    dg += (double)v;
+    ++j;
+  };
+  if (s.wl != 0.f) put(i - 1, s.wl);
+  if (s.wu != 0.f) put(i - s.ou, s.wu);
+  if (s.wd != 0.f) put(i + s.od, s.wd);
+  if (s.wr != 0.f) put(i + 1, s.wr);
+  diag[i] = dg;
+  int q = pair_off[i];
+  if (s.wr != 0.f) {
+    plo[q] = i;
+    phi[q] = i + 1;
+    pw[q] = (double)s.wr;
+    ++q;
+  }
+  if (s.wd != 0.f) {
+    plo[q] = i;
+    phi[q] = i + s.od;
+    pw[q] = (double)s.wd;
+  }
+  gc[i] = k;
+  b64[i] = (double)rhs[i];
+  x64[i] = (double)x32[i];
+}
+
+__global__ void k_mg_out(int N, const uint32_t* __restrict__ skey, const int* __restrict__ comp_off, int cap,
+                         const double* __restrict__ x64, float* __restrict__ x32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int k;
+  if (i < N && is_large(skey, comp_off, i, cap, k)) x32[i] = (float)x64[i];
+}
+
 __global__ void k_zero_grid(float* z, int P) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < P) z[p] = 0.f;
@@ -850,6 +934,37 @@ hipError_t large_iter(const LargeArgs& a, int it, hipStream_t st) {
     k_lg_a<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
   }
   k_lg_b<<<a.nchunks, LNT, 0, st>>>(S, it, a.K);
+  return hipGetLastError();
+}
+
+hipError_t mg_count(int N, const float4* cst, const uint32_t* skey, const int* comp_off, int* deg, int* npair,
+                    hipStream_t st) {
+  if (N > 0) k_mg_count<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, cst, skey, comp_off, fill_small_cap(), deg, npair);
+  return hipGetLastError();
+}
+
+hipError_t mg_build(int N, int W, const float4* cst, const float* rhs, const float* x32, const uint32_t* cpix,
+                    const uint32_t* skey, const int* comp_off, const int* row_off, const int* pair_off, int* col,
+                    double* w, double* diag, int* plo, int* phi, double* pw, int* gy, int* gx, int* gc, double* b64,
+                    double* x64, hipStream_t st) {
+  if (N > 0)
+    k_mg_build<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, W, cst, rhs, x32, cpix, skey, comp_off, fill_small_cap(),
+                                                     row_off, pair_off, col, w, diag, plo, phi, pw, gy, gx, gc, b64,
+                                                     x64);
+  return hipGetLastError();
+}
+
+hipError_t mg_out(int N, const uint32_t* skey, const int* comp_off, const double* x64, float* x32, hipStream_t st) {
+  if (N > 0) k_mg_out<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, skey, comp_off, fill_small_cap(), x64, x32);
+  return hipGetLastError();
+}
+
+// zero mean per large component of the start (a learned start: only
+// differences matter)
+hipError_t large_center(const LargeArgs& a, hipStream_t st) {
+  LargeState S = to_state(a);
+  k_lg_sum<<<a.nchunks, LNT, 0, st>>>(S, 0);
+  k_lg_center<<<a.nchunks, LNT, 0, st>>>(S, 0, nullptr, nullptr);
   return hipGetLastError();
 }
 
