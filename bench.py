@@ -6,19 +6,20 @@ system stopped at ||r_c|| <= 1e-6 ||b_c||.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
 
-The roofline object describes the batched CG iteration of the large fill
-components.  The library's autotuner runs it either as two launches
-(k_lg_a: p_i = D^-1 r + beta p_{i-1} recomputed at the pixel and its
-neighbours, q = L p_i; k_lg_b: x and r updates) or as three (k_lg_p
-materialises p_i, k_lg_q applies the stencil, k_lg_b).  Algorithmic bytes
-= 64 B per active pixel per CG iteration: the two-launch form reads r,
-1/diag, p_{i-1} and the packed stencil (16 B) and writes p_i and q, then
-reads r, q, x, p_i, 1/diag and writes x and r (the three-launch form moves
-4 B more, not counted).  achieved = 64 B x the active pixel-iterations of
-one iteration / the event-timed duration of that iteration's launches.
+The roofline object describes one PCG iteration of the large fill
+components.  By default they are solved together by one PCG preconditioned
+by a multigrid V-cycle (aggregates of 2x2 pixel blocks per component); one
+iteration is the cycle's launches on every level plus the (p, q) and
+(x, r) updates on level 0.  Its algorithmic bytes come from the library
+(ni_report.fill_mg_bytes: per level, the CSR rows, entries and FP64
+vectors each kernel must read or write once; neighbour re-reads are cache
+hits).  achieved = those bytes / the event-timed duration of one iteration
+(the solve's launches, batched, divided by the iterations).  With the
+Jacobi preconditioner (fill_precond = 0) the unit is the two- or
+three-launch chunked iteration (k_lg_*) at 64 B per active pixel.
 traffic = calibrated FETCH_SIZE + WRITE_SIZE per iteration from committed
-counter runs (profiles/fill_cg_traffic_<workload>.json), while they match
-the kernel source.  The CPU baseline is the FP64 oracle on this host.
+counter runs (profiles/fill_mg_traffic_<workload>.json), while they match
+the kernel sources.  The CPU baseline is the FP64 oracle on this host.
 
 With a trained warm-start model (paper_2510_11508_amd/weights/, or
 --model) the same map is also integrated with warm_start = 1 and the
@@ -60,21 +61,22 @@ WORKLOADS = {
 
 def kernel_hash():
     h = hashlib.sha256()
-    h.update(open(os.path.join(ROOT, "paper_2510_11508_amd", "csrc", "ni_fill.hip"), "rb").read())
+    for f in ("ni_fill.hip", "ni_amg.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2510_11508_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_record(workload, chunk, split):
-    """HBM bytes per launch of the fill CG kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel source with the
-    schedule this run uses."""
-    path = os.path.join(ROOT, "profiles", f"fill_cg_traffic_{workload}.json")
+def traffic_record(workload, key):
+    """HBM bytes per fill CG iteration from committed rocprofv3 counter
+    runs, if they were taken on the current kernel sources with the same
+    preconditioner and schedule (key: "multigrid" or "CHUNK:SPLIT")."""
+    path = os.path.join(ROOT, "profiles", f"fill_mg_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_hash") != kernel_hash():
         return None
-    return rec.get("schedules", {}).get(f"{chunk}:{split}", {}).get("bytes_per_launch")
+    return rec.get("schedules", {}).get(key, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(sample, params, budget_s=12.0):
@@ -107,6 +109,8 @@ def main():
                     help="skip the pixel-level comparison (theta_c = 0: every pixel its own component)")
     ap.add_argument("--fill-schedule", default=None, metavar="CHUNK:SPLIT",
                     help="fix the large-path fill schedule (e.g. 4096:1) instead of autotuning it")
+    ap.add_argument("--fill-precond", type=int, default=None, choices=[0, 1],
+                    help="preconditioner of the large fill components (default: the library's, multigrid)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     a = ap.parse_args()
@@ -127,6 +131,8 @@ def main():
     if a.fill_schedule:
         ch, sp = a.fill_schedule.split(":")
         sched = dict(fill_chunk=int(ch), fill_split=int(sp))
+    if a.fill_precond is not None:
+        sched["fill_precond"] = a.fill_precond
     p = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T, **sched)
     dev = torch.device("cuda:0")
     normals = torch.from_numpy(s.normals).to(dev)
@@ -214,19 +220,29 @@ def main():
 
     rep = reps[-1]
     k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
-    px_iters = rep["fill_large_px_iters"]
     launches = max(rep["fill_large_launches"], 1)
-    launch_bytes = CG_BYTES_PER_PX_ITER * px_iters / launches
     launch_ms = k_ms / launches
+    mg = rep["fill_mg_levels"] > 0
+    if mg:
+        launch_bytes = rep["fill_mg_bytes"]
+        key = "multigrid"
+        kernel = ("one multigrid-preconditioned PCG iteration of the large fill components: k_cy_down, "
+                  "k_cy_restrict, k_cy_up on every level, k_cy_coarsest, k_fs_scal1, k_cg_pq, k_cg_scal, k_fs_xr")
+    else:
+        px_iters = rep["fill_large_px_iters"]
+        launch_bytes = CG_BYTES_PER_PX_ITER * px_iters / launches
+        key = f"{rep['fill_chunk']}:{rep['fill_split']}"
+        kernel = (("k_lg_p + k_lg_q + k_lg_b" if rep["fill_split"] else "k_lg_a + k_lg_b")
+                  + " (one Jacobi-PCG iteration of the large components)")
     achieved = launch_bytes / (launch_ms / 1000.0) / 1e9 if k_ms > 0 else 0.0
-    traffic = traffic_record(a.workload, rep["fill_chunk"], rep["fill_split"])
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=("k_lg_p + k_lg_q + k_lg_b" if rep["fill_split"] else "k_lg_a + k_lg_b")
-                + " (one CG iteration of the large components)",
-                bytes_per_px_iter=CG_BYTES_PER_PX_ITER,
-                px_iters_per_iteration=round(px_iters / launches, 1), iterations=launches,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_record(a.workload, key),
+                kernel=kernel, bytes_per_iteration=round(launch_bytes), iterations=launches,
                 ms_per_iteration=round(launch_ms, 5))
+    if mg:
+        roof["levels"] = rep["fill_mg_levels"]
+    else:
+        roof["bytes_per_px_iter"] = CG_BYTES_PER_PX_ITER
 
     line = dict(metric=METRIC, value=round(value, 3), unit="Mpx/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
                 ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -236,8 +252,10 @@ def main():
                 stages_ms=stage_ms(reps),
                 fill=dict(iters_max=rep["fill_iters_max"], n_small=rep["n_small"], n_large=rep["n_large"],
                           px_iters=rep["fill_px_iters"], max_relres=rep["fill_max_relres"],
-                          tuned_schedule=dict(chunk_px=rep["fill_chunk"],
-                                              launches_per_iteration=3 if rep["fill_split"] else 2)),
+                          preconditioner="multigrid" if mg else "jacobi",
+                          **(dict(mg_levels=rep["fill_mg_levels"], mg_iterations=launches)
+                             if mg else dict(tuned_schedule=dict(chunk_px=rep["fill_chunk"],
+                                                                 launches_per_iteration=3 if rep["fill_split"] else 2)))),
                 quot_iters=rep["quot_iters"],
                 roofline=roof)
     if warm is not None:

@@ -121,6 +121,8 @@ typedef struct {
                              launches per iteration) instead of recomputed */
   int32_t fill_mg_levels; /* levels of the fill multigrid (0: Jacobi path)  */
   float ms_fill_mg_build; /* its level-0 system and hierarchy build         */
+  double fill_mg_bytes;   /* algorithmic HBM bytes of one of its PCG
+                             iterations (every level; FP64 values)         */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;

@@ -49,7 +49,8 @@ class ni_report(C.Structure):
                 ("ms_assemble", C.c_float), ("ms_warm", C.c_float), ("ms_fill_small", C.c_float),
                 ("ms_fill_large", C.c_float), ("ms_irls", C.c_float), ("ms_finalize", C.c_float),
                 ("ms_total", C.c_float), ("ms_large_kernel", C.c_float), ("fill_chunk", C.c_int32),
-                ("fill_split", C.c_int32), ("fill_mg_levels", C.c_int32), ("ms_fill_mg_build", C.c_float)]
+                ("fill_split", C.c_int32), ("fill_mg_levels", C.c_int32), ("ms_fill_mg_build", C.c_float),
+                ("fill_mg_bytes", C.c_double)]
 
     def as_dict(self):
         d = {}

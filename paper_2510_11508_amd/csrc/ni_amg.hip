@@ -817,23 +817,36 @@ __global__ void __launch_bounds__(ANT) k_fs_scal1(const double* __restrict__ par
   }
 }
 
-// x += alpha p, r -= alpha q, per-component |r|^2
+// x += alpha p, r -= alpha q, per-component |r|^2.  A thread takes FS_R
+// rows ANT apart and sums the rows of one component before one atomic per
+// wavefront: the largest components span millions of rows, and a per-wave
+// atomic on one address would serialise.
+constexpr int FS_R = 16;
 __global__ void __launch_bounds__(ANT) k_fs_xr(int n, const int* __restrict__ comp, double* __restrict__ x,
                                                double* __restrict__ r, const double* __restrict__ p,
                                                const double* __restrict__ q, const double* __restrict__ sc,
                                                double* __restrict__ rrc, const int* done) {
   if (is_done(done)) return;
-  const int c = blockIdx.x * ANT + threadIdx.x;
-  const bool in = c < n;
-  const int k = in ? comp[c] : -1;
-  double rv = 0.0;
-  if (in) {
-    const double a = sc[S_ALPHA];
+  const double a = sc[S_ALPHA];
+  const int base = blockIdx.x * (ANT * FS_R) + threadIdx.x;
+  int cur = -1;
+  double acc = 0.0;
+  for (int k = 0; k < FS_R; ++k) {
+    const int c = base + k * ANT;
+    if (c >= n) break;
+    const int key = comp[c];
+    if (key < 0) continue;
     x[c] += a * p[c];
-    rv = r[c] - a * q[c];
+    const double rv = r[c] - a * q[c];
     r[c] = rv;
+    if (key != cur) {
+      if (cur >= 0) atomicAdd(&rrc[cur], acc);
+      cur = key;
+      acc = 0.0;
+    }
+    acc += rv * rv;
   }
-  ni::acc1_by_key(k >= 0, k, rv * rv, rrc);
+  ni::acc1_by_key(cur >= 0, cur, acc, rrc);
 }
 
 // ------------------------------------------------------------ host side
@@ -920,6 +933,34 @@ struct Amg {
 Amg* amg_new() { return new Amg(); }
 void amg_free(Amg* a) { delete a; }
 int amg_levels(const Amg* a) { return a ? a->nlev : 0; }
+// Algorithmic HBM bytes of one batched-fill PCG iteration on this
+// hierarchy (values FP64, indices int32; neighbour re-reads are cache hits
+// and not counted).  Per level l with n rows and e entries, below the
+// coarsest: down reads row_off, col, w, b, diag and writes r
+// (28 n + 12 e); restrict reads mem_off, mem, r and writes b' (12 n +
+// 12 n'); up reads row_off, col, w, b, diag, cid, y' and writes y (32 n +
+// 12 e + 8 n').  Coarsest: the inverse and two vectors (8 n^2 + 16 n).
+// Level 0 also: (p, q) reads row_off, col, w, z and updates p, q
+// (44 n + 12 e); the update reads comp of every row and updates x, r from
+// p, q on the rows of a system (4 n + 48 n_sys).
+double amg_fill_bytes(const Amg* A, long long n_sys) {
+  if (!A || A->nlev <= 0) return 0.0;
+  double by = 0.0;
+  for (int l = 0; l < A->nlev; ++l) {
+    const AmgLevel* L = A->lv[l];
+    const double n = L->n, e = 2.0 * L->np;
+    if (l == A->nlev - 1) {
+      by += A->dense ? 8.0 * n * n + 16.0 * n : 60.0 * n + 24.0 * e;
+      break;
+    }
+    const double nc = A->lv[l + 1]->n;
+    by += 28.0 * n + 12.0 * e + 12.0 * n + 12.0 * nc + 32.0 * n + 12.0 * e + 8.0 * nc;
+  }
+  const AmgLevel* L0 = A->lv[0];
+  by += 44.0 * L0->n + 12.0 * 2.0 * L0->np + 4.0 * L0->n + 48.0 * (double)n_sys;
+  return by;
+}
+
 void amg_set_corr(Amg* a, double corr) {
   if (a) a->corr = corr;
 }
@@ -1415,7 +1456,7 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
                                     flag);
       k_cg_pq<<<nblk, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
       k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
-      k_fs_xr<<<nblk, ANT, 0, st>>>(n, comp, x, r, p, q, sc, rrc, done);
+      k_fs_xr<<<nb256((n + FS_R - 1) / FS_R), ANT, 0, st>>>(n, comp, x, r, p, q, sc, rrc, done);
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

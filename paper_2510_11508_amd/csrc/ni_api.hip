@@ -518,6 +518,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   mark(c, 6);
   int launches = 0, mg_levels = 0;
   float large_kernel_ms = 0.f, mg_build_ms = 0.f;
+  double mg_bytes = 0.0;
   if (mg) {
     // one multigrid-preconditioned CG over all large components together
     nil::LargeArgs a = large_args();
@@ -620,6 +621,12 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
         itmax = std::max(itmax, it[k]);
         rmax = std::max(rmax, rel[k]);
       }
+      if (mg) {
+        long long nsys = 0;
+        for (int k = 0; k < K; ++k)
+          if (off[k + 1] - off[k] > cap) nsys += off[k + 1] - off[k];
+        mg_bytes = nil::amg_fill_bytes(c->amg_fill, nsys);
+      }
       rep->fill_px_iters = pxit;
       rep->fill_large_px_iters = lpxit;
       rep->fill_iters_max = itmax;
@@ -639,6 +646,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->fill_split = n_large > 0 && !mg ? c->fill_split : 0;
     rep->fill_mg_levels = mg_levels;
     rep->ms_fill_mg_build = mg_build_ms;
+    rep->fill_mg_bytes = mg_bytes;
   }
   if (notconv > 0) {
     c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";

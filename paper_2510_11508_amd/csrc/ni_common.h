@@ -165,6 +165,9 @@ int amg_levels(const Amg*);
 hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, const double* qw, const double* diag,
                      const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st,
                      const int* gy = nullptr, const int* gx = nullptr, const int* gc = nullptr, int ncomp = 0);
+// algorithmic HBM bytes of one batched-fill PCG iteration (n_sys: rows that
+// belong to a system)
+double amg_fill_bytes(const Amg*, long long n_sys);
 // coarse-correction factor of the cycle (1 unless set)
 void amg_set_corr(Amg*, double corr);
 // Batched PCG of independent component systems on level 0 (block
