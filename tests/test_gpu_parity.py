@@ -146,6 +146,44 @@ def test_fill_fixed_schedules(ctx, chunk, split):
     assert rep["fill_notconv"] == 0
 
 
+def degenerate_large_map():
+    """Two components that just take the large path: a serpentine one pixel
+    wide (8256 px: 2x2 aggregates of a line only halve it per level) and a
+    block of exactly 8193 px, on a smooth orthographic quadric with a little
+    seeded noise (every neighbour pair similar at 2 degrees)."""
+    H, W = 160, 330
+    n, _, _, cam = synth.quadric_ortho(H, W, (1e-4, 2e-5, 1.5e-4, 0.01, -0.02, 5.0))
+    rng = np.random.default_rng(7)
+    n = n + rng.normal(0.0, 0.002, n.shape)
+    n = (n / np.linalg.norm(n, axis=-1, keepdims=True)).astype(np.float32)
+    m = np.zeros((H, W), np.uint8)
+    m[0:128:2, 0:128] = 1
+    for r in range(1, 128, 2):
+        m[r, 127 if (r // 2) % 2 == 0 else 0] = 1
+    m[0:43, 140:330] = 1
+    m[43, 140:163] = 1
+    return n, m, cam
+
+
+@pytest.mark.parametrize("precond", [1, 0])
+def test_fill_degenerate_large_components(ctx, precond):
+    n, m, cam = degenerate_large_map()
+    e = O.edges(n, m, cam, 2.0)
+    lab, K = O.labels(e)
+    sizes = sorted(np.bincount(lab[lab >= 0]).tolist())
+    assert K == 2 and sizes == [8193, 8256], sizes
+    zref = O.fill(e, lab, K)
+    log(f"[fill degenerate] serpentine + 8193-px block, precond {precond}")
+    z, rep = ctx.ni_fill(dev(n), dev(m), cam.as_dict(), dev(lab), K, params(fill_precond=precond))
+    assert rep["n_large"] == 2
+    if precond == 1:
+        assert rep["fill_mg_levels"] > 1
+    z = z.cpu().numpy().astype(np.float64)
+    v = m > 0
+    assert np.abs(z[v] - zref[v]).max() <= 1e-6 + 1e-4 * np.abs(zref[v]).max()
+    assert rep["fill_notconv"] == 0
+
+
 # ------------------------------------------------------------------- IRLS
 @pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0), ("tiny-persp", 1), ("tiny-ortho", 0)])
 @pytest.mark.parametrize("mode", [1, 2, 0])
