@@ -468,6 +468,211 @@ __global__ void __launch_bounds__(QWG) k_qcg_wg(QMat M, double* __restrict__ s, 
   if (threadIdx.x == 0) *iters_out = it;
 }
 
+// The same iteration for K <= QR3 * QWG with the matrix staged once per
+// solve, so that the loop touches no global memory: rows of at most QRE
+// entries keep them in registers (column indices packed two per register),
+// longer rows are listed in LDS with their entries (summed by the thread
+// that owns the row, or by a wavefront with lanes strided over the entries
+// above QMID entries), and the solution stays in registers until the end.
+// If the long rows do not fit (more than QHROWS rows, QHCAP entries or
+// QBROWS wavefront rows), each thread sums its own long rows from global
+// memory.
+constexpr int QR3 = 3, QRE = 4, QHCAP = 8192, QHROWS = 1536, QMID = 32, QBROWS = 256;
+__global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s, double rtol, int maxit,
+                                                 int* __restrict__ iters_out) {
+  __shared__ double ul[QR3 * QWG];
+  __shared__ double wl[QR3 * QWG];
+  __shared__ double hw[QHCAP];
+  __shared__ uint16_t hc[QHCAP];
+  __shared__ int hoff[QHROWS + 1];
+  __shared__ int hrow[QHROWS];
+  __shared__ int blist[QBROWS];
+  __shared__ double red0[QNW];
+  __shared__ double red[3 * QNW];
+  __shared__ int nlong_s, nbig_s;
+  const int K = M.K;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    nlong_s = 0;
+    nbig_s = 0;
+  }
+  __syncthreads();
+  // rows of this thread: entries in registers, or listed as long
+  uint32_t lc[QR3][QRE / 2];
+  double lw[QR3][QRE];
+  double r[QR3], p[QR3], h[QR3], di[QR3], sx[QR3];
+  int smask = 0;  // bit k: row k is short (entries in registers)
+  int lmask = 0;  // bit k: row k is long
+  int tmask = 0;  // bit k: row k is long and summed by this thread
+  int lidx[QR3];  // list index of a long row
+  double v0[1] = {0.0};
+#pragma unroll
+  for (int k = 0; k < QR3; ++k) {
+    const int c = threadIdx.x + k * QWG;
+    r[k] = p[k] = h[k] = di[k] = sx[k] = 0.0;
+    lidx[k] = 0;
+    int j0 = 0, n = 0;
+    if (c < K) {
+      j0 = M.row_off[c];
+      n = M.row_off[c + 1] - j0;
+      if (n <= QRE) {
+        smask |= 1 << k;
+      } else {
+        lmask |= 1 << k;
+        const int idx = atomicAdd(&nlong_s, 1);
+        lidx[k] = idx;
+        if (idx < QHROWS) {
+          hrow[idx] = c;
+          hoff[idx] = n;  // the length for now; offsets below
+          if (n > QMID) {
+            const int b = atomicAdd(&nbig_s, 1);
+            if (b < QBROWS) blist[b] = idx;
+          } else {
+            tmask |= 1 << k;
+          }
+        }
+      }
+    }
+    const bool sh = (smask >> k) & 1;
+#pragma unroll
+    for (int e = 0; e < QRE; e += 2) {
+      const uint32_t c0 = sh && e < n ? (uint32_t)M.qcol[j0 + e] : (uint32_t)max(c, 0);
+      const uint32_t c1 = sh && e + 1 < n ? (uint32_t)M.qcol[j0 + e + 1] : (uint32_t)max(c, 0);
+      lc[k][e / 2] = c0 | (c1 << 16);
+      lw[k][e] = sh && e < n ? M.qw[j0 + e] : 0.0;
+      lw[k][e + 1] = sh && e + 1 < n ? M.qw[j0 + e + 1] : 0.0;
+    }
+    if (c < K) {
+      const double dg = M.diag[c];
+      di[k] = dg > 0 ? 1.0 / dg : 0.0;
+      r[k] = M.rhs[c];
+      ul[c] = r[k] * di[k];
+      v0[0] += M.babs[c] * M.babs[c];
+    }
+  }
+  __syncthreads();
+  const int nlong = nlong_s;
+  // offsets of the listed rows (one wavefront, 64 rows at a time)
+  if (wid == 0 && nlong <= QHROWS) {
+    int base = 0;
+    for (int h0 = 0; h0 < nlong; h0 += 64) {
+      const int hh = h0 + lane;
+      const int len = hh < nlong ? hoff[hh] : 0;
+      int inc = len;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+      }
+      if (hh < nlong) hoff[hh] = base + inc - len;
+      base += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) hoff[nlong] = base;
+  }
+  __syncthreads();
+  const int nbig = nbig_s;
+  const bool hl = nlong <= QHROWS && nbig <= QBROWS && hoff[nlong] <= QHCAP;
+  if (hl) {
+    for (int hh = wid; hh < nlong; hh += QNW) {
+      const int c = hrow[hh], j0 = M.row_off[c], o = hoff[hh], n = hoff[hh + 1] - o;
+      for (int j = lane; j < n; j += 64) {
+        hc[o + j] = (uint16_t)M.qcol[j0 + j];
+        hw[o + j] = M.qw[j0 + j];
+      }
+    }
+  }
+  ni::block_sum<1>(v0, red0);  // its barrier also publishes ul and the LDS rows
+  const double tol2 = rtol * rtol * v0[0];
+  double gam_old = 1.0, alp_old = 1.0;
+  int it = 0;
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < QR3; ++k) {
+      const int c = threadIdx.x + k * QWG;
+      if ((smask >> k) & 1) {
+        const double uc = ul[c];
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < QRE; ++e) {
+          const int d = (int)((lc[k][e / 2] >> (16 * (e & 1))) & 0xFFFFu);
+          acc += lw[k][e] * (uc - ul[d]);
+        }
+        wl[c] = acc;
+      }
+    }
+    if (hl) {
+#pragma unroll
+      for (int k = 0; k < QR3; ++k) {
+        if ((tmask >> k) & 1) {
+          const int c = threadIdx.x + k * QWG;
+          const double uc = ul[c];
+          double acc = 0.0;
+          for (int j = hoff[lidx[k]]; j < hoff[lidx[k] + 1]; ++j) acc += hw[j] * (uc - ul[hc[j]]);
+          wl[c] = acc;
+        }
+      }
+      for (int bb = wid; bb < nbig; bb += QNW) {
+        const int hh = blist[bb];
+        const int c = hrow[hh];
+        const double uc = ul[c];
+        double acc = 0.0;
+        for (int j = hoff[hh] + lane; j < hoff[hh + 1]; j += 64) acc += hw[j] * (uc - ul[hc[j]]);
+        acc = ni::wave_sum(acc);
+        if (lane == 0) wl[c] = acc;
+      }
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < QR3; ++k) {
+        const int c = threadIdx.x + k * QWG;
+        if ((lmask >> k) & 1) {
+          const double uc = ul[c];
+          double acc = 0.0;
+          for (int j = M.row_off[c]; j < M.row_off[c + 1]; ++j) acc += M.qw[j] * (uc - ul[M.qcol[j]]);
+          wl[c] = acc;
+        }
+      }
+    }
+    if (nlong > 0) __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < QR3; ++k) {
+      const int c = threadIdx.x + k * QWG;
+      if (c < K) {
+        const double uc = r[k] * di[k];
+        v[0] += r[k] * uc;
+        v[1] += wl[c] * uc;
+        v[2] += r[k] * r[k];
+      }
+    }
+    ni::block_sum<3>(v, red);
+    if (!(v[2] > tol2) || it >= maxit) break;
+    const double gam = v[0], del = v[1];
+    const double beta = it == 0 ? 0.0 : gam / gam_old;
+    const double alpha = it == 0 ? gam / del : gam / (del - beta * gam / alp_old);
+    gam_old = gam;
+    alp_old = alpha;
+#pragma unroll
+    for (int k = 0; k < QR3; ++k) {
+      const int c = threadIdx.x + k * QWG;
+      if (c < K) {
+        p[k] = r[k] * di[k] + beta * p[k];
+        h[k] = wl[c] + beta * h[k];
+        sx[k] += alpha * p[k];
+        r[k] -= alpha * h[k];
+        ul[c] = r[k] * di[k];
+      }
+    }
+    __syncthreads();  // u complete before the next product; red and wl free again
+    ++it;
+  }
+#pragma unroll
+  for (int k = 0; k < QR3; ++k) {
+    const int c = threadIdx.x + k * QWG;
+    if (c < K) s[c] = sx[k];
+  }
+  if (threadIdx.x == 0) *iters_out = it;
+}
+
 // Larger quotient systems: the same iteration, one launch per iteration.
 // Blocks [0, nblk) own QB consecutive rows each (light rows through the ELL
 // copy); the next nbig blocks form L u for one big row each, all QNT
@@ -912,7 +1117,10 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   M.row_off = a.row_off; M.qcol = a.qcol; M.qw = a.qw; M.ecol = a.ell_col; M.ew = a.ell_w;
   M.diag = a.diag; M.rhs = a.rhs; M.babs = a.babs; M.K = a.K;
   M.heavy = a.heavy; M.nheavy = a.nheavy; M.nbig = a.nbig;
-  if (a.K <= QCAP) {
+  if (a.K <= QR3 * QWG) {
+    k_qcg_wgr<<<1, QWG, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
+    e = hipGetLastError();
+  } else if (a.K <= QCAP) {
     k_qcg_wg<<<1, QWG, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
     e = hipGetLastError();
   } else if (a.amg) {
