@@ -222,7 +222,7 @@ def main():
     k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
     launches = max(rep["fill_large_launches"], 1)
     launch_ms = k_ms / launches
-    mg = rep["fill_mg_levels"] > 0
+    mg = rep["fill_mg_levels"] > 0 and not rep["fill_mg_fallback"]
     if mg:
         launch_bytes = rep["fill_mg_bytes"]
         key = "multigrid"
@@ -253,6 +253,7 @@ def main():
                 fill=dict(iters_max=rep["fill_iters_max"], n_small=rep["n_small"], n_large=rep["n_large"],
                           px_iters=rep["fill_px_iters"], max_relres=rep["fill_max_relres"],
                           preconditioner="multigrid" if mg else "jacobi",
+                          mg_fallback=rep["fill_mg_fallback"],
                           **(dict(mg_levels=rep["fill_mg_levels"], mg_iterations=launches)
                              if mg else dict(tuned_schedule=dict(chunk_px=rep["fill_chunk"],
                                                                  launches_per_iteration=3 if rep["fill_split"] else 2)))),

@@ -93,6 +93,9 @@ typedef struct {
                            1 multigrid (aggregates of 2x2 pixel blocks per
                            component, V(1,1) cycle), 0 Jacobi (the chunked
                            schedule above)                                   */
+  int32_t fill_mg_maxit; /* iteration cap of the multigrid fill solve before
+                            the large components fall back to the Jacobi
+                            path (0: 2000)                                   */
 } ni_params;
 
 typedef struct {
@@ -123,6 +126,10 @@ typedef struct {
   float ms_fill_mg_build; /* its level-0 system and hierarchy build         */
   double fill_mg_bytes;   /* algorithmic HBM bytes of one of its PCG
                              iterations (every level; FP64 values)         */
+  int32_t fill_mg_fallback; /* 1: the multigrid solve did not converge
+                               within fill_mg_maxit iterations and the
+                               large components were solved again with
+                               the Jacobi path                             */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;

@@ -234,6 +234,7 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
     return bad("fill_chunk must be 0, 512, 1024, 2048 or 4096");
   if (prm->fill_split != 0 && prm->fill_split != 1) return bad("fill_split must be 0 or 1");
   if (prm->fill_precond != 0 && prm->fill_precond != 1) return bad("fill_precond must be 0 or 1");
+  if (prm->fill_mg_maxit < 0) return bad("fill_mg_maxit must be >= 0");
   if (prm->warm_start && !c->unet) {
     c->err = "warm_start needs a model (ni_unet_load)";
     return NI_E_MODEL;
@@ -516,7 +517,11 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
                              c->stream),
           "fill small");
   mark(c, 6);
-  int launches = 0, mg_levels = 0;
+  int launches = 0, mg_levels = 0, mg_fallback = 0;
+  bool jacobi = n_large > 0 && !mg;
+  // iteration cap of the multigrid solve (it needs tens); a stall beyond it
+  // falls back to the Jacobi path with the caller's cap
+  const int mg_maxit = std::min(pb.prm.cg_max_iter, pb.prm.fill_mg_maxit > 0 ? pb.prm.fill_mg_maxit : 2000);
   float large_kernel_ms = 0.f, mg_build_ms = 0.f;
   double mg_bytes = 0.0;
   if (mg) {
@@ -562,18 +567,29 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     mark(c, 12);
     int its = 0;
     check(c,
-          nil::amg_fill_solve(c->amg_fill, gc, lists + 3 * K1, n_large, K, b64, x64, pb.prm.cg_rtol,
-                              pb.prm.cg_max_iter, warm, rr, bb, iters, misc(c) + M_STATS, c->host, &its, c->stream),
+          nil::amg_fill_solve(c->amg_fill, gc, lists + 3 * K1, n_large, K, b64, x64, pb.prm.cg_rtol, mg_maxit,
+                              warm, rr, bb, iters, misc(c) + M_STATS, c->host, &its, c->stream),
           "mg solve");
     mark(c, 13);
-    check(c, nil::mg_out(N, ptr<uint32_t>(c->skey), comp_off, x64, x, c->stream), "mg out");
-    check(c, nil::large_finish(a, cpix, zout, c->stream), "large finish");
-    check(c, hipStreamSynchronize(c->stream), "sync");
+    readback(c, misc(c) + M_STATS, sizeof(int), c->host);
     launches = its;
     large_kernel_ms = ev_ms(c, 12, 13);
     mg_build_ms = ev_ms(c, 14, 12);
     mg_levels = nil::amg_levels(c->amg_fill);
-  } else if (n_large > 0) {
+    if (c->host[0] > 0 && mg_maxit < pb.prm.cg_max_iter) {
+      // the multigrid solve stalled: solve the large components again with
+      // the Jacobi preconditioner, from the same start
+      check(c, hipMemsetAsync(misc(c) + M_STATS, 0, sizeof(int), c->stream), "memset");
+      check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
+      mg_fallback = 1;
+      jacobi = true;
+      launches = 0;
+    } else {
+      check(c, nil::mg_out(N, ptr<uint32_t>(c->skey), comp_off, x64, x, c->stream), "mg out");
+      check(c, nil::large_finish(a, cpix, zout, c->stream), "large finish");
+    }
+  }
+  if (jacobi) {
     nil::LargeArgs a = large_args();
     check(c, hipMemsetAsync(a.active, 0, 2 * sizeof(int), c->stream), "memset");
     check(c, nil::large_init(a, warm, c->stream), "large init");
@@ -647,6 +663,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->fill_mg_levels = mg_levels;
     rep->ms_fill_mg_build = mg_build_ms;
     rep->fill_mg_bytes = mg_bytes;
+    rep->fill_mg_fallback = mg_fallback;
   }
   if (notconv > 0) {
     c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";
@@ -856,6 +873,7 @@ ni_status ni_params_default(ni_params* p) {
   p->fill_chunk = 0;
   p->fill_split = 0;
   p->fill_precond = 1;
+  p->fill_mg_maxit = 0;
   return NI_OK;
 }
 

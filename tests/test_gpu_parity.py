@@ -165,6 +165,24 @@ def degenerate_large_map():
     return n, m, cam
 
 
+def test_fill_multigrid_fallback(ctx):
+    """A multigrid solve stopped early (cap 3) hands the large components
+    to the Jacobi path, which finishes them to the same bound."""
+    s = sample("c2", 0)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0)
+    lab, K = O.labels(e)
+    zref = O.fill(e, lab, K)
+    log("[fill fallback] c2 seed 0, multigrid cap 3")
+    z, rep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K, params(fill_mg_maxit=3))
+    assert rep["fill_mg_fallback"] == 1 and rep["n_large"] > 0
+    z = z.cpu().numpy().astype(np.float64)
+    v = s.mask > 0
+    assert np.abs(z[v] - zref[v]).max() <= 1e-6 + 1e-4
+    assert rep["fill_notconv"] == 0
+    z2, rep2 = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(lab), K, params())
+    assert rep2["fill_mg_fallback"] == 0
+
+
 @pytest.mark.parametrize("precond", [1, 0])
 def test_fill_degenerate_large_components(ctx, precond):
     n, m, cam = degenerate_large_map()
@@ -403,7 +421,7 @@ def test_bad_arguments(ctx):
     s = synth.tiny(0)
     for kw in [dict(connectivity=8), dict(irls_iters=0), dict(outlier_mode=5), dict(out_L=1e-2),
                dict(warm_start=1), dict(fill_chunk=300), dict(fill_chunk=1024, fill_split=2),
-               dict(fill_precond=2)]:
+               dict(fill_precond=2), dict(fill_mg_maxit=-1)]:
         log(f"[edge] bad params {kw}")
         with pytest.raises(ni.NIError) as ex:
             ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), params(**kw))
