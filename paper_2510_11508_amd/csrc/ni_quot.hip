@@ -504,6 +504,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   int smask = 0;  // bit k: row k is short (entries in registers)
   int lmask = 0;  // bit k: row k is long
   int tmask = 0;  // bit k: row k is long and summed by this thread
+  int bmask = 0;  // bit k: row k is summed by a wavefront (its (w, u) term too)
   int lidx[QR3];  // list index of a long row
   double v0[1] = {0.0};
 #pragma unroll
@@ -527,6 +528,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
           if (n > QMID) {
             const int b = atomicAdd(&nbig_s, 1);
             if (b < QBROWS) blist[b] = idx;
+            bmask |= 1 << k;
           } else {
             tmask |= 1 << k;
           }
@@ -572,6 +574,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   __syncthreads();
   const int nbig = nbig_s;
   const bool hl = nlong <= QHROWS && nbig <= QBROWS && hoff[nlong] <= QHCAP;
+  if (!hl) bmask = 0;
   if (hl) {
     for (int hh = wid; hh < nlong; hh += QNW) {
       const int c = hrow[hh], j0 = M.row_off[c], o = hoff[hh], n = hoff[hh + 1] - o;
@@ -586,6 +589,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   double gam_old = 1.0, alp_old = 1.0;
   int it = 0;
   for (;;) {
+    double vbig = 0.0;
 #pragma unroll
     for (int k = 0; k < QR3; ++k) {
       const int c = threadIdx.x + k * QWG;
@@ -618,7 +622,10 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
         double acc = 0.0;
         for (int j = hoff[hh] + lane; j < hoff[hh + 1]; j += 64) acc += hw[j] * (uc - ul[hc[j]]);
         acc = ni::wave_sum(acc);
-        if (lane == 0) wl[c] = acc;
+        if (lane == 0) {
+          wl[c] = acc;
+          vbig += acc * uc;
+        }
       }
     } else {
 #pragma unroll 1
@@ -632,15 +639,16 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
         }
       }
     }
-    if (nlong > 0) __syncthreads();
-    double v[3] = {0.0, 0.0, 0.0};
+    // no barrier here: every row's (w, u) term is added by the thread that
+    // formed w (the reduction's barrier then publishes wl for the update)
+    double v[3] = {0.0, vbig, 0.0};
 #pragma unroll
     for (int k = 0; k < QR3; ++k) {
       const int c = threadIdx.x + k * QWG;
       if (c < K) {
         const double uc = r[k] * di[k];
         v[0] += r[k] * uc;
-        v[1] += wl[c] * uc;
+        if (!((bmask >> k) & 1)) v[1] += wl[c] * uc;
         v[2] += r[k] * r[k];
       }
     }
