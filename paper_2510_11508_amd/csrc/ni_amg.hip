@@ -44,7 +44,7 @@ constexpr int AMAXL = 24;     // levels at most
 constexpr double AOMEGA = 2.0 / 3.0;
 
 // scalars of the PCG, one double each
-enum { S_RHO = 0, S_RHOP, S_BETA, S_ALPHA, S_RR, S_BS, S_PQ, S_N };
+enum { S_RHO = 0, S_RHOP, S_BETA, S_ALPHA, S_RR, S_BS, S_PQ, S_RH0, S_RH1, S_N };
 
 // device view of one level
 struct ALev {
@@ -347,6 +347,76 @@ __global__ void __launch_bounds__(ANT) k_cg_scal(int mode, const double* __restr
       sc[S_ALPHA] = pq != 0.0 ? sc[S_RHO] / pq : 0.0;
     }
   }
+}
+
+// Fused forms of the scalar steps (stream launches; the iteration index `it`
+// comes from the host).  Every block sums the same partials in the same
+// order, so all blocks take the same decisions and scalars without a
+// one-block kernel between the launches.  rho of iteration it is kept in
+// slot S_RH0 + (it & 1): blocks read the previous iteration's slot while
+// block 0 writes the current one.  Partials: rho at parts (from the
+// finest k_cy_up), (r, r) at parts + pstride, (p, q) at parts + 2 pstride.
+__global__ void __launch_bounds__(ANT) k_cg_pq_f(ALev L, double* __restrict__ p, double* __restrict__ q,
+                                                 double* __restrict__ sc, double* __restrict__ parts, int pstride,
+                                                 int np, int nrr, int it, double rtol, int maxit,
+                                                 int* __restrict__ done, int* __restrict__ flag,
+                                                 int* __restrict__ iters_out) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const double rho = sum_parts(parts, np, red);
+  __syncthreads();
+  const double rr = it > 0 ? sum_parts(parts + pstride, nrr, red) : sc[S_RR];
+  if (!(rr > rtol * rtol * sc[S_BS]) || it >= maxit) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *done = 1;
+      *flag = 0;
+      *iters_out = it;
+    }
+    return;
+  }
+  const double beta = it == 0 ? 0.0 : rho / sc[S_RH0 + ((it - 1) & 1)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_RH0 + (it & 1)] = rho;
+  const RowSel s = row_sel(L);
+  const double* z = L.y;
+  auto zv = [&](int d) { return z[d]; };
+  double acc = 0.0;
+  if (s.c >= 0) acc = row_diff_sum(L, s, z[s.c], zv);
+  __syncthreads();  // red is reused below
+  if (s.big) {
+    double t[1] = {acc};
+    ni::block_sum<1>(t, red);
+    acc = t[0];
+  }
+  double v[1] = {0.0};
+  if (s.c >= 0 && (!s.big || threadIdx.x == 0)) {
+    const double pn = z[s.c] + beta * p[s.c];
+    const double qn = acc + beta * q[s.c];
+    p[s.c] = pn;
+    q[s.c] = qn;
+    v[0] = pn * qn;
+  }
+  __syncthreads();
+  put_parts<1>(v, red, parts + 2 * (size_t)pstride, pstride);
+}
+
+__global__ void __launch_bounds__(ANT) k_cg_xr_f(int n, double* __restrict__ x, double* __restrict__ r,
+                                                 const double* __restrict__ p, const double* __restrict__ q,
+                                                 const double* __restrict__ sc, double* __restrict__ parts,
+                                                 int pstride, int np, int it, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const double pq = sum_parts(parts + 2 * (size_t)pstride, np, red);
+  const double a = pq != 0.0 ? sc[S_RH0 + (it & 1)] / pq : 0.0;
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  double v[1] = {0.0};
+  if (c < n) {
+    x[c] += a * p[c];
+    const double rn = r[c] - a * q[c];
+    r[c] = rn;
+    v[0] = rn * rn;
+  }
+  __syncthreads();  // red is reused below
+  put_parts<1>(v, red, parts + pstride, pstride);
 }
 
 // ------------------------------------------------------------------ setup
@@ -1360,7 +1430,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   double* q = grow<double>(A->q, n, err);
   double* r = grow<double>(A->r, n, err);
   const int pstride = nblk + L0->nheavy;
-  double* parts = grow<double>(A->parts, 2 * (size_t)pstride, err);
+  double* parts = grow<double>(A->parts, 3 * (size_t)pstride, err);
   double* sc = grow<double>(A->sc, S_N, err);
   int* ctr = grow<int>(A->ctr, 8, err);  // [0] done, [1] iteration, [2] flag
   AMG_TRY(err);
@@ -1403,11 +1473,19 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
       if (e) (void)hipGraphExecDestroy(e);
     }
   } guard{ge};
+  // stream launches: the scalar steps fused into the (p, q) and (x, r)
+  // kernels (the captured graph keeps the separate one-block kernels)
+  auto fused = [&](int it) {
+    launch_cycle(A, V, parts, pstride, done, st);
+    k_cg_pq_f<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, pstride, nblk, it, rtol,
+                                                      maxit, done, flag, iters_out);
+    k_cg_xr_f<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts, pstride, pstride, it, done);
+  };
   const int batch = 8;
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
       if (ge) AMG_TRY(hipGraphLaunch(ge, st));
-      else iteration(st);
+      else fused(it + k);
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
