@@ -91,6 +91,7 @@ struct Fail {
 struct ni_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // small-component tiers, concurrent with the large solve
   std::string err;
   std::vector<Buf*> bufs;
   // grid
@@ -510,13 +511,17 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     xw = xg;
   }
   check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
+  // the small components run on a side stream while the large ones are
+  // solved here: they touch disjoint pixels, components and counters
+  // (the large solve counts into M_STATS + 2 .. 3); joined before the end
   mark(c, 5);
+  check(c, hipStreamWaitEvent(c->side, c->ev[5], 0), "fork");
   for (int t = 1; t <= 3; ++t)
     check(c, nil::fill_small(t, lists + (t - 1) * K1, ntier[t - 1], comp_off, cst, rhs, dinv, x,
                              cpix, zout, pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, iters, relres, misc(c) + M_STATS,
-                             c->stream),
+                             c->side),
           "fill small");
-  mark(c, 6);
+  check(c, hipEventRecord(c->ev[6], c->side), "event");
   int launches = 0, mg_levels = 0, mg_fallback = 0;
   bool jacobi = n_large > 0 && !mg;
   // iteration cap of the multigrid solve (it needs tens); a stall beyond it
@@ -568,10 +573,10 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     int its = 0;
     check(c,
           nil::amg_fill_solve(c->amg_fill, gc, lists + 3 * K1, n_large, K, b64, x64, pb.prm.cg_rtol, mg_maxit,
-                              warm, rr, bb, iters, misc(c) + M_STATS, c->host, &its, c->stream),
+                              warm, rr, bb, iters, misc(c) + M_STATS + 2, c->host, &its, c->stream),
           "mg solve");
     mark(c, 13);
-    readback(c, misc(c) + M_STATS, sizeof(int), c->host);
+    readback(c, misc(c) + M_STATS + 2, sizeof(int), c->host);
     launches = its;
     large_kernel_ms = ev_ms(c, 12, 13);
     mg_build_ms = ev_ms(c, 14, 12);
@@ -579,7 +584,8 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     if (c->host[0] > 0 && mg_maxit < pb.prm.cg_max_iter) {
       // the multigrid solve stalled: solve the large components again with
       // the Jacobi preconditioner, from the same start
-      check(c, hipMemsetAsync(misc(c) + M_STATS, 0, sizeof(int), c->stream), "memset");
+      check(c, hipStreamWaitEvent(c->stream, c->ev[6], 0), "join");  // the small tiers read x
+      check(c, hipMemsetAsync(misc(c) + M_STATS + 2, 0, 2 * sizeof(int), c->stream), "memset");
       check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
       mg_fallback = 1;
       jacobi = true;
@@ -610,9 +616,11 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     large_kernel_ms = kms;
     check(c, nil::large_finish(a, cpix, zout, c->stream), "large finish");
   }
+  check(c, hipEventRecord(c->ev[15], c->stream), "event");  // end of the large solve
+  check(c, hipStreamWaitEvent(c->stream, c->ev[6], 0), "join");
   mark(c, 7);
   readback(c, misc(c) + M_STATS, 4 * sizeof(int), c->host);
-  const int notconv = c->host[0], fallbacks = c->host[1];
+  const int notconv = c->host[0] + c->host[2], fallbacks = c->host[1] + c->host[3];
   if (rep) {
     std::vector<int> it(K), off(K1);
     std::vector<double> rel(K), hrr(K), hbb(K);
@@ -656,7 +664,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->ms_assemble = ev_ms(c, 3, 4);
     rep->ms_warm = ev_ms(c, 4, 5);
     rep->ms_fill_small = ev_ms(c, 5, 6);
-    rep->ms_fill_large = ev_ms(c, 6, 7);
+    rep->ms_fill_large = ev_ms(c, 5, 15);
     rep->ms_large_kernel = large_kernel_ms;
     rep->fill_chunk = n_large > 0 && !mg ? c->fill_chunk : 0;
     rep->fill_split = n_large > 0 && !mg ? c->fill_split : 0;
@@ -889,6 +897,7 @@ ni_status ni_create(ni_ctx** out, int device) {
     check(c, hipSetDevice(device), "hipSetDevice");
     check(c, hipHostMalloc((void**)&c->host, 64 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     for (auto& e : c->ev) check(c, hipEventCreate(&e), "hipEventCreate");
+    check(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "hipStreamCreate");
   });
   if (s != NI_OK) {
     ni_destroy(c);
@@ -903,6 +912,10 @@ ni_status ni_destroy(ni_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
   for (Buf* b : c->bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& e : c->ev)
