@@ -1474,7 +1474,11 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
     }
   } guard{ge};
   // stream launches: the scalar steps fused into the (p, q) and (x, r)
-  // kernels (the captured graph keeps the separate one-block kernels)
+  // kernels (the captured graph keeps the separate one-block kernels).
+  // Every block re-reads every block's partials, so this pays only while
+  // the partials are few: beyond FUSE_MAX the one-block kernels stay.
+  constexpr int FUSE_MAX = 1024;
+  const bool fuse = pstride <= FUSE_MAX;
   auto fused = [&](int it) {
     launch_cycle(A, V, parts, pstride, done, st);
     k_cg_pq_f<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, pstride, nblk, it, rtol,
@@ -1485,7 +1489,8 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
       if (ge) AMG_TRY(hipGraphLaunch(ge, st));
-      else fused(it + k);
+      else if (fuse) fused(it + k);
+      else iteration(st);
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
