@@ -142,7 +142,10 @@ typedef struct ni_ctx ni_ctx;
 ni_status ni_params_default(ni_params* p);
 
 /* Create a context on HIP device `device`; it owns a device workspace that
- * grows on demand and is freed by ni_destroy.  *out is set to NULL on error. */
+ * grows on demand and is freed by ni_destroy, and a second stream (default
+ * priority) on which the small components are filled while the large ones
+ * are solved on the caller's stream; every call joins it before it
+ * returns.  *out is set to NULL on error. */
 ni_status ni_create(ni_ctx** out, int device);
 ni_status ni_destroy(ni_ctx* ctx);
 
