@@ -159,19 +159,24 @@ __global__ void __launch_bounds__(ANT) k_cy_restrict(int n, int nblk, const int*
   if (C >= 0 && (!big || threadIdx.x == 0)) bc[C] = acc;
 }
 
-// exact coarsest solve y = A^+ b with the pinned inverse (one block)
-__global__ void __launch_bounds__(AMAXC) k_cy_coarsest(int n, const double* __restrict__ ainv,
+// exact coarsest solve y = A^+ b with the pinned inverse: one block of
+// CO_NT threads, CO_P per output (strided over the inverse's rows, then
+// summed over those lanes in a fixed order)
+constexpr int CO_P = 8, CO_NT = AMAXC * CO_P;
+__global__ void __launch_bounds__(CO_NT) k_cy_coarsest(int n, const double* __restrict__ ainv,
                                                        const uint8_t* __restrict__ pin, const double* __restrict__ b,
                                                        double* __restrict__ y, const int* done) {
   if (is_done(done)) return;
   __shared__ double bl[AMAXC];
   for (int i = threadIdx.x; i < n; i += blockDim.x) bl[i] = pin[i] ? 0.0 : b[i];
   __syncthreads();
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += ainv[(size_t)j * n + c] * bl[j];  // symmetric: column c = row c
-    y[c] = acc;
-  }
+  const int c = threadIdx.x / CO_P, part = threadIdx.x % CO_P;
+  double acc = 0.0;
+  if (c < n)
+    for (int j = part; j < n; j += CO_P) acc += ainv[(size_t)j * n + c] * bl[j];  // symmetric: column c = row c
+#pragma unroll
+  for (int o = 1; o < CO_P; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (c < n && part == 0) y[c] = acc;
 }
 
 // prolongation and post-smoothing: x = w D^-1 b + corr P y',
@@ -1404,7 +1409,7 @@ static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts
   }
   const ALev& Lc = V[A->nlev - 1];
   if (A->dense) {
-    k_cy_coarsest<<<1, AMAXC, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
+    k_cy_coarsest<<<1, CO_NT, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
                                        static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
   } else {  // no exact coarsest: smoothing only
     k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, A->corr,
