@@ -306,11 +306,12 @@ __device__ __forceinline__ double sum_parts(const double* parts, int n, double* 
 // parts; rr of the last update from nrr partials at parts + pstride (none
 // before the first update); convergence test, beta.  mode 2 (after (p, q)):
 // alpha.
-__global__ void __launch_bounds__(ANT) k_cg_scal(int mode, const double* __restrict__ parts, int np, int pstride,
-                                                 int nrr, double* __restrict__ sc, int* __restrict__ done,
-                                                 int* it_ctr, double rtol, int maxit, int* __restrict__ iters_out,
-                                                 int* __restrict__ flag) {
-  __shared__ double red[ANT / 64];
+constexpr int SC_NT = 1024;  // threads of the one-block scalar kernel (a short chain of loads each)
+__global__ void __launch_bounds__(SC_NT) k_cg_scal(int mode, const double* __restrict__ parts, int np, int pstride,
+                                                   int nrr, double* __restrict__ sc, int* __restrict__ done,
+                                                   int* it_ctr, double rtol, int maxit, int* __restrict__ iters_out,
+                                                   int* __restrict__ flag) {
+  __shared__ double red[SC_NT / 64];
   if (mode != 0 && is_done(done)) return;
   if (mode == 0) {
     const double rr = sum_parts(parts, nrr, red);
@@ -1443,7 +1444,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   int* itc = ctr + 1;
   int* flag = ctr + 2;
   k_cg_init<<<nblk, ANT, 0, st>>>(n, rhs, babs, s, r, p, q, parts, pstride);
-  k_cg_scal<<<1, ANT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+  k_cg_scal<<<1, SC_NT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
   // one PCG iteration: V-cycle on r -> z (= y of level 0), then the CG
@@ -1451,9 +1452,9 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   auto iteration = [&](hipStream_t q_) {
     launch_cycle(A, V, parts, pstride, done, q_);
     // rho = (r, z) -> beta; convergence on ||r||
-    k_cg_scal<<<1, ANT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+    k_cg_scal<<<1, SC_NT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
     k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, q_>>>(V[0], p, q, sc, parts, pstride, done);
-    k_cg_scal<<<1, ANT, 0, q_>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+    k_cg_scal<<<1, SC_NT, 0, q_>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
     k_cg_xr<<<nblk, ANT, 0, q_>>>(n, s, r, p, q, sc, parts + pstride, done);
   };
   // optionally the iteration's ~3 launches per level are captured once per
@@ -1543,7 +1544,7 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
       k_fs_scal1<<<1, ANT, 0, st>>>(parts, pstride, list, nl, rrc, rr, bb, iters, stats, sc, done, itc, rtol, maxit,
                                     flag);
       k_cg_pq<<<nblk, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
-      k_cg_scal<<<1, ANT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
+      k_cg_scal<<<1, SC_NT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
       k_fs_xr<<<nb256((n + FS_R - 1) / FS_R), ANT, 0, st>>>(n, comp, x, r, p, q, sc, rrc, done);
     }
     AMG_TRY(hipGetLastError());
