@@ -246,7 +246,7 @@ def main():
 
     line = dict(metric=METRIC, value=round(value, 3), unit="Mpx/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
                 ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
-                dtype="f32 vectors / f64 reductions", data="synthetic",
+                dtype="f32 stencil and small-component CG, f64 multigrid CG and reductions", data="synthetic",
                 config=dict(workload=f"{a.workload}: {WORKLOADS[a.workload]}", seed=a.seed, n_valid=n_valid,
                             K=out["K"], H=int(s.mask.shape[0]), W=int(s.mask.shape[1])),
                 stages_ms=stage_ms(reps),
