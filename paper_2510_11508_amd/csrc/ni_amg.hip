@@ -731,16 +731,16 @@ __global__ void __launch_bounds__(1024) k_am_invert(int n, const int* __restrict
 // Pixel graphs carry coordinates: a node of level l stands for the pixels
 // of one component inside a 2^l x 2^l block.  Its aggregate on level l+1 is
 // the set of nodes of the same component in the same 2x2 block of level-l
-// cells (at most four).  Keys: the cell of the aggregate (y>>1, x>>1, 14
-// bits each) and the component.
+// cells (at most four).  Keys: the cell of the aggregate ((y>>1) << bx |
+// x>>1, bx bits for x>>1 on this level) and the component.
 __global__ void k_gm_keys(int n, const double* __restrict__ diag, const int* __restrict__ gy,
-                          const int* __restrict__ gx, const int* __restrict__ gc, int* __restrict__ kcell,
+                          const int* __restrict__ gx, const int* __restrict__ gc, int bx, int* __restrict__ kcell,
                           uint32_t* __restrict__ kcomp, int* __restrict__ flag) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const bool a = diag[c] > 0.0 && gc[c] >= 0;
   flag[c] = a ? 1 : 0;
-  kcell[c] = ((gy[c] >> 1) << 14) | (gx[c] >> 1);
+  kcell[c] = ((gy[c] >> 1) << bx) | (gx[c] >> 1);
   kcomp[c] = a ? (uint32_t)gc[c] : 0u;
 }
 
@@ -1127,7 +1127,11 @@ static void level_values(AmgLevel* L, const double* pwf, hipStream_t st) {
 // sum > 0) is sorted on (component, aggregate cell) with its index as the
 // value (stable sorts keep equal keys in index order), and joins the
 // aggregate led by the first node of its run.  Inactive nodes: agg2 = -1.
-static hipError_t geo_aggregate(Amg* A, const AmgLevel* F, int ncomp, int* agg2, int* lead, hipStream_t st) {
+// (a level-l coordinate is the level-0 one shifted right by l, so x >> 1 is
+// at most (gw - 1) >> (l + 1): the key takes bx + by bits)
+static hipError_t geo_aggregate(Amg* A, const AmgLevel* F, int l, int gw, int gh, int ncomp, int* agg2, int* lead,
+                                hipStream_t st) {
+  const int bx = bits_for(((gw - 1) >> (l + 1)) + 1), by = bits_for(((gh - 1) >> (l + 1)) + 1);
   hipError_t err = hipSuccess;
   const int n = F->n;
   int* kcell = grow<int>(A->s[14], n, err);
@@ -1149,13 +1153,13 @@ static hipError_t geo_aggregate(Amg* A, const AmgLevel* F, int ncomp, int* agg2,
   AMG_TRY(err);
   k_am_fill<<<nb256(n), 256, 0, st>>>(agg2, n, -1);
   k_am_fill<<<nb256(n), 256, 0, st>>>(lead, n, 0);
-  k_gm_keys<<<nb256(n), 256, 0, st>>>(n, F->diag, F->gy, F->gx, F->gc, kcell, kcomp, flag);
+  k_gm_keys<<<nb256(n), 256, 0, st>>>(n, F->diag, F->gy, F->gx, F->gc, bx, kcell, kcomp, flag);
   AMG_TRY(scan_exclusive_i32(flag, fpos, n, tot, scan, st));
   int m = 0;
   AMG_TRY(read_int(tot, &m, st));
   if (m <= 0) return hipGetLastError();
   k_am_compact<<<nb256(n), 256, 0, st>>>(n, flag, fpos, kcell, ko, vo);
-  AMG_TRY(radix_sort_pairs(ko, vo, k1, v1, tk, tv, m, 28, scan, st));
+  AMG_TRY(radix_sort_pairs(ko, vo, k1, v1, tk, tv, m, std::max(bx + by, 1), scan, st));
   k_am_gather<<<nb256(m), 256, 0, st>>>(m, kcomp, v1, k2);
   AMG_TRY(radix_sort_pairs(k2, v1, k3, v3, tk, tv, m, std::max(bits_for(ncomp), 1), scan, st));
   k_am_runs<<<nb256(m), 256, 0, st>>>(m, v3, kcomp, reinterpret_cast<const uint32_t*>(kcell), rflag);
@@ -1172,7 +1176,7 @@ static hipError_t geo_aggregate(Amg* A, const AmgLevel* F, int ncomp, int* agg2,
 // diag.
 hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, const double* qw,
                      const double* diag, const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st,
-                     const int* gy, const int* gx, const int* gc, int ncomp) {
+                     const int* gy, const int* gx, const int* gc, int ncomp, int gw, int gh) {
   const bool geo = gy && gx && gc;
   hipError_t err = hipSuccess;
   if (A->lv.empty()) A->lv.push_back(new AmgLevel());
@@ -1223,7 +1227,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
                                             scan_tmp_ints(std::max(F->np, n) + 1)), err);
     AMG_TRY(err);
     if (geo) {
-      AMG_TRY(geo_aggregate(A, F, ncomp, agg2, lead, st));
+      AMG_TRY(geo_aggregate(A, F, l, gw, gh, ncomp, agg2, lead, st));
     } else {
       k_am_active<<<nb256(n), 256, 0, st>>>(n, F->row_off, F->diag, agg, act);
       for (int round = 0; round < 3; ++round) {

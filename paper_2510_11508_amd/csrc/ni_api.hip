@@ -565,7 +565,8 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
                         phi, pw, gy, gx, gc, b64, x64, c->stream),
           "mg build");
     if (!c->amg_fill) c->amg_fill = nil::amg_new();
-    check(c, nil::amg_build(c->amg_fill, N, npr, row_off, col, w, dg, plo, phi, pw, c->stream, gy, gx, gc, K),
+    check(c, nil::amg_build(c->amg_fill, N, npr, row_off, col, w, dg, plo, phi, pw, c->stream, gy, gx, gc, K, W,
+                            pb.H),
           "mg hierarchy");
     nil::amg_set_corr(c->amg_fill, 1.8);
     check(c, nil::amg_update(c->amg_fill, w, dg, pw, c->stream), "mg values");

@@ -161,10 +161,12 @@ void amg_free(Amg*);
 int amg_levels(const Amg*);
 // gy / gx / gc (optional): pixel coordinates and component of every node;
 // when given, aggregates are 2x2 blocks of one component (pixel graphs),
-// otherwise pairwise handshakes (general graphs).  gc < ncomp.
+// otherwise pairwise handshakes (general graphs).  gc < ncomp, gx < gw,
+// gy < gh.
 hipError_t amg_build(Amg*, int K, int P, const int* row_off, const int* qcol, const double* qw, const double* diag,
                      const int* pair_lo, const int* pair_hi, const double* pW, hipStream_t st,
-                     const int* gy = nullptr, const int* gx = nullptr, const int* gc = nullptr, int ncomp = 0);
+                     const int* gy = nullptr, const int* gx = nullptr, const int* gc = nullptr, int ncomp = 0,
+                     int gw = 32768, int gh = 32768);
 // algorithmic HBM bytes of one batched-fill PCG iteration (n_sys: rows that
 // belong to a system)
 double amg_fill_bytes(const Amg*, long long n_sys);
