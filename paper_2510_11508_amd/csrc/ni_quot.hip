@@ -492,6 +492,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   __shared__ int nlong_s, nbig_s;
   const int K = M.K;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nt = blockDim.x, nw = nt >> 6;  // a multiple of 64 with QR3 * nt >= K
   if (threadIdx.x == 0) {
     nlong_s = 0;
     nbig_s = 0;
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   double v0[1] = {0.0};
 #pragma unroll
   for (int k = 0; k < QR3; ++k) {
-    const int c = threadIdx.x + k * QWG;
+    const int c = threadIdx.x + k * nt;
     r[k] = p[k] = h[k] = di[k] = sx[k] = 0.0;
     lidx[k] = 0;
     int j0 = 0, n = 0;
@@ -576,7 +577,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   const bool hl = nlong <= QHROWS && nbig <= QBROWS && hoff[nlong] <= QHCAP;
   if (!hl) bmask = 0;
   if (hl) {
-    for (int hh = wid; hh < nlong; hh += QNW) {
+    for (int hh = wid; hh < nlong; hh += nw) {
       const int c = hrow[hh], j0 = M.row_off[c], o = hoff[hh], n = hoff[hh + 1] - o;
       for (int j = lane; j < n; j += 64) {
         hc[o + j] = (uint16_t)M.qcol[j0 + j];
@@ -592,7 +593,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
     double vbig = 0.0;
 #pragma unroll
     for (int k = 0; k < QR3; ++k) {
-      const int c = threadIdx.x + k * QWG;
+      const int c = threadIdx.x + k * nt;
       if ((smask >> k) & 1) {
         const double uc = ul[c];
         double acc = 0.0;
@@ -608,14 +609,14 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
 #pragma unroll
       for (int k = 0; k < QR3; ++k) {
         if ((tmask >> k) & 1) {
-          const int c = threadIdx.x + k * QWG;
+          const int c = threadIdx.x + k * nt;
           const double uc = ul[c];
           double acc = 0.0;
           for (int j = hoff[lidx[k]]; j < hoff[lidx[k] + 1]; ++j) acc += hw[j] * (uc - ul[hc[j]]);
           wl[c] = acc;
         }
       }
-      for (int bb = wid; bb < nbig; bb += QNW) {
+      for (int bb = wid; bb < nbig; bb += nw) {
         const int hh = blist[bb];
         const int c = hrow[hh];
         const double uc = ul[c];
@@ -630,7 +631,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
     } else {
 #pragma unroll 1
       for (int k = 0; k < QR3; ++k) {
-        const int c = threadIdx.x + k * QWG;
+        const int c = threadIdx.x + k * nt;
         if ((lmask >> k) & 1) {
           const double uc = ul[c];
           double acc = 0.0;
@@ -644,7 +645,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
     double v[3] = {0.0, vbig, 0.0};
 #pragma unroll
     for (int k = 0; k < QR3; ++k) {
-      const int c = threadIdx.x + k * QWG;
+      const int c = threadIdx.x + k * nt;
       if (c < K) {
         const double uc = r[k] * di[k];
         v[0] += r[k] * uc;
@@ -661,7 +662,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
     alp_old = alpha;
 #pragma unroll
     for (int k = 0; k < QR3; ++k) {
-      const int c = threadIdx.x + k * QWG;
+      const int c = threadIdx.x + k * nt;
       if (c < K) {
         p[k] = r[k] * di[k] + beta * p[k];
         h[k] = wl[c] + beta * h[k];
@@ -675,7 +676,7 @@ __global__ void __launch_bounds__(QWG) k_qcg_wgr(QMat M, double* __restrict__ s,
   }
 #pragma unroll
   for (int k = 0; k < QR3; ++k) {
-    const int c = threadIdx.x + k * QWG;
+    const int c = threadIdx.x + k * nt;
     if (c < K) s[c] = sx[k];
   }
   if (threadIdx.x == 0) *iters_out = it;
@@ -1126,7 +1127,9 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   M.diag = a.diag; M.rhs = a.rhs; M.babs = a.babs; M.K = a.K;
   M.heavy = a.heavy; M.nheavy = a.nheavy; M.nbig = a.nbig;
   if (a.K <= QR3 * QWG) {
-    k_qcg_wgr<<<1, QWG, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
+    // as few wavefronts as hold QR3 rows per thread (cheaper barriers)
+    const int nt = std::max(64, ni::ceil_div(ni::ceil_div(a.K, QR3), 64) * 64);
+    k_qcg_wgr<<<1, nt, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
     e = hipGetLastError();
   } else if (a.K <= QCAP) {
     k_qcg_wg<<<1, QWG, 0, st>>>(M, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t);
