@@ -160,24 +160,115 @@ def irls_rows(normals, mask, cam, lab, K, zfill, usable, info, params):
     rhs omega_{b->a} - (z_a - z_b) (Eq. 16); its weight is 1 in the
     alignment iterations and gamma_{b->a}^2 sigma_k(gamma^2 ((z_{-b}-z_a)^2 -
     (z_b-z_a)^2)) W^out otherwise, with -b the pixel across a from b.
-    Returns (S, energies)."""
+    No relative weight cut: a row is dropped only when its weight is exactly
+    zero (FP64 underflow).  Returns (S, energies)."""
     H, W = lab.shape
     usable_set = set(usable)
+    inter = [(a, b) for (a, b) in usable if lab[a[1], a[0]] != lab[b[1], b[0]]]
+    return _irls_loop(lab, K, zfill, inter, lambda a, b: info[(a, b)],
+                      lambda p, q: (p, q) in usable_set or (q, p) in usable_set, params)
+
+
+def irls_exact(normals, mask, cam, lab, K, zfill, params):
+    """The same loop on a map of any size: the inter-component pairs are
+    found from the labels and only their pair models (and those of the
+    pairs across each end) are evaluated, one scalar pair at a time."""
+    lab = np.asarray(lab)
+    H, W = lab.shape
+    valid = np.asarray(mask) != 0
+    cache = {}
+
+    def pm(a, b):
+        if (a, b) not in cache:
+            ok = valid[a[1], a[0]] and valid[b[1], b[0]]
+            cache[(a, b)] = pair_model(normals, cam, a, b) if ok else (False, 0.0, 0.0, 0.0)
+        return cache[(a, b)]
+
+    inter = []
+    vs, us = np.nonzero((lab[:, :-1] != lab[:, 1:]) & valid[:, :-1] & valid[:, 1:])
+    for v, u in zip(vs.tolist(), us.tolist()):
+        if pm((u, v), (u + 1, v))[0]:
+            inter.append(((u, v), (u + 1, v)))
+    vs, us = np.nonzero((lab[:-1, :] != lab[1:, :]) & valid[:-1, :] & valid[1:, :])
+    for v, u in zip(vs.tolist(), us.tolist()):
+        if pm((u, v), (u, v + 1))[0]:
+            inter.append(((u, v), (u, v + 1)))
+
+    def info(a, b):
+        return pm(a, b)[1:]
+
+    def edge_ok(p, q):
+        if (p[1], p[0]) > (q[1], q[0]):
+            p, q = q, p
+        return pm(p, q)[0]
+
+    return _irls_loop(lab, K, zfill, inter, info, edge_ok, params)
+
+
+def _solve_pieces(N, rhs, K, rows_c, rows_d, keep):
+    """Minimum-norm solution of the normal equations N s = rhs of a graph
+    Laplacian: connected pieces over the kept rows by a breadth-first walk,
+    one node pinned per piece, a dense solve of the rest, zero mean per piece."""
+    adj = [[] for _ in range(K)]
+    for c, d, k in zip(rows_c, rows_d, keep):
+        if k:
+            adj[c].append(d)
+            adj[d].append(c)
+    seen = np.zeros(K, bool)
+    s = np.zeros(K)
+    Nd = N.tocsr()
+    for root in range(K):
+        if seen[root]:
+            continue
+        piece, stack = [], [root]
+        seen[root] = True
+        while stack:
+            x = stack.pop()
+            piece.append(x)
+            for y in adj[x]:
+                if not seen[y]:
+                    seen[y] = True
+                    stack.append(y)
+        piece.sort()
+        if len(piece) < 2:
+            continue
+        free = piece[1:]
+        M = Nd[free][:, free].toarray()
+        s[free] = np.linalg.solve(M, rhs[free])
+        s[piece] -= s[piece].mean()
+    return s
+
+
+def _irls_loop(lab, K, zfill, inter, info, edge_ok, params):
+    import scipy.sparse as sp
+    H, W = lab.shape
     S = np.zeros(K)
     energies = []
     k = params["bini_k"]
-    inter = [(a, b) for (a, b) in usable if lab[a[1], a[0]] != lab[b[1], b[0]]]
 
     def zval(p):
         return zfill[p[1], p[0]] + S[lab[p[1], p[0]]]
 
-    def edge_ok(p, q):
-        return (p, q) in usable_set or (q, p) in usable_set
-
+    cidx = np.array([lab[a[1], a[0]] for (a, b) in inter], dtype=np.int64)
+    didx = np.array([lab[b[1], b[0]] for (a, b) in inter], dtype=np.int64)
+    n = len(inter)
+    # stacked directed rows: 2i = row b->a (+1 at pi(a)), 2i+1 = row a->b (+1 at pi(b))
+    ridx = np.repeat(np.arange(2 * n), 2)
+    cols = np.empty(4 * n, dtype=np.int64)
+    vals = np.empty(4 * n)
+    cols[0::4], vals[0::4] = cidx, 1.0
+    cols[1::4], vals[1::4] = didx, -1.0
+    cols[2::4], vals[2::4] = didx, 1.0
+    cols[3::4], vals[3::4] = cidx, -1.0
+    A = sp.csr_matrix((vals, (ridx, cols)), shape=(2 * n, max(K, 1)))
     for t in range(params["irls_iters"]):
-        rows, rhs, wts, keys = [], [], [], []
-        for (a, b) in inter:
-            om, g2a, g2b = info[(a, b)]
+        if n == 0:
+            energies.append(0.0)
+            continue
+        wts = np.empty(2 * n)
+        rhs = np.empty(2 * n)
+        for i, (a, b) in enumerate(inter):
+            om, g2a, g2b = info(a, b)
             za, zb = zval(a), zval(b)
             chi = za - zb - om
             if t < params["align_iters"]:
@@ -191,24 +282,13 @@ def irls_rows(normals, mask, cam, lab, K, zfill, usable, info, params):
                 wo = _wout(chi, params["out_L"], params["out_U"], params["outlier_mode"])
                 wba = g2a * _sig(g2a * (dm * dm - (zb - za) ** 2), k) * wo
                 wab = g2b * _sig(g2b * (dm2 * dm2 - (za - zb) ** 2), k) * wo
-            ca, cb = lab[a[1], a[0]], lab[b[1], b[0]]
-            r1 = np.zeros(K); r1[ca] = 1; r1[cb] = -1
-            rows.append(r1); rhs.append(om - (za - zb)); wts.append(wba)
-            rows.append(-r1); rhs.append(-om - (zb - za)); wts.append(wab)
-            keys.append(len(keys))
-        if not rows:
-            energies.append(0.0)
-            continue
-        wts = np.array(wts)
-        we = wts[0::2] + wts[1::2]
-        cut = we < params["w_cut_rel"] * we.max()
-        wts[0::2][cut] = 0.0
-        wts[1::2][cut] = 0.0
-        sw = np.sqrt(wts)
-        A = np.array(rows)
-        s = np.linalg.lstsq(A * sw[:, None], np.array(rhs) * sw, rcond=None)[0]
-        # minimum-norm: zero mean on every piece, 0 on isolated components
-        res = A @ s - np.array(rhs)
+            wts[2 * i], rhs[2 * i] = wba, om - (za - zb)
+            wts[2 * i + 1], rhs[2 * i + 1] = wab, -om - (zb - za)
+        keep = (wts[0::2] + wts[1::2]) > 0
+        Wd = sp.diags(wts)
+        N = (A.T @ Wd @ A)
+        s = _solve_pieces(N, A.T @ (wts * rhs), K, cidx, didx, keep)
+        res = A @ s - rhs
         energies.append(float(np.sum(wts * res * res)))
         S = S + s
     return S, energies

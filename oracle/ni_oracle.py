@@ -47,7 +47,7 @@ DEFAULT_PARAMS = dict(
     out_U=1e-3,           # Eq. 18 upper threshold [1e-3]
     outlier_mode=1,       # 0 off, 1 soft (Eq. 18), 2 hard (Suppl. ablation)
     delta_e_max=0.0,      # relative-energy stop; 0 runs exactly T iterations (A13)
-    w_cut_rel=1e-4,       # quotient edges below this fraction of the max weight are cut (A16)
+    w_cut_rel=1e-12,      # quotient edges below this fraction of the max weight are cut (A16)
 )
 
 
@@ -427,32 +427,38 @@ def quotient_step(ie: InterEdges, K, w, r, w_cut_rel):
     return s, E, w
 
 
-def irls(e: Edges, lab, K, zfill, params=None):
+def irls(e: Edges, lab, K, zfill, params=None, S0=None, t0=0, trace=None):
     """Relative-scale optimisation (Sec. 3.4; Alg. 1's loop without merging).
 
     z^(t) = zfill + S_pi; each iteration solves for s^(t) with the weights of
     iteration t, then S += s (Eq. 12).  Stops after T iterations, or earlier
     when delta_e_max > 0 and |E_t - E_{t-1}| / E_{t-1} < delta_e_max with
-    both t-1, t past the alignment phase (A13)."""
+    both t-1, t past the alignment phase (A13).
+
+    S0 / t0 resume the loop at iteration t0 from the scales S0 (a test hook:
+    one step at a time); trace, when a list, receives (t, S before step t,
+    s^(t), E_t) for every iteration run."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
     ie = inter_edges(e, lab)
-    S = np.zeros(K)
+    S = np.zeros(K) if S0 is None else np.array(S0, dtype=np.float64)
     labf = lab.ravel()
     valid = labf >= 0
     energies = []
     margin = np.inf
-    for t in range(int(p["irls_iters"])):
+    for t in range(int(t0), int(p["irls_iters"])):
         z = np.where(valid, zfill.ravel() + S[np.where(valid, labf, 0)], 0.0)
         w, r = edge_weights(e, ie, z, t, p)
         if w.size and p["w_cut_rel"] > 0 and w.max() > 0:
             pos = w[w > 0]
             margin = min(margin, float(np.min(np.abs(np.log10(pos / (p["w_cut_rel"] * w.max()))))))
         s, E, _ = quotient_step(ie, K, w, r, p["w_cut_rel"])
+        if trace is not None:
+            trace.append((t, S.copy(), s.copy(), E))
         S += s
         energies.append(E)
-        if p["delta_e_max"] > 0 and t >= p["align_iters"] + 1:
+        if p["delta_e_max"] > 0 and t >= p["align_iters"] + 1 and len(energies) >= 2:
             Ep = energies[-2]
             if Ep == 0.0 or abs(E - Ep) / Ep < p["delta_e_max"]:
                 break

@@ -211,6 +211,104 @@ def test_irls_matches_dense_rows(seed, mode):
     assert np.allclose(En, Er, rtol=1e-8, atol=1e-14)
 
 
+def _exact_logz(s, ref, p):
+    """Log-depth from the brute-force uncut solve of Eq. 16-17 (every row
+    with a non-zero weight kept), on the oracle's labels and fill, shifted to
+    zero mean on each connected region of the mask (scipy.ndimage.label;
+    every edge of these maps is usable, which the test asserts)."""
+    S, _ = BF.irls_exact(s.normals, s.mask, s.cam.as_dict(), ref.labels, ref.K, ref.zfill, p)
+    v = ref.labels >= 0
+    z = np.where(v, ref.zfill + S[np.maximum(ref.labels, 0)], 0.0)
+    reg, R = ndimage.label(v)
+    for r in range(1, R + 1):
+        z[reg == r] -= z[reg == r].mean()
+    return z, v
+
+
+def _depth_err(s, z, v, ref_logz):
+    """max violation of |d - d_ref| <= 1e-6 + 1e-4 |d_ref| (perspective depth)
+    or the norm-wise 1e-4 max|h_ref| bound (orthographic heights cross zero)."""
+    if s.cam.proj == "persp":
+        d, dr = np.exp(z[v]), np.exp(ref_logz[v])
+        return float(np.max(np.abs(d - dr) / (1e-6 + 1e-4 * np.abs(dr))))
+    return float(np.max(np.abs(z[v] - ref_logz[v])) / (1e-4 * np.max(np.abs(ref_logz[v]))))
+
+
+@pytest.mark.parametrize("name,seed", [("c1", 0), ("c1", 1), ("c1", 2), ("c2", 0)])
+def test_irls_equals_uncut_exact_solve(name, seed):
+    """Eq. 17 solved with no relative weight cut (only rows whose weight is
+    exactly zero are dropped) by the brute-force directed-row formulation
+    gives the oracle's output (cut at 1e-12 of the largest weight, A16)
+    within the depth parity bound."""
+    s = synth.make(name, seed)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=synth.CONFIGS[name]["T"])
+    ref = O.integrate(s.normals, s.mask, s.cam, p)
+    e = O.edges(s.normals, s.mask, s.cam, p["theta_c_deg"])
+    v = s.mask > 0
+    assert np.array_equal(e.valid_r[:, :-1], v[:, :-1] & v[:, 1:])
+    assert np.array_equal(e.valid_d[:-1, :], v[:-1, :] & v[1:, :])
+    z, v = _exact_logz(s, ref, p)
+    assert _depth_err(s, z, v, ref.logz) <= 1.0
+
+
+@pytest.mark.parametrize("name,seed", [("c1", 0), ("c2", 0)])
+def test_coarse_cut_reading_fails_exact_pin(name, seed):
+    """The pin above is sharp: a cut at 1e-4 of the largest weight (which
+    drops links that Eq. 17 keeps) misses the uncut solution by far more
+    than the parity bound."""
+    s = synth.make(name, seed)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=synth.CONFIGS[name]["T"])
+    ref = O.integrate(s.normals, s.mask, s.cam, p)
+    z, v = _exact_logz(s, ref, p)
+    coarse = O.integrate(s.normals, s.mask, s.cam, dict(p, w_cut_rel=1e-4))
+    assert _depth_err(s, z, v, coarse.logz) > 20.0
+
+
+# -------------------------------------------------------------- finalize ----
+@pytest.mark.parametrize("name,seed", [("c1", 1), ("c2", 0), ("tiny", 3)])
+def test_finalize_gauge_and_scales(name, seed):
+    """The output gauge (A15) characterised without the oracle's own code:
+    log-depth = fill + S_pi + one constant per connected region of G_0, with
+    zero pixel mean on every region; log_scale_c = log-depth - fill on the
+    pixels of c; depth = exp(log-depth) (perspective) or the height itself
+    (orthographic); NaN off the mask.  Regions come from scipy.ndimage.label
+    where every edge of the mask is usable."""
+    s = synth.tiny(seed, proj="persp", H=12, W=13) if name == "tiny" else synth.make(name, seed)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=synth.CONFIGS[name]["T"] if name in synth.CONFIGS else 6)
+    e = O.edges(s.normals, s.mask, s.cam, p["theta_c_deg"])
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    S, _, _ = O.irls(e, lab, K, zf, p)
+    depth, log_scale, logz = O.finalize(e, lab, zf, S)
+    v = lab >= 0
+    assert np.all(np.isnan(depth[~v]))
+    reg, R = ndimage.label(v)
+    # G_0 regions: the same partition as the mask's 4-connected regions here
+    ours, R2 = O.regions(e)
+    assert R2 == R
+    for r in range(1, R + 1):
+        m = reg == r
+        assert np.unique(ours[m]).size == 1
+        # one constant shift per region, and zero mean
+        shift = logz[m] - (zf[m] + S[lab[m]])
+        assert np.ptp(shift) < 1e-12
+        assert abs(logz[m].mean()) < 1e-12
+    # log-scale = log-depth - fill on every pixel of the component
+    assert np.max(np.abs(logz[v] - zf[v] - log_scale[lab[v]])) < 1e-12
+    if s.cam.proj == "persp":
+        assert np.allclose(depth[v], np.exp(logz[v]), rtol=1e-15, atol=0)
+    else:
+        assert np.array_equal(depth[v], logz[v])
+    # gauge invariance: a constant added to S on a whole region changes nothing
+    rng = np.random.default_rng(seed)
+    comp_reg = np.zeros(K, np.int64)
+    comp_reg[lab[v]] = reg[v]
+    S2 = S + rng.normal(0, 0.5, R + 1)[comp_reg]
+    d2, ls2, z2 = O.finalize(e, lab, zf, S2)
+    assert np.max(np.abs(z2[v] - logz[v])) < 1e-12
+    assert np.max(np.abs(ls2 - log_scale)) < 1e-12
+
+
 def test_alignment_restitches_cut_plane():
     """Uniform-weight iterations re-stitch a plane cut into artificial components."""
     n, m, z, cam = synth.plane_persp(16, 20, 30.0, [0.2, 0.1, -1.0], 3.0)
