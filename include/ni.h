@@ -40,8 +40,8 @@
 extern "C" {
 #endif
 
-#define NI_ABI_VERSION 1
-#define NI_MAX_IRLS 64
+#define NI_ABI_VERSION 2
+#define NI_MAX_IRLS 256
 
 typedef enum {
   NI_OK = 0,
@@ -74,11 +74,17 @@ typedef struct {
   int32_t outlier_mode; /* 0 off, 1 soft (Eq. 18), 2 hard threshold at U      */
   double delta_e_max;   /* relative-energy stop; 0 = run exactly T iterations */
   double w_cut_rel;     /* quotient edges lighter than w_cut_rel * max weight
-                           are dropped before each relative-scale solve       */
+                           are dropped before each relative-scale solve
+                           (1e-12: only weights at the edge of underflow;
+                           Eq. 17 keeps every positive weight)              */
   double cg_rtol;       /* fill CG: stop at ||r_c|| <= cg_rtol * ||b_c||      */
   int32_t cg_max_iter;  /* fill CG iteration cap per component                */
-  double q_rtol;        /* quotient CG: stop at ||r|| <= q_rtol * ||b||_abs   */
-  int32_t q_max_iter;   /* quotient CG iteration cap                          */
+  double q_rtol;        /* quotient solve, two rounds of multigrid PCG: the
+                           first stops at ||r|| <= q_rtol ||b||, the second
+                           solves for the correction from the flow-form
+                           residual b - L s to q_rtol of that residual      */
+  int32_t q_max_iter;   /* iteration cap of each round; reaching it makes the
+                           call return NI_E_NOTCONV (outputs still written) */
   int32_t warm_start;   /* 0 zero start; 1 learned start (needs ni_unet_load) */
   int32_t graphs;       /* 1: the multigrid quotient CG replays each iteration's
                            launches from a HIP graph; 0: plain stream launches
@@ -113,7 +119,7 @@ typedef struct {
   int32_t fill_large_launches;   /* CG iteration launches of the large path   */
   int32_t warm_fallbacks;        /* components whose learned start was reset */
   double fill_max_relres;        /* max_c ||r_c|| / ||b_c|| (recursive)       */
-  int32_t quot_iters[NI_MAX_IRLS];
+  int32_t quot_iters[NI_MAX_IRLS]; /* both quotient solve rounds together */
   double energy[NI_MAX_IRLS];    /* E_t of Alg. 1 per iteration               */
   float ms_setup, ms_label, ms_segments, ms_assemble, ms_warm,
         ms_fill_small, ms_fill_large, ms_irls, ms_finalize, ms_total;
@@ -135,8 +141,8 @@ typedef struct {
 typedef struct ni_ctx ni_ctx;
 
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
- * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-4, cg_rtol 1e-6,
- * cg_max_iter 50000, q_rtol 1e-10, q_max_iter 20000, zero start, no
+ * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-12, cg_rtol 1e-6,
+ * cg_max_iter 50000, q_rtol 1e-5, q_max_iter 20000, zero start, no
  * graphs, autotuned fill schedule, multigrid fill preconditioner.
  * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);

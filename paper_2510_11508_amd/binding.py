@@ -11,7 +11,7 @@ import ctypes as C
 import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libni.so")
-NI_MAX_IRLS = 64
+NI_MAX_IRLS = 256
 
 NI_OK, NI_E_ARG, NI_E_SHAPE, NI_E_NONFINITE, NI_E_NOMEM, NI_E_DEVICE, NI_E_NOTCONV, NI_E_MODEL = range(8)
 NI_ORTHO, NI_PERSP = 0, 1

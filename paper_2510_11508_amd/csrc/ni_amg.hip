@@ -8,11 +8,13 @@
 // one V-cycle of an aggregation hierarchy:
 //
 //   aggregation   pairwise handshakes (each free node proposes its strongest
-//                 free neighbour, equal weights ordered by a hash of the
-//                 edge; mutual proposals pair up; three rounds),
-//                 then every node left over joins the aggregate of its
-//                 strongest aggregated neighbour; nodes without a weighted
-//                 edge take no part.  Aggregate ids follow the smallest
+//                 free neighbour among its strong entries, those within a
+//                 factor ATHETA of the row's heaviest; equal weights
+//                 ordered by a hash of the edge; mutual proposals pair up;
+//                 three rounds), then every node left over joins the
+//                 aggregate of its strongest aggregated strong neighbour,
+//                 or stays alone; nodes without a weighted edge take no
+//                 part.  Aggregate ids follow the smallest
 //                 member, so the hierarchy is deterministic.
 //   coarse graph  Galerkin product with piecewise-constant prolongation: a
 //                 coarse pair's weight is the sum of the fine pair weights
@@ -177,6 +179,17 @@ __global__ void __launch_bounds__(CO_NT) k_cy_coarsest(int n, const double* __re
 #pragma unroll
   for (int o = 1; o < CO_P; o <<= 1) acc += __shfl_xor(acc, o, 64);
   if (c < n && part == 0) y[c] = acc;
+}
+
+// block partials of (b, y) on a level whose cycle is the exact solve alone
+// (a hierarchy of one level); heavy blocks write zero partials
+__global__ void __launch_bounds__(ANT) k_cy_dot(ALev L, double* __restrict__ parts, int pstride, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[ANT / 64];
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  double v[1] = {0.0};
+  if ((int)blockIdx.x < L.nblk && c < L.n) v[0] = L.b[c] * L.y[c];
+  put_parts<1>(v, red, parts, pstride);
 }
 
 // prolongation and post-smoothing: x = w D^-1 b + corr P y',
@@ -457,17 +470,31 @@ __device__ __forceinline__ uint32_t edge_hash(int c, int d) {
   return (uint32_t)k;
 }
 
-// strongest neighbour with agg == -1 (want_free) or agg >= 0; ties ->
-// larger edge hash, then smaller index
+// Strength of connection: an entry (c, d) is strong for c when its weight
+// is at least ATHETA times the heaviest entry of row c.  Aggregates grow
+// along strong entries only.  The relative-scale weights span many orders
+// of magnitude (the BiNI sigmoid of Eq. 5 decays exponentially across a
+// depth step), and a node whose strong neighbours are already taken must
+// not pair up over a link a million times weaker: the aggregate's constant
+// vector would then not be a near-null vector of its rows, and the cycle
+// would lose the pieces that hang by weak links.
+constexpr double ATHETA = 0.1;
+
+// strongest strong neighbour with agg == -1 (want_free) or agg >= 0; ties
+// -> larger edge hash, then smaller index
 __device__ __forceinline__ int strongest(int c, const int* row_off, const int* col, const double* w, const int* agg,
                                          const uint8_t* act, bool want_free) {
+  double rmax = 0.0;
+  for (int j = row_off[c]; j < row_off[c + 1]; ++j)
+    if (col[j] != c && act[col[j]]) rmax = fmax(rmax, w[j]);
+  const double floor_w = ATHETA * rmax;
   int best = -1;
   double bw = 0.0;
   uint32_t bh = 0;
   for (int j = row_off[c]; j < row_off[c + 1]; ++j) {
     const int d = col[j];
     const double v = w[j];
-    if (v <= 0.0 || d == c || !act[d] || ((agg[d] < 0) != want_free)) continue;
+    if (v <= 0.0 || v < floor_w || d == c || !act[d] || ((agg[d] < 0) != want_free)) continue;
     const uint32_t h = edge_hash(c, d);
     if (v > bw || (v == bw && (h > bh || (h == bh && d < best)))) {
       bw = v;
@@ -1416,6 +1443,7 @@ static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts
   if (A->dense) {
     k_cy_coarsest<<<1, CO_NT, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
                                        static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
+    if (A->nlev == 1) k_cy_dot<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, parts, pstride, done);
   } else {  // no exact coarsest: smoothing only
     k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, A->corr,
                                                  done);

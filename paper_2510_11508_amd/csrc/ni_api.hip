@@ -100,13 +100,12 @@ struct ni_ctx {
   Buf key, val, skey, spix, ktmp, vtmp, kout2, cst, rhs, dinv, x, r, z, p0, p1, q, w0, w1, s0, s1;
   // components
   Buf comp_off, fsmall, flarge, nchunk, spos, lpos, cbase, small_list, large_list, cnt, done, iters, active,
-      rho, bb, tol2, alpha, beta, rr, relres, S, qs, qr, qz, qp0, qp1, qq, diag, qrhs, babs, psum, pcnt, qparent,
-      csum, comp_rid;
+      rho, bb, tol2, beta, rr, relres, S, qs, diag, qrhs, psum, pcnt, qparent, csum, comp_rid;
   // chunks
   Buf chunk_comp, chunk_start, part;
   // edges / pairs
   Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
-      row_off, epart, qpart, rsum, rcnt, qcol, qw, qt0, qt1, qsc, qpv, qst, qecol, qew;
+      row_off, epart, rsum, rcnt, qcol, qw, qt0, qt1;
   // fill multigrid: level-0 system of the large components
   Buf mg_deg, mg_pc, mg_row, mg_poff, mg_col, mg_w, mg_diag, mg_plo, mg_phi, mg_pw, mg_gy, mg_gx, mg_gc, mg_b, mg_x;
   // scratch
@@ -126,11 +125,11 @@ struct ni_ctx {
     Buf* all[] = {&ebits, &om_r, &om_d, &nt, &parent, &flag, &scanv, &pos, &zgrid, &tab, &xwarm, &key, &val,
                   &skey, &spix, &ktmp, &vtmp, &kout2, &cst, &rhs, &dinv, &x, &r, &z, &p0,
                   &p1, &q, &w0, &w1, &s0, &s1, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
-                  &cnt, &done, &iters, &active, &rho, &bb, &tol2, &alpha, &beta, &rr, &relres, &S, &qs, &qr,
-                  &qz, &qp0, &qp1, &qq, &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
+                  &cnt, &done, &iters, &active, &rho, &bb, &tol2, &beta, &rr, &relres, &S, &qs,
+                  &diag, &qrhs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
-                  &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &qpart, &rsum,
-                  &rcnt, &qcol, &qw, &qt0, &qt1, &qsc, &qpv, &qst, &qecol, &qew, &mg_deg, &mg_pc, &mg_row,
+                  &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &rsum,
+                  &rcnt, &qcol, &qw, &qt0, &qt1, &mg_deg, &mg_pc, &mg_row,
                   &mg_poff, &mg_col, &mg_w, &mg_diag, &mg_plo, &mg_phi, &mg_pw, &mg_gy, &mg_gx, &mg_gc, &mg_b,
                   &mg_x, &scan_tmp, &misc, &unet_ws};
     bufs.assign(std::begin(all), std::end(all));
@@ -148,8 +147,9 @@ enum {
   M_QFLAG = 24,   // 2 ints (quotient: still iterating, by launch parity)
   M_WMAX = 32,    // u64 (8-byte aligned)
   M_ENERGY = 64,  // NI_MAX_IRLS doubles (8-byte aligned)
-  M_QITERS = 64 + 2 * NI_MAX_IRLS,
-  M_TOTAL = 64 + 3 * NI_MAX_IRLS
+  M_QITERS = 64 + 2 * NI_MAX_IRLS,   // quotient iterations, first round
+  M_QITERS2 = 64 + 3 * NI_MAX_IRLS,  // quotient iterations, refinement round
+  M_TOTAL = 64 + 4 * NI_MAX_IRLS
 };
 
 void check(ni_ctx* c, hipError_t e, const char* what) {
@@ -434,7 +434,6 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     a.chunk_start = chunk_start; a.chunk_end = chunk_end;
     a.part = ensure<double>(c, c->part, 2 * 4 * (size_t)n_chunks);
     a.gam = ensure<double>(c, c->rho, 2 * K1);
-    a.alp = ensure<double>(c, c->alpha, 2 * K1);
     a.tol2 = ensure<double>(c, c->tol2, K1);
     a.rr = rr; a.bb = bb; a.iters = iters;
     a.active = misc(c) + M_ACTIVE; a.stats = misc(c) + M_STATS;
@@ -753,20 +752,14 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.pB = ensure<double>(c, c->pB, std::max(Pp, 1));
   a.diag = ensure<double>(c, c->diag, K1);
   a.rhs = ensure<double>(c, c->qrhs, K1);
-  a.babs = ensure<double>(c, c->babs, K1);
   a.s = ensure<double>(c, c->qs, K1);
-  a.r = ensure<double>(c, c->qr, K1);
-  a.z = ensure<double>(c, c->qz, K1);
-  a.p0 = ensure<double>(c, c->qp0, K1);
-  a.p1 = ensure<double>(c, c->qp1, K1);
-  a.q = ensure<double>(c, c->qq, K1);
   a.psum = ensure<double>(c, c->psum, K1);
   a.pcnt = ensure<int>(c, c->pcnt, K1);
   a.parent = ensure<int>(c, c->qparent, K1);
   a.wmax = (unsigned long long*)(misc(c) + M_WMAX);
-  a.bar = nullptr;
   a.energy_out = (double*)(misc(c) + M_ENERGY);
   a.qiters_out = misc(c) + M_QITERS;
+  a.qiters2_out = misc(c) + M_QITERS2;
   a.epart = ensure<double>(c, c->epart, (size_t)ni::ceil_div(std::max(Pp, 1), 256));
   a.g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
   a.g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
@@ -778,14 +771,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.qw = ensure<double>(c, c->qw, std::max(a.nnz, 1));
   a.t0 = ensure<double>(c, c->qt0, K1);
   a.t1 = ensure<double>(c, c->qt1, K1);
-  a.pv = ensure<double>(c, c->qpv, K1);
-  a.qst = ensure<double>(c, c->qst, 8 * (size_t)K1);
-  a.ell_col = ensure<int>(c, c->qecol, 8 * (size_t)K1);
-  a.ell_w = ensure<double>(c, c->qew, 8 * (size_t)K1);
-  a.sc = ensure<double>(c, c->qsc, 4);
-  a.qflag = misc(c) + M_QFLAG;
   a.host_flag = c->host + 32;
-  a.part = ensure<double>(c, c->qpart, 2 * 4 * ((size_t)std::max(ni::ceil_div(K, 256), 1) + nheavy));
   check(c, hipMemsetAsync(a.S, 0, K1 * sizeof(double), c->stream), "memset");
   const int T = pb.prm.irls_iters;
   int ran = 0;
@@ -800,6 +786,17 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     }
   }
   mark(c, 9);
+  // a quotient solve round that stopped at its cap leaves the scales
+  // unconverged: the outputs are still written, and the call reports it
+  std::vector<int> qi(NI_MAX_IRLS, 0), qi2(NI_MAX_IRLS, 0);
+  check(c, hipMemcpyAsync(qi.data(), a.qiters_out, sizeof(int) * NI_MAX_IRLS, hipMemcpyDeviceToHost, c->stream),
+        "D2H");
+  check(c, hipMemcpyAsync(qi2.data(), a.qiters2_out, sizeof(int) * NI_MAX_IRLS, hipMemcpyDeviceToHost, c->stream),
+        "D2H");
+  check(c, hipStreamSynchronize(c->stream), "sync");
+  int capped = -1;
+  for (int t = 0; t < ran && capped < 0; ++t)
+    if (qi[t] >= pb.prm.q_max_iter || qi2[t] >= pb.prm.q_max_iter) capped = t;
   // regions of G_0 and outputs
   check(c,
         nil::grid_components(ptr<uint8_t>(c->ebits), pb.H, W, EB_VR, EB_VD, ptr<int>(c->parent), ptr<int>(c->flag),
@@ -822,15 +819,17 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->n_inter_edges = E;
     rep->n_pairs = Pp;
     rep->irls_iters_run = ran;
-    std::vector<int> qi(NI_MAX_IRLS, 0);
     check(c, hipMemcpy(en.data(), a.energy_out, sizeof(double) * NI_MAX_IRLS, hipMemcpyDeviceToHost), "D2H");
-    check(c, hipMemcpy(qi.data(), a.qiters_out, sizeof(int) * NI_MAX_IRLS, hipMemcpyDeviceToHost), "D2H");
     for (int t = 0; t < NI_MAX_IRLS; ++t) {
       rep->energy[t] = t < ran ? en[t] : 0.0;
-      rep->quot_iters[t] = t < ran ? qi[t] : 0;
+      rep->quot_iters[t] = t < ran ? qi[t] + qi2[t] : 0;
     }
     rep->ms_irls = ev_ms(c, 8, 9);
     rep->ms_finalize = ev_ms(c, 9, 10);
+  }
+  if (capped >= 0) {
+    c->err = "relative-scale solve of iteration " + std::to_string(capped) + " stopped at q_max_iter";
+    throw Fail{NI_E_NOTCONV};
   }
 }
 
@@ -872,10 +871,10 @@ ni_status ni_params_default(ni_params* p) {
   p->out_U = 1e-3;
   p->outlier_mode = 1;
   p->delta_e_max = 0.0;
-  p->w_cut_rel = 1e-4;
+  p->w_cut_rel = 1e-12;
   p->cg_rtol = 1e-6;
   p->cg_max_iter = 50000;
-  p->q_rtol = 1e-10;
+  p->q_rtol = 1e-5;
   p->q_max_iter = 20000;
   p->warm_start = 0;
   p->graphs = 0;
@@ -952,12 +951,17 @@ ni_status ni_integrate(ni_ctx* c, const float* normals, const uint8_t* mask, int
     int k = stage_label(c, pb, labels);
     mark(c, 2);
     *K = k;
-    if (rep) {
+    // stage times are read once their end events have completed (an
+    // event still pending reads as not ready)
+    auto label_times = [&] {
+      if (!rep) return;
+      check(c, hipEventSynchronize(c->ev[2]), "sync");
       rep->K = k;
       rep->ms_setup = ev_ms(c, 0, 1);
       rep->ms_label = ev_ms(c, 1, 2);
-    }
+    };
     if ((int64_t)k > cap) {
+      label_times();
       c->err = "log_scale capacity smaller than K";
       throw Fail{NI_E_SHAPE};
     }
@@ -971,14 +975,22 @@ ni_status ni_integrate(ni_ctx* c, const float* normals, const uint8_t* mask, int
       if (f.s != NI_E_NOTCONV) throw;
       fs = f.s;
     }
-    stage_irls(c, pb, labels, sg, zf, depth, log_scale, rep);
+    ni_status qs = NI_OK;
+    try {
+      stage_irls(c, pb, labels, sg, zf, depth, log_scale, rep);
+    } catch (const Fail& f) {
+      if (f.s != NI_E_NOTCONV) throw;
+      qs = f.s;
+    }
     if (rep) {
       mark(c, 11);
       check(c, hipEventSynchronize(c->ev[11]), "sync");
+      label_times();
       rep->ms_segments = ev_ms(c, 2, 3);
       rep->ms_total = ev_ms(c, 0, 11);
     }
     if (fs != NI_OK) throw Fail{fs};
+    if (qs != NI_OK) throw Fail{qs};
   });
 }
 

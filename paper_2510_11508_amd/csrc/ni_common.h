@@ -97,29 +97,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   }
 }
 
-// ------------------------------------------------------------- grid barrier
-// Sense-reversing barrier for a co-resident (cooperatively launched) grid.
-// bar[0] = arrival count, bar[1] = generation.  The fences make every global
-// write issued before the barrier visible to every block after it, across
-// the XCDs' separate L2 caches (agent-scope release / acquire).
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
-        __builtin_amdgcn_s_sleep(1);
-    }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  }
-  __syncthreads();
-}
-
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace ni
@@ -143,7 +120,7 @@ size_t radix_tmp_ints(int n);
 // arguments of the batched CG of the large fill components (ni_fill.hip)
 struct LargeArgs {
   const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start, *chunk_end;
-  double *part, *gam, *alp, *tol2, *rr, *bb;
+  double *part, *gam, *tol2, *rr, *bb;
   int *iters, *active, *stats;
   const float4* cst;  // per pixel (w_right, w_down, w_up, packed offsets)
   const float *rhs, *dinv;
@@ -195,26 +172,23 @@ struct IrlsArgs {
   const float *nt, *om_r, *om_d, *zfill;
   const int *pair_start, *pair_lo, *pair_hi, *row_off;
   const uint32_t* ent;
-  double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
-  double *s, *r, *z, *p0, *p1, *q, *part, *psum;
+  double *S, *ew, *erho, *pW, *pB, *diag, *rhs;
+  double *s, *psum;
   int *pcnt, *parent;
   unsigned long long* wmax;
-  unsigned* bar;
   double* energy_out;  // [t]
-  int* qiters_out;     // [t]
+  int* qiters_out;     // [t] iterations of the first solve round
+  int* qiters2_out;    // [t] iterations of the refinement round
   double* epart;
   double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
   int align, outlier_mode, q_maxit, nnz;
   int* qcol;
-  double *qw, *t0, *t1, *sc, *pv, *qst;
-  int* qflag;
+  double *qw, *t0, *t1;  // t0: flow-form residual, t1: correction [K]
   int* host_flag;
   const int* heavy;
   int nheavy, nbig;
-  int* ell_col;   // [8][K] ELL copy of the light quotient rows
-  double* ell_w;
-  Amg* amg;       // multigrid for K above the one-workgroup solver (null: Jacobi)
-  int graphs;     // replay the multigrid iteration from a HIP graph
+  Amg* amg;   // multigrid of the quotient solve
+  int graphs; // replay the multigrid iteration from a HIP graph
 };
 
 }  // namespace nil

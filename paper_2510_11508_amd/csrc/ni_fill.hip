@@ -371,7 +371,6 @@ struct LargeState {
   const int* chunk_end;
   double* part;           // [2][nchunks][4] = (rho, rr, pq, bb) by launch parity
   double* gam;            // [2][K] rho_i by iteration parity
-  double* alp;            // [K] unused scratch
   double* tol2;           // [K]
   double* rr;             // [K] last ||r||^2
   double* bb;             // [K] ||b||^2
@@ -904,7 +903,7 @@ hipError_t fill_small(int tier, const int* list, int n, const int* comp_off, con
 static LargeState to_state(const LargeArgs& a) {
   LargeState S;
   S.comp_off = a.comp_off; S.cbase = a.cbase; S.nchunk = a.nchunk; S.chunk_comp = a.chunk_comp;
-  S.chunk_start = a.chunk_start; S.chunk_end = a.chunk_end; S.part = a.part; S.gam = a.gam; S.alp = a.alp; S.tol2 = a.tol2;
+  S.chunk_start = a.chunk_start; S.chunk_end = a.chunk_end; S.part = a.part; S.gam = a.gam; S.tol2 = a.tol2;
   S.rr = a.rr; S.bb = a.bb; S.iters = a.iters; S.active = a.active; S.stats = a.stats;
   S.cst = a.cst; S.rhs = a.rhs; S.dinv = a.dinv;
   S.x = a.x; S.p = a.p; S.r0 = a.r0; S.r1 = a.r1; S.w0 = a.w0; S.w1 = a.w1; S.s0 = a.s0; S.s1 = a.s1;

@@ -39,7 +39,7 @@ def test_host_only_calls():
     assert p.cg_rtol == 1e-6 and p.connectivity == 4 and p.outlier_mode == 1
     assert L.ni_params_default(None) == ni.NI_E_ARG
     assert L.ni_status_str(ni.NI_E_SHAPE) == b"output capacity too small"
-    assert L.ni_abi_version() == 1
+    assert L.ni_abi_version() == 2
     assert L.ni_destroy(None) == ni.NI_E_ARG
     assert L.ni_integrate(None, None, None, 1, 1, None, None, None, None, None, 0, None, None) == ni.NI_E_ARG
 
