@@ -13,6 +13,8 @@ namespace nil {
 // ni_setup.hip
 hipError_t launch_setup(const float*, const uint8_t*, int, int, int, double, const double*, double, int,
                         uint8_t*, float*, float*, float*, int*, hipStream_t);
+hipError_t launch_inter_geom(const uint32_t*, int, int, int, const float*, int, double, const double*, double*,
+                             double*, double*, hipStream_t);
 hipError_t grid_components(const uint8_t*, int, int, uint8_t, uint8_t, int*, int*, int*, int*, int*, int*,
                            hipStream_t);
 // ni_fill.hip
@@ -105,7 +107,7 @@ struct ni_ctx {
   Buf chunk_comp, chunk_start, part;
   // edges / pairs
   Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
-      row_off, epart, rsum, rcnt, qcol, qw, qt0, qt1;
+      row_off, epart, rsum, rcnt, qcol, qw, qt0, qt1, eom, eta, etb;
   // fill multigrid: level-0 system of the large components
   Buf mg_deg, mg_pc, mg_row, mg_poff, mg_col, mg_w, mg_diag, mg_plo, mg_phi, mg_pw, mg_gy, mg_gx, mg_gc, mg_b, mg_x;
   // scratch
@@ -129,7 +131,7 @@ struct ni_ctx {
                   &diag, &qrhs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &rsum,
-                  &rcnt, &qcol, &qw, &qt0, &qt1, &mg_deg, &mg_pc, &mg_row,
+                  &rcnt, &qcol, &qw, &qt0, &qt1, &eom, &eta, &etb, &mg_deg, &mg_pc, &mg_row,
                   &mg_poff, &mg_col, &mg_w, &mg_diag, &mg_plo, &mg_phi, &mg_pw, &mg_gy, &mg_gx, &mg_gc, &mg_b,
                   &mg_x, &scan_tmp, &misc, &unet_ws};
     bufs.assign(std::begin(all), std::end(all));
@@ -743,7 +745,16 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.amg = c->amg;
   a.graphs = pb.prm.graphs ? 1 : 0;
   a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
-  a.nt = ptr<float>(c->nt); a.om_r = ptr<float>(c->om_r); a.om_d = ptr<float>(c->om_d); a.zfill = zfill;
+  a.zfill = zfill;
+  {
+    double* eom = ensure<double>(c, c->eom, srt);
+    double* eta = ensure<double>(c, c->eta, srt);
+    double* etb = ensure<double>(c, c->etb, srt);
+    check(c, nil::launch_inter_geom(eidx, E, pb.H, W, pb.normals, persp ? 1 : 0, pb.cam.pixel_pitch, ptr<double>(c->tab),
+                                    eom, eta, etb, c->stream),
+          "inter-edge geometry");
+    a.eom = eom; a.eta = eta; a.etb = etb;
+  }
   a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
   a.S = ensure<double>(c, c->S, K1);
   a.ew = ensure<double>(c, c->ew, srt);

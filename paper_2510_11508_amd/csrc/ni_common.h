@@ -169,7 +169,8 @@ struct IrlsArgs {
   int E, P, K, W;
   const int* label;
   const uint8_t* ebits;
-  const float *nt, *om_r, *om_d, *zfill;
+  const double *eom, *eta, *etb;  // FP64 omega and gamma factors per inter edge
+  const float* zfill;
   const int *pair_start, *pair_lo, *pair_hi, *row_off;
   const uint32_t* ent;
   double *S, *ew, *erho, *pW, *pB, *diag, *rhs;

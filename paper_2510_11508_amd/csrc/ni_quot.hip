@@ -147,7 +147,7 @@ __device__ __forceinline__ double outlier_w(double chi, const EdgeParams& q) {
 
 __global__ void __launch_bounds__(256) k_irls_edges(
     const uint32_t* __restrict__ eidx, int E, const int* __restrict__ label, const uint8_t* __restrict__ ebits,
-    const float* __restrict__ nt, const float* __restrict__ om_r, const float* __restrict__ om_d,
+    const double* __restrict__ eom, const double* __restrict__ eta, const double* __restrict__ etb,
     const float* __restrict__ zfill, const double* __restrict__ S, EdgeParams q, double* __restrict__ ew,
     double* __restrict__ erho, unsigned long long* __restrict__ wmax_bits) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_irls_edges(
     const int c = label[a], d = label[b];
     const double za = (double)zfill[a] + S[c];
     const double zb = (double)zfill[b] + S[d];
-    const double om = h ? (double)om_r[a] : (double)om_d[a];
+    const double om = eom[i];
     const double r = za - zb - om;
     if (q.t < q.align) {
       w = 2.0;
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_irls_edges(
         dm = ((double)zfill[m] + S[label[m]]) - za;
       }
       const double dp = zb - za;
-      const double ta = nt[a];
+      const double ta = eta[i];
       const double g2a = g2f * (ta * ta);
       const double wba = g2a * sigmoid_k(g2a * (dm * dm - dp * dp), q.k);
       // row a -> b, opposite pixel b + step
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) k_irls_edges(
         dm2 = ((double)zfill[m] + S[label[m]]) - zb;
       }
       const double dp2 = za - zb;
-      const double tb = nt[b];
+      const double tb = etb[i];
       const double g2b = g2f * (tb * tb);
       const double wab = g2b * sigmoid_k(g2b * (dm2 * dm2 - dp2 * dp2), q.k);
       w = (wba + wab) * outlier_w(r, q);
@@ -527,7 +527,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (a.E > 0) {
     e = hipMemsetAsync(a.wmax, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
-    k_irls_edges<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.label, a.ebits, a.nt, a.om_r, a.om_d,
+    k_irls_edges<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.label, a.ebits, a.eom, a.eta, a.etb,
                                                         a.zfill, a.S, q, a.ew, a.erho, a.wmax);
     k_irls_pairs<<<ni::ceil_div(a.P, 256), 256, 0, st>>>(a.pair_start, a.P, a.ew, a.erho, a.wmax, a.cut_rel, a.pW,
                                                         a.pB);

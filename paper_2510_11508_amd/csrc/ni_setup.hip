@@ -16,20 +16,54 @@ __device__ __forceinline__ bool same_sign_nz(double a, double b) {
   return a != 0.0 && b != 0.0 && ((a > 0.0) == (b > 0.0));
 }
 
+// Model of continuity of one edge a -> b = a + (du, dv), (du, dv) = (1, 0)
+// or (0, 1), in FP64 from the FP32 normals.  Perspective (Eq. 3): the four
+// dots d_aa = n_a.tau_a, d_am = n_a.tau_m, d_bb = n_b.tau_b, d_bm =
+// n_b.tau_m (m the midpoint of the two pixel centres); the edge is usable
+// iff (d_aa, d_am) and (d_bb, d_bm) are non-zero pairs of one sign, and
+// omega = log((d_am/d_aa)*(d_bb/d_bm)).  Orthographic: usable iff n_az,
+// n_bz != 0, omega = s*(n_a.d/(2 n_az) + n_b.d/(2 n_bz)).  On return
+// *ta = d_aa and *tb = d_bb (n_az, n_bz orthographic): gamma = f * ta of
+// the row ending at a (Eq. 7).
+struct RayTabs {
+  const double *tx, *ty, *txm, *tym;
+};
+
+__device__ __forceinline__ bool edge_model(const float* __restrict__ nrm, long long p, long long q, int u, int v,
+                                           bool horiz, int persp, double pitch, const RayTabs& T, double* om,
+                                           double* ta, double* tb) {
+  const double nax = nrm[3 * p], nay = nrm[3 * p + 1], naz = nrm[3 * p + 2];
+  const double nbx = nrm[3 * q], nby = nrm[3 * q + 1], nbz = nrm[3 * q + 2];
+  if (persp) {
+    const double ub = horiz ? T.tx[u + 1] : T.tx[u], vb = horiz ? T.ty[v] : T.ty[v + 1];
+    const double um = horiz ? T.txm[u] : T.tx[u], vm = horiz ? T.ty[v] : T.tym[v];
+    const double daa = ndot(nax, nay, naz, T.tx[u], T.ty[v]);
+    const double dam = ndot(nax, nay, naz, um, vm);
+    const double dbb = ndot(nbx, nby, nbz, ub, vb);
+    const double dbm = ndot(nbx, nby, nbz, um, vm);
+    *ta = daa;
+    *tb = dbb;
+    if (!(same_sign_nz(daa, dam) && same_sign_nz(dbb, dbm))) return false;
+    *om = log((dam / daa) * (dbb / dbm));
+  } else {
+    *ta = naz;
+    *tb = nbz;
+    if (!(naz != 0.0 && nbz != 0.0)) return false;
+    *om = horiz ? pitch * (nax / (2.0 * naz) + nbx / (2.0 * nbz)) : pitch * (nay / (2.0 * naz) + nby / (2.0 * nbz));
+  }
+  return true;
+}
+
 // One thread per pixel a; it owns the edges to its right and lower
 // neighbours b.  Writes:
 //   ebits[a]  EB_VALID | usable/similar bits of its two edges
-//   om_r/om_d omega_{b->a} (FP32), 0 where unusable
+//   om_r/om_d omega_{b->a} (FP32, the fill's stencil precision), 0 where
+//             unusable
 //   nt[a]     n_a . tau_a (perspective) or n_az (orthographic), FP32
-// Perspective: the four dots d_aa, d_am, d_bb, d_bm of Eq. 3; the edge is
-// usable iff (d_aa, d_am) and (d_bb, d_bm) are non-zero pairs of one sign,
-// and omega = log((d_am/d_aa)*(d_bb/d_bm)).  Orthographic: usable iff
-// n_az, n_bz != 0, omega = s*(n_a.d/(2 n_az) + n_b.d/(2 n_bz)).
 // Similar iff usable and (n_ax n_bx + n_ay n_by) + n_az n_bz > cos(theta_c).
 __global__ void __launch_bounds__(256) k_setup(
     const float* __restrict__ nrm, const uint8_t* __restrict__ mask, int H, int W, int persp,
-    double pitch, const double* __restrict__ tx, const double* __restrict__ ty,
-    const double* __restrict__ txm, const double* __restrict__ tym, double cth, int use_sim,
+    double pitch, RayTabs T, double cth, int use_sim,
     uint8_t* __restrict__ ebits, float* __restrict__ om_r, float* __restrict__ om_d,
     float* __restrict__ nt, int* __restrict__ err) {
   long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,55 +75,47 @@ __global__ void __launch_bounds__(256) k_setup(
     const float ax = nrm[3 * p], ay = nrm[3 * p + 1], az = nrm[3 * p + 2];
     if (!(isfinite(ax) && isfinite(ay) && isfinite(az))) atomicOr(err, 1);
     const double nax = ax, nay = ay, naz = az;
-    const double daa = persp ? ndot(nax, nay, naz, tx[u], ty[v]) : naz;
-    ntp = (float)daa;
+    ntp = (float)(persp ? ndot(nax, nay, naz, T.tx[u], T.ty[v]) : naz);
     eb = EB_VALID;
-    if (u + 1 < W && mask[p + 1]) {
+    double om, ta, tb;
+    if (u + 1 < W && mask[p + 1] && edge_model(nrm, p, p + 1, u, v, true, persp, pitch, T, &om, &ta, &tb)) {
+      eb |= EB_VR;
+      o_r = (float)om;
       const double nbx = nrm[3 * p + 3], nby = nrm[3 * p + 4], nbz = nrm[3 * p + 5];
-      bool ok;
-      double om = 0.0;
-      if (persp) {
-        const double dam = ndot(nax, nay, naz, txm[u], ty[v]);
-        const double dbb = ndot(nbx, nby, nbz, tx[u + 1], ty[v]);
-        const double dbm = ndot(nbx, nby, nbz, txm[u], ty[v]);
-        ok = same_sign_nz(daa, dam) && same_sign_nz(dbb, dbm);
-        if (ok) om = log((dam / daa) * (dbb / dbm));
-      } else {
-        ok = naz != 0.0 && nbz != 0.0;
-        if (ok) om = pitch * (nax / (2.0 * naz) + nbx / (2.0 * nbz));
-      }
-      if (ok) {
-        eb |= EB_VR;
-        o_r = (float)om;
-        if (use_sim && add(add(mul(nax, nbx), mul(nay, nby)), mul(naz, nbz)) > cth) eb |= EB_SR;
-      }
+      if (use_sim && add(add(mul(nax, nbx), mul(nay, nby)), mul(naz, nbz)) > cth) eb |= EB_SR;
     }
-    if (v + 1 < H && mask[p + W]) {
+    if (v + 1 < H && mask[p + W] && edge_model(nrm, p, p + W, u, v, false, persp, pitch, T, &om, &ta, &tb)) {
       const long long q = p + W;
+      eb |= EB_VD;
+      o_d = (float)om;
       const double nbx = nrm[3 * q], nby = nrm[3 * q + 1], nbz = nrm[3 * q + 2];
-      bool ok;
-      double om = 0.0;
-      if (persp) {
-        const double dam = ndot(nax, nay, naz, tx[u], tym[v]);
-        const double dbb = ndot(nbx, nby, nbz, tx[u], ty[v + 1]);
-        const double dbm = ndot(nbx, nby, nbz, tx[u], tym[v]);
-        ok = same_sign_nz(daa, dam) && same_sign_nz(dbb, dbm);
-        if (ok) om = log((dam / daa) * (dbb / dbm));
-      } else {
-        ok = naz != 0.0 && nbz != 0.0;
-        if (ok) om = pitch * (nay / (2.0 * naz) + nby / (2.0 * nbz));
-      }
-      if (ok) {
-        eb |= EB_VD;
-        o_d = (float)om;
-        if (use_sim && add(add(mul(nax, nbx), mul(nay, nby)), mul(naz, nbz)) > cth) eb |= EB_SD;
-      }
+      if (use_sim && add(add(mul(nax, nbx), mul(nay, nby)), mul(naz, nbz)) > cth) eb |= EB_SD;
     }
   }
   ebits[p] = eb;
   om_r[p] = o_r;
   om_d[p] = o_d;
   nt[p] = ntp;
+}
+
+// FP64 model of every inter-component edge (code = 2 a + (0 right, 1
+// down)): omega and the two gamma factors, for the relative-scale
+// weights and residuals, which are computed in FP64 throughout
+__global__ void __launch_bounds__(256) k_inter_geom(const uint32_t* __restrict__ eidx, int E, int W,
+                                                    const float* __restrict__ nrm, int persp, double pitch,
+                                                    RayTabs T, double* __restrict__ eom, double* __restrict__ eta,
+                                                    double* __restrict__ etb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  const uint32_t code = eidx[i];
+  const long long p = code >> 1;
+  const bool horiz = (code & 1u) == 0u;
+  const int u = (int)(p % W), v = (int)(p / W);
+  double om = 0.0, ta = 0.0, tb = 0.0;
+  (void)edge_model(nrm, p, horiz ? p + 1 : p + W, u, v, horiz, persp, pitch, T, &om, &ta, &tb);
+  eom[i] = om;
+  eta[i] = ta;
+  etb[i] = tb;
 }
 
 // ------------------------------------------------------------ union-find
@@ -184,8 +210,16 @@ hipError_t launch_setup(const float* nrm, const uint8_t* mask, int H, int W, int
   const double* ty = tables + W;
   const double* txm = tables + W + H;
   const double* tym = tables + 2 * W + H;
-  k_setup<<<ni::ceil_div(P, 256), 256, 0, st>>>(nrm, mask, H, W, persp, pitch, tx, ty, txm, tym, cth,
+  k_setup<<<ni::ceil_div(P, 256), 256, 0, st>>>(nrm, mask, H, W, persp, pitch, RayTabs{tx, ty, txm, tym}, cth,
                                                 use_sim, ebits, om_r, om_d, nt, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_inter_geom(const uint32_t* eidx, int E, int H, int W, const float* nrm, int persp, double pitch,
+                             const double* tables, double* eom, double* eta, double* etb, hipStream_t st) {
+  if (E <= 0) return hipSuccess;
+  const RayTabs T{tables, tables + W, tables + W + H, tables + 2 * W + H};
+  k_inter_geom<<<ni::ceil_div(E, 256), 256, 0, st>>>(eidx, E, W, nrm, persp, pitch, T, eom, eta, etb);
   return hipGetLastError();
 }
 
