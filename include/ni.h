@@ -185,6 +185,21 @@ ni_status ni_label(ni_ctx* ctx, const float* normals, const uint8_t* mask,
                    const ni_params* params, int32_t* labels, int32_t* K,
                    ni_report* rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): stage (a)
+ * as ni_label, with no allocation of any kind.  Its scratch (edge arrays,
+ * union-find, counters; 28 MiB) is a static device array of the library,
+ * one copy per GPU, held until the process ends; its address is looked up
+ * when a context is created on the device.  Maps are limited to H, W <=
+ * 4096 and H*W <= 2^20 (NI_E_SHAPE beyond).  The call clears what must
+ * start at zero, writes labels / *K exactly as ni_label does, and blocks
+ * for *K.  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (several threads or streams) race and must not be
+ * issued. */
+ni_status ni_label_noalloc(ni_ctx* ctx, const float* normals, const uint8_t* mask,
+                           int32_t H, int32_t W, const ni_camera* cam,
+                           const ni_params* params, int32_t* labels, int32_t* K);
+
 /* Stage (b) from given labels (Eq. 14-15): labels device i32 [H][W] in
  * (ids 0..K-1 on valid pixels, each component 4-connected through usable
  * edges, -1 off the mask); zfill device f32 [H][W] out: filled log-depth

@@ -17,6 +17,7 @@ NI_OK, NI_E_ARG, NI_E_SHAPE, NI_E_NONFINITE, NI_E_NOMEM, NI_E_DEVICE, NI_E_NOTCO
 NI_ORTHO, NI_PERSP = 0, 1
 
 EXPORTED = ["ni_params_default", "ni_create", "ni_destroy", "ni_set_stream", "ni_integrate", "ni_label",
+            "ni_label_noalloc",
             "ni_fill", "ni_irls", "ni_unet_load", "ni_status_str", "ni_last_error", "ni_abi_version",
             "ni_unet_param_count", "ni_unet_blob_size", "ni_unet_init", "ni_unet_save", "ni_unet_get_params",
             "ni_unet_set_params", "ni_unet_predict", "ni_unet_forward", "ni_unet_backward", "ni_unet_train_step"]
@@ -81,6 +82,7 @@ def lib():
         L.ni_integrate.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, vp, vp, i64,
                                    P(i32), P(ni_report)]
         L.ni_label.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, P(i32), P(ni_report)]
+        L.ni_label_noalloc.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, P(i32)]
         L.ni_fill.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, P(ni_report)]
         L.ni_irls.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, vp, vp, i64,
                               P(ni_report)]
@@ -212,6 +214,21 @@ class Context:
         self._raise(lib().ni_label(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
                                    _ptr(labels), C.byref(K), C.byref(rep)))
         return labels, K.value, rep.as_dict()
+
+    def ni_label_noalloc(self, normals, mask, cam, labels, params=None):
+        """Labels into the caller's int32 [H, W] device tensor `labels`; the
+        library allocates nothing (static per-GPU scratch).  Returns K."""
+        import torch
+        H, W = _check_inputs(normals, mask)
+        p = params or ni_params_default()
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        if labels.dtype != torch.int32 or tuple(labels.shape) != (H, W) or not labels.is_contiguous():
+            raise ValueError("labels must be a contiguous int32 [H, W] tensor")
+        K = C.c_int32(0)
+        self._stream()
+        self._raise(lib().ni_label_noalloc(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
+                                           _ptr(labels), C.byref(K)))
+        return K.value
 
     def ni_fill(self, normals, mask, cam, labels, K, params=None):
         import torch

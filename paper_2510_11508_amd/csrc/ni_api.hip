@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,8 @@ hipError_t launch_setup(const float*, const uint8_t*, int, int, int, double, con
                         uint8_t*, float*, float*, float*, int*, hipStream_t);
 hipError_t launch_inter_geom(const uint32_t*, int, int, int, const float*, int, double, const double*, double*,
                              double*, double*, hipStream_t);
+hipError_t set_i32(int*, int, int, hipStream_t);
+hipError_t ray_tables(int, int, double, double, double, double, double*, hipStream_t);
 hipError_t grid_components(const uint8_t*, int, int, uint8_t, uint8_t, int*, int*, int*, int*, int*, int*,
                            hipStream_t);
 // ni_fill.hip
@@ -90,6 +93,36 @@ struct Fail {
 
 }  // namespace
 
+// Scratch of the allocation-free labelling entry point (ni_label_noalloc):
+// one copy of this array per GPU, held until the process ends.  In host
+// code its name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, looked up once per device when a context is
+// created on it, and only that address is passed to kernels and copies.
+constexpr int NOALLOC_MAX_SIDE = 4096;
+constexpr long long NOALLOC_MAX_PX = 1ll << 20;
+constexpr size_t NOALLOC_BYTES = (size_t)28 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[NOALLOC_MAX_DEV] = {};
+
+// the device address of `scratch` on the current device (looked up once)
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+}  // namespace
+
 struct ni_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -115,6 +148,7 @@ struct ni_ctx {
   int* host = nullptr;  // pinned readback area (64 ints)
   hipEvent_t ev[16] = {};
   struct nil::UnetModel* unet = nullptr;
+  void* noalloc = nullptr;       // device address of `scratch` on this device
   nil::Amg* amg = nullptr;       // quotient systems
   nil::Amg* amg_fill = nullptr;  // fill of the large components
   // autotuned schedule of the large fill path: shortest chunk per block,
@@ -909,6 +943,7 @@ ni_status ni_create(ni_ctx** out, int device) {
     check(c, hipHostMalloc((void**)&c->host, 64 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     for (auto& e : c->ev) check(c, hipEventCreate(&e), "hipEventCreate");
     check(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "hipStreamCreate");
+    check(c, scratch_address(device, &c->noalloc), "hipGetSymbolAddress(scratch)");
   });
   if (s != NI_OK) {
     ni_destroy(c);
@@ -1026,6 +1061,68 @@ ni_status ni_label(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
       rep->ms_setup = ev_ms(c, 0, 1);
       rep->ms_label = ev_ms(c, 1, 2);
     }
+  });
+}
+
+ni_status ni_label_noalloc(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                           const ni_camera* cam, const ni_params* params, int32_t* labels, int32_t* K) {
+  Problem pb;
+  ni_status s = validate(c, normals, mask, H, W, cam, params, &pb);
+  if (s != NI_OK) return s;
+  if (!labels || !K) {
+    c->err = "null output pointer";
+    return NI_E_ARG;
+  }
+  if (H > NOALLOC_MAX_SIDE || W > NOALLOC_MAX_SIDE || (long long)H * W > NOALLOC_MAX_PX) {
+    c->err = "map larger than the allocation-free scratch holds (H, W <= 4096, H*W <= 2^20)";
+    return NI_E_SHAPE;
+  }
+  if (!c->noalloc) {
+    c->err = "no scratch address for this device";
+    return NI_E_DEVICE;
+  }
+  return guarded(c, [&] {
+    check(c, hipSetDevice(c->device), "hipSetDevice");
+    const int P = H * W;
+    // carve the scratch: counters, ray tables, edge arrays, union-find
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      char* p = static_cast<char*>(c->noalloc) + off;
+      off += (bytes + 255) & ~(size_t)255;
+      return p;
+    };
+    int* cnt = reinterpret_cast<int*>(take(16 * sizeof(int)));  // [0] K, [8] non-finite flag
+    double* tab = reinterpret_cast<double*>(take((2 * (size_t)W + 2 * (size_t)H) * sizeof(double)));
+    uint8_t* ebits = reinterpret_cast<uint8_t*>(take(P));
+    float* om_r = reinterpret_cast<float*>(take((size_t)P * sizeof(float)));
+    float* om_d = reinterpret_cast<float*>(take((size_t)P * sizeof(float)));
+    float* nt = reinterpret_cast<float*>(take((size_t)P * sizeof(float)));
+    int* parent = reinterpret_cast<int*>(take((size_t)P * sizeof(int)));
+    int* flag = reinterpret_cast<int*>(take((size_t)P * sizeof(int)));
+    int* cid = reinterpret_cast<int*>(take((size_t)P * sizeof(int)));
+    int* stmp = reinterpret_cast<int*>(take(nil::scan_tmp_ints(P) * sizeof(int)));
+    if (off > NOALLOC_BYTES) {
+      c->err = "allocation-free scratch too small for this map";
+      throw Fail{NI_E_SHAPE};
+    }
+    hipStream_t st = c->stream;
+    check(c, nil::set_i32(cnt, 16, 0, st), "clear counters");
+    const bool persp = pb.cam.proj == NI_PERSP;
+    if (persp) check(c, nil::ray_tables(H, W, pb.cam.cx, pb.cam.cy, pb.cam.fx, pb.cam.fy, tab, st), "ray tables");
+    const double th = pb.prm.theta_c_deg;
+    const int use_sim = th > 0 ? 1 : 0;
+    const double cth = use_sim ? cos(th * M_PI / 180.0) : 2.0;
+    check(c, nil::launch_setup(normals, mask, H, W, persp, pb.cam.pixel_pitch, tab, cth, use_sim, ebits, om_r, om_d,
+                               nt, cnt + 8, st),
+          "setup");
+    check(c, nil::grid_components(ebits, H, W, EB_SR, EB_SD, parent, flag, cid, labels, cnt, stmp, st), "label");
+    check(c, hipMemcpyAsync(c->host, cnt, 16 * sizeof(int), hipMemcpyDeviceToHost, st), "D2H");
+    check(c, hipStreamSynchronize(st), "sync");
+    if (c->host[8]) {
+      c->err = "non-finite normal inside the mask";
+      throw Fail{NI_E_NONFINITE};
+    }
+    *K = c->host[0];
   });
 }
 

@@ -118,6 +118,26 @@ __global__ void __launch_bounds__(256) k_inter_geom(const uint32_t* __restrict__
   etb[i] = tb;
 }
 
+__global__ void k_set_i32(int* __restrict__ a, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// ray tables tau = ((u - cx)/fx, (v - cy)/fy) at pixel centres and at the
+// midpoints u + 1/2, v + 1/2, in FP64 on the device (the same correctly
+// rounded subtraction and division as the host's tables)
+__global__ void k_ray_tables(int H, int W, double cx, double cy, double fx, double fy, double* __restrict__ t) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < W) {
+    t[i] = ((double)i - cx) / fx;
+    t[W + H + i] = (((double)i + 0.5) - cx) / fx;
+  } else if (i < W + H) {
+    const int v = i - W;
+    t[W + v] = ((double)v - cy) / fy;
+    t[2 * W + H + v] = (((double)v + 0.5) - cy) / fy;
+  }
+}
+
 // ------------------------------------------------------------ union-find
 // parent[x] <= x always holds, so the root of every tree is its smallest
 // index and the final labelling is canonical whatever the order of unions.
@@ -212,6 +232,16 @@ hipError_t launch_setup(const float* nrm, const uint8_t* mask, int H, int W, int
   const double* tym = tables + 2 * W + H;
   k_setup<<<ni::ceil_div(P, 256), 256, 0, st>>>(nrm, mask, H, W, persp, pitch, RayTabs{tx, ty, txm, tym}, cth,
                                                 use_sim, ebits, om_r, om_d, nt, err);
+  return hipGetLastError();
+}
+
+hipError_t set_i32(int* a, int n, int v, hipStream_t st) {
+  if (n > 0) k_set_i32<<<ni::ceil_div(n, 256), 256, 0, st>>>(a, n, v);
+  return hipGetLastError();
+}
+
+hipError_t ray_tables(int H, int W, double cx, double cy, double fx, double fy, double* t, hipStream_t st) {
+  k_ray_tables<<<ni::ceil_div(W + H, 256), 256, 0, st>>>(H, W, cx, cy, fx, fy, t);
   return hipGetLastError();
 }
 
