@@ -6,26 +6,25 @@ system stopped at ||r_c|| <= 1e-6 ||b_c||.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
 
-The roofline object describes one PCG iteration of the large fill
-components.  By default they are solved together by one PCG preconditioned
-by a multigrid V-cycle (aggregates of 2x2 pixel blocks per component); one
-iteration is the cycle's launches on every level plus the (p, q) and
-(x, r) updates on level 0.  Its algorithmic bytes come from the library
-(ni_report.fill_mg_bytes: per level, the CSR rows, entries and FP64
-vectors each kernel must read or write once; neighbour re-reads are cache
-hits).  achieved = those bytes / the event-timed duration of one iteration
-(the solve's launches, batched, divided by the iterations).  With the
-Jacobi preconditioner (fill_precond = 0) the unit is the two- or
-three-launch chunked iteration (k_lg_*) at 64 B per active pixel.
-traffic = calibrated FETCH_SIZE + WRITE_SIZE per iteration from committed
-counter runs (profiles/fill_mg_traffic_<workload>.json), while they match
-the kernel sources.  The CPU baseline is the FP64 oracle on this host.
+The default workload is c5 (4096^2, the largest single-GPU configuration).
+Beside the zero-start rate (`value`) the line carries the learned warm
+start at the same residual, the pixel-level form (every pixel its own
+component) and the FP64 oracle on this host.
 
-With a trained warm-start model (paper_2510_11508_amd/weights/, or
---model) the same map is also integrated with warm_start = 1 and the
-report compares the two at the same 1e-6 residual (relative to ||b||):
-speedup = wall(zero start) / wall(warm start incl. network inference).
+roofline: one PCG iteration of the batched fill of the large components
+(the multigrid-preconditioned CG over all of them at once).  Algorithmic
+bytes = 32 B per active pixel per CG iteration (FP32 right and down
+weights, 8 B, plus x, r, p read and written, 24 B) times the pixels of the
+large components, all of which take part in every iteration.  achieved =
+those bytes / the HIP-event-timed duration of one iteration (the solve's
+launches divided by its iterations), measured inside this run.  The bytes
+the multigrid iteration itself moves by its own model (every level's CSR
+and FP64 vectors, ni_report.fill_mg_bytes) are reported beside it.
+traffic = calibrated FETCH_SIZE + WRITE_SIZE per iteration from committed
+counter runs (profiles/fill_mg_traffic_<workload>.json, written by
+--digest-counters), while they match the kernel sources.
 """
+import os
 import os
 
 # the oracle's CPU baseline is timed single-threaded: pin BLAS pools before numpy loads
@@ -43,7 +42,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "valid Mpixels/s integrated at 1e-6 residual; warm-start vs plain CG speedup"
 HBM_PEAK_GBS = 8000.0
-CG_BYTES_PER_PX_ITER = 64
+CG_BYTES_PER_PX_ITER = 32   # algorithmic bytes per active pixel per CG iteration
+JACOBI_BYTES_PER_PX_ITER = 64
 DEFAULT_MODEL = os.path.join(ROOT, "paper_2510_11508_amd", "weights", "unet_warmstart.niunet")
 # forward multiply-adds per input pixel of the warm-start U-Net: 3x3
 # convolutions (cin -> cout) at full, 1/4, 1/16 and 1/64 resolution, plus
@@ -79,28 +79,169 @@ def traffic_record(workload, key):
     return rec.get("schedules", {}).get(key, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(sample, params, budget_s=12.0):
-    """The FP64 oracle as it stands, on this host, single-threaded."""
+def cpu_baseline(name, seed, params):
+    """The FP64 oracle as it stands, on this host, single-threaded: one full
+    integration of the named map (c3 when the workload is c5: the oracle's
+    direct solves on a 4096^2 map take minutes)."""
+    import synth
     from oracle import ni_oracle as O
+    sample = synth.make(name, seed)
     n_valid = int((sample.mask > 0).sum())
     runs, t0 = 0, time.perf_counter()
     while True:
         O.integrate(sample.normals, sample.mask, sample.cam, params)
         runs += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 50:
+        if el >= 10.0 or runs >= 50:
             break
-    return dict(value=n_valid * runs / el / 1e6, unit="Mpx/s", cores=1, kind="oracle",
-                sample=f"{runs} full oracle integration(s) of the same {sample.name} map "
+    return dict(value=round(n_valid * runs / el / 1e6, 4), unit="Mpx/s", cores=1, kind="oracle",
+                sample=f"{runs} full oracle integration(s) of the {name} map, seed {seed} "
                        f"({n_valid} valid px), FP64 sparse-direct solves, {el:.1f} s")
+
+
+FILL_KERNELS = r"(k_cy_\w+<1>|k_cg_\w+<1>|k_fs_scal1|k_fs_xr)"
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _short(name):
+    import re
+    n = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", n).strip()
+
+
+def _kname(row):
+    return row.get("Kernel_Name") or row.get("Name") or ""
+
+
+def digest_counters(workload, fetch_dir, write_dir):
+    """profiles/fill_mg_traffic_<workload>.{json,md} from two counter runs of
+    `bench.py --workload W --steps 1 --warmup 0 --no-cpu-baseline --no-warm
+    --no-pixel-level --copy-calibration` (one integration), FETCH_SIZE then
+    WRITE_SIZE, each with its JSON line in <dir>/bench.json.  Counter values
+    (KiB per dispatch) are scaled by what the same counter reads on the
+    plain 1 GiB copy of the calibration, summed over the dispatches of the
+    fill solve's kernels and divided by its iterations."""
+    import re
+    line = json.load(open(os.path.join(fetch_dir, "bench.json")))
+    its = line["roofline"]["iterations"]
+    out = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _csv_rows(d, "counter_collection.csv") if r.get("Counter_Name") == cname]
+        cal = max((float(r["Counter_Value"]) for r in rows if "copy" in _kname(r).lower()), default=0.0)
+        if cal <= 0:
+            raise SystemExit(f"no copy-calibration dispatch in {d}")
+        factor = (1 << 30) / (cal * 1024.0)
+        per_kernel = {}
+        for r in rows:
+            k = _kname(r)
+            if re.search(FILL_KERNELS, k):
+                short = _short(k)
+                per_kernel[short] = per_kernel.get(short, 0.0) + float(r["Counter_Value"])
+        tot = sum(per_kernel.values())
+        out[cname] = dict(calibration_KiB=cal, factor=factor, fill_KiB=tot, per_kernel_KiB=per_kernel,
+                          bytes_per_iteration=tot * 1024.0 * factor / its)
+    traffic = out["FETCH_SIZE"]["bytes_per_iteration"] + out["WRITE_SIZE"]["bytes_per_iteration"]
+    alg = line["roofline"]["bytes_per_iteration"]
+    rec = dict(workload=workload, kernel_hash=kernel_hash(),
+               unit="bytes per PCG iteration of the large fill components",
+               schedules={"multigrid": dict(bytes_per_launch=round(traffic),
+                                            fetch_bytes=round(out["FETCH_SIZE"]["bytes_per_iteration"]),
+                                            write_bytes=round(out["WRITE_SIZE"]["bytes_per_iteration"]),
+                                            algorithmic_bytes=alg, ratio_to_algorithmic=round(traffic / alg, 3),
+                                            multigrid_model_bytes=line["roofline"].get("multigrid_model", {})
+                                            .get("bytes_per_iteration"),
+                                            iterations=its, counters=out)})
+    base = os.path.join(ROOT, "profiles", f"fill_mg_traffic_{workload}")
+    json.dump(rec, open(base + ".json", "w"), indent=1)
+    mm = rec["schedules"]["multigrid"]["multigrid_model_bytes"]
+    with open(base + ".md", "w") as f:
+        f.write(f"# HBM-side traffic of one PCG iteration of the large fill components, workload {workload}\n\n")
+        f.write("Two counter runs of one integration each (FETCH_SIZE, then WRITE_SIZE); the same process also\n"
+                "runs a plain 1 GiB device copy, whose reading gives the bytes-per-count factor:\n\n")
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            f.write(f"    cd /tmp && timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d <dir_{c}> -o run -- "
+                    f"python3 <repo>/bench.py --workload {workload} --steps 1 --warmup 0 --no-cpu-baseline "
+                    f"--no-warm --no-pixel-level --copy-calibration > <dir_{c}>/bench.json\n")
+        f.write(f"    python3 <repo>/bench.py --workload {workload} --digest-counters <dir_FETCH_SIZE> <dir_WRITE_SIZE>\n\n")
+        f.write(f"Fill-solve kernels (`{FILL_KERNELS}`), {its} iterations.\n\n")
+        f.write("| counter | copy reading (KiB) | factor | fill solve (KiB) | per iteration (MB) |\n|---|---|---|---|---|\n")
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            o = out[c]
+            f.write(f"| {c} | {o['calibration_KiB']:,.1f} | {o['factor']:.4f} | {o['fill_KiB']:,.0f} | "
+                    f"{o['bytes_per_iteration'] / 1e6:,.1f} |\n")
+        f.write(f"\n- Measured traffic per iteration: {traffic / 1e6:,.1f} MB.\n")
+        f.write(f"- Algorithmic bytes per iteration (32 B x {line['roofline']['active_px']:,} active px): "
+                f"{alg / 1e6:,.1f} MB (ratio {traffic / alg:.2f}).\n")
+        if mm:
+            f.write(f"- The multigrid iteration's own model (every level, FP64): {mm / 1e6:,.1f} MB "
+                    f"(ratio {traffic / mm:.2f}).\n")
+        f.write("\nFETCH_SIZE by kernel over the solve (KiB, uncalibrated):\n\n| kernel | KiB |\n|---|---|\n")
+        for k, v in sorted(out["FETCH_SIZE"]["per_kernel_KiB"].items(), key=lambda kv: -kv[1]):
+            f.write(f"| {k} | {v:,.0f} |\n")
+        f.write(f"\n`{os.path.basename(base)}.json` holds these figures with a hash of `ni_fill.hip` and "
+                "`ni_amg.hip`; `bench.py` reports them as `roofline.traffic` only while the hash matches.\n")
+    print(json.dumps(rec["schedules"]["multigrid"]["bytes_per_launch"]))
+
+
+def digest_trace(workload, d):
+    """profiles/integrate_<workload>_kernel_stats.md from a rocprofv3
+    --kernel-trace --stats run of this script (its JSON line in d/bench.json):
+    the top kernels, and the fill solve's kernel time per iteration beside
+    the bench's own event-timed figure."""
+    import re
+    line = json.load(open(os.path.join(d, "bench.json")))
+    rows = _csv_rows(d, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    calls = line["steps"] + line["warmup"]
+    fill_ns = sum(float(r["TotalDurationNs"]) for r in rows if re.search(FILL_KERNELS, r["Name"]))
+    quot_ns = sum(float(r["TotalDurationNs"]) for r in rows if re.search(r"k_cy_\w+<0>|k_cg_\w+<0>|k_cg_\w+_f\b", r["Name"]))
+    its = line["roofline"]["iterations"]
+    base = os.path.join(ROOT, "profiles", f"integrate_{workload}_kernel_stats.md")
+    with open(base, "w") as f:
+        f.write(f"# Kernel time, whole integration, workload {workload} "
+                f"({line['config']['n_valid']:,} valid px, K = {line['config']['K']:,})\n\n")
+        f.write("Command (from the repository root on the GPU box):\n\n")
+        f.write(f"    cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 "
+                f"<repo>/bench.py --workload {workload} --steps {line['steps']} --warmup {line['warmup']} "
+                "--no-cpu-baseline --no-warm --no-pixel-level > <dir>/bench.json\n")
+        f.write(f"    python3 <repo>/bench.py --workload {workload} --digest-trace <dir>\n\n")
+        f.write(f"{calls} ni_integrate calls. Kernel time {tot / 1e6 / calls:,.2f} ms per call; "
+                f"bench ms_per_step {line['ms_per_step']} (event-timed stages: {line['stages_ms']}).\n\n")
+        f.write(f"- Fill solve of the large components (`{FILL_KERNELS}`): "
+                f"{fill_ns / 1e6 / calls:,.2f} ms per call, {fill_ns / 1e3 / calls / max(its, 1):,.1f} us per "
+                f"iteration over {its} iterations; the bench's HIP-event figure for the same iteration: "
+                f"{line['roofline']['ms_per_iteration'] * 1e3:,.1f} us (it also spans the gaps between launches).\n")
+        f.write(f"- Relative-scale solves (quotient multigrid PCG, `<0>` kernels): {quot_ns / 1e6 / calls:,.2f} ms "
+                "per call.\n\n")
+        f.write("| kernel | calls | total ms | avg us | min us | max us | share |\n|---|---|---|---|---|---|---|\n")
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:24]:
+            nm = _short(r["Name"])
+            f.write(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:,.2f} | "
+                    f"{float(r['AverageNs']) / 1e3:,.2f} | {float(r['MinNs']) / 1e3:,.2f} | "
+                    f"{float(r['MaxNs']) / 1e3:,.2f} | {100 * float(r['TotalDurationNs']) / tot:.1f}% |\n")
+        f.write("\nbench.py line of the same run:\n\n    " + json.dumps({k: line[k] for k in (
+            "value", "unit", "ms_per_step", "stages_ms", "quot_iters", "roofline") if k in line}) + "\n")
+    print(base)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--model", default=DEFAULT_MODEL, help="warm-start weights (skipped if absent)")
@@ -113,7 +254,19 @@ def main():
                     help="preconditioner of the large fill components (default: the library's, multigrid)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/fill_mg_traffic_<workload>.{json,md} from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this script with --steps 1 --warmup 0 --copy-calibration")
+    ap.add_argument("--digest-trace", metavar="DIR",
+                    help="write profiles/integrate_<workload>_kernel_stats.md from a rocprofv3 --kernel-trace "
+                         "--stats run of this script (CSV output) and its JSON line (DIR/bench.json)")
     a = ap.parse_args()
+    if a.digest_counters:
+        digest_counters(a.workload, *a.digest_counters)
+        return
+    if a.digest_trace:
+        digest_trace(a.workload, a.digest_trace)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); there is no multi-GPU path",
               file=sys.stderr)
@@ -223,30 +376,36 @@ def main():
     launches = max(rep["fill_large_launches"], 1)
     launch_ms = k_ms / launches
     mg = rep["fill_mg_levels"] > 0 and not rep["fill_mg_fallback"]
+    large_px = int(rep["fill_large_px"])
+    launch_bytes = CG_BYTES_PER_PX_ITER * large_px
     if mg:
-        launch_bytes = rep["fill_mg_bytes"]
         key = "multigrid"
-        kernel = ("one multigrid-preconditioned PCG iteration of the large fill components: k_cy_down, "
-                  "k_cy_restrict, k_cy_up on every level, k_cy_coarsest, k_fs_scal1, k_cg_pq, k_cg_scal, k_fs_xr")
+        kernel = ("one multigrid-preconditioned PCG iteration of the large fill components (all of them at "
+                  "once): k_cy_down<1>, k_cy_restrict<1>, k_cy_up<1> on every level, k_cy_coarsest<1>, "
+                  "k_fs_scal1, k_cg_pq<1>, k_cg_scal<1>, k_fs_xr")
     else:
-        px_iters = rep["fill_large_px_iters"]
-        launch_bytes = CG_BYTES_PER_PX_ITER * px_iters / launches
         key = f"{rep['fill_chunk']}:{rep['fill_split']}"
         kernel = (("k_lg_p + k_lg_q + k_lg_b" if rep["fill_split"] else "k_lg_a + k_lg_b")
                   + " (one Jacobi-PCG iteration of the large components)")
     achieved = launch_bytes / (launch_ms / 1000.0) / 1e9 if k_ms > 0 else 0.0
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_record(a.workload, key),
-                kernel=kernel, bytes_per_iteration=round(launch_bytes), iterations=launches,
-                ms_per_iteration=round(launch_ms, 5))
+                kernel=kernel, bytes_per_iteration=launch_bytes, bytes_per_px_iter=CG_BYTES_PER_PX_ITER,
+                active_px=large_px, iterations=launches, ms_per_iteration=round(launch_ms, 5))
     if mg:
-        roof["levels"] = rep["fill_mg_levels"]
+        mb = rep["fill_mg_bytes"]
+        ma = mb / (launch_ms / 1000.0) / 1e9 if k_ms > 0 else 0.0
+        roof["multigrid_model"] = dict(levels=rep["fill_mg_levels"], bytes_per_iteration=round(mb),
+                                       achieved=round(ma, 1), frac=round(ma / HBM_PEAK_GBS, 4))
     else:
-        roof["bytes_per_px_iter"] = CG_BYTES_PER_PX_ITER
+        ja = JACOBI_BYTES_PER_PX_ITER * rep["fill_large_px_iters"] / launches / (launch_ms / 1000.0) / 1e9
+        roof["jacobi_model"] = dict(bytes_per_px_iter=JACOBI_BYTES_PER_PX_ITER, achieved=round(ja, 1),
+                                    frac=round(ja / HBM_PEAK_GBS, 4))
 
     line = dict(metric=METRIC, value=round(value, 3), unit="Mpx/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
                 ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
-                dtype="f32 stencil and small-component CG, f64 multigrid CG and reductions", data="synthetic",
+                dtype="f32 stencil and small-component CG; f64 multigrid fill CG, reductions and relative-scale solve",
+                data="synthetic",
                 config=dict(workload=f"{a.workload}: {WORKLOADS[a.workload]}", seed=a.seed, n_valid=n_valid,
                             K=out["K"], H=int(s.mask.shape[0]), W=int(s.mask.shape[1])),
                 stages_ms=stage_ms(reps),
@@ -264,7 +423,8 @@ def main():
     if pixel is not None:
         line["pixel_level"] = pixel
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(s, dict(theta_c_deg=2.0, irls_iters=T))
+        cname = "c3" if a.workload == "c5" else a.workload
+        line["cpu_baseline"] = cpu_baseline(cname, a.seed, dict(theta_c_deg=2.0, irls_iters=T))
     ctx.close()
     print(json.dumps(line))
 

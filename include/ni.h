@@ -80,9 +80,11 @@ typedef struct {
   double cg_rtol;       /* fill CG: stop at ||r_c|| <= cg_rtol * ||b_c||      */
   int32_t cg_max_iter;  /* fill CG iteration cap per component                */
   double q_rtol;        /* quotient solve, two rounds of multigrid PCG: the
-                           first stops at ||r|| <= q_rtol ||b||, the second
-                           solves for the correction from the flow-form
-                           residual b - L s to q_rtol of that residual      */
+                           first stops at ||r|| <= q_rtol ||b_abs|| (b_abs =
+                           row sums of the pair terms' magnitudes), the
+                           second solves for the correction from the
+                           flow-form residual b - L s to q_rtol of that
+                           residual (at least 1e-13 ||b_abs||)              */
   int32_t q_max_iter;   /* iteration cap of each round; reaching it makes the
                            call return NI_E_NOTCONV (outputs still written) */
   int32_t warm_start;   /* 0 zero start; 1 learned start (needs ni_unet_load) */
@@ -136,6 +138,7 @@ typedef struct {
                                within fill_mg_maxit iterations and the
                                large components were solved again with
                                the Jacobi path                             */
+  int64_t fill_large_px;  /* pixels of the components on the large path    */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;
@@ -217,6 +220,20 @@ ni_status ni_irls(ni_ctx* ctx, const float* normals, const uint8_t* mask,
                   const ni_params* params, const int32_t* labels, int32_t K,
                   const float* zfill, float* depth, double* log_scale,
                   int64_t cap, ni_report* rep);
+
+/* One relative-scale iteration t (Sec. 3.4, Eq. 16-17; Alg. 1's loop
+ * body) from given scales, a test hook that injects the oracle's state:
+ * labels / zfill as for ni_irls; S_in device f64 [K] the scales before the
+ * step; the weights of iteration t (uniform when t < align_iters) are
+ * formed at z = zfill + S_in, the system is solved as in ni_integrate,
+ * and the increment s^(t) (zero mean on every connected piece of the
+ * weighted quotient graph) goes to s_out device f64 [K]; *energy (host)
+ * gets E_t.  NI_E_NOTCONV if a solve round stopped at q_max_iter. */
+ni_status ni_irls_step(ni_ctx* ctx, const float* normals, const uint8_t* mask,
+                       int32_t H, int32_t W, const ni_camera* cam,
+                       const ni_params* params, const int32_t* labels, int32_t K,
+                       const float* zfill, const double* S_in, int32_t t,
+                       double* s_out, double* energy, ni_report* rep);
 
 /* ---------------------------------------------------------------------
  * Learned warm start (not in the paper): a 4-level U-Net (16-32-64-128

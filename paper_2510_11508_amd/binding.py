@@ -17,7 +17,7 @@ NI_OK, NI_E_ARG, NI_E_SHAPE, NI_E_NONFINITE, NI_E_NOMEM, NI_E_DEVICE, NI_E_NOTCO
 NI_ORTHO, NI_PERSP = 0, 1
 
 EXPORTED = ["ni_params_default", "ni_create", "ni_destroy", "ni_set_stream", "ni_integrate", "ni_label",
-            "ni_label_noalloc",
+            "ni_label_noalloc", "ni_irls_step",
             "ni_fill", "ni_irls", "ni_unet_load", "ni_status_str", "ni_last_error", "ni_abi_version",
             "ni_unet_param_count", "ni_unet_blob_size", "ni_unet_init", "ni_unet_save", "ni_unet_get_params",
             "ni_unet_set_params", "ni_unet_predict", "ni_unet_forward", "ni_unet_backward", "ni_unet_train_step"]
@@ -51,7 +51,8 @@ class ni_report(C.Structure):
                 ("ms_fill_large", C.c_float), ("ms_irls", C.c_float), ("ms_finalize", C.c_float),
                 ("ms_total", C.c_float), ("ms_large_kernel", C.c_float), ("fill_chunk", C.c_int32),
                 ("fill_split", C.c_int32), ("fill_mg_levels", C.c_int32), ("ms_fill_mg_build", C.c_float),
-                ("fill_mg_bytes", C.c_double), ("fill_mg_fallback", C.c_int32)]
+                ("fill_mg_bytes", C.c_double), ("fill_mg_fallback", C.c_int32),
+                ("fill_large_px", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -82,6 +83,8 @@ def lib():
         L.ni_integrate.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, vp, vp, i64,
                                    P(i32), P(ni_report)]
         L.ni_label.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, P(i32), P(ni_report)]
+        L.ni_irls_step.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, vp, i32, vp,
+                                   P(C.c_double), P(ni_report)]
         L.ni_label_noalloc.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, P(i32)]
         L.ni_fill.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, P(ni_report)]
         L.ni_irls.argtypes = [vp, vp, vp, i32, i32, P(ni_camera), P(ni_params), vp, i32, vp, vp, vp, i64,
@@ -242,6 +245,25 @@ class Context:
         self._raise(lib().ni_fill(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
                                   _ptr(labels), int(K), _ptr(z), C.byref(rep)))
         return z, rep.as_dict()
+
+    def ni_irls_step(self, normals, mask, cam, labels, K, zfill, S_in, t, params=None):
+        """One relative-scale iteration t from the scales S_in (f64 [K]);
+        returns (s^(t) f64 [K] device tensor, E_t, report)."""
+        import torch
+        H, W = _check_inputs(normals, mask)
+        p = params or ni_params_default()
+        camc = make_camera(cam) if not isinstance(cam, ni_camera) else cam
+        labels = labels.to(device=normals.device, dtype=torch.int32).contiguous()
+        zfill = zfill.to(device=normals.device, dtype=torch.float32).contiguous()
+        S_in = S_in.to(device=normals.device, dtype=torch.float64).contiguous()
+        s_out = torch.empty((max(int(K), 1),), dtype=torch.float64, device=normals.device)
+        e = C.c_double(0.0)
+        rep = ni_report()
+        self._stream()
+        self._raise(lib().ni_irls_step(self.h, _ptr(normals), _ptr(mask), H, W, C.byref(camc), C.byref(p),
+                                       _ptr(labels), int(K), _ptr(zfill), _ptr(S_in), int(t), _ptr(s_out),
+                                       C.byref(e), C.byref(rep)))
+        return s_out[: int(K)], e.value, rep.as_dict()
 
     def ni_irls(self, normals, mask, cam, labels, K, zfill, params=None):
         import torch

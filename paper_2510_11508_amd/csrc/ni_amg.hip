@@ -46,7 +46,7 @@ constexpr int AMAXL = 24;     // levels at most
 constexpr double AOMEGA = 2.0 / 3.0;
 
 // scalars of the PCG, one double each
-enum { S_RHO = 0, S_RHOP, S_BETA, S_ALPHA, S_RR, S_BS, S_PQ, S_RH0, S_RH1, S_N };
+enum { S_RHO = 0, S_RHOP, S_BETA, S_ALPHA, S_RR, S_BS, S_PQ, S_RH0, S_RH1, S_FL, S_N };
 
 // device view of one level
 struct ALev {
@@ -111,8 +111,12 @@ __device__ __forceinline__ void put_parts(double (&v)[NV], double* red, double* 
 }
 
 // ------------------------------------------------------------------ cycle
+// The cycle and CG kernels are instantiated twice, FILL = 1 for the fill
+// of the large components and 0 for the relative-scale systems: the same
+// code under two names, so that kernel traces separate the two solves.
 // pre-smoothing from zero and the residual: r = b - A x with x = w D^-1 b
 // (x itself is recomputed where it is needed)
+template <int FILL>
 __global__ void __launch_bounds__(ANT) k_cy_down(ALev L, const int* done) {
   if (is_done(done)) return;
   __shared__ double red[ANT / 64];
@@ -132,6 +136,7 @@ __global__ void __launch_bounds__(ANT) k_cy_down(ALev L, const int* done) {
 
 // restriction b' = P^T r: each coarse node sums its members' residuals
 // (aggregates with more than AH members are summed by a whole block)
+template <int FILL>
 __global__ void __launch_bounds__(ANT) k_cy_restrict(int n, int nblk, const int* __restrict__ mem_off,
                                                      const int* __restrict__ mem, const int* __restrict__ mheavy,
                                                      const double* __restrict__ r, double* __restrict__ bc,
@@ -165,6 +170,7 @@ __global__ void __launch_bounds__(ANT) k_cy_restrict(int n, int nblk, const int*
 // CO_NT threads, CO_P per output (strided over the inverse's rows, then
 // summed over those lanes in a fixed order)
 constexpr int CO_P = 8, CO_NT = AMAXC * CO_P;
+template <int FILL>
 __global__ void __launch_bounds__(CO_NT) k_cy_coarsest(int n, const double* __restrict__ ainv,
                                                        const uint8_t* __restrict__ pin, const double* __restrict__ b,
                                                        double* __restrict__ y, const int* done) {
@@ -183,6 +189,7 @@ __global__ void __launch_bounds__(CO_NT) k_cy_coarsest(int n, const double* __re
 
 // block partials of (b, y) on a level whose cycle is the exact solve alone
 // (a hierarchy of one level); heavy blocks write zero partials
+template <int FILL>
 __global__ void __launch_bounds__(ANT) k_cy_dot(ALev L, double* __restrict__ parts, int pstride, const int* done) {
   if (is_done(done)) return;
   __shared__ double red[ANT / 64];
@@ -198,6 +205,7 @@ __global__ void __launch_bounds__(ANT) k_cy_dot(ALev L, double* __restrict__ par
 // over 4:1 aggregates undershoots smooth errors, and a constant factor
 // below 2 keeps the cycle symmetric positive definite.  On the finest level
 // the block partials of (b, y) are written to parts.
+template <int FILL>
 __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict__ yn, double* __restrict__ parts,
                                                int pstride, double corr, const int* done) {
   if (is_done(done)) return;
@@ -239,13 +247,16 @@ __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict_
 }
 
 // -------------------------------------------------------------------- PCG
-// x = 0, r = b, p = q = 0; partials of (r, r) and |b_abs|^2
-__global__ void __launch_bounds__(ANT) k_cg_init(int n, const double* __restrict__ rhs, const double* __restrict__ babs,
+// x = 0, r = b, p = q = 0; partials of (r, r), |scale|^2 and |floor|^2
+__global__ void __launch_bounds__(ANT) k_cg_init(int n, const double* __restrict__ rhs, const double* __restrict__ scale,
+                                                 const double* __restrict__ floorv, double floor_ratio,
                                                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
-                                                 double* __restrict__ q, double* __restrict__ parts, int pstride) {
-  __shared__ double red[2 * (ANT / 64)];
+                                                 double* __restrict__ q, double* __restrict__ sc,
+                                                 double* __restrict__ parts, int pstride) {
+  __shared__ double red[3 * (ANT / 64)];
   const int c = blockIdx.x * ANT + threadIdx.x;
-  double v[2] = {0.0, 0.0};
+  if (c == 0) sc[S_FL] = floor_ratio;
+  double v[3] = {0.0, 0.0, 0.0};
   if (c < n) {
     const double b = rhs[c];
     x[c] = 0.0;
@@ -253,12 +264,14 @@ __global__ void __launch_bounds__(ANT) k_cg_init(int n, const double* __restrict
     p[c] = 0.0;
     q[c] = 0.0;
     v[0] = b * b;
-    v[1] = babs[c] * babs[c];
+    v[1] = scale[c] * scale[c];
+    v[2] = floorv ? floorv[c] * floorv[c] : 0.0;
   }
-  put_parts<2>(v, red, parts, pstride);
+  put_parts<3>(v, red, parts, pstride);
 }
 
 // p = z + beta p, q = A z + beta q (= A p), block partials of (p, q)
+template <int FILL>
 __global__ void __launch_bounds__(ANT) k_cg_pq(ALev L, double* __restrict__ p, double* __restrict__ q,
                                                const double* __restrict__ sc, double* __restrict__ parts,
                                                int pstride, const int* done) {
@@ -320,6 +333,7 @@ __device__ __forceinline__ double sum_parts(const double* parts, int n, double* 
 // before the first update); convergence test, beta.  mode 2 (after (p, q)):
 // alpha.
 constexpr int SC_NT = 1024;  // threads of the one-block scalar kernel (a short chain of loads each)
+template <int FILL>
 __global__ void __launch_bounds__(SC_NT) k_cg_scal(int mode, const double* __restrict__ parts, int np, int pstride,
                                                    int nrr, double* __restrict__ sc, int* __restrict__ done,
                                                    int* it_ctr, double rtol, int maxit, int* __restrict__ iters_out,
@@ -330,9 +344,13 @@ __global__ void __launch_bounds__(SC_NT) k_cg_scal(int mode, const double* __res
     const double rr = sum_parts(parts, nrr, red);
     __syncthreads();
     const double bs = sum_parts(parts + pstride, nrr, red);
+    __syncthreads();
+    const double fs = sum_parts(parts + 2 * (size_t)pstride, nrr, red);
     if (threadIdx.x == 0) {
       sc[S_RR] = rr;
-      sc[S_BS] = bs;
+      // stop at ||r|| <= max(rtol |scale|, floor_rel |floor|): the floor
+      // enters as an equivalent scale (floor_rel / rtol, set by k_cg_init)
+      sc[S_BS] = fmax(bs, fs * sc[S_FL] * sc[S_FL]);
       sc[S_RHOP] = 1.0;
       *done = 0;
       *it_ctr = 0;
@@ -1430,27 +1448,28 @@ static ALev view(const AmgLevel* L, double* b) {
 
 // one V-cycle on V[0].b -> V[0].y; the finest level writes the block
 // partials of (b, y) to parts
+template <int FILL>
 static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts, int pstride, const int* done,
                          hipStream_t q_) {
   for (int l = 0; l + 1 < A->nlev; ++l) {
     const ALev& L = V[l];
-    k_cy_down<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
+    k_cy_down<FILL><<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
     const AmgLevel* C = A->lv[l + 1];
-    k_cy_restrict<<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy, L.r,
+    k_cy_restrict<FILL><<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem, C->mheavy, L.r,
                                                             V[l + 1].b, done);
   }
   const ALev& Lc = V[A->nlev - 1];
   if (A->dense) {
-    k_cy_coarsest<<<1, CO_NT, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
+    k_cy_coarsest<FILL><<<1, CO_NT, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
                                        static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
-    if (A->nlev == 1) k_cy_dot<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, parts, pstride, done);
+    if (A->nlev == 1) k_cy_dot<FILL><<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, parts, pstride, done);
   } else {  // no exact coarsest: smoothing only
-    k_cy_up<<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, A->corr,
+    k_cy_up<FILL><<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, A->corr,
                                                  done);
   }
   for (int l = A->nlev - 2; l >= 0; --l) {
     const ALev& L = V[l];
-    k_cy_up<<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, A->corr, done);
+    k_cy_up<FILL><<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, A->corr, done);
   }
 }
 
@@ -1458,8 +1477,8 @@ static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts
 // in the Jacobi solver; the solution goes to s.  Iterations -> *iters_out
 // (device).  The host polls the "still iterating" flag every `batch`
 // iterations.
-hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, double rtol, int maxit,
-                     int* iters_out, int* host_flag, bool graph, hipStream_t st) {
+hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const double* floorv, double floor_rel,
+                     double* s, double rtol, int maxit, int* iters_out, int* host_flag, bool graph, hipStream_t st) {
   hipError_t err = hipSuccess;
   AmgLevel* L0 = A->lv[0];
   const int n = L0->n;
@@ -1475,18 +1494,19 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   int* done = ctr;
   int* itc = ctr + 1;
   int* flag = ctr + 2;
-  k_cg_init<<<nblk, ANT, 0, st>>>(n, rhs, babs, s, r, p, q, parts, pstride);
-  k_cg_scal<<<1, SC_NT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+  const double ratio = (floorv && rtol > 0) ? floor_rel / rtol : 0.0;
+  k_cg_init<<<nblk, ANT, 0, st>>>(n, rhs, scale, floorv, ratio, s, r, p, q, sc, parts, pstride);
+  k_cg_scal<0><<<1, SC_NT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
   // one PCG iteration: V-cycle on r -> z (= y of level 0), then the CG
   // update; every kernel returns at once after convergence
   auto iteration = [&](hipStream_t q_) {
-    launch_cycle(A, V, parts, pstride, done, q_);
+    launch_cycle<0>(A, V, parts, pstride, done, q_);
     // rho = (r, z) -> beta; convergence on ||r||
-    k_cg_scal<<<1, SC_NT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
-    k_cg_pq<<<V[0].nblk + V[0].nheavy, ANT, 0, q_>>>(V[0], p, q, sc, parts, pstride, done);
-    k_cg_scal<<<1, SC_NT, 0, q_>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+    k_cg_scal<0><<<1, SC_NT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
+    k_cg_pq<0><<<V[0].nblk + V[0].nheavy, ANT, 0, q_>>>(V[0], p, q, sc, parts, pstride, done);
+    k_cg_scal<0><<<1, SC_NT, 0, q_>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
     k_cg_xr<<<nblk, ANT, 0, q_>>>(n, s, r, p, q, sc, parts + pstride, done);
   };
   // optionally the iteration's ~3 launches per level are captured once per
@@ -1518,7 +1538,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* babs, double* s, d
   constexpr int FUSE_MAX = 1024;
   const bool fuse = pstride <= FUSE_MAX;
   auto fused = [&](int it) {
-    launch_cycle(A, V, parts, pstride, done, st);
+    launch_cycle<0>(A, V, parts, pstride, done, st);
     k_cg_pq_f<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, pstride, nblk, it, rtol,
                                                       maxit, done, flag, iters_out);
     k_cg_xr_f<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts, pstride, pstride, it, done);
@@ -1572,11 +1592,11 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
   const int batch = 8;
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
-      launch_cycle(A, V, parts, pstride, done, st);
+      launch_cycle<1>(A, V, parts, pstride, done, st);
       k_fs_scal1<<<1, ANT, 0, st>>>(parts, pstride, list, nl, rrc, rr, bb, iters, stats, sc, done, itc, rtol, maxit,
                                     flag);
-      k_cg_pq<<<nblk, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
-      k_cg_scal<<<1, SC_NT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
+      k_cg_pq<1><<<nblk, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
+      k_cg_scal<1><<<1, SC_NT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
       k_fs_xr<<<nb256((n + FS_R - 1) / FS_R), ANT, 0, st>>>(n, comp, x, r, p, q, sc, rrc, done);
     }
     AMG_TRY(hipGetLastError());

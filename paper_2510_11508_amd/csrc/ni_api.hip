@@ -60,7 +60,7 @@ hipError_t quot_heavy_rows(const int*, int, int*, int*, int*, int*, int*, hipStr
 hipError_t irls_iteration(const IrlsArgs&, int, hipStream_t);
 // ni_final.hip
 hipError_t final_outputs(const int*, const float*, const double*, const int*, const uint32_t*, const int*,
-                         const int*, int, int, int, int, double*, int*, double*, double*, float*, double*,
+                         const int*, int, int, int, int, int, double*, int*, double*, double*, float*, double*,
                          hipStream_t);
 // ni_unet.hip
 hipError_t unet_predict(struct UnetModel*, const float*, const uint8_t*, int, int, const ni_camera*, float*,
@@ -135,7 +135,7 @@ struct ni_ctx {
   Buf key, val, skey, spix, ktmp, vtmp, kout2, cst, rhs, dinv, x, r, z, p0, p1, q, w0, w1, s0, s1;
   // components
   Buf comp_off, fsmall, flarge, nchunk, spos, lpos, cbase, small_list, large_list, cnt, done, iters, active,
-      rho, bb, tol2, beta, rr, relres, S, qs, diag, qrhs, psum, pcnt, qparent, csum, comp_rid;
+      rho, bb, tol2, beta, rr, relres, S, qs, diag, qrhs, babs, psum, pcnt, qparent, csum, comp_rid;
   // chunks
   Buf chunk_comp, chunk_start, part;
   // edges / pairs
@@ -162,7 +162,7 @@ struct ni_ctx {
                   &skey, &spix, &ktmp, &vtmp, &kout2, &cst, &rhs, &dinv, &x, &r, &z, &p0,
                   &p1, &q, &w0, &w1, &s0, &s1, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
                   &cnt, &done, &iters, &active, &rho, &bb, &tol2, &beta, &rr, &relres, &S, &qs,
-                  &diag, &qrhs, &psum, &pcnt, &qparent, &csum, &comp_rid,
+                  &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &rsum,
                   &rcnt, &qcol, &qw, &qt0, &qt1, &eom, &eta, &etb, &mg_deg, &mg_pc, &mg_row,
@@ -681,12 +681,11 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
         itmax = std::max(itmax, it[k]);
         rmax = std::max(rmax, rel[k]);
       }
-      if (mg) {
-        long long nsys = 0;
-        for (int k = 0; k < K; ++k)
-          if (off[k + 1] - off[k] > cap) nsys += off[k + 1] - off[k];
-        mg_bytes = nil::amg_fill_bytes(c->amg_fill, nsys);
-      }
+      long long nsys = 0;
+      for (int k = 0; k < K; ++k)
+        if (off[k + 1] - off[k] > cap) nsys += off[k + 1] - off[k];
+      if (mg) mg_bytes = nil::amg_fill_bytes(c->amg_fill, nsys);
+      rep->fill_large_px = nsys;
       rep->fill_px_iters = pxit;
       rep->fill_large_px_iters = lpxit;
       rep->fill_iters_max = itmax;
@@ -715,8 +714,18 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   }
 }
 
+// One step only (test hook): with step_S non-null the scales start from
+// step_S, iteration step_t alone runs, and its increment s^(t) and energy go
+// to step_s / *step_e instead of the outputs.
+struct StepHook {
+  const double* S = nullptr;
+  int t = 0;
+  double* s = nullptr;
+  double* e = nullptr;
+};
+
 void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& sg, const float* zfill,
-                float* depth, double* log_scale, ni_report* rep) {
+                float* depth, double* log_scale, ni_report* rep, const StepHook& hook = StepHook()) {
   const int P = pb.P, W = pb.W, K = sg.K;
   const bool persp = pb.cam.proj == NI_PERSP;
   int* cntd = misc(c) + M_COUNT;
@@ -797,6 +806,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.pB = ensure<double>(c, c->pB, std::max(Pp, 1));
   a.diag = ensure<double>(c, c->diag, K1);
   a.rhs = ensure<double>(c, c->qrhs, K1);
+  a.babs = ensure<double>(c, c->babs, K1);
   a.s = ensure<double>(c, c->qs, K1);
   a.psum = ensure<double>(c, c->psum, K1);
   a.pcnt = ensure<int>(c, c->pcnt, K1);
@@ -818,6 +828,29 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.t1 = ensure<double>(c, c->qt1, K1);
   a.host_flag = c->host + 32;
   check(c, hipMemsetAsync(a.S, 0, K1 * sizeof(double), c->stream), "memset");
+  if (hook.S) {
+    if (K > 0)
+      check(c, hipMemcpyAsync(a.S, hook.S, K * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "copy S");
+    check(c, nil::irls_iteration(a, hook.t, c->stream), "irls");
+    if (K > 0) check(c, hipMemcpyAsync(hook.s, a.s, K * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "copy s");
+    check(c, hipMemcpyAsync(hook.e, a.energy_out + hook.t, sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
+    int qa = 0, qb = 0;
+    check(c, hipMemcpyAsync(&qa, a.qiters_out + hook.t, sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+    check(c, hipMemcpyAsync(&qb, a.qiters2_out + hook.t, sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+    check(c, hipStreamSynchronize(c->stream), "sync");
+    if (rep) {
+      rep->irls_iters_run = 1;
+      rep->energy[0] = *hook.e;
+      rep->quot_iters[0] = qa + qb;
+      rep->n_inter_edges = E;
+      rep->n_pairs = Pp;
+    }
+    if (qa >= pb.prm.q_max_iter || qb >= pb.prm.q_max_iter) {
+      c->err = "relative-scale solve stopped at q_max_iter";
+      throw Fail{NI_E_NOTCONV};
+    }
+    return;
+  }
   const int T = pb.prm.irls_iters;
   int ran = 0;
   std::vector<double> en(NI_MAX_IRLS, 0.0);
@@ -854,7 +887,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   double* rsum = ensure<double>(c, c->rsum, std::max(R, 1));
   double* rcnt = ensure<double>(c, c->rcnt, std::max(R, 1));
   check(c, nil::final_outputs(labels, zfill, a.S, ptr<int>(c->comp_off), ptr<uint32_t>(c->spix), ptr<int>(c->parent),
-                              ptr<int>(c->scanv), K, R, P, persp ? 1 : 0, csum, comp_rid, rsum, rcnt, depth,
+                              ptr<int>(c->scanv), K, sg.N, R, P, persp ? 1 : 0, csum, comp_rid, rsum, rcnt, depth,
                               log_scale, c->stream),
         "finalize");
   mark(c, 10);
@@ -1150,6 +1183,47 @@ ni_status ni_fill(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t 
     }
     stage_fill(c, pb, labels, sg, zfill, rep);
     check(c, hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+ni_status ni_irls_step(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t H, int32_t W,
+                       const ni_camera* cam, const ni_params* params, const int32_t* labels, int32_t K,
+                       const float* zfill, const double* S_in, int32_t t, double* s_out, double* energy,
+                       ni_report* rep) {
+  Problem pb;
+  ni_status s = validate(c, normals, mask, H, W, cam, params, &pb);
+  if (s != NI_OK) return s;
+  if (!labels || !zfill || !energy || K < 0 || (int64_t)K > (int64_t)H * W || (K > 0 && (!S_in || !s_out))) {
+    c->err = "null pointer or K out of range";
+    return NI_E_ARG;
+  }
+  if (t < 0 || t >= NI_MAX_IRLS) {
+    c->err = "step index out of range";
+    return NI_E_ARG;
+  }
+  return guarded(c, [&] {
+    begin(c, rep);
+    stage_setup(c, pb);
+    readback(c, misc(c), 16 * sizeof(int), c->host);
+    if (c->host[M_ERR]) {
+      c->err = "non-finite normal inside the mask";
+      throw Fail{NI_E_NONFINITE};
+    }
+    Seg sg = build_segments(c, pb, labels, K, true);
+    if (rep) {
+      rep->K = K;
+      rep->n_valid = sg.N;
+    }
+    if (K == 0) {
+      *energy = 0.0;
+      return;
+    }
+    StepHook hook;
+    hook.S = S_in;
+    hook.t = t;
+    hook.s = s_out;
+    hook.e = energy;
+    stage_irls(c, pb, labels, sg, zfill, nullptr, nullptr, rep, hook);
   });
 }
 

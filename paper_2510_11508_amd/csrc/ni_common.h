@@ -97,6 +97,36 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   }
 }
 
+// Block-level form: when every valid thread of the block has thread 0's
+// key (thread 0 valid), the block sums first and issues one pair of
+// atomics (a quotient piece or pixel region usually spans whole blocks;
+// per-wavefront atomics on one address serialise).  Otherwise as
+// acc_by_key.  Every thread of the block must call it; red must hold
+// 2 * (blockDim/64) doubles.
+template <class TB>
+__device__ __forceinline__ void acc_by_key_block(bool valid, int key, double a, TB b, double* da, TB* db,
+                                                 double* red) {
+  __shared__ int bkey, bvalid;
+  if (threadIdx.x == 0) {
+    bkey = key;
+    bvalid = valid ? 1 : 0;
+  }
+  __syncthreads();
+  const int k0 = bkey;
+  const bool uniform = bvalid && __syncthreads_and(!valid || key == k0);
+  if (uniform) {
+    double v[2] = {valid ? a : 0.0, valid ? (double)b : 0.0};
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+      atomicAdd(&da[k0], v[0]);
+      atomicAdd(&db[k0], (TB)v[1]);
+    }
+  } else {
+    acc_by_key<TB>(valid, key, a, b, da, db);
+  }
+}
+
+
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace ni
@@ -160,8 +190,10 @@ hipError_t amg_fill_solve(Amg*, const int* comp, const int* list, int nl, int K,
                           double rtol, int maxit, int warm, double* rr, double* bb, int* iters, int* stats,
                           int* host_flag, int* its, hipStream_t st);
 hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
-hipError_t amg_solve(Amg*, const double* rhs, const double* babs, double* s, double rtol, int maxit, int* iters_out,
-                     int* host_flag, bool graph, hipStream_t st);
+// PCG preconditioned by one V-cycle: s from zero until ||r|| <= max(rtol
+// ||scale||, floor_rel ||floorv||) (floorv may be null)
+hipError_t amg_solve(Amg*, const double* rhs, const double* scale, const double* floorv, double floor_rel, double* s,
+                     double rtol, int maxit, int* iters_out, int* host_flag, bool graph, hipStream_t st);
 
 // arguments of one relative-scale iteration (ni_quot.hip)
 struct IrlsArgs {
@@ -173,7 +205,7 @@ struct IrlsArgs {
   const float* zfill;
   const int *pair_start, *pair_lo, *pair_hi, *row_off;
   const uint32_t* ent;
-  double *S, *ew, *erho, *pW, *pB, *diag, *rhs;
+  double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
   double *s, *psum;
   int *pcnt, *parent;
   unsigned long long* wmax;

@@ -6,15 +6,18 @@
 
 namespace {
 
-// one block per component: FP64 sum of its filled log-depth (fixed order)
-__global__ void __launch_bounds__(256) k_comp_sums(const int* __restrict__ comp_off, const uint32_t* __restrict__ cpix,
-                                                   const float* __restrict__ zfill, double* __restrict__ csum) {
-  __shared__ double red[4];
-  const int c = blockIdx.x;
-  double v[1] = {0.0};
-  for (int i = comp_off[c] + threadIdx.x; i < comp_off[c + 1]; i += blockDim.x) v[0] += zfill[cpix[i]];
-  ni::block_sum<1>(v, red);
-  if (threadIdx.x == 0) csum[c] = v[0];
+// FP64 sum of each component's filled log-depth over the component-major
+// pixel order: a block whose pixels all belong to one component (the
+// common case inside large components) adds one partial; others add per
+// wavefront
+__global__ void __launch_bounds__(1024) k_comp_sums(const int* __restrict__ label, const uint32_t* __restrict__ cpix,
+                                                    int N, const float* __restrict__ zfill, double* __restrict__ csum,
+                                                    int* __restrict__ ccnt) {
+  __shared__ double red[2 * (1024 / 64)];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool v = i < N;
+  const uint32_t p = v ? cpix[i] : 0u;
+  ni::acc_by_key_block<int>(v, v ? label[p] : 0, v ? (double)zfill[p] : 0.0, 1, csum, ccnt, red);
 }
 
 __global__ void k_comp_region(const int* __restrict__ comp_off, const uint32_t* __restrict__ cpix,
@@ -22,6 +25,14 @@ __global__ void k_comp_region(const int* __restrict__ comp_off, const uint32_t* 
                               int* __restrict__ comp_rid) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < K) comp_rid[c] = cid[parent[cpix[comp_off[c]]]];
+}
+
+__global__ void k_zero_sums(double* csum, int* cnt, int K) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) {
+    csum[i] = 0.0;
+    cnt[i] = 0;
+  }
 }
 
 __global__ void k_region_zero(double* rsum, double* rcnt, int R) {
@@ -69,11 +80,13 @@ __global__ void k_final_scale(const double* __restrict__ S, const int* __restric
 namespace nil {
 
 hipError_t final_outputs(const int* label, const float* zfill, const double* S, const int* comp_off,
-                         const uint32_t* cpix, const int* parent, const int* cid, int K, int R, int P, int persp,
+                         const uint32_t* cpix, const int* parent, const int* cid, int K, int N, int R, int P, int persp,
                          double* csum, int* comp_rid, double* rsum, double* rcnt, float* depth, double* log_scale,
                          hipStream_t st) {
   if (K > 0) {
-    k_comp_sums<<<K, 256, 0, st>>>(comp_off, cpix, zfill, csum);
+    // csum and its count scratch (comp_rid, overwritten below) start at zero
+    k_zero_sums<<<ni::ceil_div(K, 256), 256, 0, st>>>(csum, comp_rid, K);
+    k_comp_sums<<<ni::ceil_div(N, 1024), 1024, 0, st>>>(label, cpix, N, zfill, csum, comp_rid);
     k_comp_region<<<ni::ceil_div(K, 256), 256, 0, st>>>(comp_off, cpix, parent, cid, K, comp_rid);
   }
   if (R > 0) k_region_zero<<<ni::ceil_div(R, 256), 256, 0, st>>>(rsum, rcnt, R);

@@ -229,40 +229,45 @@ __global__ void k_irls_pairs(const int* __restrict__ pair_start, int P, double* 
 
 __global__ void k_irls_nodes(const int* __restrict__ row_off, const uint32_t* __restrict__ ent, int K,
                              const double* __restrict__ pW, const double* __restrict__ pB,
-                             double* __restrict__ diag, double* __restrict__ rhs) {
+                             double* __restrict__ diag, double* __restrict__ rhs, double* __restrict__ babs) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= K || row_off[c + 1] - row_off[c] > QELL) return;  // long rows: k_irls_nodes_heavy
-  double dg = 0.0, b = 0.0;
+  double dg = 0.0, b = 0.0, ba = 0.0;
   for (int j = row_off[c]; j < row_off[c + 1]; ++j) {
     uint32_t e = ent[j];
     int pid = (int)(e >> 1);
     dg += pW[pid];
     b += (e & 1u) ? pB[pid] : -pB[pid];  // row = hi: +B, row = lo: -B
+    ba += fabs(pB[pid]);
   }
   diag[c] = dg;
   rhs[c] = b;
+  babs[c] = ba;
 }
 
 // the same for the rows with more than QELL entries, one wavefront each
 __global__ void k_irls_nodes_heavy(const int* __restrict__ row_off, const uint32_t* __restrict__ ent,
                                    const int* __restrict__ heavy, int nheavy, const double* __restrict__ pW,
                                    const double* __restrict__ pB, double* __restrict__ diag,
-                                   double* __restrict__ rhs) {
+                                   double* __restrict__ rhs, double* __restrict__ babs) {
   const int h = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (h >= nheavy) return;
   const int c = heavy[h];
-  double dg = 0.0, b = 0.0;
+  double dg = 0.0, b = 0.0, ba = 0.0;
   for (int j = row_off[c] + lane; j < row_off[c + 1]; j += 64) {
     uint32_t e = ent[j];
     int pid = (int)(e >> 1);
     dg += pW[pid];
     b += (e & 1u) ? pB[pid] : -pB[pid];
+    ba += fabs(pB[pid]);
   }
   dg = ni::wave_sum(dg);
   b = ni::wave_sum(b);
+  ba = ni::wave_sum(ba);
   if (lane == 0) {
     diag[c] = dg;
     rhs[c] = b;
+    babs[c] = ba;
   }
 }
 
@@ -356,11 +361,12 @@ __global__ void k_add_f64(double* __restrict__ a, const double* __restrict__ b, 
 }
 
 // piece gauge: zero mean of s over every connected piece (root = parent)
-__global__ void k_piece_acc(const int* __restrict__ parent, const double* __restrict__ s, int K,
-                            double* __restrict__ psum, int* __restrict__ pcnt) {
+__global__ void __launch_bounds__(1024) k_piece_acc(const int* __restrict__ parent, const double* __restrict__ s,
+                                                   int K, double* __restrict__ psum, int* __restrict__ pcnt) {
+  __shared__ double red[2 * (1024 / 64)];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const bool v = c < K;
-  ni::acc_by_key<int>(v, v ? parent[c] : 0, v ? s[c] : 0.0, 1, psum, pcnt);
+  ni::acc_by_key_block<int>(v, v ? parent[c] : 0, v ? s[c] : 0.0, 1, psum, pcnt, red);
 }
 
 // v -= its mean over the piece (a right-hand side made consistent with the
@@ -532,10 +538,10 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
     k_irls_pairs<<<ni::ceil_div(a.P, 256), 256, 0, st>>>(a.pair_start, a.P, a.ew, a.erho, a.wmax, a.cut_rel, a.pW,
                                                         a.pB);
   }
-  k_irls_nodes<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.row_off, a.ent, a.K, a.pW, a.pB, a.diag, a.rhs);
+  k_irls_nodes<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.row_off, a.ent, a.K, a.pW, a.pB, a.diag, a.rhs, a.babs);
   if (a.nheavy > 0)
     k_irls_nodes_heavy<<<ni::ceil_div(a.nheavy, 4), 256, 0, st>>>(a.row_off, a.ent, a.heavy, a.nheavy, a.pW, a.pB,
-                                                                   a.diag, a.rhs);
+                                                                   a.diag, a.rhs, a.babs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // pieces of the weighted quotient graph
@@ -547,7 +553,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   auto center = [&](double* v) {
     k_fill_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.psum, a.K, 0.0);
     k_fill_i32<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pcnt, a.K, 0);
-    k_piece_acc<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, v, a.K, a.psum, a.pcnt);
+    k_piece_acc<<<ni::ceil_div(a.K, 1024), 1024, 0, st>>>(a.parent, v, a.K, a.psum, a.pcnt);
     k_piece_center<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, v, a.K, a.psum, a.pcnt);
   };
   center(a.rhs);
@@ -562,15 +568,18 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (e == hipSuccess && !same_as_previous)
     e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
   if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
-  // round 1: s from zero to ||r|| <= q_rtol ||b||
+  // round 1: s from zero to ||r|| <= q_rtol ||b_abs|| (b_abs = row sums of
+  // |B_p|, a scale of the right-hand side that does not cancel)
   if (e == hipSuccess)
-    e = amg_solve(a.amg, a.rhs, a.rhs, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag, a.graphs != 0, st);
+    e = amg_solve(a.amg, a.rhs, a.babs, nullptr, 0.0, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag,
+                  a.graphs != 0, st);
   // round 2 (refinement): the residual of s in flow form, then the
-  // correction d from zero to ||r_d|| <= q_rtol ||b - L s||, s += d.  The
-  // recursive residual of round 1 carries rounding at the scale of the
-  // heaviest rows; the flow-form residual restores what the light links
-  // say, and the correction solve, whose right-hand side is small, resolves
-  // it.
+  // correction d from zero to ||r_d|| <= max(q_rtol ||b - L s||, 1e-13
+  // ||b_abs||), s += d.  The recursive residual of round 1 carries rounding
+  // at the scale of the heaviest rows; the flow-form residual restores what
+  // the light links say, and the correction solve, whose right-hand side
+  // is small, resolves it.  The floor is the rounding level of the
+  // right-hand side itself.
   if (e == hipSuccess) {
     k_flow_resid<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.row_off, a.ent, a.K, a.pW, a.pB, a.pair_lo, a.pair_hi,
                                                          a.s, a.t0);
@@ -581,7 +590,8 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   }
   if (e == hipSuccess) center(a.t0);
   if (e == hipSuccess)
-    e = amg_solve(a.amg, a.t0, a.t0, a.t1, a.q_rtol, a.q_maxit, a.qiters2_out + t, a.host_flag, a.graphs != 0, st);
+    e = amg_solve(a.amg, a.t0, a.t0, a.babs, 1e-13, a.t1, a.q_rtol, a.q_maxit, a.qiters2_out + t, a.host_flag,
+                  a.graphs != 0, st);
   if (e == hipSuccess) {
     k_add_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.s, a.t1, a.K);
     e = hipGetLastError();
@@ -590,7 +600,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   // piece gauge and accumulate S
   k_fill_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.psum, a.K, 0.0);
   k_fill_i32<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pcnt, a.K, 0);
-  k_piece_acc<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt);
+  k_piece_acc<<<ni::ceil_div(a.K, 1024), 1024, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt);
   k_piece_apply<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt, a.S);
   // energy
   if (a.P > 0) {
