@@ -292,3 +292,114 @@ def _irls_loop(lab, K, zfill, inter, info, edge_ok, params):
         energies.append(float(np.sum(wts * res * res)))
         S = S + s
     return S, energies
+
+
+def irls_merging(normals, mask, cam, lab, K, zfill, params):
+    """Alg. 1's loop with the optional merging of Sec. 3.5, written
+    independently of the oracle: the state is the current log-depth of
+    every pixel and the current (merged) label of every pixel; every step
+    rebuilds the inter-component rows from the current labels, solves them
+    per connected piece, and adds each component's increment to its pixels;
+    every freq_merging-th step each current component picks its boundary
+    edge of smallest |z_a - z_b - omega| counted in units of 2^-40 (equal
+    counts: smaller code 2 a + (0 right, 1 down), a the raster index of the
+    left / upper pixel), and
+    the components joined by picked edges are relabelled as one (pixel
+    labels rewritten through a plain union-find).  Returns the final
+    log-depth [H, W] (0 off the labels) and the energies."""
+    import scipy.sparse as sp
+    lab = np.asarray(lab)
+    H, W = lab.shape
+    valid = np.asarray(mask) != 0
+    cache = {}
+
+    def pm(a, b):
+        if (a, b) not in cache:
+            ok = valid[a[1], a[0]] and valid[b[1], b[0]]
+            cache[(a, b)] = pair_model(normals, cam, a, b) if ok else (False, 0.0, 0.0, 0.0)
+        return cache[(a, b)]
+
+    pairs = []
+    for v in range(H):
+        for u in range(W):
+            if lab[v, u] < 0:
+                continue
+            for (du, dv) in ((1, 0), (0, 1)):
+                b = (u + du, v + dv)
+                if b[0] < W and b[1] < H and lab[b[1], b[0]] >= 0 and pm((u, v), b)[0]:
+                    pairs.append(((u, v), b, 2 * (v * W + u) + (0 if du else 1)))
+    usable = set((a, b) for a, b, _ in pairs)
+
+    def edge_ok(p, q):
+        return (p, q) in usable or (q, p) in usable
+
+    z = np.where(lab >= 0, np.asarray(zfill, dtype=np.float64), 0.0)
+    cl = lab.copy()
+    k = params["bini_k"]
+    freq = int(params.get("freq_merging", 0))
+    T = int(params["irls_iters"])
+    energies = []
+    for t in range(T):
+        inter = [(a, b, code) for (a, b, code) in pairs if cl[a[1], a[0]] != cl[b[1], b[0]]]
+        Kc = int(cl.max()) + 1
+        n = len(inter)
+        if n:
+            cidx = np.array([cl[a[1], a[0]] for a, b, _ in inter])
+            didx = np.array([cl[b[1], b[0]] for a, b, _ in inter])
+            ridx = np.repeat(np.arange(2 * n), 2)
+            cols = np.empty(4 * n, dtype=np.int64)
+            vals = np.empty(4 * n)
+            cols[0::4], vals[0::4] = cidx, 1.0
+            cols[1::4], vals[1::4] = didx, -1.0
+            cols[2::4], vals[2::4] = didx, 1.0
+            cols[3::4], vals[3::4] = cidx, -1.0
+            A = sp.csr_matrix((vals, (ridx, cols)), shape=(2 * n, Kc))
+            wts = np.empty(2 * n)
+            rhs = np.empty(2 * n)
+            for i, (a, b, _) in enumerate(inter):
+                _, om, g2a, g2b = pm(a, b)
+                za, zb = z[a[1], a[0]], z[b[1], b[0]]
+                chi = za - zb - om
+                if t < params["align_iters"]:
+                    wba = wab = 1.0
+                else:
+                    d = (b[0] - a[0], b[1] - a[1])
+                    mb = (a[0] - d[0], a[1] - d[1])
+                    ma = (b[0] + d[0], b[1] + d[1])
+                    dm = (z[mb[1], mb[0]] - za) if (0 <= mb[0] < W and 0 <= mb[1] < H and edge_ok(mb, a)) else 0.0
+                    dm2 = (z[ma[1], ma[0]] - zb) if (0 <= ma[0] < W and 0 <= ma[1] < H and edge_ok(b, ma)) else 0.0
+                    wo = _wout(chi, params["out_L"], params["out_U"], params["outlier_mode"])
+                    wba = g2a * _sig(g2a * (dm * dm - (zb - za) ** 2), k) * wo
+                    wab = g2b * _sig(g2b * (dm2 * dm2 - (za - zb) ** 2), k) * wo
+                wts[2 * i], rhs[2 * i] = wba, om - (za - zb)
+                wts[2 * i + 1], rhs[2 * i + 1] = wab, -om - (zb - za)
+            keep = (wts[0::2] + wts[1::2]) > 0
+            N = A.T @ sp.diags(wts) @ A
+            s = _solve_pieces(N, A.T @ (wts * rhs), Kc, cidx, didx, keep)
+            energies.append(float(np.sum(wts * (A @ s - rhs) ** 2)))
+            z = np.where(cl >= 0, z + s[np.maximum(cl, 0)], 0.0)
+        else:
+            energies.append(0.0)
+        if freq > 0 and (t + 1) % freq == 0 and t + 1 < T and n:
+            pick = {}
+            for a, b, code in inter:
+                mag = math.floor(abs(z[a[1], a[0]] - z[b[1], b[0]] - pm(a, b)[1]) * 2.0 ** 40)
+                for c in (cl[a[1], a[0]], cl[b[1], b[0]]):
+                    if c not in pick or (mag, code) < pick[c][0]:
+                        pick[c] = ((mag, code), cl[a[1], a[0]], cl[b[1], b[0]])
+            parent = list(range(Kc))
+
+            def find(x):
+                while parent[x] != x:
+                    parent[x] = parent[parent[x]]
+                    x = parent[x]
+                return x
+
+            for _, c, d in pick.values():
+                rc, rd = find(c), find(d)
+                if rc != rd:
+                    parent[max(rc, rd)] = min(rc, rd)
+            roots = sorted(set(find(c) for c in range(Kc)))
+            newid = {r: i for i, r in enumerate(roots)}
+            cl = np.where(cl >= 0, np.vectorize(lambda c: newid[find(int(c))])(np.maximum(cl, 0)), -1)
+    return z, energies

@@ -48,6 +48,7 @@ DEFAULT_PARAMS = dict(
     outlier_mode=1,       # 0 off, 1 soft (Eq. 18), 2 hard (Suppl. ablation)
     delta_e_max=0.0,      # relative-energy stop; 0 runs exactly T iterations (A13)
     w_cut_rel=1e-12,      # quotient edges below this fraction of the max weight are cut (A16)
+    freq_merging=0,       # optional merging (Sec. 3.5) after every freq-th iteration; 0 off [5]
 )
 
 
@@ -427,17 +428,68 @@ def quotient_step(ie: InterEdges, K, w, r, w_cut_rel):
     return s, E, w
 
 
-def irls(e: Edges, lab, K, zfill, params=None, S0=None, t0=0, trace=None):
-    """Relative-scale optimisation (Sec. 3.4; Alg. 1's loop without merging).
+def merge_groups(ie: InterEdges, r, grp):
+    """Optional merging (Sec. 3.5, steps (i)-(iii); Alg. 1's merge block).
 
-    z^(t) = zfill + S_pi; each iteration solves for s^(t) with the weights of
-    iteration t, then S += s (Eq. 12).  Stops after T iterations, or earlier
-    when delta_e_max > 0 and |E_t - E_{t-1}| / E_{t-1} < delta_e_max with
-    both t-1, t past the alignment phase (A13).
+    grp maps every original component to its current group (a node of the
+    quotient graph Q_m).  (i) Every group selects, among the inter edges
+    incident to it (edges whose ends lie in different groups), the one
+    with the smallest residual magnitude |chi| = |r_e| at the current
+    log-depth.  Magnitudes are compared on a grid of 2^-40 (~9.1e-13 in
+    log-depth units), and equal grid values go to the smaller edge code
+    2 a + (0 right, 1 down) (reading A27): after the uniform-weight
+    alignment every bridge of the quotient graph has a residual that is
+    zero in exact arithmetic, so FP64 rounding alone would otherwise decide
+    between them.  (ii) The selected edges form a subgraph of Q_m
+    over all its nodes; (iii) its connected components are the new groups,
+    numbered by the smallest original component they contain.  Returns
+    the new map of original components to groups."""
+    gc, gd = grp[ie.c], grp[ie.d]
+    live = gc != gd
+    Kg = int(grp.max()) + 1 if grp.size else 0
+    code = 2 * ie.a + np.where(ie.horiz, 0, 1)
+    best = np.full(Kg, -1, dtype=np.int64)
+    idx = np.flatnonzero(live)
+    # smallest |r| on the 2^-40 grid, then smallest code, per group end
+    mag = np.floor(np.abs(r[idx]) * 2.0 ** 40)
+    order = idx[np.lexsort((code[idx], mag))]
+    for e in order:                      # first hit per group wins
+        for g in (gc[e], gd[e]):
+            if best[g] < 0:
+                best[g] = e
+    sel = best[best >= 0]
+    G = sp.coo_matrix((np.ones(sel.size), (gc[sel], gd[sel])), shape=(Kg, Kg))
+    _, comp = connected_components(G, directed=False)
+    # canonical numbering: by the smallest original component in the group
+    first = np.full(Kg, np.iinfo(np.int64).max, dtype=np.int64)
+    np.minimum.at(first, comp[grp], np.arange(grp.size))
+    used = np.flatnonzero(first < np.iinfo(np.int64).max)
+    rank = np.empty(comp.max() + 1 if comp.size else 0, dtype=np.int64)
+    rank[used[np.argsort(first[used], kind="stable")]] = np.arange(used.size)
+    return rank[comp[grp]]
+
+
+def irls(e: Edges, lab, K, zfill, params=None, S0=None, t0=0, trace=None):
+    """Relative-scale optimisation (Sec. 3.4; Alg. 1's loop).
+
+    z^(t) = zfill + S_pi; each iteration solves for one increment per node
+    of the current quotient graph with the weights of iteration t, then
+    adds it to every component of the node (Eq. 12).  Stops after T
+    iterations, or earlier when delta_e_max > 0 and |E_t - E_{t-1}| /
+    E_{t-1} < delta_e_max with both t-1, t past the alignment phase (A13).
+
+    With freq_merging = f > 0, after every iteration t with (t + 1) % f == 0
+    the nodes are merged (merge_groups, Sec. 3.5) on the residuals at the
+    updated log-depth; the merged node's components keep their scales (the
+    log-depth does not change at a merge) and move together from then on,
+    and edges inside a merged node leave the optimisation.  S stays one
+    value per original component.
 
     S0 / t0 resume the loop at iteration t0 from the scales S0 (a test hook:
-    one step at a time); trace, when a list, receives (t, S before step t,
-    s^(t), E_t) for every iteration run."""
+    one step at a time, without merging); trace, when a list, receives (t,
+    S before step t, s^(t) per original component, E_t) for every
+    iteration run.  irls.last_groups holds the final node of every
+    component."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
@@ -447,22 +499,34 @@ def irls(e: Edges, lab, K, zfill, params=None, S0=None, t0=0, trace=None):
     valid = labf >= 0
     energies = []
     margin = np.inf
+    grp = np.arange(K, dtype=np.int64)
+    freq = int(p.get("freq_merging", 0))
     for t in range(int(t0), int(p["irls_iters"])):
         z = np.where(valid, zfill.ravel() + S[np.where(valid, labf, 0)], 0.0)
         w, r = edge_weights(e, ie, z, t, p)
+        live = grp[ie.c] != grp[ie.d]
+        w = np.where(live, w, 0.0)
         if w.size and p["w_cut_rel"] > 0 and w.max() > 0:
             pos = w[w > 0]
             margin = min(margin, float(np.min(np.abs(np.log10(pos / (p["w_cut_rel"] * w.max()))))))
-        s, E, _ = quotient_step(ie, K, w, r, p["w_cut_rel"])
+        Kg = int(grp.max()) + 1 if K else 0
+        ieg = InterEdges(ie.a, ie.b, ie.horiz, ie.omega, grp[ie.c], grp[ie.d])
+        sg, E, _ = quotient_step(ieg, Kg, w, r, p["w_cut_rel"])
+        s = sg[grp] if K else sg
         if trace is not None:
             trace.append((t, S.copy(), s.copy(), E))
         S += s
         energies.append(E)
+        if freq > 0 and (t + 1) % freq == 0 and t + 1 < int(p["irls_iters"]):
+            z = np.where(valid, zfill.ravel() + S[np.where(valid, labf, 0)], 0.0)
+            r_now = z[ie.a] - z[ie.b] - ie.omega
+            grp = merge_groups(ie, r_now, grp)
         if p["delta_e_max"] > 0 and t >= p["align_iters"] + 1 and len(energies) >= 2:
             Ep = energies[-2]
             if Ep == 0.0 or abs(E - Ep) / Ep < p["delta_e_max"]:
                 break
     irls.last_cut_margin = margin
+    irls.last_groups = grp
     return S, energies, ie
 
 

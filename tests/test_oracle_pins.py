@@ -354,3 +354,81 @@ def test_generator_deterministic():
     assert np.array_equal(a.normals, b.normals) and np.array_equal(a.mask, b.mask)
     c = synth.make("c1", 4)
     assert not np.array_equal(a.normals, c.normals)
+
+
+# --------------------------------------------------------------- merging ----
+def _region_gauge(z, v):
+    from scipy import ndimage
+    reg, R = ndimage.label(v)
+    z = z.copy()
+    for r in range(1, R + 1):
+        z[reg == r] -= z[reg == r].mean()
+    return z
+
+
+@pytest.mark.parametrize("which,seed,freq,T", [("tiny", 1, 3, 10), ("tiny", 2, 2, 6), ("tiny", 4, 5, 8),
+                                               ("c1", 0, 5, 8), ("c1", 1, 3, 10), ("c1", 2, 4, 9)])
+def test_merging_equals_bruteforce(which, seed, freq, T):
+    """Optional merging (Sec. 3.5 (i)-(iii), Alg. 1): the oracle's grouped
+    form (one scale per original component, nodes regrouped) equals a
+    brute force that rewrites pixel labels and carries the log-depth itself
+    through every merge."""
+    s = synth.tiny(seed, 12, 14, "persp") if which == "tiny" else synth.make(which, seed)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=T, freq_merging=freq)
+    e = O.edges(s.normals, s.mask, s.cam, p["theta_c_deg"])
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    S, En, _ = O.irls(e, lab, K, zf, p)
+    v = lab >= 0
+    zo = np.where(v, zf + S[np.maximum(lab, 0)], 0.0)
+    zb, Eb = BF.irls_merging(s.normals, s.mask, s.cam.as_dict(), lab, K, zf, p)
+    assert np.max(np.abs(_region_gauge(zo, v) - _region_gauge(zb, v))[v]) < 1e-9
+    assert np.allclose(En, Eb, rtol=1e-8, atol=1e-14)
+
+
+def test_merge_selection_and_halving():
+    """One merge on c1 after two reweighted steps: every group's selected
+    edge has the smallest |residual| among its live edges (on the 2^-40
+    grid, ties to the smaller code), and every new group holds at least two
+    old ones unless
+    the old one had no live edge, so the node count at least halves."""
+    s = synth.make("c1", 3)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=4)
+    e = O.edges(s.normals, s.mask, s.cam, p["theta_c_deg"])
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    S, _, ie = O.irls(e, lab, K, zf, p)
+    z = np.where(lab >= 0, zf + S[np.maximum(lab, 0)], 0.0).ravel()
+    r = z[ie.a] - z[ie.b] - ie.omega
+    grp0 = np.arange(K)
+    new = O.merge_groups(ie, r, grp0)
+    code = 2 * ie.a + np.where(ie.horiz, 0, 1)
+    for g in range(K):
+        inc = np.flatnonzero((ie.c == g) | (ie.d == g))
+        if inc.size == 0:
+            continue
+        best = inc[np.lexsort((code[inc], np.floor(np.abs(r[inc]) * 2.0 ** 40)))[0]]
+        other = ie.d[best] if ie.c[best] == g else ie.c[best]
+        assert new[g] == new[other]
+    sizes = np.bincount(new)
+    has_edge = np.zeros(K, bool)
+    has_edge[ie.c] = True
+    has_edge[ie.d] = True
+    for h in range(sizes.size):
+        members = np.flatnonzero(new == h)
+        assert members.size >= 2 or not has_edge[members[0]]
+    assert sizes.size <= (K + 1) // 2 + np.sum(~has_edge)
+
+
+def test_merging_after_the_last_step_changes_nothing():
+    """A merge frequency beyond T leaves the loop without merging; a merge
+    that would fall after the last iteration is not taken."""
+    s = synth.make("c1", 0)
+    base = dict(O.DEFAULT_PARAMS, irls_iters=7)
+    e = O.edges(s.normals, s.mask, s.cam, base["theta_c_deg"])
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    S0, E0, _ = O.irls(e, lab, K, zf, base)
+    for f in (7, 50):
+        S1, E1, _ = O.irls(e, lab, K, zf, dict(base, freq_merging=f))
+        assert np.array_equal(S0, S1) and E0 == E1
