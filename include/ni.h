@@ -104,6 +104,12 @@ typedef struct {
   int32_t fill_mg_maxit; /* iteration cap of the multigrid fill solve before
                             the large components fall back to the Jacobi
                             path (0: 2000)                                   */
+  int32_t freq_merging; /* optional merging (Sec. 3.5, Alg. 1): after every
+                           freq_merging-th relative-scale iteration each
+                           quotient node joins the neighbour across its
+                           edge of smallest |residual| (on a 2^-40 grid,
+                           ties to the smaller edge code) and the joined
+                           nodes move as one from then on; 0 = off        */
 } ni_params;
 
 typedef struct {
@@ -139,6 +145,8 @@ typedef struct {
                                large components were solved again with
                                the Jacobi path                             */
   int64_t fill_large_px;  /* pixels of the components on the large path    */
+  int32_t merges;         /* merge steps taken (freq_merging > 0)          */
+  int32_t nodes_final;    /* quotient nodes after the last merge (K if none) */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;
@@ -146,7 +154,8 @@ typedef struct ni_ctx ni_ctx;
 /* Defaults: theta_c 2 deg, T 15, 2 alignment iterations, k 2, L 1e-5,
  * U 1e-3, soft outliers, delta_e_max 0, w_cut_rel 1e-12, cg_rtol 1e-6,
  * cg_max_iter 50000, q_rtol 1e-5, q_max_iter 20000, zero start, no
- * graphs, autotuned fill schedule, multigrid fill preconditioner.
+ * graphs, autotuned fill schedule, multigrid fill preconditioner, no
+ * merging.
  * Returns NI_E_ARG on a null pointer. */
 ni_status ni_params_default(ni_params* p);
 
@@ -162,7 +171,8 @@ ni_status ni_destroy(ni_ctx* ctx);
  * torch.cuda.current_stream().cuda_stream); NULL selects the null stream. */
 ni_status ni_set_stream(ni_ctx* ctx, void* hip_stream);
 
-/* Whole path (Alg. 1 without merging): components, fill, relative scales.
+/* Whole path (Alg. 1): components, fill, relative scales (with optional
+ * merging when params->freq_merging > 0).
  *   normals   device f32 [H][W][3], read only; NaN/Inf allowed off the mask
  *   mask      device u8  [H][W]; non-zero = valid pixel
  *   depth     device f32 [H][W] out: exp(z~) (perspective) or z~ (ortho),

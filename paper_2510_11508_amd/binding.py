@@ -35,7 +35,7 @@ class ni_params(C.Structure):
                 ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
                 ("graphs", C.c_int32), ("fill_chunk", C.c_int32), ("fill_split", C.c_int32),
-                ("fill_precond", C.c_int32), ("fill_mg_maxit", C.c_int32)]
+                ("fill_precond", C.c_int32), ("fill_mg_maxit", C.c_int32), ("freq_merging", C.c_int32)]
 
 
 class ni_report(C.Structure):
@@ -52,7 +52,7 @@ class ni_report(C.Structure):
                 ("ms_total", C.c_float), ("ms_large_kernel", C.c_float), ("fill_chunk", C.c_int32),
                 ("fill_split", C.c_int32), ("fill_mg_levels", C.c_int32), ("ms_fill_mg_build", C.c_float),
                 ("fill_mg_bytes", C.c_double), ("fill_mg_fallback", C.c_int32),
-                ("fill_large_px", C.c_int64)]
+                ("fill_large_px", C.c_int64), ("merges", C.c_int32), ("nodes_final", C.c_int32)]
 
     def as_dict(self):
         d = {}

@@ -141,6 +141,8 @@ struct ni_ctx {
   // edges / pairs
   Buf eidx_raw, eidx, ew, erho, pflag, ppos, pair_start, pair_lo, pair_hi, pW, pB, ent, ent_tmp, rowcnt,
       row_off, epart, rsum, rcnt, qcol, qw, qt0, qt1, eom, eta, etb;
+  // merging
+  Buf mgrp, mglab, mkey, mcode, mpa, mpb, mkeep, mrank;
   // fill multigrid: level-0 system of the large components
   Buf mg_deg, mg_pc, mg_row, mg_poff, mg_col, mg_w, mg_diag, mg_plo, mg_phi, mg_pw, mg_gy, mg_gx, mg_gc, mg_b, mg_x;
   // scratch
@@ -165,7 +167,8 @@ struct ni_ctx {
                   &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &rsum,
-                  &rcnt, &qcol, &qw, &qt0, &qt1, &eom, &eta, &etb, &mg_deg, &mg_pc, &mg_row,
+                  &rcnt, &qcol, &qw, &qt0, &qt1, &eom, &eta, &etb, &mgrp, &mglab, &mkey, &mcode, &mpa,
+                  &mpb, &mkeep, &mrank, &mg_deg, &mg_pc, &mg_row,
                   &mg_poff, &mg_col, &mg_w, &mg_diag, &mg_plo, &mg_phi, &mg_pw, &mg_gy, &mg_gx, &mg_gc, &mg_b,
                   &mg_x, &scan_tmp, &misc, &unet_ws};
     bufs.assign(std::begin(all), std::end(all));
@@ -265,6 +268,7 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
   if (!(prm->out_L > 0 && prm->out_U > prm->out_L)) return bad("need 0 < out_L < out_U");
   if (prm->outlier_mode < 0 || prm->outlier_mode > 2) return bad("outlier_mode must be 0, 1 or 2");
   if (!(prm->w_cut_rel >= 0 && prm->w_cut_rel < 1)) return bad("w_cut_rel must be in [0, 1)");
+  if (prm->freq_merging < 0) return bad("freq_merging must be >= 0");
   if (!(prm->bini_k > 0)) return bad("bini_k must be > 0");
   if (prm->fill_chunk != 0 && prm->fill_chunk != 512 && prm->fill_chunk != 1024 && prm->fill_chunk != 2048 &&
       prm->fill_chunk != 4096)
@@ -730,84 +734,14 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   const bool persp = pb.cam.proj == NI_PERSP;
   int* cntd = misc(c) + M_COUNT;
   mark(c, 8);
-  // inter-component edges
-  check(c, nil::quot_inter_edges(labels, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
-                                 nullptr, ptr<int>(c->scan_tmp), c->stream, 0),
-        "inter edges");
-  readback(c, cntd, sizeof(int), c->host);
-  const int E = c->host[0];
-  uint32_t* eidx_raw = ensure<uint32_t>(c, c->eidx_raw, E);
-  uint32_t* eidx = ensure<uint32_t>(c, c->eidx, E);
-  check(c, nil::quot_inter_edges(labels, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
-                                 eidx_raw, ptr<int>(c->scan_tmp), c->stream, 1),
-        "inter compact");
-  size_t srt = std::max<size_t>(E, 1);
-  uint32_t* keys = ensure<uint32_t>(c, c->key, std::max<size_t>(srt, P));
-  uint32_t* ktmp = ensure<uint32_t>(c, c->ktmp, srt);
-  uint32_t* vtmp = ensure<uint32_t>(c, c->vtmp, srt);
-  uint32_t* kout2 = ensure<uint32_t>(c, c->kout2, srt);
-  int* pflag = ensure<int>(c, c->pflag, srt);
-  int* ppos = ensure<int>(c, c->ppos, srt);
-  ensure_scan(c, std::max<size_t>(2 * (size_t)P, srt));
-  check(c, nil::quot_sort_edges(eidx_raw, E, W, K, labels, keys, eidx, ktmp, vtmp, kout2, pflag, ppos, cntd,
-                                ptr<int>(c->scan_tmp), c->stream),
-        "sort edges");
-  readback(c, cntd, sizeof(int), c->host);
-  const int Pp = c->host[0];
-  int* pair_start = ensure<int>(c, c->pair_start, (size_t)Pp + 1);
-  int* pair_lo = ensure<int>(c, c->pair_lo, Pp);
-  int* pair_hi = ensure<int>(c, c->pair_hi, Pp);
-  check(c, nil::quot_pairs(eidx, pflag, ppos, E, W, labels, Pp, pair_start, pair_lo, pair_hi, c->stream), "pairs");
-  size_t P2 = std::max<size_t>(2 * (size_t)Pp, 1);
-  uint32_t* ent = ensure<uint32_t>(c, c->ent, P2);
-  uint32_t* ent_tmp = ensure<uint32_t>(c, c->ent_tmp, P2);
-  keys = ensure<uint32_t>(c, c->key, std::max<size_t>({srt, (size_t)P, P2}));
-  ktmp = ensure<uint32_t>(c, c->ktmp, std::max(srt, P2));
-  vtmp = ensure<uint32_t>(c, c->vtmp, std::max(srt, P2));
-  kout2 = ensure<uint32_t>(c, c->kout2, std::max(srt, P2));
-  ensure_scan(c, std::max<size_t>({2 * (size_t)P, srt, P2}));
   size_t K1 = (size_t)K + 1;
-  int* rowcnt = ensure<int>(c, c->rowcnt, K1);
-  int* row_off = ensure<int>(c, c->row_off, K1);
-  check(c, nil::quot_csr(pair_lo, pair_hi, Pp, K, keys, ent, ktmp, vtmp, kout2, ent_tmp, rowcnt, row_off,
-                         ptr<int>(c->scan_tmp), c->stream),
-        "csr");
-  // rows multiplied by a whole wavefront
-  int* heavy = ensure<int>(c, c->lpos, K1);
-  check(c, nil::quot_heavy_rows(row_off, K, ptr<int>(c->flag), ptr<int>(c->scanv), heavy, cntd + 2,
-                                ptr<int>(c->scan_tmp), c->stream),
-        "heavy rows");
-  readback(c, cntd + 2, 2 * sizeof(int), c->host);
-  const int nbig = c->host[0], nheavy = c->host[0] + c->host[1];
-  // per-iteration arrays
   nil::IrlsArgs a;
-  a.heavy = heavy;
-  a.nheavy = nheavy;
-  a.nbig = nbig;
   if (!c->amg) c->amg = nil::amg_new();
   a.amg = c->amg;
   a.graphs = pb.prm.graphs ? 1 : 0;
-  a.eidx = eidx; a.E = E; a.P = Pp; a.K = K; a.W = W; a.label = labels; a.ebits = ptr<uint8_t>(c->ebits);
+  a.W = W; a.label = labels; a.K0 = K; a.grp = nullptr; a.ebits = ptr<uint8_t>(c->ebits);
   a.zfill = zfill;
-  {
-    double* eom = ensure<double>(c, c->eom, srt);
-    double* eta = ensure<double>(c, c->eta, srt);
-    double* etb = ensure<double>(c, c->etb, srt);
-    check(c, nil::launch_inter_geom(eidx, E, pb.H, W, pb.normals, persp ? 1 : 0, pb.cam.pixel_pitch, ptr<double>(c->tab),
-                                    eom, eta, etb, c->stream),
-          "inter-edge geometry");
-    a.eom = eom; a.eta = eta; a.etb = etb;
-  }
-  a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
   a.S = ensure<double>(c, c->S, K1);
-  a.ew = ensure<double>(c, c->ew, srt);
-  a.erho = ensure<double>(c, c->erho, srt);
-  a.pW = ensure<double>(c, c->pW, std::max(Pp, 1));
-  a.pB = ensure<double>(c, c->pB, std::max(Pp, 1));
-  a.diag = ensure<double>(c, c->diag, K1);
-  a.rhs = ensure<double>(c, c->qrhs, K1);
-  a.babs = ensure<double>(c, c->babs, K1);
-  a.s = ensure<double>(c, c->qs, K1);
   a.psum = ensure<double>(c, c->psum, K1);
   a.pcnt = ensure<int>(c, c->pcnt, K1);
   a.parent = ensure<int>(c, c->qparent, K1);
@@ -815,18 +749,95 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.energy_out = (double*)(misc(c) + M_ENERGY);
   a.qiters_out = misc(c) + M_QITERS;
   a.qiters2_out = misc(c) + M_QITERS2;
-  a.epart = ensure<double>(c, c->epart, (size_t)ni::ceil_div(std::max(Pp, 1), 256));
   a.g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
   a.g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
   a.k = pb.prm.bini_k; a.L = pb.prm.out_L; a.U = pb.prm.out_U; a.cut_rel = pb.prm.w_cut_rel;
   a.q_rtol = pb.prm.q_rtol; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
   a.q_maxit = pb.prm.q_max_iter;
-  a.nnz = 2 * Pp;
-  a.qcol = ensure<int>(c, c->qcol, std::max(a.nnz, 1));
-  a.qw = ensure<double>(c, c->qw, std::max(a.nnz, 1));
-  a.t0 = ensure<double>(c, c->qt0, K1);
-  a.t1 = ensure<double>(c, c->qt1, K1);
   a.host_flag = c->host + 32;
+  // The quotient structure of a node labelling (the components, or merged
+  // nodes after a merge): inter edges, sorted pairs, CSR, heavy rows and the
+  // FP64 edge geometry.  A rebuild after a merge only shrinks every size,
+  // so no buffer in use is reallocated.
+  auto build = [&](const int* gl, int Kg) {
+    // inter-component edges
+    check(c, nil::quot_inter_edges(gl, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
+                                   nullptr, ptr<int>(c->scan_tmp), c->stream, 0),
+          "inter edges");
+    readback(c, cntd, sizeof(int), c->host);
+    const int E = c->host[0];
+    uint32_t* eidx_raw = ensure<uint32_t>(c, c->eidx_raw, E);
+    uint32_t* eidx = ensure<uint32_t>(c, c->eidx, E);
+    check(c, nil::quot_inter_edges(gl, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
+                                   eidx_raw, ptr<int>(c->scan_tmp), c->stream, 1),
+          "inter compact");
+    size_t srt = std::max<size_t>(E, 1);
+    uint32_t* keys = ensure<uint32_t>(c, c->key, std::max<size_t>(srt, P));
+    uint32_t* ktmp = ensure<uint32_t>(c, c->ktmp, srt);
+    uint32_t* vtmp = ensure<uint32_t>(c, c->vtmp, srt);
+    uint32_t* kout2 = ensure<uint32_t>(c, c->kout2, srt);
+    int* pflag = ensure<int>(c, c->pflag, srt);
+    int* ppos = ensure<int>(c, c->ppos, srt);
+    ensure_scan(c, std::max<size_t>(2 * (size_t)P, srt));
+    check(c, nil::quot_sort_edges(eidx_raw, E, W, Kg, gl, keys, eidx, ktmp, vtmp, kout2, pflag, ppos, cntd,
+                                  ptr<int>(c->scan_tmp), c->stream),
+          "sort edges");
+    readback(c, cntd, sizeof(int), c->host);
+    const int Pp = c->host[0];
+    int* pair_start = ensure<int>(c, c->pair_start, (size_t)Pp + 1);
+    int* pair_lo = ensure<int>(c, c->pair_lo, Pp);
+    int* pair_hi = ensure<int>(c, c->pair_hi, Pp);
+    check(c, nil::quot_pairs(eidx, pflag, ppos, E, W, gl, Pp, pair_start, pair_lo, pair_hi, c->stream), "pairs");
+    size_t P2 = std::max<size_t>(2 * (size_t)Pp, 1);
+    uint32_t* ent = ensure<uint32_t>(c, c->ent, P2);
+    uint32_t* ent_tmp = ensure<uint32_t>(c, c->ent_tmp, P2);
+    keys = ensure<uint32_t>(c, c->key, std::max<size_t>({srt, (size_t)P, P2}));
+    ktmp = ensure<uint32_t>(c, c->ktmp, std::max(srt, P2));
+    vtmp = ensure<uint32_t>(c, c->vtmp, std::max(srt, P2));
+    kout2 = ensure<uint32_t>(c, c->kout2, std::max(srt, P2));
+    ensure_scan(c, std::max<size_t>({2 * (size_t)P, srt, P2}));
+    const size_t Kg1 = (size_t)Kg + 1;
+    int* rowcnt = ensure<int>(c, c->rowcnt, Kg1);
+    int* row_off = ensure<int>(c, c->row_off, Kg1);
+    check(c, nil::quot_csr(pair_lo, pair_hi, Pp, Kg, keys, ent, ktmp, vtmp, kout2, ent_tmp, rowcnt, row_off,
+                           ptr<int>(c->scan_tmp), c->stream),
+          "csr");
+    // rows multiplied by a whole wavefront
+    int* heavy = ensure<int>(c, c->lpos, Kg1);
+    check(c, nil::quot_heavy_rows(row_off, Kg, ptr<int>(c->flag), ptr<int>(c->scanv), heavy, cntd + 2,
+                                  ptr<int>(c->scan_tmp), c->stream),
+          "heavy rows");
+    readback(c, cntd + 2, 2 * sizeof(int), c->host);
+    a.heavy = heavy;
+    a.nbig = c->host[0];
+    a.nheavy = c->host[0] + c->host[1];
+    a.glabel = gl;
+    a.eidx = eidx; a.E = E; a.P = Pp; a.K = Kg;
+    a.pair_start = pair_start; a.pair_lo = pair_lo; a.pair_hi = pair_hi; a.row_off = row_off; a.ent = ent;
+    double* eom = ensure<double>(c, c->eom, srt);
+    double* eta = ensure<double>(c, c->eta, srt);
+    double* etb = ensure<double>(c, c->etb, srt);
+    check(c, nil::launch_inter_geom(eidx, E, pb.H, W, pb.normals, persp ? 1 : 0, pb.cam.pixel_pitch,
+                                    ptr<double>(c->tab), eom, eta, etb, c->stream),
+          "inter-edge geometry");
+    a.eom = eom; a.eta = eta; a.etb = etb;
+    a.ew = ensure<double>(c, c->ew, srt);
+    a.erho = ensure<double>(c, c->erho, srt);
+    a.pW = ensure<double>(c, c->pW, std::max(Pp, 1));
+    a.pB = ensure<double>(c, c->pB, std::max(Pp, 1));
+    a.diag = ensure<double>(c, c->diag, Kg1);
+    a.rhs = ensure<double>(c, c->qrhs, Kg1);
+    a.babs = ensure<double>(c, c->babs, Kg1);
+    a.s = ensure<double>(c, c->qs, Kg1);
+    a.epart = ensure<double>(c, c->epart, (size_t)ni::ceil_div(std::max(Pp, 1), 256));
+    a.nnz = 2 * Pp;
+    a.qcol = ensure<int>(c, c->qcol, std::max(a.nnz, 1));
+    a.qw = ensure<double>(c, c->qw, std::max(a.nnz, 1));
+    a.t0 = ensure<double>(c, c->qt0, Kg1);
+    a.t1 = ensure<double>(c, c->qt1, Kg1);
+  };
+  build(labels, K);
+  const int E = a.E, Pp = a.P;
   check(c, hipMemsetAsync(a.S, 0, K1 * sizeof(double), c->stream), "memset");
   if (hook.S) {
     if (K > 0)
@@ -852,11 +863,44 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     return;
   }
   const int T = pb.prm.irls_iters;
-  int ran = 0;
+  const int freq = pb.prm.freq_merging;
+  int ran = 0, merges = 0;
   std::vector<double> en(NI_MAX_IRLS, 0.0);
+  int* grp = nullptr;
+  int* gl = nullptr;
+  if (freq > 0 && freq < T && K > 0) {
+    grp = ensure<int>(c, c->mgrp, K1);
+    gl = ensure<int>(c, c->mglab, (size_t)P);
+    ensure<unsigned long long>(c, c->mkey, K1);
+    ensure<unsigned>(c, c->mcode, K1);
+    ensure<int>(c, c->mpa, K1);
+    ensure<int>(c, c->mpb, K1);
+    ensure<double>(c, c->mkeep, K1);
+    ensure<int>(c, c->mrank, K1);
+    ensure_scan(c, K1);
+    check(c, nil::identity_groups(grp, K, c->stream), "groups");
+  }
   for (int t = 0; t < T; ++t) {
     check(c, nil::irls_iteration(a, t, c->stream), "irls");
+    a.fresh = 0;
     ran = t + 1;
+    if (grp && (t + 1) % freq == 0 && t + 1 < T) {
+      // optional merging (Sec. 3.5): new nodes from the residuals at the
+      // updated log-depth, then the quotient structure of the new nodes (a
+      // single node left: the merge is a no-op)
+      if (a.K > 1) {
+        a.grp = grp;
+        check(c,
+              nil::merge_nodes(a, grp, gl, P, ptr<unsigned long long>(c->mkey), ptr<unsigned>(c->mcode),
+                               ptr<int>(c->mpa), ptr<int>(c->mpb), ptr<double>(c->mkeep), ptr<int>(c->qparent),
+                               ptr<int>(c->flag), ptr<int>(c->mrank), cntd + 4, ptr<int>(c->scan_tmp), c->stream),
+              "merge");
+        readback(c, cntd + 4, sizeof(int), c->host);
+        build(gl, c->host[0]);
+        a.fresh = 1;  // the next step cannot reuse the previous hierarchy
+      }
+      ++merges;
+    }
     if (pb.prm.delta_e_max > 0 && t >= pb.prm.align_iters + 1) {
       readback(c, a.energy_out, sizeof(double) * (t + 1), en.data());
       double Ep = en[t - 1], Et = en[t];
@@ -897,6 +941,8 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     rep->n_inter_edges = E;
     rep->n_pairs = Pp;
     rep->irls_iters_run = ran;
+    rep->merges = merges;
+    rep->nodes_final = a.K;
     check(c, hipMemcpy(en.data(), a.energy_out, sizeof(double) * NI_MAX_IRLS, hipMemcpyDeviceToHost), "D2H");
     for (int t = 0; t < NI_MAX_IRLS; ++t) {
       rep->energy[t] = t < ran ? en[t] : 0.0;
@@ -957,6 +1003,7 @@ ni_status ni_params_default(ni_params* p) {
   p->warm_start = 0;
   p->graphs = 0;
   p->fill_chunk = 0;
+  p->freq_merging = 0;
   p->fill_split = 0;
   p->fill_precond = 1;
   p->fill_mg_maxit = 0;

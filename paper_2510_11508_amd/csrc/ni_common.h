@@ -199,7 +199,11 @@ hipError_t amg_solve(Amg*, const double* rhs, const double* scale, const double*
 struct IrlsArgs {
   const uint32_t* eidx;
   int E, P, K, W;
-  const int* label;
+  const int* label;   // component of every pixel (indexes S)
+  const int* glabel;  // quotient node of every pixel (the component, or its merged node)
+  const int* grp;     // node of every component (null: the identity)
+  int K0;             // components (K = quotient nodes)
+  int fresh = 0;      // 1: the node structure changed since the last step
   const uint8_t* ebits;
   const double *eom, *eta, *etb;  // FP64 omega and gamma factors per inter edge
   const float* zfill;
@@ -223,5 +227,9 @@ struct IrlsArgs {
   Amg* amg;   // multigrid of the quotient solve
   int graphs; // replay the multigrid iteration from a HIP graph
 };
+hipError_t merge_nodes(const IrlsArgs& a, int* grp, int* glabel_out, int P, unsigned long long* gkey, unsigned* gcode,
+                       int* pa, int* pb, double* pkeep, int* parent, int* flag, int* rank, int* cnt, int* scan_tmp,
+                       hipStream_t st);
+hipError_t identity_groups(int* grp, int K0, hipStream_t st);
 
 }  // namespace nil

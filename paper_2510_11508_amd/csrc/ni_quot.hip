@@ -123,6 +123,16 @@ __global__ void k_iota_u32(uint32_t* a, int n) {
   if (i < n) a[i] = (uint32_t)i;
 }
 
+__global__ void k_fill_u64(unsigned long long* a, int n, unsigned long long v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_u32(unsigned* a, int n, unsigned v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
 __global__ void k_fill_f64(double* a, int n, double v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
@@ -146,8 +156,9 @@ __device__ __forceinline__ double outlier_w(double chi, const EdgeParams& q) {
 }
 
 __global__ void __launch_bounds__(256) k_irls_edges(
-    const uint32_t* __restrict__ eidx, int E, const int* __restrict__ label, const uint8_t* __restrict__ ebits,
-    const double* __restrict__ eom, const double* __restrict__ eta, const double* __restrict__ etb,
+    const uint32_t* __restrict__ eidx, int E, const int* __restrict__ label, const int* __restrict__ glabel,
+    const uint8_t* __restrict__ ebits, const double* __restrict__ eom, const double* __restrict__ eta,
+    const double* __restrict__ etb,
     const float* __restrict__ zfill, const double* __restrict__ S, EdgeParams q, double* __restrict__ ew,
     double* __restrict__ erho, unsigned long long* __restrict__ wmax_bits) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,7 +202,7 @@ __global__ void __launch_bounds__(256) k_irls_edges(
       w = (wba + wab) * outlier_w(r, q);
     }
     ew[i] = w;
-    erho[i] = (c < d) ? r : -r;
+    erho[i] = (glabel[a] < glabel[b]) ? r : -r;  // oriented lo -> hi of the node pair
   }
   // block max, one atomic per block (non-negative doubles order like their bits)
   __shared__ double bm[4];
@@ -380,14 +391,19 @@ __global__ void k_piece_center(const int* __restrict__ parent, double* __restric
 }
 
 __global__ void k_piece_apply(const int* __restrict__ parent, double* __restrict__ s, int K,
-                              const double* __restrict__ psum, const int* __restrict__ pcnt,
-                              double* __restrict__ S) {
+                              const double* __restrict__ psum, const int* __restrict__ pcnt) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= K) return;
   int r = parent[c];
-  double sc = s[c] - psum[r] / (double)pcnt[r];
-  s[c] = sc;
-  S[c] += sc;
+  s[c] -= psum[r] / (double)pcnt[r];
+}
+
+// S_c += s of the node that holds component c (Eq. 12; every component of a
+// merged node moves with it)
+__global__ void k_scale_add(const double* __restrict__ s, const int* __restrict__ grp, int K0,
+                            double* __restrict__ S) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K0) S[c] += s[grp ? grp[c] : c];
 }
 
 // per pair energy contribution; block partials
@@ -416,6 +432,94 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ pa
   for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += part[i];
   ni::block_sum<1>(v, red);
   if (threadIdx.x == 0) *out = v[0];
+}
+
+// ------------------------------------------------------------ merging
+// Optional merging (Sec. 3.5 (i)-(iii)).  Every node picks the live inter
+// edge incident to it with the smallest |residual| at the current
+// log-depth, compared on a 2^-40 grid, equal values to the smaller edge
+// code; the nodes joined by picked edges become one.  The key of an edge
+// is floor(|r| 2^40) (|r| < 2^23 holds for any log-depth residual).
+__device__ __forceinline__ unsigned long long merge_key(const uint32_t* eidx, const int* label, const float* zfill,
+                                                         const double* S, const double* eom, int W, int i) {
+  int a, b;
+  bool h;
+  edge_ends(eidx[i], W, a, b, h);
+  const double r = ((double)zfill[a] + S[label[a]]) - ((double)zfill[b] + S[label[b]]) - eom[i];
+  return (unsigned long long)floor(fabs(r) * 1099511627776.0);  // 2^40
+}
+
+__global__ void k_merge_min(const uint32_t* __restrict__ eidx, int E, int W, const int* __restrict__ label,
+                            const int* __restrict__ glabel, const float* __restrict__ zfill,
+                            const double* __restrict__ S, const double* __restrict__ eom,
+                            unsigned long long* __restrict__ gkey) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  const unsigned long long k = merge_key(eidx, label, zfill, S, eom, W, i);
+  int a, b;
+  bool h;
+  edge_ends(eidx[i], W, a, b, h);
+  atomicMin(&gkey[glabel[a]], k);
+  atomicMin(&gkey[glabel[b]], k);
+}
+
+__global__ void k_merge_code(const uint32_t* __restrict__ eidx, int E, int W, const int* __restrict__ label,
+                             const int* __restrict__ glabel, const float* __restrict__ zfill,
+                             const double* __restrict__ S, const double* __restrict__ eom,
+                             const unsigned long long* __restrict__ gkey, unsigned* __restrict__ gcode) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  const unsigned long long k = merge_key(eidx, label, zfill, S, eom, W, i);
+  int a, b;
+  bool h;
+  edge_ends(eidx[i], W, a, b, h);
+  const int ga = glabel[a], gb = glabel[b];
+  if (gkey[ga] == k) atomicMin(&gcode[ga], eidx[i]);
+  if (gkey[gb] == k) atomicMin(&gcode[gb], eidx[i]);
+}
+
+// the picked edge of node g as a pair (g, other end), or (g, g)
+__global__ void k_merge_pairs(const unsigned* __restrict__ gcode, int Kg, int W, const int* __restrict__ glabel,
+                              int* __restrict__ pa, int* __restrict__ pb, double* __restrict__ pkeep) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= Kg) return;
+  const unsigned code = gcode[g];
+  int o = g;
+  if (code != 0xffffffffu) {
+    int a, b;
+    bool h;
+    edge_ends(code, W, a, b, h);
+    o = glabel[a] == g ? glabel[b] : glabel[a];
+  }
+  pa[g] = g;
+  pb[g] = o;
+  pkeep[g] = o != g ? 1.0 : 0.0;
+}
+
+__global__ void k_root_flags(const int* __restrict__ parent, int n, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = parent[i] == i ? 1 : 0;
+}
+
+// new node of every component and of every pixel
+__global__ void k_merge_relabel(int* __restrict__ grp, int K0, const int* __restrict__ parent,
+                                const int* __restrict__ rank) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K0) grp[c] = rank[parent[grp[c]]];
+}
+
+__global__ void k_merge_pixels(const int* __restrict__ label, const int* __restrict__ grp, int P,
+                               int* __restrict__ glabel) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) {
+    const int c = label[p];
+    glabel[p] = c >= 0 ? grp[c] : -1;
+  }
+}
+
+__global__ void k_iota_i32(int* a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
 }
 
 }  // namespace
@@ -516,6 +620,41 @@ hipError_t quot_csr(const int* pair_lo, const int* pair_hi, int P, int K, uint32
 
 
 
+// One merge of the quotient nodes (Sec. 3.5): a.glabel / a.K describe the
+// current nodes, grp maps components to them; on return grp and glabel_out
+// hold the merged nodes and *kg_out their number (device count in cnt).
+hipError_t merge_nodes(const IrlsArgs& a, int* grp, int* glabel_out, int P, unsigned long long* gkey, unsigned* gcode,
+                       int* pa, int* pb, double* pkeep, int* parent, int* flag, int* rank, int* cnt, int* scan_tmp,
+                       hipStream_t st) {
+  const int Kg = a.K;
+  if (Kg <= 0) return hipSuccess;
+  hipError_t e;
+  k_fill_u64<<<ni::ceil_div(Kg, 256), 256, 0, st>>>(gkey, Kg, ~0ull);
+  k_fill_u32<<<ni::ceil_div(Kg, 256), 256, 0, st>>>(gcode, Kg, 0xffffffffu);
+  if (a.E > 0) {
+    k_merge_min<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.W, a.label, a.glabel, a.zfill, a.S, a.eom, gkey);
+    k_merge_code<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.W, a.label, a.glabel, a.zfill, a.S, a.eom,
+                                                         gkey, gcode);
+  }
+  k_merge_pairs<<<ni::ceil_div(Kg, 256), 256, 0, st>>>(gcode, Kg, a.W, a.glabel, pa, pb, pkeep);
+  e = list_components(Kg, pa, pb, pkeep, Kg, parent, st);
+  if (e != hipSuccess) return e;
+  // roots are the smallest node of each merged set, and node order follows
+  // the smallest original component, so ranking the roots numbers the new
+  // nodes by their smallest component
+  k_root_flags<<<ni::ceil_div(Kg, 256), 256, 0, st>>>(parent, Kg, flag);
+  e = scan_exclusive_i32(flag, rank, Kg, cnt, scan_tmp, st);
+  if (e != hipSuccess) return e;
+  k_merge_relabel<<<ni::ceil_div(a.K0, 256), 256, 0, st>>>(grp, a.K0, parent, rank);
+  k_merge_pixels<<<ni::ceil_div(P, 256), 256, 0, st>>>(a.label, grp, P, glabel_out);
+  return hipGetLastError();
+}
+
+hipError_t identity_groups(int* grp, int K0, hipStream_t st) {
+  if (K0 > 0) k_iota_i32<<<ni::ceil_div(K0, 256), 256, 0, st>>>(grp, K0);
+  return hipGetLastError();
+}
+
 hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   hipError_t e;
   EdgeParams q;
@@ -533,7 +672,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (a.E > 0) {
     e = hipMemsetAsync(a.wmax, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
-    k_irls_edges<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.label, a.ebits, a.eom, a.eta, a.etb,
+    k_irls_edges<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.label, a.glabel, a.ebits, a.eom, a.eta, a.etb,
                                                         a.zfill, a.S, q, a.ew, a.erho, a.wmax);
     k_irls_pairs<<<ni::ceil_div(a.P, 256), 256, 0, st>>>(a.pair_start, a.P, a.ew, a.erho, a.wmax, a.cut_rel, a.pW,
                                                         a.pB);
@@ -564,7 +703,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (a.nnz > 0) k_q_matrix<<<ni::ceil_div(a.nnz, 256), 256, 0, st>>>(a.row_off, a.ent, a.pair_lo, a.pair_hi, a.pW,
                                                                        a.nnz, a.qcol, a.qw);
   e = hipGetLastError();
-  const bool same_as_previous = t > 0 && t < a.align;
+  const bool same_as_previous = t > 0 && t < a.align && !a.fresh;
   if (e == hipSuccess && !same_as_previous)
     e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
   if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
@@ -601,7 +740,8 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   k_fill_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.psum, a.K, 0.0);
   k_fill_i32<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pcnt, a.K, 0);
   k_piece_acc<<<ni::ceil_div(a.K, 1024), 1024, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt);
-  k_piece_apply<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt, a.S);
+  k_piece_apply<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt);
+  k_scale_add<<<ni::ceil_div(a.K0, 256), 256, 0, st>>>(a.s, a.grp, a.K0, a.S);
   // energy
   if (a.P > 0) {
     int nb = ni::ceil_div(a.P, 256);

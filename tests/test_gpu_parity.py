@@ -51,7 +51,7 @@ def params(**kw):
 def oracle_params(p):
     return dict(theta_c_deg=p.theta_c_deg, irls_iters=p.irls_iters, align_iters=p.align_iters, bini_k=p.bini_k,
                 out_L=p.out_L, out_U=p.out_U, outlier_mode=p.outlier_mode, delta_e_max=p.delta_e_max,
-                w_cut_rel=p.w_cut_rel)
+                w_cut_rel=p.w_cut_rel, freq_merging=p.freq_merging)
 
 
 def assert_depth_close(d_gpu, d_ref, mask, what="", ortho=False):
@@ -451,6 +451,24 @@ def test_irls_steps_match_oracle(ctx, name, seed, theta):
     zf = fp32(O.fill(e, lab, K))
     log(f"[irls steps] {name} seed {seed} theta {theta} K {K}")
     check_irls_steps(ctx, s, p, op, lab, K, zf, f"{name} {seed} theta {theta}")
+
+
+@pytest.mark.parametrize("name,seed,freq,T", [("c1", 0, 3, 10), ("c1", 1, 5, 10), ("c2", 0, 5, 15),
+                                             ("c2", 2, 3, 15), ("tiny-persp", 3, 2, 6), ("c2", 0, 1, 6)])
+def test_integrate_merging(ctx, name, seed, freq, T):
+    """Optional merging (Sec. 3.5, Alg. 1's merge block every freq
+    iterations): the same node count after the merges as the oracle, then
+    the same output."""
+    s = sample(name, seed)
+    p = params(theta_c_deg=2.0, irls_iters=T, freq_merging=freq)
+    log(f"[merging] {name} seed {seed} freq {freq} T {T}")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    ref = O.integrate(s.normals, s.mask, s.cam, oracle_params(p))
+    groups = O.irls.last_groups
+    rep = out["report"]
+    assert rep["merges"] == (T - 1) // freq
+    assert rep["nodes_final"] == (int(groups.max()) + 1 if groups.size else 0)
+    check_whole_path(ctx, s, p, out, ref, f"merging {name} {seed} freq {freq}")
 
 
 def test_quotient_not_converged_is_reported(ctx):
