@@ -256,6 +256,9 @@ def main():
                     help="preconditioner of the large fill components (default: the library's, multigrid)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--unet-only", type=int, default=0, metavar="N",
+                    help="only run the warm-start network's inference N times on the workload's map "
+                         "(for counter runs of its MFMA kernels) and print its timing")
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/fill_mg_traffic_<workload>.{json,md} from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this script with --steps 1 --warmup 0 --copy-calibration")
@@ -318,6 +321,23 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000.0 / a.steps
         return ms, reps, out
+
+    if a.unet_only:
+        ctx.ni_unet_load(open(a.model, "rb").read())
+        hw = int(s.mask.shape[0]) * int(s.mask.shape[1])
+        ctx.ni_unet_predict(normals, mask, cam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.unet_only):
+            ctx.ni_unet_predict(normals, mask, cam)
+        torch.cuda.synchronize()
+        ms_u = (time.perf_counter() - t0) * 1000.0 / a.unet_only
+        tfl = UNET_FLOP_PER_PX * hw / (ms_u / 1000.0) / 1e12
+        print(json.dumps(dict(workload=a.workload, calls=a.unet_only + 1, ms_per_map=round(ms_u, 3),
+                              flop_per_px=round(UNET_FLOP_PER_PX), tflops=round(tfl, 2),
+                              frac_bf16_peak=round(tfl / BF16_PEAK_TFLOPS, 4))))
+        ctx.close()
+        return
 
     ms, reps, out = timed(p)
     value = n_valid / (ms / 1000.0) / 1e6

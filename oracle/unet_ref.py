@@ -134,19 +134,35 @@ def forward(prm, feat, bf=False):
     c["d0a"] = cv(12, c["cat0"])
     c["d0b"] = cv(13, c["d0a"])
     out = c["d0b"] @ hw + hb
+    c["hb"] = hb
     return out, c
 
 
-def backward(prm, c, dout):
-    """Gradient of sum(dout * out) w.r.t. the parameter vector."""
+def output_magnitude(c):
+    """Per pixel, the sum of the magnitudes of the head's terms:
+    |d0b| . |w_head| + |b_head| (the scale of the rounding error a sum of
+    those terms can carry)."""
+    hw = c["hw"]
+    return np.abs(c["d0b"]) @ np.abs(hw) + abs(c.get("hb", 0.0))
+
+
+def backward(prm, c, dout, magnitudes=False):
+    """Gradient of sum(dout * out) w.r.t. the parameter vector.  With
+    magnitudes=True, also the same contractions over absolute values
+    (sum_pixels |x| |delta| per weight, sum |delta| per bias), the scale of
+    each gradient entry's rounding error."""
     layers, hw = c["layers"], c["hw"]
     R = bf16 if c["bf"] else (lambda a: np.asarray(a, np.float64))
     grads = [None] * len(SPECS)
+    mags = [None] * len(SPECS)
 
     def cb(l, x, y, dy, need_dx=True):
         g = dy * (y > 0)
         dx, dw, db = conv3x3_bwd(x, layers[l][0], g)
         grads[l] = (dw, db)
+        if magnitudes:
+            _, mw, mb = conv3x3_bwd(np.abs(x), np.abs(layers[l][0]), np.abs(g))
+            mags[l] = (mw, mb)
         return R(dx) if need_dx else None
 
     dhw = np.einsum("bhwc,bhw->c", c["d0b"], dout)
@@ -178,7 +194,15 @@ def backward(prm, c, dout):
         out.append(db)
     out.append(dhw)
     out.append(np.array([dhb]))
-    return np.concatenate(out)
+    if not magnitudes:
+        return np.concatenate(out)
+    mag = []
+    for mw, mb in mags:
+        mag.append(mw.ravel())
+        mag.append(mb)
+    mag.append(np.einsum("bhwc,bhw->c", np.abs(c["d0b"]), np.abs(dout)))
+    mag.append(np.array([np.abs(dout).sum()]))
+    return np.concatenate(out), np.concatenate(mag)
 
 
 def init_params(seed):

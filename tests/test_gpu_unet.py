@@ -1,9 +1,23 @@
 """Warm-start U-Net on the GPU (through the C ABI) against the FP64 reference.
 
-Forward / backward are compared with the reference in its BF16-emulating
-mode (it rounds where the kernels store BF16), so what remains is FP32
-accumulation order plus the rare BF16 rounding flip it causes: relative L2
-error bounds 1e-2 (output) and 3e-2 (per-layer gradients)."""
+The forward pass is compared element by element with the reference in its
+BF16-emulating mode (it rounds where the kernels store BF16).  The bound per
+element comes from the error analysis of a rounded sum: a result that sums
+terms t_i carries at most gamma * sum |t_i| of error; the terms are BF16
+values whose rounding can flip when FP32 accumulation order moves a value
+across a BF16 rounding boundary, and gamma = 4 u_bf16 = 2^-6 covers one
+such flip per operand on top of FP32 accumulation.  The scale sum |t_i| per
+element is the same contraction over absolute values (oracle.unet_ref).
+
+Gradients are compared the same way on the small map.  On the map that
+reaches the full tiling (6144 px per image at level 0, i.e. three
+2048-px weight-gradient slabs, FP32 atomics across them) the data gradients
+pass through 13 BF16 stores and ReLU masks, and single rounding flips
+cascade: an exact BF16 emulation itself lands 4-25 % (relative L2) from the
+FP64 gradient there.  The bar at that size is therefore per layer: the
+library's weight and bias gradients are no further from the FP64 gradient
+than 1.25x the exact BF16 emulation's.
+"""
 import sys
 
 import numpy as np
@@ -35,29 +49,66 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
-def test_forward_backward_match_reference(ctx):
+GAMMA = 2.0 ** -6
+
+
+def run_case(ctx, B, H, W):
     rng = np.random.default_rng(0)
+    ctx.ni_unet_init(1234)
     prm = ctx.ni_unet_get_params().astype(np.float64)
     prm[:] += rng.normal(0, 0.01, prm.size)  # non-zero biases
     ctx.ni_unet_set_params(prm.astype(np.float32))
     prm = ctx.ni_unet_get_params().astype(np.float64)
-    feat = rng.normal(0, 1, (2, 16, 24, 6)).astype(np.float32)
-    log("[unet] forward 2x16x24")
-    out = ctx.ni_unet_forward(torch.from_numpy(feat).cuda()).cpu().numpy()
+    feat = rng.normal(0, 1, (B, H, W, 6)).astype(np.float32)
+    log(f"[unet] forward {B}x{H}x{W}")
+    out = ctx.ni_unet_forward(torch.from_numpy(feat).cuda()).cpu().numpy().astype(np.float64)
     ref, cache = U.forward(prm, feat.astype(np.float64), bf=True)
-    assert rel(out, ref) < 1e-2, rel(out, ref)
+    bound = GAMMA * U.output_magnitude(cache) + 1e-30
+    ratio = np.abs(out - ref) / bound
+    log(f"[unet] forward: max |out - ref| / bound = {ratio.max():.3f}, rel L2 {rel(out, ref):.2e}")
+    assert np.all(ratio <= 1.0), (ratio.max(), np.unravel_index(np.argmax(ratio), ratio.shape))
     dout = rng.normal(0, 1, out.shape).astype(np.float32)
     log("[unet] backward")
     g = ctx.ni_unet_backward(torch.from_numpy(dout).cuda()).cpu().numpy().astype(np.float64)
-    gr = U.backward(prm, cache, dout.astype(np.float64))
-    o, errs = 0, []
+    gr, gm = U.backward(prm, cache, dout.astype(np.float64), magnitudes=True)
+    return prm, feat, dout, g, gr, gm
+
+
+def layer_slices():
+    o = 0
     for l, (ci, co) in enumerate(U.SPECS):
         nw = 9 * ci * co
-        errs.append((l, round(rel(g[o:o + nw], gr[o:o + nw]), 4), round(rel(g[o + nw:o + nw + co], gr[o + nw:o + nw + co]), 4)))
+        yield l, slice(o, o + nw), slice(o + nw, o + nw + co)
         o += nw + co
-    errs.append(("head", round(rel(g[o:], gr[o:]), 4), 0.0))
-    log(f"[unet] grad rel err (layer, weights, bias): {errs}")
-    assert all(ew < 3e-2 and eb < 3e-2 for _, ew, eb in errs), errs
+    yield "head", slice(o, o + U.HEAD_C + 1), slice(0, 0)
+
+
+def test_forward_backward_match_reference_elementwise(ctx):
+    """2 x 16 x 24: forward and every gradient element within its bound."""
+    _, _, _, g, gr, gm = run_case(ctx, 2, 16, 24)
+    ratio = np.abs(g - gr) / (GAMMA * gm + 1e-30)
+    worst = [(l, round(float(ratio[w].max()), 3), round(float(ratio[b].max()) if b.stop > b.start else 0.0, 3))
+             for l, w, b in layer_slices()]
+    log(f"[unet] grad max |g - g_ref| / bound per layer (weights, bias): {worst}")
+    assert np.all(ratio <= 1.0), worst
+
+
+def test_full_tiling_matches_reference(ctx):
+    """2 x 64 x 96: forward element by element; weight and bias gradients per
+    layer no further from FP64 than the exact BF16 emulation (x 1.25)."""
+    prm, feat, dout, g, gr, gm = run_case(ctx, 2, 64, 96)
+    _, c64 = U.forward(prm, feat.astype(np.float64), bf=False)
+    g64 = U.backward(prm, c64, dout.astype(np.float64))
+    rows = []
+    for l, w, b in layer_slices():
+        for part in (w, b):
+            if part.stop <= part.start:
+                continue
+            e_lib = np.linalg.norm(g[part] - g64[part]) / np.linalg.norm(g64[part])
+            e_bf = np.linalg.norm(gr[part] - g64[part]) / np.linalg.norm(g64[part])
+            rows.append((l, round(e_lib, 4), round(e_bf, 4)))
+            assert e_lib <= 1.25 * e_bf + 1e-3, (l, e_lib, e_bf)
+    log(f"[unet] per layer (layer, |g_lib - g_64| / |g_64|, |g_bf16emu - g_64| / |g_64|): {rows}")
 
 
 def test_train_step_reduces_loss(ctx):
