@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start comparison")
     ap.add_argument("--no-merging", action="store_true",
                     help="skip the optional-merging leg (freq_merging = 5, the paper's large-map setting)")
+    ap.add_argument("--no-baseline", action="store_true",
+                    help="skip the pixel-level log-depth baseline leg (variant 1, ND form)")
     ap.add_argument("--no-pixel-level", action="store_true",
                     help="skip the pixel-level comparison (theta_c = 0: every pixel its own component)")
     ap.add_argument("--fill-schedule", default=None, metavar="CHUNK:SPLIT",
@@ -407,6 +409,20 @@ def main():
         pixel = dict(ms_per_step=round(ms_p, 3), value=round(n_valid / (ms_p / 1000.0) / 1e6, 3), K=op["K"],
                      component_speedup=round(ms_p / ms, 2), quot_iters=op["report"]["quot_iters"])
 
+    baseline = None
+    if not a.no_baseline:
+        # the pixel-level log-depth baseline without discontinuity term (ND):
+        # one warm-up, one timed call, the same T and tolerances
+        pb = ni.ni_params_default(irls_iters=T, variant=1)
+        ctx.ni_integrate(normals, mask, cam, pb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ob = ctx.ni_integrate(normals, mask, cam, pb)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1000.0
+        baseline = dict(ms_per_step=round(ms_b, 3), value=round(n_valid / (ms_b / 1000.0) / 1e6, 3),
+                        component_speedup=round(ms_b / ms, 2), quot_iters=ob["report"]["quot_iters"])
+
     rep = reps[-1]
     k_ms = float(np.mean([r["ms_large_kernel"] for r in reps]))
     launches = max(rep["fill_large_launches"], 1)
@@ -460,6 +476,8 @@ def main():
         line["merging"] = merging
     if pixel is not None:
         line["pixel_level"] = pixel
+    if baseline is not None:
+        line["logdepth_baseline_nd"] = baseline
     if not a.no_cpu_baseline:
         cname = "c3" if a.workload == "c5" else a.workload
         line["cpu_baseline"] = cpu_baseline(cname, a.seed, dict(theta_c_deg=2.0, irls_iters=T))

@@ -110,6 +110,14 @@ typedef struct {
                            edge of smallest |residual| (on a 2^-40 grid,
                            ties to the smaller edge code) and the joined
                            nodes move as one from then on; 0 = off        */
+  int32_t variant;      /* 0: the component method (Alg. 1); 1: the
+                           pixel-level log-depth baseline the paper compares
+                           with, without its discontinuity term (ND, Sec. 4,
+                           Table 1): every pixel its own node, no alignment
+                           phase (the first iteration weighs each row by
+                           the BiNI weight at z = 0), outlier weights from
+                           the second iteration, no merging; theta_c,
+                           align_iters and freq_merging are ignored      */
 } ni_params;
 
 typedef struct {

@@ -403,3 +403,87 @@ def irls_merging(normals, mask, cam, lab, K, zfill, params):
             newid = {r: i for i, r in enumerate(roots)}
             cl = np.where(cl >= 0, np.vectorize(lambda c: newid[find(int(c))])(np.maximum(cl, 0)), -1)
     return z, energies
+
+
+def logdepth_irls(normals, mask, cam, params):
+    """The pixel-level log-depth baseline (ND form), written directly: the
+    unknown is the log-depth of every pixel, z = 0 to start; iteration t
+    minimises sum over both directed rows of every usable pixel pair of
+    W_{b->a} (z_a - z_b - omega_{b->a})^2 with W_{b->a} = g^2 sigma_k(g^2
+    ((z_{-b} - z_a)^2 - (z_b - z_a)^2)) at the previous z, times the outlier
+    weight of the previous residual from the second iteration on; the new z
+    is the minimum-norm solution per connected piece.  Returns (z [H, W],
+    energies)."""
+    import scipy.sparse as sp
+    mask = np.asarray(mask)
+    H, W = mask.shape
+    valid = mask != 0
+    cache = {}
+
+    def pm(a, b):
+        if (a, b) not in cache:
+            ok = valid[a[1], a[0]] and valid[b[1], b[0]]
+            cache[(a, b)] = pair_model(normals, cam, a, b) if ok else (False, 0.0, 0.0, 0.0)
+        return cache[(a, b)]
+
+    pix = {}
+    for v in range(H):
+        for u in range(W):
+            if valid[v, u]:
+                pix[(u, v)] = len(pix)
+    pairs = []
+    for (u, v) in pix:
+        for (du, dv) in ((1, 0), (0, 1)):
+            b = (u + du, v + dv)
+            if b in pix and pm((u, v), b)[0]:
+                pairs.append(((u, v), b))
+    usable = set(pairs)
+
+    def edge_ok(p, q):
+        return (p, q) in usable or (q, p) in usable
+
+    n, N = len(pairs), len(pix)
+    ci = np.array([pix[a] for a, _ in pairs], dtype=np.int64)
+    di = np.array([pix[b] for _, b in pairs], dtype=np.int64)
+    ridx = np.repeat(np.arange(2 * n), 2)
+    cols = np.empty(4 * n, dtype=np.int64)
+    vals = np.empty(4 * n)
+    cols[0::4], vals[0::4] = ci, 1.0
+    cols[1::4], vals[1::4] = di, -1.0
+    cols[2::4], vals[2::4] = di, 1.0
+    cols[3::4], vals[3::4] = ci, -1.0
+    A = sp.csr_matrix((vals, (ridx, cols)), shape=(2 * n, max(N, 1)))
+    z = np.zeros(N)
+    k = params["bini_k"]
+    energies = []
+
+    def zv(p):
+        return z[pix[p]]
+
+    for t in range(int(params["irls_iters"])):
+        if n == 0:
+            energies.append(0.0)
+            continue
+        wts = np.empty(2 * n)
+        rhs = np.empty(2 * n)
+        for i, (a, b) in enumerate(pairs):
+            _, om, g2a, g2b = pm(a, b)
+            za, zb = zv(a), zv(b)
+            d = (b[0] - a[0], b[1] - a[1])
+            mb = (a[0] - d[0], a[1] - d[1])
+            ma = (b[0] + d[0], b[1] + d[1])
+            dm = (zv(mb) - za) if (mb in pix and edge_ok(mb, a)) else 0.0
+            dm2 = (zv(ma) - zb) if (ma in pix and edge_ok(b, ma)) else 0.0
+            wo = _wout(za - zb - om, params["out_L"], params["out_U"], params["outlier_mode"]) if t >= 1 else 1.0
+            wts[2 * i] = g2a * _sig(g2a * (dm * dm - (zb - za) ** 2), k) * wo
+            wts[2 * i + 1] = g2b * _sig(g2b * (dm2 * dm2 - (za - zb) ** 2), k) * wo
+            rhs[2 * i], rhs[2 * i + 1] = om, -om
+        keep = (wts[0::2] + wts[1::2]) > 0
+        Nm = A.T @ sp.diags(wts) @ A
+        znew = _solve_pieces(Nm, A.T @ (wts * rhs), N, ci, di, keep)
+        energies.append(float(np.sum(wts * (A @ znew - rhs) ** 2)))
+        z = znew
+    out = np.zeros((H, W))
+    for (u, v), i in pix.items():
+        out[v, u] = z[i]
+    return out, energies

@@ -49,6 +49,7 @@ DEFAULT_PARAMS = dict(
     delta_e_max=0.0,      # relative-energy stop; 0 runs exactly T iterations (A13)
     w_cut_rel=1e-12,      # quotient edges below this fraction of the max weight are cut (A16)
     freq_merging=0,       # optional merging (Sec. 3.5) after every freq-th iteration; 0 off [5]
+    variant=0,            # 0 the component method; 1 the pixel-level log-depth baseline, ND form (A28)
 )
 
 
@@ -397,6 +398,8 @@ def edge_weights(e: Edges, ie: InterEdges, z, t, params):
     g2b = np.where(ie.horiz, g2h[ie.b], g2v[ie.b])
     Wab = g2b * sigmoid(g2b * (dm2 * dm2 - dp2 * dp2), k)
     wout = outlier_weight(r, params["out_L"], params["out_U"], params["outlier_mode"])
+    if t < params.get("out_from", 0):
+        wout = np.ones_like(wout)
     return (Wba + Wab) * wout, r
 
 
@@ -568,14 +571,33 @@ class Result:
     extra: dict = field(default_factory=dict)
 
 
+def baseline_params(p):
+    """The pixel-level log-depth baseline without discontinuity term (the ND
+    form of the method the paper compares with, Sec. 4, Table 1; reading
+    A28), as parameters of the same loop: every pixel its own node (no
+    continuous components, so every fill is 0 and z starts at 0); no
+    alignment phase, so the first iteration weighs each row by the BiNI
+    weight at z = 0, gamma^2 sigma_k(0) = gamma^2 / 2 (Eq. 5-7); the outlier
+    weights of Eq. 18 from the second iteration on (at z = 0 no residual
+    carries information).  Each iteration then solves the full pixel system
+    for the new log-depth, which is what solving for the increment of every
+    pixel's log-depth amounts to."""
+    q = dict(p)
+    q.update(theta_c_deg=0.0, align_iters=0, out_from=1, freq_merging=0)
+    return q
+
+
 def integrate(normals, mask, cam, params=None, labels_in=None, zfill_in=None) -> Result:
     """The whole path: edges -> components -> fill -> relative scales -> output.
 
     labels_in / zfill_in inject a partition or a fill (test hooks that mirror
-    the HIP library's staged entry points)."""
+    the HIP library's staged entry points).  variant = 1 runs the pixel-level
+    baseline instead (baseline_params)."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
+    if p.get("variant", 0) == 1:
+        p = baseline_params(p)
     e = edges(normals, mask, cam, p["theta_c_deg"])
     if labels_in is None:
         lab, K = labels(e)

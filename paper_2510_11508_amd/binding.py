@@ -35,7 +35,8 @@ class ni_params(C.Structure):
                 ("w_cut_rel", C.c_double), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
                 ("graphs", C.c_int32), ("fill_chunk", C.c_int32), ("fill_split", C.c_int32),
-                ("fill_precond", C.c_int32), ("fill_mg_maxit", C.c_int32), ("freq_merging", C.c_int32)]
+                ("fill_precond", C.c_int32), ("fill_mg_maxit", C.c_int32), ("freq_merging", C.c_int32),
+                ("variant", C.c_int32)]
 
 
 class ni_report(C.Structure):

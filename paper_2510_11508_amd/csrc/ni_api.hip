@@ -269,6 +269,7 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
   if (prm->outlier_mode < 0 || prm->outlier_mode > 2) return bad("outlier_mode must be 0, 1 or 2");
   if (!(prm->w_cut_rel >= 0 && prm->w_cut_rel < 1)) return bad("w_cut_rel must be in [0, 1)");
   if (prm->freq_merging < 0) return bad("freq_merging must be >= 0");
+  if (prm->variant != 0 && prm->variant != 1) return bad("variant must be 0 or 1");
   if (!(prm->bini_k > 0)) return bad("bini_k must be > 0");
   if (prm->fill_chunk != 0 && prm->fill_chunk != 512 && prm->fill_chunk != 1024 && prm->fill_chunk != 2048 &&
       prm->fill_chunk != 4096)
@@ -287,6 +288,14 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
   pb->P = H * W;
   pb->cam = *cam;
   pb->prm = *prm;
+  if (prm->variant == 1) {
+    // the pixel-level log-depth baseline (ND form): every pixel its own
+    // node, no alignment phase, no merging; outlier weights from the second
+    // iteration (set where the step parameters are formed)
+    pb->prm.theta_c_deg = 0.0;
+    pb->prm.align_iters = 0;
+    pb->prm.freq_merging = 0;
+  }
   return NI_OK;
 }
 
@@ -753,6 +762,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
   a.k = pb.prm.bini_k; a.L = pb.prm.out_L; a.U = pb.prm.out_U; a.cut_rel = pb.prm.w_cut_rel;
   a.q_rtol = pb.prm.q_rtol; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
+  a.out_from = pb.prm.variant == 1 ? 1 : 0;
   a.q_maxit = pb.prm.q_max_iter;
   a.host_flag = c->host + 32;
   // The quotient structure of a node labelling (the components, or merged
@@ -1004,6 +1014,7 @@ ni_status ni_params_default(ni_params* p) {
   p->graphs = 0;
   p->fill_chunk = 0;
   p->freq_merging = 0;
+  p->variant = 0;
   p->fill_split = 0;
   p->fill_precond = 1;
   p->fill_mg_maxit = 0;

@@ -219,6 +219,7 @@ struct IrlsArgs {
   double* epart;
   double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
   int align, outlier_mode, q_maxit, nnz;
+  int out_from;  // first iteration with outlier weights (the baseline: 1)
   int* qcol;
   double *qw, *t0, *t1;  // t0: flow-form residual, t1: correction [K]
   int* host_flag;

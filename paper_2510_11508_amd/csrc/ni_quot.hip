@@ -140,7 +140,7 @@ __global__ void k_fill_f64(double* a, int n, double v) {
 
 // ---------------------------------------------------------- per iteration
 struct EdgeParams {
-  int W, align, outlier_mode, t;
+  int W, align, outlier_mode, t, out_from;
   double g2fx, g2fy, k, lL, lU, U;
 };
 
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) k_irls_edges(
       const double tb = etb[i];
       const double g2b = g2f * (tb * tb);
       const double wab = g2b * sigmoid_k(g2b * (dm2 * dm2 - dp2 * dp2), q.k);
-      w = (wba + wab) * outlier_w(r, q);
+      w = (wba + wab) * (q.t >= q.out_from ? outlier_w(r, q) : 1.0);
     }
     ew[i] = w;
     erho[i] = (glabel[a] < glabel[b]) ? r : -r;  // oriented lo -> hi of the node pair
@@ -660,6 +660,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   EdgeParams q;
   q.W = a.W;
   q.align = a.align;
+  q.out_from = a.out_from;
   q.outlier_mode = a.outlier_mode;
   q.t = t;
   q.g2fx = a.g2fx;

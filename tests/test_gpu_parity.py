@@ -49,9 +49,13 @@ def params(**kw):
 
 
 def oracle_params(p):
-    return dict(theta_c_deg=p.theta_c_deg, irls_iters=p.irls_iters, align_iters=p.align_iters, bini_k=p.bini_k,
-                out_L=p.out_L, out_U=p.out_U, outlier_mode=p.outlier_mode, delta_e_max=p.delta_e_max,
-                w_cut_rel=p.w_cut_rel, freq_merging=p.freq_merging)
+    """The oracle's parameters for the library's; the baseline variant's
+    effective parameters are spelled out, so that every oracle stage (not
+    only integrate) runs the same loop."""
+    op = dict(theta_c_deg=p.theta_c_deg, irls_iters=p.irls_iters, align_iters=p.align_iters, bini_k=p.bini_k,
+              out_L=p.out_L, out_U=p.out_U, outlier_mode=p.outlier_mode, delta_e_max=p.delta_e_max,
+              w_cut_rel=p.w_cut_rel, freq_merging=p.freq_merging, variant=p.variant)
+    return O.baseline_params(op) if p.variant == 1 else op
 
 
 def assert_depth_close(d_gpu, d_ref, mask, what="", ortho=False):
@@ -469,6 +473,20 @@ def test_integrate_merging(ctx, name, seed, freq, T):
     assert rep["merges"] == (T - 1) // freq
     assert rep["nodes_final"] == (int(groups.max()) + 1 if groups.size else 0)
     check_whole_path(ctx, s, p, out, ref, f"merging {name} {seed} freq {freq}")
+
+
+@pytest.mark.parametrize("name,seed", [("tiny-persp", 1), ("c1", 0), ("c2", 0)])
+def test_logdepth_baseline_matches_oracle(ctx, name, seed):
+    """The pixel-level log-depth baseline, ND form (variant = 1, reading
+    A28): every pixel its own node, BiNI weights from z = 0, outlier weights
+    from the second iteration."""
+    s = sample(name, seed)
+    p = params(irls_iters=int(s.params["irls_iters"]), variant=1)
+    log(f"[baseline ND] {name} seed {seed}")
+    out = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+    ref = O.integrate(s.normals, s.mask, s.cam, oracle_params(p))
+    assert out["K"] == int((s.mask > 0).sum())
+    check_whole_path(ctx, s, p, out, ref, f"baseline {name} {seed}")
 
 
 def test_quotient_not_converged_is_reported(ctx):

@@ -432,3 +432,21 @@ def test_merging_after_the_last_step_changes_nothing():
     for f in (7, 50):
         S1, E1, _ = O.irls(e, lab, K, zf, dict(base, freq_merging=f))
         assert np.array_equal(S0, S1) and E0 == E1
+
+
+# ------------------------------------------------- pixel-level baseline ----
+@pytest.mark.parametrize("which,seed", [("tiny", 1), ("tiny", 2), ("tiny", 3), ("c1", 0)])
+def test_logdepth_baseline_equals_direct_solve(which, seed):
+    """The pixel-level log-depth baseline (ND form, reading A28) run through
+    the oracle's relative-scale loop (every pixel a node, increments) equals
+    a brute force that solves each iteration for the log-depth itself."""
+    s = synth.tiny(seed, 12, 14, "persp") if which == "tiny" else synth.make(which, seed)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=8, variant=1)
+    ref = O.integrate(s.normals, s.mask, s.cam, p)
+    zb, Eb = BF.logdepth_irls(s.normals, s.mask, s.cam.as_dict(), p)
+    v = s.mask > 0
+    assert ref.K == int(v.sum())
+    # two exact FP64 solves of the same pixel-level systems (weights spanning
+    # many decades on c1) agree to ~1e-9 of the unit-scale log-depth
+    assert np.max(np.abs(ref.logz[v] - _region_gauge(zb, v)[v])) < 1e-8
+    assert np.allclose(ref.energies, Eb, rtol=1e-9, atol=1e-14)
