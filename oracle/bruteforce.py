@@ -23,11 +23,14 @@ def _tau(cam, u, v):
 
 def pair_model(n, cam, a, b):
     """(usable, omega_{b->a}, gamma2_{b->a}, gamma2_{a->b}) of one neighbour
-    pair a=(u,v), b=(u',v') from the two-tangent-planes construction."""
+    pair a=(u,v), b=(u',v') from the two-tangent-planes construction; the
+    focal factor of gamma is fx along a row, fy along a column and
+    sqrt(fx fy) along a diagonal."""
     (ua, va), (ub, vb) = a, b
     na = n[va, ua].astype(np.float64)
     nb = n[vb, ub].astype(np.float64)
     horiz = va == vb
+    vert = ua == ub
     if cam["proj"] == "persp":
         ta = _tau(cam, ua, va)
         tb = _tau(cam, ub, vb)
@@ -39,8 +42,8 @@ def pair_model(n, cam, a, b):
             return False, 0.0, 0.0, 0.0
         # z_m from a's tangent plane equals z_m from b's: z_a daa/dam = z_b dbb/dbm
         om = math.log(dam / daa) - math.log(dbm / dbb)
-        f = cam["fx"] if horiz else cam["fy"]
-        return True, om, (f * daa) ** 2, (f * dbb) ** 2
+        f2 = cam["fx"] ** 2 if horiz else cam["fy"] ** 2 if vert else cam["fx"] * cam["fy"]
+        return True, om, f2 * daa ** 2, f2 * dbb ** 2
     if na[2] == 0 or nb[2] == 0:
         return False, 0.0, 0.0, 0.0
     s = cam["pixel_pitch"]
@@ -51,13 +54,18 @@ def pair_model(n, cam, a, b):
     return True, zm_from_b - zm_from_a, na[2] ** 2, nb[2] ** 2
 
 
-def neighbour_pairs(H, W):
+def neighbour_pairs(H, W, connectivity=4):
     for v in range(H):
         for u in range(W):
             if u + 1 < W:
                 yield (u, v), (u + 1, v)
             if v + 1 < H:
                 yield (u, v), (u, v + 1)
+            if connectivity == 8 and v + 1 < H:
+                if u + 1 < W:
+                    yield (u, v), (u + 1, v + 1)
+                if u >= 1:
+                    yield (u, v), (u - 1, v + 1)
 
 
 def closure_labels(H, W, valid, linked):
@@ -83,12 +91,12 @@ def closure_labels(H, W, valid, linked):
     return out, len(uniq)
 
 
-def model(normals, mask, cam, theta_c_deg):
+def model(normals, mask, cam, theta_c_deg, connectivity=4):
     H, W, _ = normals.shape
     valid = np.asarray(mask) != 0
     usable, similar = [], []
     info = {}
-    for a, b in neighbour_pairs(H, W):
+    for a, b in neighbour_pairs(H, W, connectivity):
         if not (valid[a[1], a[0]] and valid[b[1], b[0]]):
             continue
         ok, om, g2a, g2b = pair_model(normals, cam, a, b)
@@ -302,8 +310,8 @@ def irls_merging(normals, mask, cam, lab, K, zfill, params):
     per connected piece, and adds each component's increment to its pixels;
     every freq_merging-th step each current component picks its boundary
     edge of smallest |z_a - z_b - omega| counted in units of 2^-40 (equal
-    counts: smaller code 2 a + (0 right, 1 down), a the raster index of the
-    left / upper pixel), and
+    counts: smaller code 4 a + dir, dir 0 right, 1 down, 2 down-right, 3
+    down-left, a the raster index of the upper / left pixel), and
     the components joined by picked edges are relabelled as one (pixel
     labels rewritten through a plain union-find).  Returns the final
     log-depth [H, W] (0 off the labels) and the energies."""
@@ -324,10 +332,11 @@ def irls_merging(normals, mask, cam, lab, K, zfill, params):
         for u in range(W):
             if lab[v, u] < 0:
                 continue
-            for (du, dv) in ((1, 0), (0, 1)):
+            dirs = ((1, 0), (0, 1), (1, 1), (-1, 1)) if params.get("connectivity", 4) == 8 else ((1, 0), (0, 1))
+            for k, (du, dv) in enumerate(dirs):
                 b = (u + du, v + dv)
-                if b[0] < W and b[1] < H and lab[b[1], b[0]] >= 0 and pm((u, v), b)[0]:
-                    pairs.append(((u, v), b, 2 * (v * W + u) + (0 if du else 1)))
+                if 0 <= b[0] < W and b[1] < H and lab[b[1], b[0]] >= 0 and pm((u, v), b)[0]:
+                    pairs.append(((u, v), b, 4 * (v * W + u) + k))
     usable = set((a, b) for a, b, _ in pairs)
 
     def edge_ok(p, q):
@@ -433,7 +442,8 @@ def logdepth_irls(normals, mask, cam, params):
                 pix[(u, v)] = len(pix)
     pairs = []
     for (u, v) in pix:
-        for (du, dv) in ((1, 0), (0, 1)):
+        dirs = ((1, 0), (0, 1), (1, 1), (-1, 1)) if params.get("connectivity", 4) == 8 else ((1, 0), (0, 1))
+        for (du, dv) in dirs:
             b = (u + du, v + dv)
             if b in pix and pm((u, v), b)[0]:
                 pairs.append(((u, v), b))

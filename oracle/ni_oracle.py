@@ -50,6 +50,7 @@ DEFAULT_PARAMS = dict(
     w_cut_rel=1e-12,      # quotient edges below this fraction of the max weight are cut (A16)
     freq_merging=0,       # optional merging (Sec. 3.5) after every freq-th iteration; 0 off [5]
     variant=0,            # 0 the component method; 1 the pixel-level log-depth baseline, ND form (A28)
+    connectivity=4,       # 4 or 8 neighbours (A21, A29) [8]
 )
 
 
@@ -71,6 +72,27 @@ class Edges:
     omega_d: np.ndarray     # f64 [H, W]       omega_{b->a} for b = lower neighbour
     g2_h: np.ndarray        # f64 [H, W]       gamma^2 of horizontal rows ending at the pixel
     g2_v: np.ndarray        # f64 [H, W]       gamma^2 of vertical rows ending at the pixel
+    # 8-connectivity (A29): edge (u,v)-(u+1,v+1) ("dr") and (u,v)-(u-1,v+1)
+    # ("dl"); all False / 0 with 4-connectivity
+    valid_dr: np.ndarray = None
+    valid_dl: np.ndarray = None
+    sim_dr: np.ndarray = None
+    sim_dl: np.ndarray = None
+    omega_dr: np.ndarray = None
+    omega_dl: np.ndarray = None
+    g2_x: np.ndarray = None  # f64 [H, W]       gamma^2 of diagonal rows ending at the pixel
+    conn: int = 4
+
+    def directions(self):
+        """(dir, du, dv, usable, similar, omega, gamma^2 per pixel) of every
+        edge direction owned by the upper / left end: 0 right, 1 down, and
+        with 8-connectivity 2 down-right, 3 down-left."""
+        out = [(0, 1, 0, self.valid_r, self.sim_r, self.omega_r, self.g2_h),
+               (1, 0, 1, self.valid_d, self.sim_d, self.omega_d, self.g2_v)]
+        if self.conn == 8:
+            out += [(2, 1, 1, self.valid_dr, self.sim_dr, self.omega_dr, self.g2_x),
+                    (3, -1, 1, self.valid_dl, self.sim_dl, self.omega_dl, self.g2_x)]
+        return out
 
 
 def ray_tables(cam, H, W):
@@ -102,7 +124,7 @@ class _Cam:
         self.pixel_pitch = float(_cam_get(cam, "pixel_pitch"))
 
 
-def edges(normals, mask, cam, theta_c_deg) -> Edges:
+def edges(normals, mask, cam, theta_c_deg, connectivity=4) -> Edges:
     """Per-edge quantities of the model of continuity (Sec. 3.1).
 
     Perspective (Eq. 3): with the four dot products d_aa = n_a.tau_a,
@@ -194,25 +216,102 @@ def edges(normals, mask, cam, theta_c_deg) -> Edges:
         sd[:-1, :] = vd[:-1, :] & (dot_d > cth)
     g2h = np.where(valid, g2h, 0.0)
     g2v = np.where(valid, g2v, 0.0)
-    return Edges(H, W, cam.proj, valid, vr, vd, sr, sd, om_r, om_d, g2h, g2v)
+    e = Edges(H, W, cam.proj, valid, vr, vd, sr, sd, om_r, om_d, g2h, g2v)
+    z = np.zeros((H, W), bool)
+    e.valid_dr, e.valid_dl, e.sim_dr, e.sim_dl = z, z.copy(), z.copy(), z.copy()
+    e.omega_dr, e.omega_dl, e.g2_x = np.zeros((H, W)), np.zeros((H, W)), np.zeros((H, W))
+    if connectivity == 8:
+        _diagonal_edges(e, nx, ny, nz, cam, theta_c_deg)
+    elif connectivity != 4:
+        raise ValueError("connectivity must be 4 or 8")
+    return e
 
 
-def _grid_graph(e: Edges, use_r, use_d):
-    """Sparse symmetric adjacency over the H*W raster indices."""
+def _diagonal_edges(e: Edges, nx, ny, nz, cam, theta_c_deg):
+    """Diagonal edges of 8-connectivity (reading A29): the same model of
+    continuity with the interpolating subpixel at the midpoint of the two
+    pixel centres (A2), i.e. the ray (u + 1/2, v + 1/2) for a = (u, v) and
+    b = (u+1, v+1), and (u - 1/2, v + 1/2) for b = (u-1, v+1); gamma =
+    f n_a.tau_a with f^2 = fx fy (the geometric mean of the two focal
+    lengths, A4's choice for each axis); orthographic: A1 with (du, dv) =
+    (+-1, 1) and gamma = n_z.  Similarity and usability as for the axis
+    edges."""
+    H, W = e.H, e.W
+    valid = e.valid
+    vdr = np.zeros((H, W), bool)
+    vdl = np.zeros((H, W), bool)
+    vdr[:-1, :-1] = valid[:-1, :-1] & valid[1:, 1:]
+    vdl[:-1, 1:] = valid[:-1, 1:] & valid[1:, :-1]
+    om_dr = np.zeros((H, W))
+    om_dl = np.zeros((H, W))
+    if cam.proj == "persp":
+        tx, ty, txm, tym = ray_tables(cam, H, W)
+        TX, TY = tx[None, :], ty[:, None]
+        nt = (nx * TX + ny * TY) + nz
+        # down-right: a = [:-1, :-1], b = [1:, 1:], midpoint ray (txm[u], tym[v])
+        dam = (nx[:-1, :-1] * txm[None, :-1] + ny[:-1, :-1] * tym[:-1, None]) + nz[:-1, :-1]
+        dbm = (nx[1:, 1:] * txm[None, :-1] + ny[1:, 1:] * tym[:-1, None]) + nz[1:, 1:]
+        daa, dbb = nt[:-1, :-1], nt[1:, 1:]
+        ok = (daa != 0) & (dam != 0) & (dbb != 0) & (dbm != 0) \
+            & ((daa > 0) == (dam > 0)) & ((dbb > 0) == (dbm > 0))
+        vdr[:-1, :-1] &= ok
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_dr[:-1, :-1] = np.where(vdr[:-1, :-1], np.log((dam / daa) * (dbb / dbm)), 0.0)
+        # down-left: a = [:-1, 1:] (u >= 1), b = [1:, :-1], midpoint ray (txm[u-1], tym[v])
+        dam = (nx[:-1, 1:] * txm[None, :-1] + ny[:-1, 1:] * tym[:-1, None]) + nz[:-1, 1:]
+        dbm = (nx[1:, :-1] * txm[None, :-1] + ny[1:, :-1] * tym[:-1, None]) + nz[1:, :-1]
+        daa, dbb = nt[:-1, 1:], nt[1:, :-1]
+        ok = (daa != 0) & (dam != 0) & (dbb != 0) & (dbm != 0) \
+            & ((daa > 0) == (dam > 0)) & ((dbb > 0) == (dbm > 0))
+        vdl[:-1, 1:] &= ok
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_dl[:-1, 1:] = np.where(vdl[:-1, 1:], np.log((dam / daa) * (dbb / dbm)), 0.0)
+        g2x = (cam.fx * cam.fy) * nt ** 2
+    else:
+        s = cam.pixel_pitch
+        okz = nz != 0
+        vdr[:-1, :-1] &= okz[:-1, :-1] & okz[1:, 1:]
+        vdl[:-1, 1:] &= okz[:-1, 1:] & okz[1:, :-1]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_dr[:-1, :-1] = np.where(vdr[:-1, :-1], s * ((nx[:-1, :-1] + ny[:-1, :-1]) / (2.0 * nz[:-1, :-1])
+                                                         + (nx[1:, 1:] + ny[1:, 1:]) / (2.0 * nz[1:, 1:])), 0.0)
+            om_dl[:-1, 1:] = np.where(vdl[:-1, 1:], s * ((-nx[:-1, 1:] + ny[:-1, 1:]) / (2.0 * nz[:-1, 1:])
+                                                       + (-nx[1:, :-1] + ny[1:, :-1]) / (2.0 * nz[1:, :-1])), 0.0)
+        g2x = nz ** 2
+    sdr = np.zeros((H, W), bool)
+    sdl = np.zeros((H, W), bool)
+    if theta_c_deg > 0:
+        cth = math.cos(theta_c_deg * math.pi / 180.0)
+        dot_dr = (nx[:-1, :-1] * nx[1:, 1:] + ny[:-1, :-1] * ny[1:, 1:]) + nz[:-1, :-1] * nz[1:, 1:]
+        dot_dl = (nx[:-1, 1:] * nx[1:, :-1] + ny[:-1, 1:] * ny[1:, :-1]) + nz[:-1, 1:] * nz[1:, :-1]
+        sdr[:-1, :-1] = vdr[:-1, :-1] & (dot_dr > cth)
+        sdl[:-1, 1:] = vdl[:-1, 1:] & (dot_dl > cth)
+    e.valid_dr, e.valid_dl, e.sim_dr, e.sim_dl = vdr, vdl, sdr, sdl
+    e.omega_dr, e.omega_dl = om_dr, om_dl
+    e.g2_x = np.where(valid, g2x, 0.0)
+    e.conn = 8
+
+
+def _grid_graph(e: Edges, masks):
+    """Sparse adjacency over the H*W raster indices; masks[k] flags the
+    edges of direction k (0 right, 1 down, 2 down-right, 3 down-left) at
+    their upper / left end."""
     H, W = e.H, e.W
     idx = np.arange(H * W).reshape(H, W)
-    a = np.concatenate([idx[use_r], idx[use_d]])
-    b = np.concatenate([idx[use_r] + 1, idx[use_d] + W])
+    step = {0: 1, 1: W, 2: W + 1, 3: W - 1}
+    a = np.concatenate([idx[m] for m in masks])
+    b = np.concatenate([idx[m] + step[k] for k, m in enumerate(masks)])
     G = sp.coo_matrix((np.ones(a.size), (a, b)), shape=(H * W, H * W))
     return G
 
 
-def canonical_components(e: Edges, use_r, use_d):
-    """Connected components of the valid pixels over the given edges,
-    numbered by ascending minimum raster index (A20); -1 off the mask."""
+def canonical_components(e: Edges, masks):
+    """Connected components of the valid pixels over the given edges (one
+    mask per direction), numbered by ascending minimum raster index (A20);
+    -1 off the mask."""
     H, W = e.H, e.W
     N = H * W
-    ncomp, lab = connected_components(_grid_graph(e, use_r, use_d), directed=False)
+    ncomp, lab = connected_components(_grid_graph(e, masks), directed=False)
     valid = e.valid.ravel()
     roots = np.full(ncomp, N, dtype=np.int64)
     pix = np.arange(N)
@@ -228,12 +327,12 @@ def canonical_components(e: Edges, use_r, use_d):
 def labels(e: Edges):
     """Continuous components (Sec. 3.3): connected components of the
     subgraph of G_0 keeping only edges with theta_ab < theta_c."""
-    return canonical_components(e, e.sim_r, e.sim_d)
+    return canonical_components(e, [d[4] for d in e.directions()])
 
 
 def regions(e: Edges):
     """Connected regions of G_0 itself (all usable edges)."""
-    return canonical_components(e, e.valid_r, e.valid_d)
+    return canonical_components(e, [d[3] for d in e.directions()])
 
 
 def _intra_system(e: Edges, lab):
@@ -246,21 +345,23 @@ def _intra_system(e: Edges, lab):
     H, W = e.H, e.W
     N = H * W
     idx = np.arange(N).reshape(H, W)
-    L = lab
-    in_r = e.valid_r.copy()
-    in_r[:, :-1] &= L[:, :-1] == L[:, 1:]
-    in_d = e.valid_d.copy()
-    in_d[:-1, :] &= L[:-1, :] == L[1:, :]
-    a_r = idx[in_r]
-    a_d = idx[in_d]
-    g2h = e.g2_h.ravel()
-    g2v = e.g2_v.ravel()
-    w_r = 0.5 * g2h[a_r] + 0.5 * g2h[a_r + 1]
-    w_d = 0.5 * g2v[a_d] + 0.5 * g2v[a_d + W]
-    a = np.concatenate([a_r, a_d])
-    b = np.concatenate([a_r + 1, a_d + W])
-    w = np.concatenate([w_r, w_d])
-    om = np.concatenate([e.omega_r[in_r], e.omega_d[in_d]])
+    labf = lab.ravel()
+    step = {0: 1, 1: W, 2: W + 1, 3: W - 1}
+    aa, bb, ww, oo = [], [], [], []
+    for k, du, dv, usable, _, omega, g2 in e.directions():
+        ai = idx[usable]
+        bi = ai + step[k]
+        inside = labf[ai] == labf[bi]
+        ai, bi = ai[inside], bi[inside]
+        g2f = g2.ravel()
+        aa.append(ai)
+        bb.append(bi)
+        ww.append(0.5 * g2f[ai] + 0.5 * g2f[bi])
+        oo.append(omega[usable][inside])
+    a = np.concatenate(aa)
+    b = np.concatenate(bb)
+    w = np.concatenate(ww)
+    om = np.concatenate(oo)
     Lap = sp.coo_matrix((np.concatenate([w, w, -w, -w]),
                          (np.concatenate([a, b, a, b]), np.concatenate([a, b, b, a]))),
                         shape=(N, N)).tocsr()
@@ -311,29 +412,37 @@ def fill(e: Edges, lab, K):
 
 @dataclass
 class InterEdges:
-    a: np.ndarray       # raster index of the left / upper pixel
-    b: np.ndarray       # raster index of the right / lower pixel
-    horiz: np.ndarray   # bool: b = a + 1 (else b = a + W)
+    a: np.ndarray       # raster index of the upper / left pixel
+    b: np.ndarray       # raster index of the other end
+    dir: np.ndarray     # 0 right (b = a+1), 1 down (a+W), 2 down-right (a+W+1), 3 down-left (a+W-1)
     omega: np.ndarray   # omega_{b->a}
     c: np.ndarray       # pi(a)
     d: np.ndarray       # pi(b)
+
+    @property
+    def code(self):
+        """Edge code 4 a + dir (the order of the merge tie-break, A27)."""
+        return 4 * self.a + self.dir
 
 
 def inter_edges(e: Edges, lab) -> InterEdges:
     """E_inter (Eq. 9): usable edges whose ends lie in different components."""
     H, W = e.H, e.W
     idx = np.arange(H * W).reshape(H, W)
-    L = lab
-    xr = e.valid_r.copy()
-    xr[:, :-1] &= L[:, :-1] != L[:, 1:]
-    xd = e.valid_d.copy()
-    xd[:-1, :] &= L[:-1, :] != L[1:, :]
-    a = np.concatenate([idx[xr], idx[xd]])
-    horiz = np.concatenate([np.ones(int(xr.sum()), bool), np.zeros(int(xd.sum()), bool)])
-    b = np.where(horiz, a + 1, a + W)
-    om = np.concatenate([e.omega_r[xr], e.omega_d[xd]])
-    lf = L.ravel()
-    return InterEdges(a, b, horiz, om, lf[a].astype(np.int64), lf[b].astype(np.int64))
+    labf = lab.ravel()
+    step = {0: 1, 1: W, 2: W + 1, 3: W - 1}
+    aa, dd, oo = [], [], []
+    for k, du, dv, usable, _, omega, g2 in e.directions():
+        ai = idx[usable]
+        x = labf[ai] != labf[ai + step[k]]
+        aa.append(ai[x])
+        dd.append(np.full(int(x.sum()), k, dtype=np.int64))
+        oo.append(omega[usable][x])
+    a = np.concatenate(aa)
+    dirs = np.concatenate(dd)
+    b = a + np.array([1, W, W + 1, W - 1], dtype=np.int64)[dirs]
+    om = np.concatenate(oo)
+    return InterEdges(a, b, dirs, om, labf[a].astype(np.int64), labf[b].astype(np.int64))
 
 
 def sigmoid(x, k=1.0):
@@ -376,26 +485,26 @@ def edge_weights(e: Edges, ie: InterEdges, z, t, params):
     if t < params["align_iters"]:
         return np.full(r.size, 2.0), r
     k = params["bini_k"]
-    vr = e.valid_r.ravel()
-    vd = e.valid_d.ravel()
-    g2h = e.g2_h.ravel()
-    g2v = e.g2_v.ravel()
-    step = np.where(ie.horiz, 1, W)
-    # row b -> a: opposite pixel -b = a - step, edge (a - step, a)
-    ma = ie.a - step
-    has_ma = np.where(ie.horiz, (ie.a % W) > 0, ie.a >= W)
-    ma_c = np.where(has_ma, ma, 0)
-    ok_ma = has_ma & np.where(ie.horiz, vr[ma_c], vd[ma_c])
-    dm = np.where(ok_ma, zf[ma_c] - zf[ie.a], 0.0)
+    dirs = e.directions()
+    usable = np.stack([d[3].ravel() for d in dirs] + [np.zeros(H * W, bool)] * (4 - len(dirs)))
+    g2 = np.stack([d[6].ravel() for d in dirs] + [np.zeros(H * W)] * (4 - len(dirs)))
+    step = np.array([1, W, W + 1, W - 1], dtype=np.int64)[ie.dir]
+    ua, va = ie.a % W, ie.a // W
+    # row b -> a: opposite pixel -b = a - step, edge (a - step, a) of the same direction
+    has_ma = np.select([ie.dir == 0, ie.dir == 1, ie.dir == 2], [ua > 0, va > 0, (ua > 0) & (va > 0)],
+                       (ua < W - 1) & (va > 0))
+    ma = np.where(has_ma, ie.a - step, 0)
+    ok_ma = has_ma & usable[ie.dir, ma]
+    dm = np.where(ok_ma, zf[ma] - zf[ie.a], 0.0)
     dp = zf[ie.b] - zf[ie.a]
-    g2a = np.where(ie.horiz, g2h[ie.a], g2v[ie.a])
+    g2a = g2[ie.dir, ie.a]
     Wba = g2a * sigmoid(g2a * (dm * dm - dp * dp), k)
     # row a -> b: opposite pixel -a = b + step, edge (b, b + step)
-    ok_pb = np.where(ie.horiz, vr[ie.b], vd[ie.b])
+    ok_pb = usable[ie.dir, ie.b]
     pb = np.where(ok_pb, ie.b + step, 0)
     dm2 = np.where(ok_pb, zf[pb] - zf[ie.b], 0.0)
     dp2 = zf[ie.a] - zf[ie.b]
-    g2b = np.where(ie.horiz, g2h[ie.b], g2v[ie.b])
+    g2b = g2[ie.dir, ie.b]
     Wab = g2b * sigmoid(g2b * (dm2 * dm2 - dp2 * dp2), k)
     wout = outlier_weight(r, params["out_L"], params["out_U"], params["outlier_mode"])
     if t < params.get("out_from", 0):
@@ -440,7 +549,8 @@ def merge_groups(ie: InterEdges, r, grp):
     with the smallest residual magnitude |chi| = |r_e| at the current
     log-depth.  Magnitudes are compared on a grid of 2^-40 (~9.1e-13 in
     log-depth units), and equal grid values go to the smaller edge code
-    2 a + (0 right, 1 down) (reading A27): after the uniform-weight
+    4 a + dir (dir 0 right, 1 down, 2 down-right, 3 down-left; reading A27):
+    after the uniform-weight
     alignment every bridge of the quotient graph has a residual that is
     zero in exact arithmetic, so FP64 rounding alone would otherwise decide
     between them.  (ii) The selected edges form a subgraph of Q_m
@@ -450,7 +560,7 @@ def merge_groups(ie: InterEdges, r, grp):
     gc, gd = grp[ie.c], grp[ie.d]
     live = gc != gd
     Kg = int(grp.max()) + 1 if grp.size else 0
-    code = 2 * ie.a + np.where(ie.horiz, 0, 1)
+    code = ie.code
     best = np.full(Kg, -1, dtype=np.int64)
     idx = np.flatnonzero(live)
     # smallest |r| on the 2^-40 grid, then smallest code, per group end
@@ -513,7 +623,7 @@ def irls(e: Edges, lab, K, zfill, params=None, S0=None, t0=0, trace=None):
             pos = w[w > 0]
             margin = min(margin, float(np.min(np.abs(np.log10(pos / (p["w_cut_rel"] * w.max()))))))
         Kg = int(grp.max()) + 1 if K else 0
-        ieg = InterEdges(ie.a, ie.b, ie.horiz, ie.omega, grp[ie.c], grp[ie.d])
+        ieg = InterEdges(ie.a, ie.b, ie.dir, ie.omega, grp[ie.c], grp[ie.d])
         sg, E, _ = quotient_step(ieg, Kg, w, r, p["w_cut_rel"])
         s = sg[grp] if K else sg
         if trace is not None:
@@ -598,7 +708,7 @@ def integrate(normals, mask, cam, params=None, labels_in=None, zfill_in=None) ->
         p.update(params)
     if p.get("variant", 0) == 1:
         p = baseline_params(p)
-    e = edges(normals, mask, cam, p["theta_c_deg"])
+    e = edges(normals, mask, cam, p["theta_c_deg"], p.get("connectivity", 4))
     if labels_in is None:
         lab, K = labels(e)
     else:

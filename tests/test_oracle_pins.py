@@ -357,9 +357,9 @@ def test_generator_deterministic():
 
 
 # --------------------------------------------------------------- merging ----
-def _region_gauge(z, v):
+def _region_gauge(z, v, conn=4):
     from scipy import ndimage
-    reg, R = ndimage.label(v)
+    reg, R = ndimage.label(v, structure=np.ones((3, 3)) if conn == 8 else None)
     z = z.copy()
     for r in range(1, R + 1):
         z[reg == r] -= z[reg == r].mean()
@@ -402,7 +402,7 @@ def test_merge_selection_and_halving():
     r = z[ie.a] - z[ie.b] - ie.omega
     grp0 = np.arange(K)
     new = O.merge_groups(ie, r, grp0)
-    code = 2 * ie.a + np.where(ie.horiz, 0, 1)
+    code = ie.code
     for g in range(K):
         inc = np.flatnonzero((ie.c == g) | (ie.d == g))
         if inc.size == 0:
@@ -449,4 +449,125 @@ def test_logdepth_baseline_equals_direct_solve(which, seed):
     # two exact FP64 solves of the same pixel-level systems (weights spanning
     # many decades on c1) agree to ~1e-9 of the unit-scale log-depth
     assert np.max(np.abs(ref.logz[v] - _region_gauge(zb, v)[v])) < 1e-8
+    assert np.allclose(ref.energies, Eb, rtol=1e-9, atol=1e-14)
+
+
+# --------------------------------------------------------- 8-connectivity ----
+def _dir_of(a, b):
+    du, dv = b[0] - a[0], b[1] - a[1]
+    return {(1, 0): 0, (0, 1): 1, (1, 1): 2, (-1, 1): 3}[(du, dv)]
+
+
+@pytest.mark.parametrize("proj", ["persp", "ortho"])
+def test_edges8_match_bruteforce_pairs(proj):
+    """Diagonal edges (reading A29): usability, omega and gamma^2 of every
+    pair equal the scalar two-tangent-planes model with the midpoint ray and
+    f^2 = fx fy."""
+    s = synth.tiny(2, 11, 13, proj=proj, noise=0.03)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0, connectivity=8)
+    valid, usable, similar, info = BF.model(s.normals, s.mask, s.cam.as_dict(), 2.0, connectivity=8)
+    H, W = s.mask.shape
+    dirs = e.directions()
+    flags = [np.zeros((H, W), bool) for _ in range(4)]
+    simf = [np.zeros((H, W), bool) for _ in range(4)]
+    for (a, b) in usable:
+        flags[_dir_of(a, b)][a[1], a[0]] = True
+    for (a, b) in similar:
+        simf[_dir_of(a, b)][a[1], a[0]] = True
+    for k, du, dv, use, sim, om, g2 in dirs:
+        assert np.array_equal(flags[k], use), k
+        assert np.array_equal(simf[k], sim), k
+    for (a, b), (om, g2a, g2b) in info.items():
+        k, _, _, _, _, omk, g2k = dirs[_dir_of(a, b)]
+        assert abs(omk[a[1], a[0]] - om) < 1e-13
+        assert abs(g2k[a[1], a[0]] - g2a) <= 1e-12 * g2a
+        assert abs(g2k[b[1], b[0]] - g2b) <= 1e-12 * g2b
+
+
+def test_diagonal_omega_exact_on_planes_and_quadrics():
+    """The diagonal model of continuity is exact where the axis one is: a
+    perspective plane, and (orthographic) any quadratic height field."""
+    n, m, z, cam = synth.plane_persp(16, 20, 30.0, [0.2, 0.1, -1.0], 3.0)
+    e = O.edges(n, m, cam, 2.0, connectivity=8)
+    lz = np.log(z)
+    assert e.valid_dr[:-1, :-1].all() and e.valid_dl[:-1, 1:].all()
+    assert np.max(np.abs(e.omega_dr[:-1, :-1] - (lz[:-1, :-1] - lz[1:, 1:]))) < 1e-6
+    assert np.max(np.abs(e.omega_dl[:-1, 1:] - (lz[:-1, 1:] - lz[1:, :-1]))) < 1e-6
+    n, m, z, cam = synth.quadric_ortho(14, 17, (0.01, -0.02, 0.015, 0.1, -0.2, 3.0))
+    e = O.edges(n.astype(np.float64), m, cam, 2.0, connectivity=8)
+    assert np.max(np.abs(e.omega_dr[:-1, :-1] - (z[:-1, :-1] - z[1:, 1:]))) < 1e-12
+    assert np.max(np.abs(e.omega_dl[:-1, 1:] - (z[:-1, 1:] - z[1:, :-1]))) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_labels8_match_transitive_closure(seed):
+    proj = "persp" if seed % 2 else "ortho"
+    s = synth.tiny(seed, proj=proj)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0, connectivity=8)
+    lab, K = O.labels(e)
+    valid, usable, similar, info = BF.model(s.normals, s.mask, s.cam.as_dict(), 2.0, connectivity=8)
+    ref, Kr = BF.closure_labels(*s.mask.shape, valid, similar)
+    assert K == Kr and np.array_equal(lab, ref)
+
+
+def test_labels8_theta_180_is_mask_8_connectivity():
+    s = synth.tiny(4, 12, 12, "persp", noise=0.0, step=0.0)
+    e = O.edges(s.normals, s.mask, s.cam, 180.0, connectivity=8)
+    lab, K = O.labels(e)
+    ref, nref = ndimage.label(s.mask, structure=np.ones((3, 3)))
+    assert K == nref and np.array_equal(lab, ref - 1)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_fill8_matches_dense_rows(seed):
+    proj = "persp" if seed % 2 == 0 else "ortho"
+    s = synth.tiny(seed, proj=proj, noise=0.02)
+    e = O.edges(s.normals, s.mask, s.cam, 2.0, connectivity=8)
+    lab, K = O.labels(e)
+    z = O.fill(e, lab, K)
+    valid, usable, similar, info = BF.model(s.normals, s.mask, s.cam.as_dict(), 2.0, connectivity=8)
+    zr = BF.fill_rows(s.normals, s.mask, s.cam.as_dict(), lab, info)
+    v = s.mask > 0
+    assert np.max(np.abs(z[v] - zr[v])) < 1e-10
+
+
+@pytest.mark.parametrize("seed,mode", [(0, 1), (1, 1), (2, 2)])
+def test_irls8_matches_dense_rows(seed, mode):
+    proj = "persp" if seed % 2 == 0 else "ortho"
+    s = synth.tiny(seed, proj=proj, noise=0.01)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=6, outlier_mode=mode, connectivity=8)
+    if proj == "ortho":
+        p["bini_k"] = 50.0
+    e = O.edges(s.normals, s.mask, s.cam, 2.0, connectivity=8)
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    S, En, _ = O.irls(e, lab, K, zf, p)
+    valid, usable, similar, info = BF.model(s.normals, s.mask, s.cam.as_dict(), 2.0, connectivity=8)
+    Sr, Er = BF.irls_rows(s.normals, s.mask, s.cam.as_dict(), lab, K, zf, usable, info, p)
+    assert np.max(np.abs(S - Sr)) < 1e-8
+    assert np.allclose(En, Er, rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("which,seed,freq", [("tiny", 1, 3), ("c1", 0, 4)])
+def test_merging8_equals_bruteforce(which, seed, freq):
+    s = synth.tiny(seed, 12, 14, "persp") if which == "tiny" else synth.make(which, seed)
+    p = dict(O.DEFAULT_PARAMS, irls_iters=9, freq_merging=freq, connectivity=8)
+    e = O.edges(s.normals, s.mask, s.cam, p["theta_c_deg"], connectivity=8)
+    lab, K = O.labels(e)
+    zf = O.fill(e, lab, K)
+    S, En, _ = O.irls(e, lab, K, zf, p)
+    v = lab >= 0
+    zo = np.where(v, zf + S[np.maximum(lab, 0)], 0.0)
+    zb, Eb = BF.irls_merging(s.normals, s.mask, s.cam.as_dict(), lab, K, zf, p)
+    assert np.max(np.abs(_region_gauge(zo, v, 8) - _region_gauge(zb, v, 8))[v]) < 1e-9
+    assert np.allclose(En, Eb, rtol=1e-8, atol=1e-14)
+
+
+def test_baseline8_equals_direct_solve():
+    s = synth.tiny(2, 12, 14, "persp")
+    p = dict(O.DEFAULT_PARAMS, irls_iters=6, variant=1, connectivity=8)
+    ref = O.integrate(s.normals, s.mask, s.cam, p)
+    zb, Eb = BF.logdepth_irls(s.normals, s.mask, s.cam.as_dict(), p)
+    v = s.mask > 0
+    assert np.max(np.abs(ref.logz[v] - _region_gauge(zb, v, p.get("connectivity", 4))[v])) < 1e-8
     assert np.allclose(ref.energies, Eb, rtol=1e-9, atol=1e-14)
