@@ -66,7 +66,11 @@ typedef struct {
 typedef struct {
   double theta_c_deg;   /* similarity threshold theta_c (Sec. 3.3); <= 0 means
                            every pixel is its own component (theta_c = None)  */
-  int32_t connectivity; /* 4 (only supported value)                           */
+  int32_t connectivity; /* 4, or 8: the diagonal neighbours join the pixel
+                           graph too, each diagonal edge modelled with its
+                           subpixel at the midpoint of the two pixel centres
+                           and f^2 = fx * fy (Sec. 3.1 names 4- and
+                           8-connectivity); edge codes are 4 a + direction  */
   int32_t irls_iters;   /* T: relative-scale iterations (1..NI_MAX_IRLS)      */
   int32_t align_iters;  /* leading uniform-weight iterations (Alg. 1: 2)      */
   double bini_k;        /* sharpness k of the BiNI sigmoid (Eq. 5)            */

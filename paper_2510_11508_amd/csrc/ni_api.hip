@@ -13,13 +13,13 @@
 namespace nil {
 // ni_setup.hip
 hipError_t launch_setup(const float*, const uint8_t*, int, int, int, double, const double*, double, int,
-                        uint8_t*, float*, float*, float*, int*, hipStream_t);
+                        uint8_t*, float*, float*, float*, int*, hipStream_t, uint8_t*, float*, float*);
 hipError_t launch_inter_geom(const uint32_t*, int, int, int, const float*, int, double, const double*, double*,
                              double*, double*, hipStream_t);
 hipError_t set_i32(int*, int, int, hipStream_t);
 hipError_t ray_tables(int, int, double, double, double, double, double*, hipStream_t);
 hipError_t grid_components(const uint8_t*, int, int, uint8_t, uint8_t, int*, int*, int*, int*, int*, int*,
-                           hipStream_t);
+                           hipStream_t, const uint8_t*, uint8_t, uint8_t);
 // ni_fill.hip
 int fill_small_cap();
 int fill_chunk();
@@ -46,9 +46,17 @@ hipError_t mg_build(int, int, const float4*, const float*, const float*, const u
                     const int*, const int*, int*, double*, double*, int*, int*, double*, int*, int*, int*, double*,
                     double*, hipStream_t);
 hipError_t mg_out(int, const uint32_t*, const int*, const double*, float*, hipStream_t);
+hipError_t fill8_count(int, int, const uint32_t*, const uint32_t*, const int*, const int*, const uint8_t*,
+                       const uint8_t*, int*, int*, hipStream_t);
+hipError_t fill8_build(int, int, const uint32_t*, const uint32_t*, const int*, const int*, const uint8_t*,
+                       const uint8_t*, const float*, const float* const*, const int*, double, double, double,
+                       const int*, const int*, const float*, int*, double*, double*, int*, int*, double*, int*, int*,
+                       int*, double*, double*, hipStream_t);
+hipError_t fill8_out(int, int, const uint32_t*, const uint32_t*, const int*, const double*, double*, int*, float*,
+                     hipStream_t);
 // ni_quot.hip
-hipError_t quot_inter_edges(const int*, const uint8_t*, int, int, int*, int*, int*, uint32_t*, int*, hipStream_t,
-                            int);
+hipError_t quot_inter_edges(const int*, const uint8_t*, const uint8_t*, int, int, int*, int*, int*, uint32_t*, int*,
+                            hipStream_t, int);
 hipError_t quot_sort_edges(uint32_t*, int, int, int, const int*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
                            uint32_t*, int*, int*, int*, int*, hipStream_t);
 hipError_t quot_pairs(const uint32_t*, const int*, const int*, int, int, const int*, int, int*, int*, int*,
@@ -131,6 +139,7 @@ struct ni_ctx {
   std::vector<Buf*> bufs;
   // grid
   Buf ebits, om_r, om_d, nt, parent, flag, scanv, pos, zgrid, tab, xwarm;
+  Buf eb2, om_dr, om_dl;  // diagonal edges (8-connectivity)
   // compact / sort
   Buf key, val, skey, spix, ktmp, vtmp, kout2, cst, rhs, dinv, x, r, z, p0, p1, q, w0, w1, s0, s1;
   // components
@@ -160,7 +169,7 @@ struct ni_ctx {
 
 
   ni_ctx() {
-    Buf* all[] = {&ebits, &om_r, &om_d, &nt, &parent, &flag, &scanv, &pos, &zgrid, &tab, &xwarm, &key, &val,
+    Buf* all[] = {&ebits, &om_r, &om_d, &nt, &eb2, &om_dr, &om_dl, &parent, &flag, &scanv, &pos, &zgrid, &tab, &xwarm, &key, &val,
                   &skey, &spix, &ktmp, &vtmp, &kout2, &cst, &rhs, &dinv, &x, &r, &z, &p0,
                   &p1, &q, &w0, &w1, &s0, &s1, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
                   &cnt, &done, &iters, &active, &rho, &bb, &tol2, &beta, &rr, &relres, &S, &qs,
@@ -260,7 +269,7 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
   if (cam->proj == NI_PERSP && !(cam->fx > 0 && cam->fy > 0 && isfinite(cam->cx) && isfinite(cam->cy)))
     return bad("perspective camera needs fx, fy > 0 and finite cx, cy");
   if (cam->proj == NI_ORTHO && !(cam->pixel_pitch > 0)) return bad("orthographic camera needs pixel_pitch > 0");
-  if (prm->connectivity != 4) return bad("only 4-connectivity is supported");
+  if (prm->connectivity != 4 && prm->connectivity != 8) return bad("connectivity must be 4 or 8");
   if (prm->irls_iters < 1 || prm->irls_iters > NI_MAX_IRLS) return bad("irls_iters out of range");
   if (prm->align_iters < 0) return bad("align_iters < 0");
   if (!(prm->cg_rtol > 0) || prm->cg_max_iter < 1 || !(prm->q_rtol > 0) || prm->q_max_iter < 1)
@@ -312,6 +321,12 @@ void ensure_scan(ni_ctx* c, size_t n) {
   ensure<int>(c, c->scan_tmp, std::max(a, b));
 }
 
+// edge directions per pixel: 2 (right, down), or 4 with the diagonals
+size_t ndirs(const Problem& pb) { return pb.prm.connectivity == 8 ? 4 : 2; }
+
+// diagonal edge bits (null under 4-connectivity)
+uint8_t* eb2(ni_ctx* c, const Problem& pb) { return pb.prm.connectivity == 8 ? ptr<uint8_t>(c->eb2) : nullptr; }
+
 // ----------------------------------------------------------------- stages
 void stage_setup(ni_ctx* c, const Problem& pb) {
   const int H = pb.H, W = pb.W, P = pb.P;
@@ -321,11 +336,17 @@ void stage_setup(ni_ctx* c, const Problem& pb) {
   ensure<float>(c, c->om_d, P);
   ensure<float>(c, c->nt, P);
   ensure<int>(c, c->parent, P);
-  ensure<int>(c, c->flag, 2 * (size_t)P);
-  ensure<int>(c, c->scanv, 2 * (size_t)P);
+  const size_t nd = ndirs(pb);
+  ensure<int>(c, c->flag, nd * P);
+  ensure<int>(c, c->scanv, nd * P);
   ensure<int>(c, c->pos, P);
   ensure<float>(c, c->zgrid, P);
-  ensure_scan(c, 2 * (size_t)P);
+  ensure_scan(c, nd * P);
+  if (nd == 4) {
+    ensure<uint8_t>(c, c->eb2, P);
+    ensure<float>(c, c->om_dr, P);
+    ensure<float>(c, c->om_dl, P);
+  }
   // ray tables in FP64 on the host: tau = ((u - cx)/fx, (v - cy)/fy, 1) at
   // pixel centres and at the midpoints u + 1/2, v + 1/2
   std::vector<double> t(2 * (size_t)W + 2 * (size_t)H, 0.0);
@@ -349,7 +370,8 @@ void stage_setup(ni_ctx* c, const Problem& pb) {
   check(c,
         nil::launch_setup(pb.normals, pb.mask, H, W, pb.cam.proj == NI_PERSP, pb.cam.pixel_pitch, tab, cth, use_sim,
                           ptr<uint8_t>(c->ebits), ptr<float>(c->om_r), ptr<float>(c->om_d), ptr<float>(c->nt),
-                          misc(c) + M_ERR, c->stream),
+                          misc(c) + M_ERR, c->stream, eb2(c, pb), nd == 4 ? ptr<float>(c->om_dr) : nullptr,
+                          nd == 4 ? ptr<float>(c->om_dl) : nullptr),
         "setup");
 }
 
@@ -358,7 +380,7 @@ int stage_label(ni_ctx* c, const Problem& pb, int32_t* labels) {
   check(c,
         nil::grid_components(ptr<uint8_t>(c->ebits), pb.H, pb.W, EB_SR, EB_SD, ptr<int>(c->parent),
                              ptr<int>(c->flag), ptr<int>(c->scanv), labels, misc(c) + M_COUNT,
-                             ptr<int>(c->scan_tmp), c->stream),
+                             ptr<int>(c->scan_tmp), c->stream, eb2(c, pb), EB2_SDR, EB2_SDL),
         "label");
   readback(c, misc(c), 16 * sizeof(int), c->host);
   if (c->host[M_ERR]) {
@@ -409,7 +431,7 @@ Seg build_segments(ni_ctx* c, const Problem& pb, const int32_t* labels, int K, b
   ensure<uint32_t>(c, c->ktmp, N);
   ensure<uint32_t>(c, c->vtmp, N);
   ensure<int>(c, c->comp_off, (size_t)K + 1);
-  ensure_scan(c, std::max<size_t>(2 * (size_t)P, N));
+  ensure_scan(c, std::max<size_t>(ndirs(pb) * P, N));
   check(c,
         nil::fill_segments(labels, P, K, nullptr, nullptr, nullptr, ptr<uint32_t>(c->key), ptr<uint32_t>(c->val),
                            ptr<uint32_t>(c->skey), ptr<uint32_t>(c->spix), ptr<uint32_t>(c->ktmp),
@@ -428,8 +450,164 @@ Seg build_segments(ni_ctx* c, const Problem& pb, const int32_t* labels, int K, b
   return sg;
 }
 
+// Fill under 8-connectivity: every component of two or more pixels in one
+// multigrid-preconditioned CG over their block-diagonal system, assembled
+// in FP64 from the edge bits; zero mean per component.
+void stage_fill8(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& sg, float* zout, ni_report* rep) {
+  const int P = pb.P, W = pb.W, N = sg.N, K = sg.K;
+  const bool persp = pb.cam.proj == NI_PERSP;
+  const size_t K1 = (size_t)K + 1;
+  const uint32_t* cpix = ptr<uint32_t>(c->spix);
+  const uint32_t* skey = ptr<uint32_t>(c->skey);
+  const int* comp_off = ptr<int>(c->comp_off);
+  int* iters = ensure<int>(c, c->iters, K1);
+  double* rr = ensure<double>(c, c->rr, K1);
+  double* bb = ensure<double>(c, c->bb, K1);
+  int* list = ensure<int>(c, c->small_list, K1);
+  int* tflag = ensure<int>(c, c->fsmall, K1);
+  int* tpos = ensure<int>(c, c->spos, K1);
+  float* x = ensure<float>(c, c->x, N);
+  int* cntd = misc(c) + M_COUNT;
+  int* stats = misc(c) + M_STATS;
+  mark(c, 3);
+  check(c, nil::fill_zero_grid(zout, P, c->stream), "zero");
+  check(c, hipMemsetAsync(iters, 0, K1 * sizeof(int), c->stream), "memset");
+  check(c, hipMemsetAsync(rr, 0, K1 * sizeof(double), c->stream), "memset");
+  check(c, hipMemsetAsync(stats, 0, 4 * sizeof(int), c->stream), "memset");
+  check(c, nil::fill_tier_list(comp_off, K, 5, tflag, tpos, list, cntd, ptr<int>(c->scan_tmp), c->stream), "list");
+  readback(c, cntd, sizeof(int), c->host);
+  const int nl = c->host[0];
+  const int warm = pb.prm.warm_start ? 1 : 0;
+  mark(c, 4);
+  const float* xw = nullptr;
+  if (warm) {
+    float* xg = ensure<float>(c, c->xwarm, P);
+    size_t wsb = nil::unet_workspace_bytes(pb.H, pb.W);
+    void* ws = ensure<uint8_t>(c, c->unet_ws, wsb);
+    check(c, nil::unet_predict(c->unet, pb.normals, pb.mask, pb.H, pb.W, &pb.cam, xg, ws, wsb, c->stream), "unet");
+    xw = xg;
+  }
+  check(c, nil::fill_gather_x0(cpix, N, xw, x, c->stream), "gather");
+  mark(c, 5);
+  int its = 0, levels = 0;
+  double mg_bytes = 0.0;
+  if (nl > 0) {
+    int* deg = ensure<int>(c, c->mg_deg, N);
+    int* npair = ensure<int>(c, c->mg_pc, N);
+    int* row_off = ensure<int>(c, c->mg_row, (size_t)N + 1);
+    int* poff = ensure<int>(c, c->mg_poff, (size_t)N + 1);
+    check(c, nil::fill8_count(N, W, cpix, skey, comp_off, labels, ptr<uint8_t>(c->ebits), eb2(c, pb), deg, npair,
+                              c->stream),
+          "count");
+    check(c, nil::scan_exclusive_i32(deg, row_off, N, row_off + N, ptr<int>(c->scan_tmp), c->stream), "scan");
+    check(c, nil::scan_exclusive_i32(npair, poff, N, poff + N, ptr<int>(c->scan_tmp), c->stream), "scan");
+    readback(c, row_off + N, sizeof(int), c->host);
+    const int nnz = c->host[0];
+    readback(c, poff + N, sizeof(int), c->host);
+    const int npr = c->host[0];
+    if (nnz != 2 * npr) {
+      c->err = "fill: inconsistent 8-connected level-0 graph";
+      throw Fail{NI_E_DEVICE};
+    }
+    int* col = ensure<int>(c, c->mg_col, nnz);
+    double* w = ensure<double>(c, c->mg_w, nnz);
+    double* dg = ensure<double>(c, c->mg_diag, N);
+    int* plo = ensure<int>(c, c->mg_plo, npr);
+    int* phi = ensure<int>(c, c->mg_phi, npr);
+    double* pw = ensure<double>(c, c->mg_pw, npr);
+    int* gy = ensure<int>(c, c->mg_gy, N);
+    int* gx = ensure<int>(c, c->mg_gx, N);
+    int* gc = ensure<int>(c, c->mg_gc, N);
+    double* b64 = ensure<double>(c, c->mg_b, N);
+    double* x64 = ensure<double>(c, c->mg_x, N);
+    const float* om[4] = {ptr<float>(c->om_r), ptr<float>(c->om_d), ptr<float>(c->om_dr), ptr<float>(c->om_dl)};
+    const double g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
+    const double g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
+    const double g2fd = persp ? pb.cam.fx * pb.cam.fy : 1.0;
+    check(c,
+          nil::fill8_build(N, W, cpix, skey, comp_off, labels, ptr<uint8_t>(c->ebits), eb2(c, pb), ptr<float>(c->nt),
+                           om, ptr<int>(c->pos), g2fx, g2fy, g2fd, row_off, poff, x, col, w, dg, plo, phi, pw, gy, gx,
+                           gc, b64, x64, c->stream),
+          "assemble");
+    if (!c->amg_fill) c->amg_fill = nil::amg_new();
+    check(c, nil::amg_build(c->amg_fill, N, npr, row_off, col, w, dg, plo, phi, pw, c->stream, gy, gx, gc, K, W,
+                            pb.H),
+          "mg hierarchy");
+    nil::amg_set_corr(c->amg_fill, 1.8);
+    check(c, nil::amg_update(c->amg_fill, w, dg, pw, c->stream), "mg values");
+    mark(c, 12);
+    check(c,
+          nil::amg_fill_solve(c->amg_fill, gc, list, nl, K, b64, x64, pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, rr,
+                              bb, iters, stats, c->host, &its, c->stream),
+          "mg solve");
+    mark(c, 13);
+    double* csum = ensure<double>(c, c->csum, K1);
+    int* ccnt = ensure<int>(c, c->comp_rid, K1);
+    check(c, nil::fill8_out(N, K, cpix, skey, comp_off, x64, csum, ccnt, zout, c->stream), "out");
+    levels = nil::amg_levels(c->amg_fill);
+  } else {
+    mark(c, 12);
+    mark(c, 13);
+  }
+  mark(c, 15);
+  readback(c, stats, 4 * sizeof(int), c->host);
+  const int notconv = c->host[0], fallbacks = c->host[1];
+  if (rep) {
+    std::vector<int> it(K), off(K1);
+    std::vector<double> hrr(K), hbb(K);
+    if (K > 0) {
+      check(c, hipMemcpyAsync(it.data(), iters, K * sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipMemcpyAsync(off.data(), comp_off, K1 * sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipMemcpyAsync(hrr.data(), rr, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipMemcpyAsync(hbb.data(), bb, K * sizeof(double), hipMemcpyDeviceToHost, c->stream), "D2H");
+      check(c, hipStreamSynchronize(c->stream), "sync");
+    }
+    long long pxit = 0, nsys = 0;
+    int itmax = 0;
+    double rmax = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const int n = off[k + 1] - off[k];
+      if (n < 2) continue;
+      nsys += n;
+      pxit += (long long)n * it[k];
+      itmax = std::max(itmax, it[k]);
+      rmax = std::max(rmax, hbb[k] > 0 ? sqrt(hrr[k] / hbb[k]) : 0.0);
+    }
+    if (nl > 0) mg_bytes = nil::amg_fill_bytes(c->amg_fill, nsys);
+    rep->fill_large_px = nsys;
+    rep->fill_px_iters = pxit;
+    rep->fill_large_px_iters = pxit;
+    rep->fill_iters_max = itmax;
+    rep->fill_max_relres = rmax;
+    rep->n_small = 0;
+    rep->n_large = nl;
+    rep->fill_notconv = notconv;
+    rep->fill_large_launches = its;
+    rep->warm_fallbacks = fallbacks;
+    rep->ms_assemble = ev_ms(c, 5, 12);
+    rep->ms_warm = ev_ms(c, 4, 5);
+    rep->ms_fill_small = 0.f;
+    rep->ms_fill_large = ev_ms(c, 12, 15);
+    rep->ms_large_kernel = ev_ms(c, 12, 13);
+    rep->fill_chunk = 0;
+    rep->fill_split = 0;
+    rep->fill_mg_levels = levels;
+    rep->ms_fill_mg_build = ev_ms(c, 5, 12);
+    rep->fill_mg_bytes = mg_bytes;
+    rep->fill_mg_fallback = 0;
+  }
+  if (notconv > 0) {
+    c->err = std::to_string(notconv) + " component(s) hit cg_max_iter";
+    throw Fail{NI_E_NOTCONV};
+  }
+}
+
 void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& sg, float* zout,
                 ni_report* rep) {
+  if (pb.prm.connectivity == 8) {
+    stage_fill8(c, pb, labels, sg, zout, rep);
+    return;
+  }
   const int P = pb.P, W = pb.W, N = sg.N, K = sg.K;
   const bool persp = pb.cam.proj == NI_PERSP;
   const double g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
@@ -748,7 +926,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   if (!c->amg) c->amg = nil::amg_new();
   a.amg = c->amg;
   a.graphs = pb.prm.graphs ? 1 : 0;
-  a.W = W; a.label = labels; a.K0 = K; a.grp = nullptr; a.ebits = ptr<uint8_t>(c->ebits);
+  a.W = W; a.label = labels; a.K0 = K; a.grp = nullptr; a.ebits = ptr<uint8_t>(c->ebits); a.eb2 = eb2(c, pb);
   a.zfill = zfill;
   a.S = ensure<double>(c, c->S, K1);
   a.psum = ensure<double>(c, c->psum, K1);
@@ -760,6 +938,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.qiters2_out = misc(c) + M_QITERS2;
   a.g2fx = persp ? pb.cam.fx * pb.cam.fx : 1.0;
   a.g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
+  a.g2fd = persp ? pb.cam.fx * pb.cam.fy : 1.0;
   a.k = pb.prm.bini_k; a.L = pb.prm.out_L; a.U = pb.prm.out_U; a.cut_rel = pb.prm.w_cut_rel;
   a.q_rtol = pb.prm.q_rtol; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
   a.out_from = pb.prm.variant == 1 ? 1 : 0;
@@ -771,15 +950,15 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   // so no buffer in use is reallocated.
   auto build = [&](const int* gl, int Kg) {
     // inter-component edges
-    check(c, nil::quot_inter_edges(gl, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
-                                   nullptr, ptr<int>(c->scan_tmp), c->stream, 0),
+    check(c, nil::quot_inter_edges(gl, ptr<uint8_t>(c->ebits), eb2(c, pb), P, W, ptr<int>(c->flag),
+                                   ptr<int>(c->scanv), cntd, nullptr, ptr<int>(c->scan_tmp), c->stream, 0),
           "inter edges");
     readback(c, cntd, sizeof(int), c->host);
     const int E = c->host[0];
     uint32_t* eidx_raw = ensure<uint32_t>(c, c->eidx_raw, E);
     uint32_t* eidx = ensure<uint32_t>(c, c->eidx, E);
-    check(c, nil::quot_inter_edges(gl, ptr<uint8_t>(c->ebits), P, W, ptr<int>(c->flag), ptr<int>(c->scanv), cntd,
-                                   eidx_raw, ptr<int>(c->scan_tmp), c->stream, 1),
+    check(c, nil::quot_inter_edges(gl, ptr<uint8_t>(c->ebits), eb2(c, pb), P, W, ptr<int>(c->flag),
+                                   ptr<int>(c->scanv), cntd, eidx_raw, ptr<int>(c->scan_tmp), c->stream, 1),
           "inter compact");
     size_t srt = std::max<size_t>(E, 1);
     uint32_t* keys = ensure<uint32_t>(c, c->key, std::max<size_t>(srt, P));
@@ -788,7 +967,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     uint32_t* kout2 = ensure<uint32_t>(c, c->kout2, srt);
     int* pflag = ensure<int>(c, c->pflag, srt);
     int* ppos = ensure<int>(c, c->ppos, srt);
-    ensure_scan(c, std::max<size_t>(2 * (size_t)P, srt));
+    ensure_scan(c, std::max<size_t>(ndirs(pb) * P, srt));
     check(c, nil::quot_sort_edges(eidx_raw, E, W, Kg, gl, keys, eidx, ktmp, vtmp, kout2, pflag, ppos, cntd,
                                   ptr<int>(c->scan_tmp), c->stream),
           "sort edges");
@@ -805,7 +984,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     ktmp = ensure<uint32_t>(c, c->ktmp, std::max(srt, P2));
     vtmp = ensure<uint32_t>(c, c->vtmp, std::max(srt, P2));
     kout2 = ensure<uint32_t>(c, c->kout2, std::max(srt, P2));
-    ensure_scan(c, std::max<size_t>({2 * (size_t)P, srt, P2}));
+    ensure_scan(c, std::max<size_t>({ndirs(pb) * P, srt, P2}));
     const size_t Kg1 = (size_t)Kg + 1;
     int* rowcnt = ensure<int>(c, c->rowcnt, Kg1);
     int* row_off = ensure<int>(c, c->row_off, Kg1);
@@ -932,7 +1111,8 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   // regions of G_0 and outputs
   check(c,
         nil::grid_components(ptr<uint8_t>(c->ebits), pb.H, W, EB_VR, EB_VD, ptr<int>(c->parent), ptr<int>(c->flag),
-                             ptr<int>(c->scanv), nullptr, cntd + 1, ptr<int>(c->scan_tmp), c->stream),
+                             ptr<int>(c->scanv), nullptr, cntd + 1, ptr<int>(c->scan_tmp), c->stream, eb2(c, pb),
+                             EB2_VDR, EB2_VDL),
         "regions");
   readback(c, cntd + 1, sizeof(int), c->host);
   const int R = c->host[0];
@@ -1185,8 +1365,7 @@ ni_status ni_label_noalloc(ni_ctx* c, const float* normals, const uint8_t* mask,
     int* cnt = reinterpret_cast<int*>(take(16 * sizeof(int)));  // [0] K, [8] non-finite flag
     double* tab = reinterpret_cast<double*>(take((2 * (size_t)W + 2 * (size_t)H) * sizeof(double)));
     uint8_t* ebits = reinterpret_cast<uint8_t*>(take(P));
-    float* om_r = reinterpret_cast<float*>(take((size_t)P * sizeof(float)));
-    float* om_d = reinterpret_cast<float*>(take((size_t)P * sizeof(float)));
+    uint8_t* eb2 = pb.prm.connectivity == 8 ? reinterpret_cast<uint8_t*>(take(P)) : nullptr;
     float* nt = reinterpret_cast<float*>(take((size_t)P * sizeof(float)));
     int* parent = reinterpret_cast<int*>(take((size_t)P * sizeof(int)));
     int* flag = reinterpret_cast<int*>(take((size_t)P * sizeof(int)));
@@ -1203,10 +1382,12 @@ ni_status ni_label_noalloc(ni_ctx* c, const float* normals, const uint8_t* mask,
     const double th = pb.prm.theta_c_deg;
     const int use_sim = th > 0 ? 1 : 0;
     const double cth = use_sim ? cos(th * M_PI / 180.0) : 2.0;
-    check(c, nil::launch_setup(normals, mask, H, W, persp, pb.cam.pixel_pitch, tab, cth, use_sim, ebits, om_r, om_d,
-                               nt, cnt + 8, st),
+    check(c, nil::launch_setup(normals, mask, H, W, persp, pb.cam.pixel_pitch, tab, cth, use_sim, ebits, nullptr,
+                               nullptr, nt, cnt + 8, st, eb2, nullptr, nullptr),
           "setup");
-    check(c, nil::grid_components(ebits, H, W, EB_SR, EB_SD, parent, flag, cid, labels, cnt, stmp, st), "label");
+    check(c, nil::grid_components(ebits, H, W, EB_SR, EB_SD, parent, flag, cid, labels, cnt, stmp, st, eb2, EB2_SDR,
+                                  EB2_SDL),
+          "label");
     check(c, hipMemcpyAsync(c->host, cnt, 16 * sizeof(int), hipMemcpyDeviceToHost, st), "D2H");
     check(c, hipStreamSynchronize(st), "sync");
     if (c->host[8]) {

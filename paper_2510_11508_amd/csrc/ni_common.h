@@ -14,6 +14,14 @@ enum : uint8_t {
   EB_VALID = 128
 };
 
+// diagonal edge bits of 8-connectivity, a second byte per pixel
+enum : uint8_t {
+  EB2_VDR = 1,  // edge to the lower-right neighbour usable
+  EB2_VDL = 2,  // edge to the lower-left neighbour usable
+  EB2_SDR = 4,  // ... and normals similar
+  EB2_SDL = 8
+};
+
 namespace ni {
 
 // ---------------------------------------------------------------- reductions
@@ -129,6 +137,26 @@ __device__ __forceinline__ void acc_by_key_block(bool valid, int key, double a, 
 
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Edge directions, each edge owned by its upper end (in a row: the left
+// one): 0 right, 1 down, 2 down-right, 3 down-left (8-connectivity only).
+// An edge's code is 4 a + dir, a its owner pixel.
+__device__ __forceinline__ int dir_step(int d, int W) { return d == 0 ? 1 : d == 1 ? W : d == 2 ? W + 1 : W - 1; }
+
+// usable edge of direction d at owner p; eb2 is null under 4-connectivity
+__device__ __forceinline__ bool dir_usable(const uint8_t* eb, const uint8_t* eb2, int p, int d) {
+  if (d < 2) return (eb[p] & (d == 0 ? EB_VR : EB_VD)) != 0;
+  return eb2 && (eb2[p] & (d == 2 ? EB2_VDR : EB2_VDL)) != 0;
+}
+
+// the pixel a - step(d) lies on the grid (the owner of the edge of
+// direction d that ends at a)
+__device__ __forceinline__ bool has_back(int a, int d, int W) {
+  const int u = a % W;
+  if (d == 0) return u > 0;
+  if (a < W) return false;
+  return d == 1 || (d == 2 ? u > 0 : u < W - 1);
+}
+
 }  // namespace ni
 
 // ------------------------------------------------------------- host launchers
@@ -205,6 +233,7 @@ struct IrlsArgs {
   int K0;             // components (K = quotient nodes)
   int fresh = 0;      // 1: the node structure changed since the last step
   const uint8_t* ebits;
+  const uint8_t* eb2 = nullptr;   // diagonal edge bits (8-connectivity), else null
   const double *eom, *eta, *etb;  // FP64 omega and gamma factors per inter edge
   const float* zfill;
   const int *pair_start, *pair_lo, *pair_hi, *row_off;
@@ -217,7 +246,7 @@ struct IrlsArgs {
   int* qiters_out;     // [t] iterations of the first solve round
   int* qiters2_out;    // [t] iterations of the refinement round
   double* epart;
-  double g2fx, g2fy, k, L, U, cut_rel, q_rtol;
+  double g2fx, g2fy, g2fd, k, L, U, cut_rel, q_rtol;  // g2f*: f^2 per right, down, diagonal row
   int align, outlier_mode, q_maxit, nnz;
   int out_from;  // first iteration with outlier weights (the baseline: 1)
   int* qcol;

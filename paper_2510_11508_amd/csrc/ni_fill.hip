@@ -126,9 +126,12 @@ __device__ __forceinline__ int size_tier(int n) {
   return n <= 1 ? 0 : n <= 256 ? 1 : n <= 2048 ? 2 : n <= 8192 ? 3 : 4;
 }
 
+// tier 1..4 as size_tier; tier 5: every component of two or more pixels
 __global__ void k_tier_flags(const int* __restrict__ comp_off, int K, int tier, int* __restrict__ flag) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < K) flag[c] = size_tier(comp_off[c + 1] - comp_off[c]) == tier ? 1 : 0;
+  if (c >= K) return;
+  const int t = size_tier(comp_off[c + 1] - comp_off[c]);
+  flag[c] = (tier == 5 ? t >= 1 : t == tier) ? 1 : 0;
 }
 
 __global__ void k_tier_list(const int* __restrict__ flag, const int* __restrict__ pos, int K, int* __restrict__ list) {
@@ -796,6 +799,133 @@ __global__ void k_zero_grid(float* z, int P) {
   if (p < P) z[p] = 0.f;
 }
 
+// ===================================================== 8-connectivity
+// The level-0 system of every component of two or more pixels, assembled
+// straight from the edge bits in FP64 (a pixel row holds up to eight
+// neighbours, beyond the packed four-neighbour stencil) and solved by the
+// multigrid PCG.  Neighbour slot k of pixel p: k < 4 the edge of direction
+// k that p owns, k >= 4 the edge of direction k - 4 that ends at p.
+struct Om4 {
+  const float* o[4];  // omega_{b->a} per direction at the owner a
+};
+
+__device__ __forceinline__ bool nb8(const uint8_t* __restrict__ eb, const uint8_t* __restrict__ eb2, int p, int W,
+                                    int k, int& owner, int& other, int& d) {
+  d = k & 3;
+  const int step = ni::dir_step(d, W);
+  if (k < 4) {
+    owner = p;
+    other = p + step;
+    return ni::dir_usable(eb, eb2, p, d);
+  }
+  owner = p - step;
+  other = p;
+  return ni::has_back(p, d, W) && ni::dir_usable(eb, eb2, owner, d);
+}
+
+// w = (gamma^2_{b->a} + gamma^2_{a->b}) / 2 with gamma^2 = f^2 t^2, in a
+// fixed rounding order so that both ends of an edge compute the same bits
+__device__ __forceinline__ double edge_w(double ta, double tb, double g2f) {
+  return __dadd_rn(__dmul_rn(__dmul_rn(0.5, g2f), __dmul_rn(ta, ta)),
+                   __dmul_rn(__dmul_rn(0.5, g2f), __dmul_rn(tb, tb)));
+}
+
+__global__ void k_fill8_count(int N, int W, const uint32_t* __restrict__ cpix, const int* __restrict__ label,
+                              const uint8_t* __restrict__ eb, const uint8_t* __restrict__ eb2, int* __restrict__ deg,
+                              int* __restrict__ npair) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int p = (int)cpix[i];
+  const int c = label[p];
+  int dg = 0, pr = 0;
+  for (int k = 0; k < 8; ++k) {
+    int a, b, d;
+    if (nb8(eb, eb2, p, W, k, a, b, d) && label[k < 4 ? b : a] == c) {
+      ++dg;
+      pr += k < 4;
+    }
+  }
+  deg[i] = dg;
+  npair[i] = pr;
+}
+
+__global__ void k_fill8_build(int N, int W, const uint32_t* __restrict__ cpix, const uint32_t* __restrict__ skey,
+                              const int* __restrict__ comp_off, const int* __restrict__ label,
+                              const uint8_t* __restrict__ eb, const uint8_t* __restrict__ eb2,
+                              const float* __restrict__ nt, Om4 om, const int* __restrict__ pos, double g2fx,
+                              double g2fy, double g2fd, const int* __restrict__ row_off,
+                              const int* __restrict__ pair_off, const float* __restrict__ x32, int* __restrict__ col,
+                              double* __restrict__ w, double* __restrict__ diag, int* __restrict__ plo,
+                              int* __restrict__ phi, double* __restrict__ pw, int* __restrict__ gy,
+                              int* __restrict__ gx, int* __restrict__ gc, double* __restrict__ b64,
+                              double* __restrict__ x64) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int p = (int)cpix[i];
+  const int c = label[p];
+  const int k0 = (int)skey[i];
+  gy[i] = p / W;
+  gx[i] = p % W;
+  gc[i] = comp_off[k0 + 1] - comp_off[k0] >= 2 ? k0 : -1;
+  int j = row_off[i], q = pair_off[i];
+  double dg = 0.0, b = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    int a, o, d;
+    if (!nb8(eb, eb2, p, W, k, a, o, d)) continue;
+    const int nbr = k < 4 ? o : a;
+    if (label[nbr] != c) continue;
+    const double g2f = d == 0 ? g2fx : d == 1 ? g2fy : g2fd;
+    const double wv = edge_w((double)nt[a], (double)nt[o], g2f);
+    const double omv = (double)om.o[d][a];
+    col[j] = pos[nbr];
+    w[j] = wv;
+    ++j;
+    dg += wv;
+    if (k < 4) {
+      b += wv * omv;
+      plo[q] = i;
+      phi[q] = pos[nbr];
+      pw[q] = wv;
+      ++q;
+    } else {
+      b -= wv * omv;
+    }
+  }
+  diag[i] = dg;
+  b64[i] = b;
+  x64[i] = (double)x32[i];
+}
+
+// per-component sums of the solution over the component-major order
+__global__ void __launch_bounds__(1024) k_fill8_sums(int N, const uint32_t* __restrict__ skey,
+                                                     const double* __restrict__ x64, double* __restrict__ csum,
+                                                     int* __restrict__ ccnt) {
+  __shared__ double red[2 * (1024 / 64)];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool v = i < N;
+  ni::acc_by_key_block<int>(v, v ? (int)skey[i] : 0, v ? x64[i] : 0.0, 1, csum, ccnt, red);
+}
+
+__global__ void k_fill8_zero(int K, double* __restrict__ csum, int* __restrict__ ccnt) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < K) {
+    csum[c] = 0.0;
+    ccnt[c] = 0;
+  }
+}
+
+// zero mean per component (the gauge of Eq. 15), scattered to the grid;
+// a singleton's log-depth is 0
+__global__ void k_fill8_out(int N, const uint32_t* __restrict__ cpix, const uint32_t* __restrict__ skey,
+                            const int* __restrict__ comp_off, const double* __restrict__ x64,
+                            const double* __restrict__ csum, float* __restrict__ z) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int k = (int)skey[i];
+  const int n = comp_off[k + 1] - comp_off[k];
+  z[cpix[i]] = n >= 2 ? (float)(x64[i] - csum[k] / (double)n) : 0.f;
+}
+
 }  // namespace
 
 namespace nil {
@@ -971,6 +1101,38 @@ hipError_t large_finish(const LargeArgs& a, const uint32_t* cpix, float* zgrid, 
   LargeState S = to_state(a);
   k_lg_sum<<<a.nchunks, LNT, 0, st>>>(S, 0);
   k_lg_center<<<a.nchunks, LNT, 0, st>>>(S, 0, zgrid, cpix);
+  return hipGetLastError();
+}
+
+hipError_t fill8_count(int N, int W, const uint32_t* cpix, const uint32_t* skey, const int* comp_off,
+                       const int* label, const uint8_t* eb, const uint8_t* eb2, int* deg, int* npair,
+                       hipStream_t st) {
+  (void)skey;
+  (void)comp_off;
+  if (N > 0) k_fill8_count<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, W, cpix, label, eb, eb2, deg, npair);
+  return hipGetLastError();
+}
+
+hipError_t fill8_build(int N, int W, const uint32_t* cpix, const uint32_t* skey, const int* comp_off,
+                       const int* label, const uint8_t* eb, const uint8_t* eb2, const float* nt,
+                       const float* const* om, const int* pos, double g2fx, double g2fy, double g2fd,
+                       const int* row_off, const int* pair_off, const float* x32, int* col, double* w, double* diag,
+                       int* plo, int* phi, double* pw, int* gy, int* gx, int* gc, double* b64, double* x64,
+                       hipStream_t st) {
+  const Om4 o{{om[0], om[1], om[2], om[3]}};
+  if (N > 0)
+    k_fill8_build<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, W, cpix, skey, comp_off, label, eb, eb2, nt, o, pos, g2fx,
+                                                        g2fy, g2fd, row_off, pair_off, x32, col, w, diag, plo, phi,
+                                                        pw, gy, gx, gc, b64, x64);
+  return hipGetLastError();
+}
+
+hipError_t fill8_out(int N, int K, const uint32_t* cpix, const uint32_t* skey, const int* comp_off,
+                     const double* x64, double* csum, int* ccnt, float* z, hipStream_t st) {
+  if (N <= 0 || K <= 0) return hipSuccess;
+  k_fill8_zero<<<ni::ceil_div(K, 256), 256, 0, st>>>(K, csum, ccnt);
+  k_fill8_sums<<<ni::ceil_div(N, 1024), 1024, 0, st>>>(N, skey, x64, csum, ccnt);
+  k_fill8_out<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, cpix, skey, comp_off, x64, csum, z);
   return hipGetLastError();
 }
 

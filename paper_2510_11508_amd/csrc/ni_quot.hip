@@ -23,26 +23,29 @@ namespace {
 // quotient rows with more entries than QELL are "heavy" (see the row classes below)
 constexpr int QELL = 8, QBIG = 512;
 
-__global__ void k_inter_flags(const int* __restrict__ label, const uint8_t* __restrict__ ebits, int P, int W,
-                              int* __restrict__ flag) {
+// flag[nd p + d]: the usable edge of direction d owned by p joins two
+// nodes (nd = 2 directions, or 4 with the diagonals: eb2 non-null)
+__global__ void k_inter_flags(const int* __restrict__ label, const uint8_t* __restrict__ ebits,
+                              const uint8_t* __restrict__ eb2, int P, int W, int* __restrict__ flag) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  uint8_t e = ebits[p];
-  int c = label[p];
-  flag[2 * p] = ((e & EB_VR) && label[p + 1] != c) ? 1 : 0;
-  flag[2 * p + 1] = ((e & EB_VD) && label[p + W] != c) ? 1 : 0;
+  const int c = label[p];
+  const int nd = eb2 ? 4 : 2;
+  for (int d = 0; d < nd; ++d)
+    flag[nd * p + d] = (ni::dir_usable(ebits, eb2, p, d) && label[p + ni::dir_step(d, W)] != c) ? 1 : 0;
 }
 
-__global__ void k_inter_compact(const int* __restrict__ flag, const int* __restrict__ epos, int P2,
+// edge codes 4 a + d in ascending order
+__global__ void k_inter_compact(const int* __restrict__ flag, const int* __restrict__ epos, long long n, int nd,
                                 uint32_t* __restrict__ eidx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < P2 && flag[i]) eidx[epos[i]] = (uint32_t)i;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) eidx[epos[i]] = (uint32_t)(4 * (i / nd) + i % nd);
 }
 
-__device__ __forceinline__ void edge_ends(uint32_t code, int W, int& a, int& b, bool& horiz) {
-  a = (int)(code >> 1);
-  horiz = (code & 1u) == 0u;
-  b = horiz ? a + 1 : a + W;
+__device__ __forceinline__ void edge_ends(uint32_t code, int W, int& a, int& b, int& d) {
+  a = (int)(code >> 2);
+  d = (int)(code & 3u);
+  b = a + ni::dir_step(d, W);
 }
 
 // key = max(pi(a), pi(b)) (which = 1) or min (which = 0)
@@ -50,8 +53,7 @@ __global__ void k_edge_keys(const uint32_t* __restrict__ eidx, int E, int W, con
                             int which, uint32_t* __restrict__ key) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
-  int a, b;
-  bool h;
+  int a, b, h;
   edge_ends(eidx[i], W, a, b, h);
   int c = label[a], d = label[b];
   key[i] = (uint32_t)(which ? max(c, d) : min(c, d));
@@ -61,8 +63,7 @@ __global__ void k_pair_flags(const uint32_t* __restrict__ eidx, int E, int W, co
                              int* __restrict__ flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
-  int a, b, a0, b0;
-  bool h;
+  int a, b, a0, b0, h;
   edge_ends(eidx[i], W, a, b, h);
   int f = 1;
   if (i > 0) {
@@ -80,8 +81,7 @@ __global__ void k_pair_build(const uint32_t* __restrict__ eidx, const int* __res
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
   if (flag[i]) {
-    int a, b;
-    bool h;
+    int a, b, h;
     edge_ends(eidx[i], W, a, b, h);
     int c = label[a], d = label[b];
     int pid = ppos[i];
@@ -141,7 +141,7 @@ __global__ void k_fill_f64(double* a, int n, double v) {
 // ---------------------------------------------------------- per iteration
 struct EdgeParams {
   int W, align, outlier_mode, t, out_from;
-  double g2fx, g2fy, k, lL, lU, U;
+  double g2fx, g2fy, g2fd, k, lL, lU, U;  // f^2 of the right, down and diagonal rows
 };
 
 __device__ __forceinline__ double sigmoid_k(double x, double k) { return 1.0 / (1.0 + exp(-k * x)); }
@@ -157,16 +157,14 @@ __device__ __forceinline__ double outlier_w(double chi, const EdgeParams& q) {
 
 __global__ void __launch_bounds__(256) k_irls_edges(
     const uint32_t* __restrict__ eidx, int E, const int* __restrict__ label, const int* __restrict__ glabel,
-    const uint8_t* __restrict__ ebits, const double* __restrict__ eom, const double* __restrict__ eta,
-    const double* __restrict__ etb,
-    const float* __restrict__ zfill, const double* __restrict__ S, EdgeParams q, double* __restrict__ ew,
-    double* __restrict__ erho, unsigned long long* __restrict__ wmax_bits) {
+    const uint8_t* __restrict__ ebits, const uint8_t* __restrict__ eb2, const double* __restrict__ eom,
+    const double* __restrict__ eta, const double* __restrict__ etb, const float* __restrict__ zfill,
+    const double* __restrict__ S, EdgeParams q, double* __restrict__ ew, double* __restrict__ erho, unsigned long long* __restrict__ wmax_bits) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   double w = 0.0;
   if (i < E) {
-    int a, b;
-    bool h;
-    edge_ends(eidx[i], q.W, a, b, h);
+    int a, b, dir;
+    edge_ends(eidx[i], q.W, a, b, dir);
     const int c = label[a], d = label[b];
     const double za = (double)zfill[a] + S[c];
     const double zb = (double)zfill[b] + S[d];
@@ -175,13 +173,12 @@ __global__ void __launch_bounds__(256) k_irls_edges(
     if (q.t < q.align) {
       w = 2.0;
     } else {
-      const int step = h ? 1 : q.W;
-      const uint8_t bit = h ? EB_VR : EB_VD;
-      const double g2f = h ? q.g2fx : q.g2fy;
-      // row b -> a, opposite pixel a - step
-      const bool has_ma = h ? (a % q.W) > 0 : a >= q.W;
+      const int step = ni::dir_step(dir, q.W);
+      const double g2f = dir == 0 ? q.g2fx : dir == 1 ? q.g2fy : q.g2fd;
+      // row b -> a, opposite pixel a - step (a missing or unusable edge
+      // there contributes no difference)
       double dm = 0.0;
-      if (has_ma && (ebits[a - step] & bit)) {
+      if (ni::has_back(a, dir, q.W) && ni::dir_usable(ebits, eb2, a - step, dir)) {
         int m = a - step;
         dm = ((double)zfill[m] + S[label[m]]) - za;
       }
@@ -191,7 +188,7 @@ __global__ void __launch_bounds__(256) k_irls_edges(
       const double wba = g2a * sigmoid_k(g2a * (dm * dm - dp * dp), q.k);
       // row a -> b, opposite pixel b + step
       double dm2 = 0.0;
-      if (ebits[b] & bit) {
+      if (ni::dir_usable(ebits, eb2, b, dir)) {
         int m = b + step;
         dm2 = ((double)zfill[m] + S[label[m]]) - zb;
       }
@@ -442,8 +439,7 @@ __global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ pa
 // is floor(|r| 2^40) (|r| < 2^23 holds for any log-depth residual).
 __device__ __forceinline__ unsigned long long merge_key(const uint32_t* eidx, const int* label, const float* zfill,
                                                          const double* S, const double* eom, int W, int i) {
-  int a, b;
-  bool h;
+  int a, b, h;
   edge_ends(eidx[i], W, a, b, h);
   const double r = ((double)zfill[a] + S[label[a]]) - ((double)zfill[b] + S[label[b]]) - eom[i];
   return (unsigned long long)floor(fabs(r) * 1099511627776.0);  // 2^40
@@ -456,8 +452,7 @@ __global__ void k_merge_min(const uint32_t* __restrict__ eidx, int E, int W, con
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
   const unsigned long long k = merge_key(eidx, label, zfill, S, eom, W, i);
-  int a, b;
-  bool h;
+  int a, b, h;
   edge_ends(eidx[i], W, a, b, h);
   atomicMin(&gkey[glabel[a]], k);
   atomicMin(&gkey[glabel[b]], k);
@@ -470,8 +465,7 @@ __global__ void k_merge_code(const uint32_t* __restrict__ eidx, int E, int W, co
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
   const unsigned long long k = merge_key(eidx, label, zfill, S, eom, W, i);
-  int a, b;
-  bool h;
+  int a, b, h;
   edge_ends(eidx[i], W, a, b, h);
   const int ga = glabel[a], gb = glabel[b];
   if (gkey[ga] == k) atomicMin(&gcode[ga], eidx[i]);
@@ -486,8 +480,7 @@ __global__ void k_merge_pairs(const unsigned* __restrict__ gcode, int Kg, int W,
   const unsigned code = gcode[g];
   int o = g;
   if (code != 0xffffffffu) {
-    int a, b;
-    bool h;
+    int a, b, h;
     edge_ends(code, W, a, b, h);
     o = glabel[a] == g ? glabel[b] : glabel[a];
   }
@@ -550,13 +543,14 @@ hipError_t quot_heavy_rows(const int* row_off, int K, int* flag, int* pos, int* 
 hipError_t list_components(int n, const int* a, const int* b, const double* keep, int m, int* parent,
                            hipStream_t st);
 
-hipError_t quot_inter_edges(const int* label, const uint8_t* ebits, int P, int W, int* flag, int* epos,
-                            int* count_dev, uint32_t* eidx_raw, int* scan_tmp, hipStream_t st, int phase) {
+hipError_t quot_inter_edges(const int* label, const uint8_t* ebits, const uint8_t* eb2, int P, int W, int* flag,
+                            int* epos, int* count_dev, uint32_t* eidx_raw, int* scan_tmp, hipStream_t st, int phase) {
+  const int nd = eb2 ? 4 : 2;
   if (phase == 0) {
-    k_inter_flags<<<ni::ceil_div(P, 256), 256, 0, st>>>(label, ebits, P, W, flag);
-    return scan_exclusive_i32(flag, epos, 2 * P, count_dev, scan_tmp, st);
+    k_inter_flags<<<ni::ceil_div(P, 256), 256, 0, st>>>(label, ebits, eb2, P, W, flag);
+    return scan_exclusive_i32(flag, epos, nd * P, count_dev, scan_tmp, st);
   }
-  k_inter_compact<<<ni::ceil_div(2 * (long long)P, 256), 256, 0, st>>>(flag, epos, 2 * P, eidx_raw);
+  k_inter_compact<<<ni::ceil_div((long long)nd * P, 256), 256, 0, st>>>(flag, epos, (long long)nd * P, nd, eidx_raw);
   return hipGetLastError();
 }
 
@@ -665,6 +659,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   q.t = t;
   q.g2fx = a.g2fx;
   q.g2fy = a.g2fy;
+  q.g2fd = a.g2fd;
   q.k = a.k;
   q.lL = log10(a.L);
   q.lU = log10(a.U);
@@ -673,8 +668,8 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (a.E > 0) {
     e = hipMemsetAsync(a.wmax, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
-    k_irls_edges<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.label, a.glabel, a.ebits, a.eom, a.eta, a.etb,
-                                                        a.zfill, a.S, q, a.ew, a.erho, a.wmax);
+    k_irls_edges<<<ni::ceil_div(a.E, 256), 256, 0, st>>>(a.eidx, a.E, a.label, a.glabel, a.ebits, a.eb2, a.eom, a.eta,
+                                                        a.etb, a.zfill, a.S, q, a.ew, a.erho, a.wmax);
     k_irls_pairs<<<ni::ceil_div(a.P, 256), 256, 0, st>>>(a.pair_start, a.P, a.ew, a.erho, a.wmax, a.cut_rel, a.pW,
                                                         a.pB);
   }

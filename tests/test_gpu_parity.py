@@ -54,7 +54,7 @@ def oracle_params(p):
     only integrate) runs the same loop."""
     op = dict(theta_c_deg=p.theta_c_deg, irls_iters=p.irls_iters, align_iters=p.align_iters, bini_k=p.bini_k,
               out_L=p.out_L, out_U=p.out_U, outlier_mode=p.outlier_mode, delta_e_max=p.delta_e_max,
-              w_cut_rel=p.w_cut_rel, freq_merging=p.freq_merging, variant=p.variant)
+              w_cut_rel=p.w_cut_rel, freq_merging=p.freq_merging, variant=p.variant, connectivity=p.connectivity)
     return O.baseline_params(op) if p.variant == 1 else op
 
 
@@ -241,7 +241,7 @@ def fill_tolerance_sensitivity(s, op, ref, seed=0):
     precision on the HIP path).  Only the oracle runs here.  Above 0.5 the
     end-to-end output is not determined to the bound by what the fill
     specification fixes, and the whole path is compared stage by stage."""
-    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"])
+    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"], op.get("connectivity", 4))
     lab, K = ref.labels, ref.K
     zf = ref.zfill
     Lap, rhs = O._intra_system(e, lab)
@@ -302,7 +302,7 @@ def irls_chaos(s, op, lab, K, zf, seed=0):
     Only the oracle runs here.  Above 0.5 the T-step loop is not determined
     by FP64 arithmetic on this input (the reweighting amplifies rounding
     from step to step), and the loop is compared one step at a time."""
-    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"])
+    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"], op.get("connectivity", 4))
     S, _, _ = O.irls(e, lab, K, zf, op)
     d0, _, _ = O.finalize(e, lab, zf, S)
     rng = np.random.default_rng(seed)
@@ -327,7 +327,7 @@ def check_irls_steps(ctx, s, p, op, lab, K, zf, what, steps=None):
     """The relative-scale loop one iteration at a time: from the oracle's
     scales before step t, the library's increment s^(t) and energy E_t
     against the oracle's (log-scale bound 1e-4, energy 1e-6 relative)."""
-    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"])
+    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"], op.get("connectivity", 4))
     trace = []
     O.irls(e, lab, K, zf, op, trace=trace)
     T = len(trace)
@@ -364,7 +364,7 @@ def check_whole_path(ctx, s, p, out, ref, what):
         return "end-to-end"
     log(f"[{what}] fill-tolerance sensitivity {sens:.2f} of the bound: stage-wise comparison")
     z, frep = ctx.ni_fill(dev(s.normals), dev(s.mask), s.cam.as_dict(), dev(ref.labels), ref.K, p)
-    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"])
+    e = O.edges(s.normals, s.mask, s.cam, op["theta_c_deg"], op.get("connectivity", 4))
     assert_fill_close(e, ref.labels, ref.K, z.cpu().numpy().astype(np.float64), ref.zfill, what)
     z32 = fp32(ref.zfill)
     chaos = irls_chaos(s, op, ref.labels, ref.K, z32)
@@ -606,7 +606,7 @@ def test_capacity_too_small(ctx):
 def test_bad_arguments(ctx):
     import paper_2510_11508_amd as ni
     s = synth.tiny(0)
-    for kw in [dict(connectivity=8), dict(irls_iters=0), dict(outlier_mode=5), dict(out_L=1e-2),
+    for kw in [dict(connectivity=6), dict(irls_iters=0), dict(outlier_mode=5), dict(out_L=1e-2),
                dict(warm_start=1), dict(fill_chunk=300), dict(fill_chunk=1024, fill_split=2),
                dict(fill_precond=2), dict(fill_mg_maxit=-1)]:
         log(f"[edge] bad params {kw}")

@@ -27,9 +27,9 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def both(ctx, s, theta):
+def both(ctx, s, theta, conn=4):
     import paper_2510_11508_amd as ni
-    p = ni.ni_params_default(theta_c_deg=theta)
+    p = ni.ni_params_default(theta_c_deg=theta, connectivity=conn)
     n, m = dev(s.normals), dev(s.mask)
     ref, Kr, _ = ctx.ni_label(n, m, s.cam.as_dict(), p)
     lab = torch.full(tuple(s.mask.shape), 12345, dtype=torch.int32, device="cuda")
@@ -43,6 +43,15 @@ def test_noalloc_labels_equal_ni_label(ctx):
         s = synth.make(name, seed)
         print(f"[noalloc] {name} seed {seed} theta {theta}", flush=True)
         K, lab, Kr, ref = both(ctx, s, theta)
+        assert K == Kr and np.array_equal(lab, ref)
+
+
+def test_noalloc_labels_8_connectivity(ctx):
+    """8-connectivity: the diagonal edge bits take one more byte per pixel
+    of the scratch; at the pixel limit too."""
+    for s, theta in [(synth.make("c2", 0), 2.0), (synth.make("c1", 0), 180.0), (synth.tiny(6, 1024, 1024), 2.0)]:
+        print(f"[noalloc] 8-connectivity {s.mask.shape} theta {theta}", flush=True)
+        K, lab, Kr, ref = both(ctx, s, theta, 8)
         assert K == Kr and np.array_equal(lab, ref)
 
 
