@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define NI_ABI_VERSION 2
+#define NI_ABI_VERSION 3
 #define NI_MAX_IRLS 256
 
 typedef enum {
@@ -87,8 +87,8 @@ typedef struct {
                            first stops at ||r|| <= q_rtol ||b_abs|| (b_abs =
                            row sums of the pair terms' magnitudes), the
                            second solves for the correction from the
-                           flow-form residual b - L s to q_rtol of that
-                           residual (at least 1e-13 ||b_abs||)              */
+                           flow-form residual b - L s to q_rtol_refine of
+                           that residual (at least 1e-13 ||b_abs||)         */
   int32_t q_max_iter;   /* iteration cap of each round; reaching it makes the
                            call return NI_E_NOTCONV (outputs still written) */
   int32_t warm_start;   /* 0 zero start; 1 learned start (needs ni_unet_load) */
@@ -122,6 +122,8 @@ typedef struct {
                            the BiNI weight at z = 0), outlier weights from
                            the second iteration, no merging; theta_c,
                            align_iters and freq_merging are ignored      */
+  double q_rtol_refine; /* relative target of the quotient solve's second
+                           (refinement) round, see q_rtol                  */
 } ni_params;
 
 typedef struct {
@@ -159,6 +161,8 @@ typedef struct {
   int64_t fill_large_px;  /* pixels of the components on the large path    */
   int32_t merges;         /* merge steps taken (freq_merging > 0)          */
   int32_t nodes_final;    /* quotient nodes after the last merge (K if none) */
+  int32_t quot_iters_refine[NI_MAX_IRLS]; /* of quot_iters: the refinement
+                                             round's iterations           */
 } ni_report;
 
 typedef struct ni_ctx ni_ctx;

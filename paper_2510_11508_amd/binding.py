@@ -36,7 +36,11 @@ class ni_params(C.Structure):
                 ("q_rtol", C.c_double), ("q_max_iter", C.c_int32), ("warm_start", C.c_int32),
                 ("graphs", C.c_int32), ("fill_chunk", C.c_int32), ("fill_split", C.c_int32),
                 ("fill_precond", C.c_int32), ("fill_mg_maxit", C.c_int32), ("freq_merging", C.c_int32),
-                ("variant", C.c_int32)]
+                ("variant", C.c_int32), ("q_rtol_refine", C.c_double)]
+
+
+# layout version of the structs below (NI_ABI_VERSION in include/ni.h)
+ABI_VERSION = 3
 
 
 class ni_report(C.Structure):
@@ -53,13 +57,14 @@ class ni_report(C.Structure):
                 ("ms_total", C.c_float), ("ms_large_kernel", C.c_float), ("fill_chunk", C.c_int32),
                 ("fill_split", C.c_int32), ("fill_mg_levels", C.c_int32), ("ms_fill_mg_build", C.c_float),
                 ("fill_mg_bytes", C.c_double), ("fill_mg_fallback", C.c_int32),
-                ("fill_large_px", C.c_int64), ("merges", C.c_int32), ("nodes_final", C.c_int32)]
+                ("fill_large_px", C.c_int64), ("merges", C.c_int32), ("nodes_final", C.c_int32),
+                ("quot_iters_refine", C.c_int32 * NI_MAX_IRLS)]
 
     def as_dict(self):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            if name in ("quot_iters", "energy"):
+            if name in ("quot_iters", "energy", "quot_iters_refine"):
                 v = list(v)[: max(self.irls_iters_run, 0)]
             d[name] = v
         return d
@@ -110,6 +115,9 @@ def lib():
             if name not in ("ni_status_str", "ni_last_error", "ni_abi_version", "ni_unet_param_count",
                             "ni_unet_blob_size"):
                 getattr(L, name).restype = C.c_int
+        if L.ni_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.ni_abi_version()}, this binding expects "
+                               f"{ABI_VERSION}: rebuild the library")
         _lib = L
     return _lib
 

@@ -272,7 +272,8 @@ ni_status validate(ni_ctx* c, const float* normals, const uint8_t* mask, int32_t
   if (prm->connectivity != 4 && prm->connectivity != 8) return bad("connectivity must be 4 or 8");
   if (prm->irls_iters < 1 || prm->irls_iters > NI_MAX_IRLS) return bad("irls_iters out of range");
   if (prm->align_iters < 0) return bad("align_iters < 0");
-  if (!(prm->cg_rtol > 0) || prm->cg_max_iter < 1 || !(prm->q_rtol > 0) || prm->q_max_iter < 1)
+  if (!(prm->cg_rtol > 0) || prm->cg_max_iter < 1 || !(prm->q_rtol > 0) || prm->q_max_iter < 1 ||
+      !(prm->q_rtol_refine > 0 && prm->q_rtol_refine < 1))
     return bad("bad CG tolerance / iteration cap");
   if (!(prm->out_L > 0 && prm->out_U > prm->out_L)) return bad("need 0 < out_L < out_U");
   if (prm->outlier_mode < 0 || prm->outlier_mode > 2) return bad("outlier_mode must be 0, 1 or 2");
@@ -940,7 +941,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.g2fy = persp ? pb.cam.fy * pb.cam.fy : 1.0;
   a.g2fd = persp ? pb.cam.fx * pb.cam.fy : 1.0;
   a.k = pb.prm.bini_k; a.L = pb.prm.out_L; a.U = pb.prm.out_U; a.cut_rel = pb.prm.w_cut_rel;
-  a.q_rtol = pb.prm.q_rtol; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
+  a.q_rtol = pb.prm.q_rtol; a.q_rtol2 = pb.prm.q_rtol_refine; a.align = pb.prm.align_iters; a.outlier_mode = pb.prm.outlier_mode;
   a.out_from = pb.prm.variant == 1 ? 1 : 0;
   a.q_maxit = pb.prm.q_max_iter;
   a.host_flag = c->host + 32;
@@ -1042,6 +1043,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
       rep->irls_iters_run = 1;
       rep->energy[0] = *hook.e;
       rep->quot_iters[0] = qa + qb;
+      rep->quot_iters_refine[0] = qb;
       rep->n_inter_edges = E;
       rep->n_pairs = Pp;
     }
@@ -1137,6 +1139,7 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     for (int t = 0; t < NI_MAX_IRLS; ++t) {
       rep->energy[t] = t < ran ? en[t] : 0.0;
       rep->quot_iters[t] = t < ran ? qi[t] + qi2[t] : 0;
+      rep->quot_iters_refine[t] = t < ran ? qi2[t] : 0;
     }
     rep->ms_irls = ev_ms(c, 8, 9);
     rep->ms_finalize = ev_ms(c, 9, 10);
@@ -1189,6 +1192,7 @@ ni_status ni_params_default(ni_params* p) {
   p->cg_rtol = 1e-6;
   p->cg_max_iter = 50000;
   p->q_rtol = 1e-5;
+  p->q_rtol_refine = 1e-5;
   p->q_max_iter = 20000;
   p->warm_start = 0;
   p->graphs = 0;

@@ -44,27 +44,38 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
-// Atomic accumulation of (a, b) into (da[key], db[key]).  When every valid
-// lane of the wavefront has the same key (the common case: one giant piece
-// or region), the wavefront sums first and issues one pair of atomics
-// instead of 64.  Every lane of the wavefront must call it.
+// Atomic accumulation of (a, b) into (da[key], db[key]).  The wavefront
+// groups its lanes by key: each round takes the key of the lowest lane
+// still pending, sums the lanes that share it and issues one pair of
+// atomics.  One round when every lane has the same key (the common case:
+// one giant piece or region); a few when a giant key is interleaved with
+// small ones, which would otherwise send up to 64 atomics to one address
+// per wavefront.  Lanes left after ACC_ROUNDS rounds add directly.  Every
+// lane of the wavefront must call it.
+constexpr int ACC_ROUNDS = 4;
+
 template <class TB>
 __device__ __forceinline__ void acc_by_key(bool valid, int key, double a, TB b, double* da, TB* db) {
-  const int lead = __shfl(key, 0, NI_WAVE);
-  const bool lead_valid = __shfl(valid ? 1 : 0, 0, NI_WAVE) != 0;
-  if (lead_valid && __all(!valid || key == lead)) {
-    double sa = valid ? a : 0.0;
-    TB sb = valid ? b : TB(0);
+  const int lane = threadIdx.x & (NI_WAVE - 1);
+  unsigned long long pend = __ballot(valid);
+  for (int round = 0; round < ACC_ROUNDS && pend; ++round) {
+    const int lead = __ffsll(pend) - 1;
+    const int k = __shfl(key, lead, NI_WAVE);
+    const bool mine = valid && key == k;
+    double sa = mine ? a : 0.0;
+    TB sb = mine ? b : TB(0);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       sa += __shfl_xor(sa, o, NI_WAVE);
       sb += __shfl_xor(sb, o, NI_WAVE);
     }
-    if ((threadIdx.x & (NI_WAVE - 1)) == 0) {
-      atomicAdd(&da[lead], sa);
-      atomicAdd(&db[lead], sb);
+    if (lane == lead) {
+      atomicAdd(&da[k], sa);
+      atomicAdd(&db[k], sb);
     }
-  } else if (valid) {
+    pend &= ~__ballot(mine);
+  }
+  if ((pend >> lane) & 1ull) {
     atomicAdd(&da[key], a);
     atomicAdd(&db[key], b);
   }
@@ -72,16 +83,19 @@ __device__ __forceinline__ void acc_by_key(bool valid, int key, double a, TB b, 
 
 // One-value form of acc_by_key.
 __device__ __forceinline__ void acc1_by_key(bool valid, int key, double a, double* da) {
-  const int lead = __shfl(key, 0, NI_WAVE);
-  const bool lead_valid = __shfl(valid ? 1 : 0, 0, NI_WAVE) != 0;
-  if (lead_valid && __all(!valid || key == lead)) {
-    double sa = valid ? a : 0.0;
+  const int lane = threadIdx.x & (NI_WAVE - 1);
+  unsigned long long pend = __ballot(valid);
+  for (int round = 0; round < ACC_ROUNDS && pend; ++round) {
+    const int lead = __ffsll(pend) - 1;
+    const int k = __shfl(key, lead, NI_WAVE);
+    const bool mine = valid && key == k;
+    double sa = mine ? a : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) sa += __shfl_xor(sa, o, NI_WAVE);
-    if ((threadIdx.x & (NI_WAVE - 1)) == 0) atomicAdd(&da[lead], sa);
-  } else if (valid) {
-    atomicAdd(&da[key], a);
+    if (lane == lead) atomicAdd(&da[k], sa);
+    pend &= ~__ballot(mine);
   }
+  if ((pend >> lane) & 1ull) atomicAdd(&da[key], a);
 }
 
 // Block-wide sum of NV doubles; every thread receives the totals.  `scratch`
@@ -246,7 +260,8 @@ struct IrlsArgs {
   int* qiters_out;     // [t] iterations of the first solve round
   int* qiters2_out;    // [t] iterations of the refinement round
   double* epart;
-  double g2fx, g2fy, g2fd, k, L, U, cut_rel, q_rtol;  // g2f*: f^2 per right, down, diagonal row
+  double g2fx, g2fy, g2fd, k, L, U, cut_rel, q_rtol;
+  double q_rtol2 = 1e-5;  // relative target of the refinement round  // g2f*: f^2 per right, down, diagonal row
   int align, outlier_mode, q_maxit, nnz;
   int out_from;  // first iteration with outlier weights (the baseline: 1)
   int* qcol;

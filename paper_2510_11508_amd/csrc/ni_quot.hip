@@ -709,7 +709,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
     e = amg_solve(a.amg, a.rhs, a.babs, nullptr, 0.0, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag,
                   a.graphs != 0, st);
   // round 2 (refinement): the residual of s in flow form, then the
-  // correction d from zero to ||r_d|| <= max(q_rtol ||b - L s||, 1e-13
+  // correction d from zero to ||r_d|| <= max(q_rtol2 ||b - L s||, 1e-13
   // ||b_abs||), s += d.  The recursive residual of round 1 carries rounding
   // at the scale of the heaviest rows; the flow-form residual restores what
   // the light links say, and the correction solve, whose right-hand side
@@ -725,7 +725,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   }
   if (e == hipSuccess) center(a.t0);
   if (e == hipSuccess)
-    e = amg_solve(a.amg, a.t0, a.t0, a.babs, 1e-13, a.t1, a.q_rtol, a.q_maxit, a.qiters2_out + t, a.host_flag,
+    e = amg_solve(a.amg, a.t0, a.t0, a.babs, 1e-13, a.t1, a.q_rtol2, a.q_maxit, a.qiters2_out + t, a.host_flag,
                   a.graphs != 0, st);
   if (e == hipSuccess) {
     k_add_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.s, a.t1, a.K);

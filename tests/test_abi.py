@@ -37,9 +37,10 @@ def test_host_only_calls():
     p = ni.ni_params_default()
     assert (p.theta_c_deg, p.irls_iters, p.align_iters, p.out_L, p.out_U) == (2.0, 15, 2, 1e-5, 1e-3)
     assert p.cg_rtol == 1e-6 and p.connectivity == 4 and p.outlier_mode == 1
+    assert p.q_rtol == 1e-5 and p.q_rtol_refine == 1e-5
     assert L.ni_params_default(None) == ni.NI_E_ARG
     assert L.ni_status_str(ni.NI_E_SHAPE) == b"output capacity too small"
-    assert L.ni_abi_version() == 2
+    assert L.ni_abi_version() == 3
     assert L.ni_destroy(None) == ni.NI_E_ARG
     assert L.ni_integrate(None, None, None, 1, 1, None, None, None, None, None, 0, None, None) == ni.NI_E_ARG
 
