@@ -1032,9 +1032,16 @@ struct Amg {
   double corr = 1.0;   // coarse-correction factor
   DBuf s[NSCR];
   DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst;
+  // host readbacks of the build: a pinned landing area, and the counts
+  // that only the solve needs (heavy rows and aggregates per level),
+  // gathered in device slots and read once at the end of the build
+  int* hpin = nullptr;
+  DBuf cnts;
+  std::vector<int*> pend;
   hipStream_t cap = nullptr;  // capture stream of the iteration graph
   ~Amg() {
     if (cap) (void)hipStreamDestroy(cap);
+    if (hpin) (void)hipHostFree(hpin);
     for (AmgLevel* L : lv) {
       DBuf* b[] = {&L->mem_off_b, &L->mem_b, &L->mheavy_b, &L->gal_off_b, &L->gal_src_b, &L->cid_b, &L->plo_b,
                    &L->phi_b, &L->row_off_b, &L->ent_b, &L->col_b, &L->heavy_b, &L->pw_b, &L->w_b, &L->diag_b,
@@ -1045,7 +1052,7 @@ struct Amg {
     }
     for (DBuf& d : s)
       if (d.p) (void)hipFree(d.p);
-    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst};
+    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts};
     for (DBuf* d : own)
       if (d->p) (void)hipFree(d->p);
   }
@@ -1086,10 +1093,35 @@ void amg_set_corr(Amg* a, double corr) {
   if (a) a->corr = corr;
 }
 
-static hipError_t read_int(const int* dev, int* host, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(host, dev, sizeof(int), hipMemcpyDeviceToHost, st);
+#define AMG_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+constexpr int NCNT = 2 * AMAXL + 2;  // deferred count slots
+
+static hipError_t read_int(Amg* A, const int* dev, int* host, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(A->hpin + NCNT, dev, sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) *host = A->hpin[NCNT];
   return e;
+}
+
+// a device slot whose value lands in *dest at the end of the build
+static int* defer_count(Amg* A, int* dest) {
+  A->pend.push_back(dest);
+  return static_cast<int*>(A->cnts.p) + (A->pend.size() - 1);
+}
+
+static hipError_t flush_counts(Amg* A, hipStream_t st) {
+  if (A->pend.empty()) return hipSuccess;
+  const size_t n = A->pend.size();
+  AMG_TRY(hipMemcpyAsync(A->hpin, A->cnts.p, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  AMG_TRY(hipStreamSynchronize(st));
+  for (size_t k = 0; k < n; ++k) *A->pend[k] = A->hpin[k];
+  A->pend.clear();
+  return hipSuccess;
 }
 
 static int bits_for(int n) {
@@ -1098,11 +1130,6 @@ static int bits_for(int n) {
   return b;
 }
 
-#define AMG_TRY(x)                      \
-  do {                                  \
-    hipError_t e_ = (x);                \
-    if (e_ != hipSuccess) return e_;    \
-  } while (0)
 
 // rows (or members) with more than AH entries of an offset array
 static hipError_t heavy_list(Amg* A, int n, const int* off, DBuf& out, int* count, const int*& view,
@@ -1111,14 +1138,13 @@ static hipError_t heavy_list(Amg* A, int n, const int* off, DBuf& out, int* coun
   int* flag = grow<int>(A->s[14], n, err);
   int* pos = grow<int>(A->s[15], n + 1, err);
   int* list = grow<int>(out, n, err);
-  int* tot = grow<int>(A->ctr, 8, err);
   int* scan = grow<int>(A->scan, scan_tmp_ints(n + 1), err);
   AMG_TRY(err);
   k_am_heavy_flag<<<nb256(n), 256, 0, st>>>(n, off, flag);
-  AMG_TRY(scan_exclusive_i32(flag, pos, n, tot, scan, st));
+  AMG_TRY(scan_exclusive_i32(flag, pos, n, defer_count(A, count), scan, st));
   k_am_list<<<nb256(n), 256, 0, st>>>(n, flag, pos, list);
   view = list;
-  return read_int(tot, count, st);
+  return hipGetLastError();
 }
 
 // CSR (row_off, ent, col) of a level's pair list, and its heavy rows
@@ -1201,7 +1227,7 @@ static hipError_t geo_aggregate(Amg* A, const AmgLevel* F, int l, int gw, int gh
   k_gm_keys<<<nb256(n), 256, 0, st>>>(n, F->diag, F->gy, F->gx, F->gc, bx, kcell, kcomp, flag);
   AMG_TRY(scan_exclusive_i32(flag, fpos, n, tot, scan, st));
   int m = 0;
-  AMG_TRY(read_int(tot, &m, st));
+  AMG_TRY(read_int(A, tot, &m, st));
   if (m <= 0) return hipGetLastError();
   k_am_compact<<<nb256(n), 256, 0, st>>>(n, flag, fpos, kcell, ko, vo);
   AMG_TRY(radix_sort_pairs(ko, vo, k1, v1, tk, tv, m, std::max(bx + by, 1), scan, st));
@@ -1245,7 +1271,10 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
     for (int i = 0; i < NSCR; ++i) grow<uint32_t>(A->s[i], big, err);
     grow<int>(A->scan, std::max(radix_tmp_ints((int)big), scan_tmp_ints((int)big)), err);
     grow<int>(A->ctr, 8, err);
+    grow<int>(A->cnts, NCNT, err);
     AMG_TRY(err);
+    if (!A->hpin) AMG_TRY(hipHostMalloc(reinterpret_cast<void**>(&A->hpin), (NCNT + 4) * sizeof(int)));
+    A->pend.clear();
   }
   AMG_TRY(heavy_list(A, K, row_off, L0->heavy_b, &L0->nheavy, L0->heavy, st));
   int* tot = static_cast<int*>(A->ctr.p);
@@ -1283,7 +1312,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
     }
     AMG_TRY(scan_exclusive_i32(lead, pos, n, tot, scan, st));
     int nc = 0;
-    AMG_TRY(read_int(tot, &nc, st));
+    AMG_TRY(read_int(A, tot, &nc, st));
     if (nc <= 0 || nc > (int)(0.9 * n)) break;  // no edges left, or coarsening stalled
     k_am_cid<<<nb256(n), 256, 0, st>>>(n, agg2, pos, cid, flag);
     F->cid = cid;
@@ -1316,7 +1345,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
       AMG_TRY(err);
       AMG_TRY(scan_exclusive_i32(flag, fpos, n, tot, scan, st));
       int m = 0;
-      AMG_TRY(read_int(tot, &m, st));
+      AMG_TRY(read_int(A, tot, &m, st));
       k_am_compact<<<nb256(n), 256, 0, st>>>(n, flag, fpos, cid, ko, vo);
       AMG_TRY(radix_sort_pairs(ko, vo, ks, vs, kt, vt, m, bits_for(nc), scan, st));
       k_am_u32<<<nb256(m), 256, 0, st>>>(vs, m, mem);
@@ -1329,10 +1358,9 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
       int* hl = grow<int>(C->mheavy_b, nc, err);
       AMG_TRY(err);
       k_am_heavy_flag<<<nb256(nc), 256, 0, st>>>(nc, mem_off, hf);
-      AMG_TRY(scan_exclusive_i32(hf, hp, nc, tot, scan, st));
+      AMG_TRY(scan_exclusive_i32(hf, hp, nc, defer_count(A, &C->nmheavy), scan, st));
       k_am_list<<<nb256(nc), 256, 0, st>>>(nc, hf, hp, hl);
       C->mheavy = hl;
-      AMG_TRY(read_int(tot, &C->nmheavy, st));
     }
     // ---- coarse pairs: fine pairs between two aggregates, grouped by (lo, hi)
     {
@@ -1357,7 +1385,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
       if (npf > 0) {
         k_am_pflag<<<nb256(npf), 256, 0, st>>>(npf, F->plo, F->phi, cid, pflag);
         AMG_TRY(scan_exclusive_i32(pflag, ppos, npf, tot, scan, st));
-        AMG_TRY(read_int(tot, &mp, st));
+        AMG_TRY(read_int(A, tot, &mp, st));
       }
       int npc = 0;
       if (mp > 0) {
@@ -1368,7 +1396,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
         AMG_TRY(radix_sort_pairs(k2, o1, k3, ord, tk, tv, mp, bc, scan, st));     // stably by lo
         k_am_runs<<<nb256(mp), 256, 0, st>>>(mp, ord, klo, khi, rflag);
         AMG_TRY(scan_exclusive_i32(rflag, rpos, mp, tot, scan, st));
-        AMG_TRY(read_int(tot, &npc, st));
+        AMG_TRY(read_int(A, tot, &npc, st));
       }
       int* plo = grow<int>(C->plo_b, npc, err);
       int* phi = grow<int>(C->phi_b, npc, err);
@@ -1395,6 +1423,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
   A->nlev = l + 1;
   AmgLevel* Lc = A->lv[l];
   Lc->cid = nullptr;
+  AMG_TRY(flush_counts(A, st));
   // cycle vectors
   for (int k = 0; k < A->nlev; ++k) {
     AmgLevel* L = A->lv[k];
@@ -1478,7 +1507,8 @@ static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts
 // (device).  The host polls the "still iterating" flag every `batch`
 // iterations.
 hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const double* floorv, double floor_rel,
-                     double* s, double rtol, int maxit, int* iters_out, int* host_flag, bool graph, hipStream_t st) {
+                     double* s, double rtol, int maxit, int* iters_out, int* host_flag, bool graph, hipStream_t st,
+                     int* hint) {
   hipError_t err = hipSuccess;
   AmgLevel* L0 = A->lv[0];
   const int n = L0->n;
@@ -1543,18 +1573,30 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const doubl
                                                       maxit, done, flag, iters_out);
     k_cg_xr_f<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts, pstride, pstride, it, done);
   };
-  const int batch = 8;
-  for (int it = 0; it <= maxit + 1; it += batch) {
+  // The host launches a batch of iterations, then reads the flag; the
+  // iterations launched after convergence return at once but still cost a
+  // dispatch each.  With a hint (the iteration count of the previous
+  // solve of this kind) the first batch stops just short of it and the
+  // next ones are short; without one, or past the hint, batches of 8.
+  int* hp = A->hpin + NCNT + 1;  // [0] flag, [1] iterations
+  const int expect = hint ? *hint : 0;
+  int batch = expect > 0 ? std::max(expect - 1, 1) : 8;
+  for (int it = 0; it <= maxit + 1;) {
     for (int k = 0; k < batch; ++k) {
       if (ge) AMG_TRY(hipGraphLaunch(ge, st));
       else if (fuse) fused(it + k);
       else iteration(st);
     }
+    it += batch;
     AMG_TRY(hipGetLastError());
-    AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    AMG_TRY(hipMemcpyAsync(hp, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    AMG_TRY(hipMemcpyAsync(hp + 1, iters_out, sizeof(int), hipMemcpyDeviceToHost, st));
     AMG_TRY(hipStreamSynchronize(st));
-    if (*host_flag == 0) break;
+    if (hp[0] == 0) break;
+    batch = (expect > 0 && it <= expect + 4) ? 2 : 8;
   }
+  *host_flag = hp[0];
+  if (hint) *hint = hp[1];
   return hipSuccess;
 }
 

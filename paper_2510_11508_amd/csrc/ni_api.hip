@@ -945,6 +945,8 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.out_from = pb.prm.variant == 1 ? 1 : 0;
   a.q_maxit = pb.prm.q_max_iter;
   a.host_flag = c->host + 32;
+  int hints[2] = {0, 0};
+  a.hints = hints;
   // The quotient structure of a node labelling (the components, or merged
   // nodes after a merge): inter edges, sorted pairs, CSR, heavy rows and the
   // FP64 edge geometry.  A rebuild after a merge only shrinks every size,

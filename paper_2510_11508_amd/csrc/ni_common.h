@@ -233,9 +233,11 @@ hipError_t amg_fill_solve(Amg*, const int* comp, const int* list, int nl, int K,
                           int* host_flag, int* its, hipStream_t st);
 hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
 // PCG preconditioned by one V-cycle: s from zero until ||r|| <= max(rtol
-// ||scale||, floor_rel ||floorv||) (floorv may be null)
+// ||scale||, floor_rel ||floorv||) (floorv may be null).  hint (host, may
+// be null): the expected iteration count in, the count run out.
 hipError_t amg_solve(Amg*, const double* rhs, const double* scale, const double* floorv, double floor_rel, double* s,
-                     double rtol, int maxit, int* iters_out, int* host_flag, bool graph, hipStream_t st);
+                     double rtol, int maxit, int* iters_out, int* host_flag, bool graph, hipStream_t st,
+                     int* hint = nullptr);
 
 // arguments of one relative-scale iteration (ni_quot.hip)
 struct IrlsArgs {
@@ -270,6 +272,7 @@ struct IrlsArgs {
   const int* heavy;
   int nheavy, nbig;
   Amg* amg;   // multigrid of the quotient solve
+  int* hints = nullptr;  // host [2]: iterations of the last first / refinement round (poll batching)
   int graphs; // replay the multigrid iteration from a HIP graph
 };
 hipError_t merge_nodes(const IrlsArgs& a, int* grp, int* glabel_out, int P, unsigned long long* gkey, unsigned* gcode,

@@ -707,7 +707,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   // |B_p|, a scale of the right-hand side that does not cancel)
   if (e == hipSuccess)
     e = amg_solve(a.amg, a.rhs, a.babs, nullptr, 0.0, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag,
-                  a.graphs != 0, st);
+                  a.graphs != 0, st, a.hints);
   // round 2 (refinement): the residual of s in flow form, then the
   // correction d from zero to ||r_d|| <= max(q_rtol2 ||b - L s||, 1e-13
   // ||b_abs||), s += d.  The recursive residual of round 1 carries rounding
@@ -726,7 +726,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (e == hipSuccess) center(a.t0);
   if (e == hipSuccess)
     e = amg_solve(a.amg, a.t0, a.t0, a.babs, 1e-13, a.t1, a.q_rtol2, a.q_maxit, a.qiters2_out + t, a.host_flag,
-                  a.graphs != 0, st);
+                  a.graphs != 0, st, a.hints ? a.hints + 1 : nullptr);
   if (e == hipSuccess) {
     k_add_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.s, a.t1, a.K);
     e = hipGetLastError();
