@@ -7,9 +7,11 @@ system stopped at ||r_c|| <= 1e-6 ||b_c||.  Prints ONE JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
 
 The default workload is c5 (4096^2, the largest single-GPU configuration).
-Beside the zero-start rate (`value`) the line carries the learned warm
-start at the same residual, the pixel-level form (every pixel its own
-component) and the FP64 oracle on this host.
+Beside the zero-start rate (`value`) the line carries, on the same map: the
+learned warm start at the same residual, optional merging every 5
+iterations, 8-connectivity, the pixel-level form (every pixel its own
+component), the pixel-level log-depth baseline without discontinuity term
+(ND), and the FP64 oracle on this host.
 
 roofline: one PCG iteration of the batched fill of the large components
 (the multigrid-preconditioned CG over all of them at once).  Algorithmic
@@ -24,7 +26,6 @@ traffic = calibrated FETCH_SIZE + WRITE_SIZE per iteration from committed
 counter runs (profiles/fill_mg_traffic_<workload>.json, written by
 --digest-counters), while they match the kernel sources.
 """
-import os
 import os
 
 # the oracle's CPU baseline is timed single-threaded: pin BLAS pools before numpy loads
@@ -173,7 +174,7 @@ def digest_counters(workload, fetch_dir, write_dir):
         for c in ("FETCH_SIZE", "WRITE_SIZE"):
             f.write(f"    cd /tmp && timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d <dir_{c}> -o run -- "
                     f"python3 <repo>/bench.py --workload {workload} --steps 1 --warmup 0 --no-cpu-baseline "
-                    f"--no-warm --no-pixel-level --copy-calibration > <dir_{c}>/bench.json\n")
+                    f"--no-warm --no-pixel-level --no-merging --no-baseline --no-conn8 --copy-calibration > <dir_{c}>/bench.json\n")
         f.write(f"    python3 <repo>/bench.py --workload {workload} --digest-counters <dir_FETCH_SIZE> <dir_WRITE_SIZE>\n\n")
         f.write(f"Fill-solve kernels (`{FILL_KERNELS}`), {its} iterations.\n\n")
         f.write("| counter | copy reading (KiB) | factor | fill solve (KiB) | per iteration (MB) |\n|---|---|---|---|---|\n")
@@ -215,7 +216,7 @@ def digest_trace(workload, d):
         f.write("Command (from the repository root on the GPU box):\n\n")
         f.write(f"    cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 "
                 f"<repo>/bench.py --workload {workload} --steps {line['steps']} --warmup {line['warmup']} "
-                "--no-cpu-baseline --no-warm --no-pixel-level > <dir>/bench.json\n")
+                "--no-cpu-baseline --no-warm --no-pixel-level --no-merging --no-baseline --no-conn8 > <dir>/bench.json\n")
         f.write(f"    python3 <repo>/bench.py --workload {workload} --digest-trace <dir>\n\n")
         f.write(f"{calls} ni_integrate calls. Kernel time {tot / 1e6 / calls:,.2f} ms per call; "
                 f"bench ms_per_step {line['ms_per_step']} (event-timed stages: {line['stages_ms']}).\n\n")
@@ -225,6 +226,26 @@ def digest_trace(workload, d):
                 f"{line['roofline']['ms_per_iteration'] * 1e3:,.1f} us (it also spans the gaps between launches).\n")
         f.write(f"- Relative-scale solves (quotient multigrid PCG, `<0>` kernels): {quot_ns / 1e6 / calls:,.2f} ms "
                 "per call.\n\n")
+        # kernel time by part of the path (first matching pattern)
+        parts = [("fill: multigrid PCG of the large components", FILL_KERNELS),
+                 ("fill: small-component tiers", r"k_fill_small"),
+                 ("relative scales: quotient PCG (V-cycle, scalars, updates)",
+                  r"k_cy_\w+<0>|k_cg_\w+<0>|k_cg_\w+_f\b|k_cg_xr\b|k_cg_init"),
+                 ("hierarchy builds (aggregation, Galerkin sums, sorts, scans)", r"k_am_|k_gm_|k_rs_|k_scan_"),
+                 ("relative scales: weights, pieces, flow residual, energy",
+                  r"k_irls_|k_flow_|k_piece_|k_uf_union_list|k_scale_add|k_add_f64|k_q_matrix|k_sum_parts"),
+                 ("other", r".")]
+        share = {}
+        for r in rows:
+            for nm, pat in parts:
+                if re.search(pat, r["Name"]):
+                    share[nm] = share.get(nm, 0.0) + float(r["TotalDurationNs"])
+                    break
+        f.write("| part | ms per call | share |\n|---|---|---|\n")
+        for nm, _ in parts:
+            v = share.get(nm, 0.0)
+            f.write(f"| {nm} | {v / 1e6 / calls:,.2f} | {100 * v / tot:.1f}% |\n")
+        f.write("\n")
         f.write("| kernel | calls | total ms | avg us | min us | max us | share |\n|---|---|---|---|---|---|---|\n")
         for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:24]:
             nm = _short(r["Name"])
@@ -250,6 +271,7 @@ def main():
                     help="skip the optional-merging leg (freq_merging = 5, the paper's large-map setting)")
     ap.add_argument("--no-baseline", action="store_true",
                     help="skip the pixel-level log-depth baseline leg (variant 1, ND form)")
+    ap.add_argument("--no-conn8", action="store_true", help="skip the 8-connectivity leg")
     ap.add_argument("--no-pixel-level", action="store_true",
                     help="skip the pixel-level comparison (theta_c = 0: every pixel its own component)")
     ap.add_argument("--fill-schedule", default=None, metavar="CHUNK:SPLIT",
@@ -347,15 +369,24 @@ def main():
     def stage_ms(rs):
         return {k[3:]: round(float(np.mean([r[k] for r in rs])), 3) for k in rs[-1] if k.startswith("ms_")}
 
+    def depth_diff(z_ref, z_x):
+        """Relative depth difference to the main leg's output: its maximum
+        and the share of valid pixels beyond the parity bound (1e-4) and
+        beyond 1e-2 (where the relative scale of a weakly linked piece moved)."""
+        v = torch.isfinite(z_ref)
+        if not bool(v.any()):
+            return dict(max=0.0, frac_px_over_1e_4=0.0, frac_px_over_1e_2=0.0)
+        d = (z_x[v] - z_ref[v]).abs() / z_ref[v].abs().clamp_min(1e-30)
+        return dict(max=float(d.max()), frac_px_over_1e_4=float((d > 1e-4).float().mean()),
+                    frac_px_over_1e_2=float((d > 1e-2).float().mean()))
+
     warm = None
     if not a.no_warm and os.path.exists(a.model):
         ctx.ni_unet_load(open(a.model, "rb").read())
         pw = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T, warm_start=1)
         ms_w, reps_w, out_w = timed(pw)
         rw = reps_w[-1]
-        z_ref, z_w = out["depth"], out_w["depth"]
-        v = torch.isfinite(z_ref)
-        dz = float(((z_w[v] - z_ref[v]).abs() / z_ref[v].abs().clamp_min(1e-30)).max()) if bool(v.any()) else 0.0
+        dz = depth_diff(out["depth"], out_w["depth"])
         warm = dict(model=os.path.relpath(a.model, ROOT), ms_per_step=round(ms_w, 3),
                     value=round(n_valid / (ms_w / 1000.0) / 1e6, 3),
                     speedup=round(ms / ms_w, 3),
@@ -365,7 +396,7 @@ def main():
                     fill_iters_max=dict(zero=reps[-1]["fill_iters_max"], warm=rw["fill_iters_max"]),
                     fill_px_iters=dict(zero=reps[-1]["fill_px_iters"], warm=rw["fill_px_iters"]),
                     fallbacks=rw["warm_fallbacks"], max_relres=rw["fill_max_relres"],
-                    max_rel_depth_diff_vs_zero_start=dz)
+                    rel_depth_diff_vs_zero_start=dz)
         # network inference alone (features, forward, crop) on this map
         hw = int(s.mask.shape[0]) * int(s.mask.shape[1])
         for _ in range(2):
@@ -387,13 +418,25 @@ def main():
         pm = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T, freq_merging=5, **sched)
         ms_m, reps_m, out_m = timed(pm)
         rm = reps_m[-1]
-        z_ref, z_m = out["depth"], out_m["depth"]
-        v = torch.isfinite(z_ref)
-        dz = float(((z_m[v] - z_ref[v]).abs() / z_ref[v].abs().clamp_min(1e-30)).max()) if bool(v.any()) else 0.0
+        dz = depth_diff(out["depth"], out_m["depth"])
         merging = dict(freq_merging=5, ms_per_step=round(ms_m, 3), value=round(n_valid / (ms_m / 1000.0) / 1e6, 3),
                        speedup_vs_no_merging=round(ms / ms_m, 3), merges=rm["merges"],
                        nodes_final=rm["nodes_final"], stages_ms=stage_ms(reps_m), quot_iters=rm["quot_iters"],
-                       max_rel_depth_diff_vs_no_merging=dz)
+                       rel_depth_diff_vs_no_merging=dz)
+
+    conn8 = None
+    if not a.no_conn8:
+        # 8-connectivity on the same map (diagonal edges in the pixel graph,
+        # the 8-connected fill systems on the multigrid path)
+        p8 = ni.ni_params_default(theta_c_deg=2.0, irls_iters=T, connectivity=8, **sched)
+        ms_8, reps_8, out_8 = timed(p8)
+        r8 = reps_8[-1]
+        conn8 = dict(ms_per_step=round(ms_8, 3), value=round(n_valid / (ms_8 / 1000.0) / 1e6, 3), K=out_8["K"],
+                     n_inter_edges=r8["n_inter_edges"], stages_ms=stage_ms(reps_8),
+                     fill=dict(iters_max=r8["fill_iters_max"], px_iters=r8["fill_px_iters"],
+                               mg_levels=r8["fill_mg_levels"], mg_iterations=r8["fill_large_launches"],
+                               max_relres=r8["fill_max_relres"]),
+                     quot_iters=r8["quot_iters"])
 
     pixel = None
     if not a.no_pixel_level:
@@ -474,6 +517,8 @@ def main():
         line["warm_start"] = warm
     if merging is not None:
         line["merging"] = merging
+    if conn8 is not None:
+        line["connectivity8"] = conn8
     if pixel is not None:
         line["pixel_level"] = pixel
     if baseline is not None:
