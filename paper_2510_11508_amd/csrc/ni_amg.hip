@@ -855,9 +855,15 @@ __global__ void __launch_bounds__(ANT) k_fs_scal0(const int* __restrict__ list, 
                                                   const double* __restrict__ bbc, int* __restrict__ reset, int warm,
                                                   int* __restrict__ iters, int* __restrict__ stats,
                                                   double* __restrict__ sc, int* __restrict__ done,
-                                                  int* __restrict__ itc, int* __restrict__ flag) {
+                                                  int* __restrict__ itc, int* __restrict__ flag,
+                                                  int* __restrict__ frozen, double* __restrict__ rzc,
+                                                  double* __restrict__ pqc, int* __restrict__ open) {
+  if (threadIdx.x == 0) *open = 0;
   for (int i = threadIdx.x; i < nl; i += blockDim.x) {
     const int c = list[i];
+    frozen[c] = 0;
+    rzc[c] = 0.0;
+    pqc[c] = 0.0;
     const bool rs = warm && !(rrc[c] < bbc[c]);
     reset[c] = rs ? 1 : 0;
     if (rs) {
@@ -885,59 +891,6 @@ __global__ void k_fs_reset(int n, const int* __restrict__ comp, const int* __res
   }
 }
 
-// one block, after the cycle: rho = (r, z); per-component test on the
-// residual of the last update (the start's before the first); a component
-// records the iteration it first passes; beta, or stop
-__global__ void __launch_bounds__(ANT) k_fs_scal1(const double* __restrict__ parts, int np,
-                                                  const int* __restrict__ list, int nl, double* __restrict__ rrc,
-                                                  double* __restrict__ rr, const double* __restrict__ bbc,
-                                                  int* __restrict__ iters, int* __restrict__ stats,
-                                                  double* __restrict__ sc, int* __restrict__ done,
-                                                  int* __restrict__ itc, double rtol, int maxit,
-                                                  int* __restrict__ flag) {
-  __shared__ double red[ANT / 64];
-  __shared__ int open_s;
-  if (is_done(done)) return;
-  const int it = *itc;
-  const double rho = sum_parts(parts, np, red);
-  if (threadIdx.x == 0) open_s = 0;
-  __syncthreads();
-  const double t2 = rtol * rtol;
-  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-    const int c = list[i];
-    const double v = rrc[c];
-    rr[c] = v;
-    rrc[c] = 0.0;
-    if (!(v > t2 * bbc[c])) {
-      if (iters[c] < 0) iters[c] = it;
-    } else {
-      atomicAdd(&open_s, 1);
-    }
-  }
-  __syncthreads();
-  const bool stop = open_s == 0 || it >= maxit;
-  if (stop) {
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-      const int c = list[i];
-      if (iters[c] < 0) {
-        iters[c] = it;
-        atomicAdd(&stats[0], 1);
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
-    if (stop) {
-      *done = 1;
-      *flag = 0;
-    } else {
-      sc[S_BETA] = it == 0 ? 0.0 : rho / sc[S_RHOP];
-      sc[S_RHO] = rho;
-      sc[S_RHOP] = rho;
-      *itc = it + 1;
-    }
-  }
-}
-
 // x += alpha p, r -= alpha q, per-component |r|^2.  A thread takes FS_R
 // rows ANT apart and sums the rows of one component before one atomic per
 // wavefront: the largest components span millions of rows, and a per-wave
@@ -945,10 +898,10 @@ __global__ void __launch_bounds__(ANT) k_fs_scal1(const double* __restrict__ par
 constexpr int FS_R = 16;
 __global__ void __launch_bounds__(ANT) k_fs_xr(int n, const int* __restrict__ comp, double* __restrict__ x,
                                                double* __restrict__ r, const double* __restrict__ p,
-                                               const double* __restrict__ q, const double* __restrict__ sc,
-                                               double* __restrict__ rrc, const int* done) {
+                                               const double* __restrict__ q, const double* __restrict__ alpha,
+                                               const int* __restrict__ frozen, double* __restrict__ rrc,
+                                               const int* done) {
   if (is_done(done)) return;
-  const double a = sc[S_ALPHA];
   const int base = blockIdx.x * (ANT * FS_R) + threadIdx.x;
   int cur = -1;
   double acc = 0.0;
@@ -956,7 +909,8 @@ __global__ void __launch_bounds__(ANT) k_fs_xr(int n, const int* __restrict__ co
     const int c = base + k * ANT;
     if (c >= n) break;
     const int key = comp[c];
-    if (key < 0) continue;
+    if (key < 0 || frozen[key]) continue;
+    const double a = alpha[key];
     x[c] += a * p[c];
     const double rv = r[c] - a * q[c];
     r[c] = rv;
@@ -968,6 +922,121 @@ __global__ void __launch_bounds__(ANT) k_fs_xr(int n, const int* __restrict__ co
     acc += rv * rv;
   }
   ni::acc1_by_key(cur >= 0, cur, acc, rrc);
+}
+
+// rho_c = (r, z) per component (z = the V-cycle's output), rows as in k_fs_xr
+__global__ void __launch_bounds__(ANT) k_fs_rz(int n, const int* __restrict__ comp, const double* __restrict__ r,
+                                               const double* __restrict__ z, const int* __restrict__ frozen,
+                                               double* __restrict__ rzc, const int* done) {
+  if (is_done(done)) return;
+  const int base = blockIdx.x * (ANT * FS_R) + threadIdx.x;
+  int cur = -1;
+  double acc = 0.0;
+  for (int k = 0; k < FS_R; ++k) {
+    const int c = base + k * ANT;
+    if (c >= n) break;
+    const int key = comp[c];
+    if (key < 0 || frozen[key]) continue;
+    if (key != cur) {
+      if (cur >= 0) atomicAdd(&rzc[cur], acc);
+      cur = key;
+      acc = 0.0;
+    }
+    acc += r[c] * z[c];
+  }
+  ni::acc1_by_key(cur >= 0, cur, acc, rzc);
+}
+
+// Per listed component, after the cycle: the test on the residual of the
+// last update (the start's before the first); a component that passes
+// records the iteration and is frozen (its x and r stay as they are); one
+// still open at maxit is counted in stats[0] and frozen; otherwise beta_c
+// = rho_c / rho_c(previous) and the component counts as open.
+__global__ void __launch_bounds__(ANT) k_fs_scal1(const int* __restrict__ list, int nl, double* __restrict__ rrc,
+                                               double* __restrict__ rr, const double* __restrict__ bbc,
+                                               double* __restrict__ rzc, double* __restrict__ rhop,
+                                               double* __restrict__ beta, int* __restrict__ frozen,
+                                               int* __restrict__ iters, int* __restrict__ stats,
+                                               const int* __restrict__ itc, double rtol, int maxit,
+                                               int* __restrict__ open, const int* done) {
+  if (is_done(done)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  const int c = list[i];
+  if (frozen[c]) return;
+  const int it = *itc;
+  const double v = rrc[c];
+  rr[c] = v;
+  rrc[c] = 0.0;
+  const double rho = rzc[c];
+  rzc[c] = 0.0;
+  if (!(v > rtol * rtol * bbc[c])) {
+    if (iters[c] < 0) iters[c] = it;
+    frozen[c] = 1;
+    return;
+  }
+  if (it >= maxit || !(rho > 0.0)) {  // cap reached, or a breakdown
+    iters[c] = it;
+    atomicAdd(&stats[0], 1);
+    frozen[c] = 1;
+    return;
+  }
+  beta[c] = it == 0 ? 0.0 : rho / rhop[c];
+  rhop[c] = rho;
+  atomicAdd(open, 1);
+}
+
+// p = z + beta_c p, q = A z + beta_c q (= A p) and (p, q) per component, on
+// the open components' rows (level 0 has no heavy rows)
+__global__ void __launch_bounds__(ANT) k_fs_pq(ALev L, const int* __restrict__ comp, const int* __restrict__ frozen,
+                                               const double* __restrict__ beta, double* __restrict__ p,
+                                               double* __restrict__ q, double* __restrict__ pqc, const int* done) {
+  if (is_done(done)) return;
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  const int k = c < L.n ? comp[c] : -1;
+  const bool act = k >= 0 && !frozen[k];
+  double v = 0.0;
+  if (act) {
+    const double* z = L.y;
+    const double zc = z[c];
+    double acc = 0.0;
+    for (int j = L.row_off[c]; j < L.row_off[c + 1]; ++j) acc += L.w[j] * (zc - z[L.col[j]]);
+    const double b = beta[k];
+    const double pn = zc + b * p[c];
+    const double qn = acc + b * q[c];
+    p[c] = pn;
+    q[c] = qn;
+    v = pn * qn;
+  }
+  ni::acc1_by_key(act, k, v, pqc);
+}
+
+// alpha_c = rho_c / (p, q)_c per open component; block 0 then ends the
+// solve when no component is open, else advances the iteration counter
+__global__ void __launch_bounds__(ANT) k_fs_alpha(const int* __restrict__ list, int nl, const int* __restrict__ frozen,
+                                                  const double* __restrict__ rhop, double* __restrict__ pqc,
+                                                  double* __restrict__ alpha, int* __restrict__ open,
+                                                  int* __restrict__ itc, int* __restrict__ done,
+                                                  int* __restrict__ flag) {
+  if (is_done(done)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nl) {
+    const int c = list[i];
+    if (!frozen[c]) {
+      const double pq = pqc[c];
+      alpha[c] = pq > 0.0 ? rhop[c] / pq : 0.0;
+    }
+    pqc[c] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (*open == 0) {
+      *done = 1;
+      *flag = 0;
+    } else {
+      *itc = *itc + 1;
+    }
+    *open = 0;
+  }
 }
 
 // ------------------------------------------------------------ host side
@@ -1031,7 +1100,7 @@ struct Amg {
   bool dense = false;  // coarsest solved exactly
   double corr = 1.0;   // coarse-correction factor
   DBuf s[NSCR];
-  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst;
+  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst, fs_c, fs_frozen;
   // host readbacks of the build: a pinned landing area, and the counts
   // that only the solve needs (heavy rows and aggregates per level),
   // gathered in device slots and read once at the end of the build
@@ -1052,7 +1121,7 @@ struct Amg {
     }
     for (DBuf& d : s)
       if (d.p) (void)hipFree(d.p);
-    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts};
+    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts, &fs_c, &fs_frozen};
     for (DBuf* d : own)
       if (d->p) (void)hipFree(d->p);
   }
@@ -1491,7 +1560,7 @@ static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts
   if (A->dense) {
     k_cy_coarsest<FILL><<<1, CO_NT, 0, q_>>>(Lc.n, static_cast<const double*>(A->ainv.p),
                                        static_cast<const uint8_t*>(A->pin.p), Lc.b, Lc.y, done);
-    if (A->nlev == 1) k_cy_dot<FILL><<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, parts, pstride, done);
+    if (A->nlev == 1 && parts) k_cy_dot<FILL><<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, parts, pstride, done);
   } else {  // no exact coarsest: smoothing only
     k_cy_up<FILL><<<Lc.nblk + Lc.nheavy, ANT, 0, q_>>>(Lc, nullptr, A->nlev == 1 ? parts : nullptr, pstride, A->corr,
                                                  done);
@@ -1613,33 +1682,43 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
   double* p = grow<double>(A->p, n, err);
   double* q = grow<double>(A->q, n, err);
   double* r = grow<double>(A->r, n, err);
-  const int pstride = nblk;
-  double* parts = grow<double>(A->parts, 2 * (size_t)pstride, err);
   double* sc = grow<double>(A->sc, S_N, err);
-  int* ctr = grow<int>(A->ctr, 8, err);  // [0] done, [1] iteration, [2] flag, [3] unused
-  double* rrc = grow<double>(A->rrc, (size_t)std::max(K, 1), err);
-  int* rst = grow<int>(A->rst, (size_t)std::max(K, 1), err);
+  int* ctr = grow<int>(A->ctr, 8, err);  // [0] done, [1] iteration, [2] flag, [3] open components
+  const size_t K1 = (size_t)std::max(K, 1);
+  double* rrc = grow<double>(A->rrc, K1, err);
+  int* rst = grow<int>(A->rst, K1, err);
+  // per-component PCG state: rho, (p, q), previous rho, beta, alpha
+  double* cs = grow<double>(A->fs_c, 5 * K1, err);
+  int* frozen = grow<int>(A->fs_frozen, K1, err);
   AMG_TRY(err);
+  double *rzc = cs, *pqc = cs + K1, *rhop = cs + 2 * K1, *beta = cs + 3 * K1, *alpha = cs + 4 * K1;
   int* done = ctr;
   int* itc = ctr + 1;
   int* flag = ctr + 2;
+  int* open = ctr + 3;
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
-  AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * std::max(K, 1), st));
-  AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * std::max(K, 1), st));
+  AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * K1, st));
+  AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * K1, st));
   k_fs_init<<<nblk, ANT, 0, st>>>(V[0], comp, x, b, r, p, q, rrc, bb);
-  k_fs_scal0<<<1, ANT, 0, st>>>(list, nl, rrc, bb, rst, warm, iters, stats, sc, done, itc, flag);
+  k_fs_scal0<<<1, ANT, 0, st>>>(list, nl, rrc, bb, rst, warm, iters, stats, sc, done, itc, flag, frozen, rzc, pqc,
+                                open);
   if (warm) k_fs_reset<<<nblk, ANT, 0, st>>>(n, comp, rst, b, x, r);
   AMG_TRY(hipGetLastError());
+  // every component runs its own PCG (its own rho, beta, alpha) through the
+  // shared V-cycle, which never couples two components; a component stops
+  // (is frozen) at its first pass of the test
+  const int nbl = nb256(nl), nbr = nb256((n + FS_R - 1) / FS_R);
   const int batch = 8;
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
-      launch_cycle<1>(A, V, parts, pstride, done, st);
-      k_fs_scal1<<<1, ANT, 0, st>>>(parts, pstride, list, nl, rrc, rr, bb, iters, stats, sc, done, itc, rtol, maxit,
-                                    flag);
-      k_cg_pq<1><<<nblk, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, done);
-      k_cg_scal<1><<<1, SC_NT, 0, st>>>(2, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, ctr + 3, flag);
-      k_fs_xr<<<nb256((n + FS_R - 1) / FS_R), ANT, 0, st>>>(n, comp, x, r, p, q, sc, rrc, done);
+      launch_cycle<1>(A, V, nullptr, 0, done, st);
+      k_fs_rz<<<nbr, ANT, 0, st>>>(n, comp, r, V[0].y, frozen, rzc, done);
+      k_fs_scal1<<<nbl, ANT, 0, st>>>(list, nl, rrc, rr, bb, rzc, rhop, beta, frozen, iters, stats, itc, rtol, maxit,
+                                      open, done);
+      k_fs_pq<<<nblk, ANT, 0, st>>>(V[0], comp, frozen, beta, p, q, pqc, done);
+      k_fs_alpha<<<nbl, ANT, 0, st>>>(list, nl, frozen, rhop, pqc, alpha, open, itc, done, flag);
+      k_fs_xr<<<nbr, ANT, 0, st>>>(n, comp, x, r, p, q, alpha, frozen, rrc, done);
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
