@@ -831,12 +831,12 @@ __global__ void k_gm_coarse(int n, const int* __restrict__ agg2, const int* __re
 __global__ void __launch_bounds__(ANT) k_fs_init(ALev L, const int* __restrict__ comp, const double* __restrict__ x,
                                                  const double* __restrict__ b, double* __restrict__ r,
                                                  double* __restrict__ p, double* __restrict__ q,
-                                                 double* __restrict__ rrc, double* __restrict__ bbc) {
+                                                 double* __restrict__ vr, double* __restrict__ vb) {
   const int c = blockIdx.x * ANT + threadIdx.x;
-  const bool in = c < L.n;
-  const int k = in ? comp[c] : -1;
+  if (c >= L.n) return;
+  const int k = comp[c];
   double rv = 0.0, bv = 0.0;
-  if (in) {
+  {
     const double xc = x[c];
     double acc = 0.0;
     for (int j = L.row_off[c]; j < L.row_off[c + 1]; ++j) acc += L.w[j] * (xc - x[L.col[j]]);
@@ -846,7 +846,8 @@ __global__ void __launch_bounds__(ANT) k_fs_init(ALev L, const int* __restrict__
     p[c] = 0.0;
     q[c] = 0.0;
   }
-  ni::acc_by_key<double>(k >= 0, k, rv * rv, bv * bv, rrc, bbc);
+  vr[c] = k >= 0 ? rv * rv : 0.0;
+  vb[c] = k >= 0 ? bv * bv : 0.0;
 }
 
 // one block: a learned start no better than zero is dropped (flag per
@@ -891,60 +892,39 @@ __global__ void k_fs_reset(int n, const int* __restrict__ comp, const int* __res
   }
 }
 
-// x += alpha p, r -= alpha q, per-component |r|^2.  A thread takes FS_R
-// rows ANT apart and sums the rows of one component before one atomic per
-// wavefront: the largest components span millions of rows, and a per-wave
-// atomic on one address would serialise.
-constexpr int FS_R = 16;
+// x += alpha_c p, r -= alpha_c q on the open components' rows; r^2 per node
+// (summed per component by run_sums).  The per-component sums of the batch
+// (r^2, b^2, r z, p q) go through run_sums rather than atomics: their
+// order, and so the iteration, is then the same on every run.
 __global__ void __launch_bounds__(ANT) k_fs_xr(int n, const int* __restrict__ comp, double* __restrict__ x,
                                                double* __restrict__ r, const double* __restrict__ p,
                                                const double* __restrict__ q, const double* __restrict__ alpha,
-                                               const int* __restrict__ frozen, double* __restrict__ rrc,
+                                               const int* __restrict__ frozen, double* __restrict__ vr,
                                                const int* done) {
   if (is_done(done)) return;
-  const int base = blockIdx.x * (ANT * FS_R) + threadIdx.x;
-  int cur = -1;
-  double acc = 0.0;
-  for (int k = 0; k < FS_R; ++k) {
-    const int c = base + k * ANT;
-    if (c >= n) break;
-    const int key = comp[c];
-    if (key < 0 || frozen[key]) continue;
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  if (c >= n) return;
+  const int key = comp[c];
+  double v = 0.0;
+  if (key >= 0 && !frozen[key]) {
     const double a = alpha[key];
     x[c] += a * p[c];
     const double rv = r[c] - a * q[c];
     r[c] = rv;
-    if (key != cur) {
-      if (cur >= 0) atomicAdd(&rrc[cur], acc);
-      cur = key;
-      acc = 0.0;
-    }
-    acc += rv * rv;
+    v = rv * rv;
   }
-  ni::acc1_by_key(cur >= 0, cur, acc, rrc);
+  vr[c] = v;
 }
 
-// rho_c = (r, z) per component (z = the V-cycle's output), rows as in k_fs_xr
+// r z per node of an open component (summed per component by run_sums)
 __global__ void __launch_bounds__(ANT) k_fs_rz(int n, const int* __restrict__ comp, const double* __restrict__ r,
                                                const double* __restrict__ z, const int* __restrict__ frozen,
-                                               double* __restrict__ rzc, const int* done) {
+                                               double* __restrict__ vz, const int* done) {
   if (is_done(done)) return;
-  const int base = blockIdx.x * (ANT * FS_R) + threadIdx.x;
-  int cur = -1;
-  double acc = 0.0;
-  for (int k = 0; k < FS_R; ++k) {
-    const int c = base + k * ANT;
-    if (c >= n) break;
-    const int key = comp[c];
-    if (key < 0 || frozen[key]) continue;
-    if (key != cur) {
-      if (cur >= 0) atomicAdd(&rzc[cur], acc);
-      cur = key;
-      acc = 0.0;
-    }
-    acc += r[c] * z[c];
-  }
-  ni::acc1_by_key(cur >= 0, cur, acc, rzc);
+  const int c = blockIdx.x * ANT + threadIdx.x;
+  if (c >= n) return;
+  const int key = comp[c];
+  vz[c] = (key >= 0 && !frozen[key]) ? r[c] * z[c] : 0.0;
 }
 
 // Per listed component, after the cycle: the test on the residual of the
@@ -967,9 +947,7 @@ __global__ void __launch_bounds__(ANT) k_fs_scal1(const int* __restrict__ list, 
   const int it = *itc;
   const double v = rrc[c];
   rr[c] = v;
-  rrc[c] = 0.0;
   const double rho = rzc[c];
-  rzc[c] = 0.0;
   if (!(v > rtol * rtol * bbc[c])) {
     if (iters[c] < 0) iters[c] = it;
     frozen[c] = 1;
@@ -986,14 +964,15 @@ __global__ void __launch_bounds__(ANT) k_fs_scal1(const int* __restrict__ list, 
   atomicAdd(open, 1);
 }
 
-// p = z + beta_c p, q = A z + beta_c q (= A p) and (p, q) per component, on
-// the open components' rows (level 0 has no heavy rows)
+// p = z + beta_c p, q = A z + beta_c q (= A p) and p q per node, on the
+// open components' rows (level 0 has no heavy rows)
 __global__ void __launch_bounds__(ANT) k_fs_pq(ALev L, const int* __restrict__ comp, const int* __restrict__ frozen,
                                                const double* __restrict__ beta, double* __restrict__ p,
-                                               double* __restrict__ q, double* __restrict__ pqc, const int* done) {
+                                               double* __restrict__ q, double* __restrict__ vpq, const int* done) {
   if (is_done(done)) return;
   const int c = blockIdx.x * ANT + threadIdx.x;
-  const int k = c < L.n ? comp[c] : -1;
+  if (c >= L.n) return;
+  const int k = comp[c];
   const bool act = k >= 0 && !frozen[k];
   double v = 0.0;
   if (act) {
@@ -1008,7 +987,7 @@ __global__ void __launch_bounds__(ANT) k_fs_pq(ALev L, const int* __restrict__ c
     q[c] = qn;
     v = pn * qn;
   }
-  ni::acc1_by_key(act, k, v, pqc);
+  vpq[c] = v;
 }
 
 // alpha_c = rho_c / (p, q)_c per open component; block 0 then ends the
@@ -1026,7 +1005,6 @@ __global__ void __launch_bounds__(ANT) k_fs_alpha(const int* __restrict__ list, 
       const double pq = pqc[c];
       alpha[c] = pq > 0.0 ? rhop[c] / pq : 0.0;
     }
-    pqc[c] = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (*open == 0) {
@@ -1100,7 +1078,7 @@ struct Amg {
   bool dense = false;  // coarsest solved exactly
   double corr = 1.0;   // coarse-correction factor
   DBuf s[NSCR];
-  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst, fs_c, fs_frozen;
+  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst, fs_c, fs_frozen, fs_v, fs_rt;
   // host readbacks of the build: a pinned landing area, and the counts
   // that only the solve needs (heavy rows and aggregates per level),
   // gathered in device slots and read once at the end of the build
@@ -1121,7 +1099,7 @@ struct Amg {
     }
     for (DBuf& d : s)
       if (d.p) (void)hipFree(d.p);
-    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts, &fs_c, &fs_frozen};
+    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts, &fs_c, &fs_frozen, &fs_v, &fs_rt};
     for (DBuf* d : own)
       if (d->p) (void)hipFree(d->p);
   }
@@ -1669,7 +1647,8 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const doubl
   return hipSuccess;
 }
 
-hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int K, const double* b, double* x,
+hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const int* list, int nl, int K,
+                          const double* b, double* x,
                           double rtol, int maxit, int warm, double* rr, double* bb, int* iters, int* stats,
                           int* host_flag, int* its, hipStream_t st) {
   *its = 0;
@@ -1690,6 +1669,9 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
   // per-component PCG state: rho, (p, q), previous rho, beta, alpha
   double* cs = grow<double>(A->fs_c, 5 * K1, err);
   int* frozen = grow<int>(A->fs_frozen, K1, err);
+  // per-node terms of the per-component sums, and the run-sum scratch
+  double* vn = grow<double>(A->fs_v, 2 * (size_t)n, err);
+  void* rtmp = grow<uint8_t>(A->fs_rt, run_sums_tmp_bytes(n), err);
   AMG_TRY(err);
   double *rzc = cs, *pqc = cs + K1, *rhop = cs + 2 * K1, *beta = cs + 3 * K1, *alpha = cs + 4 * K1;
   int* done = ctr;
@@ -1698,9 +1680,12 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
   int* open = ctr + 3;
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
+  // components without a node on this level keep zero sums
   AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * K1, st));
   AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * K1, st));
-  k_fs_init<<<nblk, ANT, 0, st>>>(V[0], comp, x, b, r, p, q, rrc, bb);
+  k_fs_init<<<nblk, ANT, 0, st>>>(V[0], comp, x, b, r, p, q, vn, vn + n);
+  AMG_TRY(run_sums(rkey, vn, n, rrc, rtmp, st));
+  AMG_TRY(run_sums(rkey, vn + n, n, bb, rtmp, st));
   k_fs_scal0<<<1, ANT, 0, st>>>(list, nl, rrc, bb, rst, warm, iters, stats, sc, done, itc, flag, frozen, rzc, pqc,
                                 open);
   if (warm) k_fs_reset<<<nblk, ANT, 0, st>>>(n, comp, rst, b, x, r);
@@ -1708,17 +1693,20 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const int* list, int nl, int 
   // every component runs its own PCG (its own rho, beta, alpha) through the
   // shared V-cycle, which never couples two components; a component stops
   // (is frozen) at its first pass of the test
-  const int nbl = nb256(nl), nbr = nb256((n + FS_R - 1) / FS_R);
+  const int nbl = nb256(nl);
   const int batch = 8;
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
       launch_cycle<1>(A, V, nullptr, 0, done, st);
-      k_fs_rz<<<nbr, ANT, 0, st>>>(n, comp, r, V[0].y, frozen, rzc, done);
+      k_fs_rz<<<nblk, ANT, 0, st>>>(n, comp, r, V[0].y, frozen, vn, done);
+      AMG_TRY(run_sums(rkey, vn, n, rzc, rtmp, st));
       k_fs_scal1<<<nbl, ANT, 0, st>>>(list, nl, rrc, rr, bb, rzc, rhop, beta, frozen, iters, stats, itc, rtol, maxit,
                                       open, done);
-      k_fs_pq<<<nblk, ANT, 0, st>>>(V[0], comp, frozen, beta, p, q, pqc, done);
+      k_fs_pq<<<nblk, ANT, 0, st>>>(V[0], comp, frozen, beta, p, q, vn, done);
+      AMG_TRY(run_sums(rkey, vn, n, pqc, rtmp, st));
       k_fs_alpha<<<nbl, ANT, 0, st>>>(list, nl, frozen, rhop, pqc, alpha, open, itc, done, flag);
-      k_fs_xr<<<nbr, ANT, 0, st>>>(n, comp, x, r, p, q, alpha, frozen, rrc, done);
+      k_fs_xr<<<nblk, ANT, 0, st>>>(n, comp, x, r, p, q, alpha, frozen, vn, done);
+      AMG_TRY(run_sums(rkey, vn, n, rrc, rtmp, st));
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -52,7 +52,7 @@ hipError_t fill8_build(int, int, const uint32_t*, const uint32_t*, const int*, c
                        const uint8_t*, const float*, const float* const*, const int*, double, double, double,
                        const int*, const int*, const float*, int*, double*, double*, int*, int*, double*, int*, int*,
                        int*, double*, double*, hipStream_t);
-hipError_t fill8_out(int, int, const uint32_t*, const uint32_t*, const int*, const double*, double*, int*, float*,
+hipError_t fill8_out(int, int, const uint32_t*, const uint32_t*, const int*, const double*, double*, void*, float*,
                      hipStream_t);
 // ni_quot.hip
 hipError_t quot_inter_edges(const int*, const uint8_t*, const uint8_t*, int, int, int*, int*, int*, uint32_t*, int*,
@@ -67,9 +67,9 @@ hipError_t quot_heavy_rows(const int*, int, int*, int*, int*, int*, int*, hipStr
 
 hipError_t irls_iteration(const IrlsArgs&, int, hipStream_t);
 // ni_final.hip
-hipError_t final_outputs(const int*, const float*, const double*, const int*, const uint32_t*, const int*,
-                         const int*, int, int, int, int, int, double*, int*, double*, double*, float*, double*,
-                         hipStream_t);
+hipError_t final_outputs(const int*, const float*, const double*, const int*, const uint32_t*, const uint32_t*,
+                         const int*, const int*, int, int, int, int, int, double*, int*, double*, double*, float*,
+                         double*, const FinalScratch&, hipStream_t);
 // ni_unet.hip
 hipError_t unet_predict(struct UnetModel*, const float*, const uint8_t*, int, int, const ni_camera*, float*,
                         void*, size_t, hipStream_t);
@@ -145,6 +145,8 @@ struct ni_ctx {
   // components
   Buf comp_off, fsmall, flarge, nchunk, spos, lpos, cbase, small_list, large_list, cnt, done, iters, active,
       rho, bb, tol2, beta, rr, relres, S, qs, diag, qrhs, babs, psum, pcnt, qparent, csum, comp_rid;
+  // the quotient nodes sorted by piece
+  Buf pkey, pnode, pnode_in, pk_tmp, pv_tmp, pscan, pval, prun, fg, fv2;
   // chunks
   Buf chunk_comp, chunk_start, part;
   // edges / pairs
@@ -173,7 +175,8 @@ struct ni_ctx {
                   &skey, &spix, &ktmp, &vtmp, &kout2, &cst, &rhs, &dinv, &x, &r, &z, &p0,
                   &p1, &q, &w0, &w1, &s0, &s1, &comp_off, &fsmall, &flarge, &nchunk, &spos, &lpos, &cbase, &small_list, &large_list,
                   &cnt, &done, &iters, &active, &rho, &bb, &tol2, &beta, &rr, &relres, &S, &qs,
-                  &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid,
+                  &diag, &qrhs, &babs, &psum, &pcnt, &qparent, &csum, &comp_rid, &pkey, &pnode, &pnode_in,
+                  &pk_tmp, &pv_tmp, &pscan, &pval, &prun, &fg, &fv2,
                   &chunk_comp, &chunk_start, &part, &eidx_raw, &eidx, &ew, &erho, &pflag, &ppos, &pair_start,
                   &pair_lo, &pair_hi, &pW, &pB, &ent, &ent_tmp, &rowcnt, &row_off, &epart, &rsum,
                   &rcnt, &qcol, &qw, &qt0, &qt1, &eom, &eta, &etb, &mgrp, &mglab, &mkey, &mcode, &mpa,
@@ -538,13 +541,13 @@ void stage_fill8(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg&
     check(c, nil::amg_update(c->amg_fill, w, dg, pw, c->stream), "mg values");
     mark(c, 12);
     check(c,
-          nil::amg_fill_solve(c->amg_fill, gc, list, nl, K, b64, x64, pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, rr,
+          nil::amg_fill_solve(c->amg_fill, gc, skey, list, nl, K, b64, x64, pb.prm.cg_rtol, pb.prm.cg_max_iter, warm, rr,
                               bb, iters, stats, c->host, &its, c->stream),
           "mg solve");
     mark(c, 13);
     double* csum = ensure<double>(c, c->csum, K1);
-    int* ccnt = ensure<int>(c, c->comp_rid, K1);
-    check(c, nil::fill8_out(N, K, cpix, skey, comp_off, x64, csum, ccnt, zout, c->stream), "out");
+    void* rtmp = ensure<uint8_t>(c, c->prun, nil::run_sums_tmp_bytes(N));
+    check(c, nil::fill8_out(N, K, cpix, skey, comp_off, x64, csum, rtmp, zout, c->stream), "out");
     levels = nil::amg_levels(c->amg_fill);
   } else {
     mark(c, 12);
@@ -800,7 +803,7 @@ void stage_fill(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
     mark(c, 12);
     int its = 0;
     check(c,
-          nil::amg_fill_solve(c->amg_fill, gc, lists + 3 * K1, n_large, K, b64, x64, pb.prm.cg_rtol, mg_maxit,
+          nil::amg_fill_solve(c->amg_fill, gc, ptr<uint32_t>(c->skey), lists + 3 * K1, n_large, K, b64, x64, pb.prm.cg_rtol, mg_maxit,
                               warm, rr, bb, iters, misc(c) + M_STATS + 2, c->host, &its, c->stream),
           "mg solve");
     mark(c, 13);
@@ -931,7 +934,15 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   a.zfill = zfill;
   a.S = ensure<double>(c, c->S, K1);
   a.psum = ensure<double>(c, c->psum, K1);
-  a.pcnt = ensure<int>(c, c->pcnt, K1);
+  a.pcnt = ensure<double>(c, c->pcnt, K1);
+  a.pkey = ensure<uint32_t>(c, c->pkey, K1);
+  a.pnode = ensure<uint32_t>(c, c->pnode, K1);
+  a.pnode_in = ensure<uint32_t>(c, c->pnode_in, K1);
+  a.pk_tmp = ensure<uint32_t>(c, c->pk_tmp, K1);
+  a.pv_tmp = ensure<uint32_t>(c, c->pv_tmp, K1);
+  a.pscan = ensure<int>(c, c->pscan, nil::radix_tmp_ints((int)K1));
+  a.pval = ensure<double>(c, c->pval, K1);
+  a.prun = ensure<uint8_t>(c, c->prun, nil::run_sums_tmp_bytes((int)K1));
   a.parent = ensure<int>(c, c->qparent, K1);
   a.wmax = (unsigned long long*)(misc(c) + M_WMAX);
   a.energy_out = (double*)(misc(c) + M_ENERGY);
@@ -1124,9 +1135,19 @@ void stage_irls(ni_ctx* c, const Problem& pb, const int32_t* labels, const Seg& 
   int* comp_rid = ensure<int>(c, c->comp_rid, K1);
   double* rsum = ensure<double>(c, c->rsum, std::max(R, 1));
   double* rcnt = ensure<double>(c, c->rcnt, std::max(R, 1));
-  check(c, nil::final_outputs(labels, zfill, a.S, ptr<int>(c->comp_off), ptr<uint32_t>(c->spix), ptr<int>(c->parent),
-                              ptr<int>(c->scanv), K, sg.N, R, P, persp ? 1 : 0, csum, comp_rid, rsum, rcnt, depth,
-                              log_scale, c->stream),
+  nil::FinalScratch fw;
+  fw.g = ensure<double>(c, c->fg, std::max<size_t>(sg.N, 2 * K1));
+  fw.k0 = ensure<uint32_t>(c, c->pkey, K1);
+  fw.v0 = ensure<uint32_t>(c, c->pnode, K1);
+  fw.k1 = ensure<uint32_t>(c, c->pnode_in, K1);
+  fw.v1 = ensure<uint32_t>(c, c->pk_tmp, K1);
+  fw.k2 = ensure<uint32_t>(c, c->pv_tmp, K1);
+  fw.v2 = ensure<uint32_t>(c, c->fv2, K1);
+  fw.scan = ensure<int>(c, c->pscan, nil::radix_tmp_ints((int)K1));
+  fw.rtmp = ensure<uint8_t>(c, c->prun, nil::run_sums_tmp_bytes((int)std::max<size_t>(sg.N, K1)));
+  check(c, nil::final_outputs(labels, zfill, a.S, ptr<int>(c->comp_off), ptr<uint32_t>(c->spix),
+                              ptr<uint32_t>(c->skey), ptr<int>(c->parent), ptr<int>(c->scanv), K, sg.N, R, P,
+                              persp ? 1 : 0, csum, comp_rid, rsum, rcnt, depth, log_scale, fw, c->stream),
         "finalize");
   mark(c, 10);
   check(c, hipStreamSynchronize(c->stream), "sync");

@@ -44,60 +44,6 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
-// Atomic accumulation of (a, b) into (da[key], db[key]).  The wavefront
-// groups its lanes by key: each round takes the key of the lowest lane
-// still pending, sums the lanes that share it and issues one pair of
-// atomics.  One round when every lane has the same key (the common case:
-// one giant piece or region); a few when a giant key is interleaved with
-// small ones, which would otherwise send up to 64 atomics to one address
-// per wavefront.  Lanes left after ACC_ROUNDS rounds add directly.  Every
-// lane of the wavefront must call it.
-constexpr int ACC_ROUNDS = 4;
-
-template <class TB>
-__device__ __forceinline__ void acc_by_key(bool valid, int key, double a, TB b, double* da, TB* db) {
-  const int lane = threadIdx.x & (NI_WAVE - 1);
-  unsigned long long pend = __ballot(valid);
-  for (int round = 0; round < ACC_ROUNDS && pend; ++round) {
-    const int lead = __ffsll(pend) - 1;
-    const int k = __shfl(key, lead, NI_WAVE);
-    const bool mine = valid && key == k;
-    double sa = mine ? a : 0.0;
-    TB sb = mine ? b : TB(0);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      sa += __shfl_xor(sa, o, NI_WAVE);
-      sb += __shfl_xor(sb, o, NI_WAVE);
-    }
-    if (lane == lead) {
-      atomicAdd(&da[k], sa);
-      atomicAdd(&db[k], sb);
-    }
-    pend &= ~__ballot(mine);
-  }
-  if ((pend >> lane) & 1ull) {
-    atomicAdd(&da[key], a);
-    atomicAdd(&db[key], b);
-  }
-}
-
-// One-value form of acc_by_key.
-__device__ __forceinline__ void acc1_by_key(bool valid, int key, double a, double* da) {
-  const int lane = threadIdx.x & (NI_WAVE - 1);
-  unsigned long long pend = __ballot(valid);
-  for (int round = 0; round < ACC_ROUNDS && pend; ++round) {
-    const int lead = __ffsll(pend) - 1;
-    const int k = __shfl(key, lead, NI_WAVE);
-    const bool mine = valid && key == k;
-    double sa = mine ? a : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) sa += __shfl_xor(sa, o, NI_WAVE);
-    if (lane == lead) atomicAdd(&da[k], sa);
-    pend &= ~__ballot(mine);
-  }
-  if ((pend >> lane) & 1ull) atomicAdd(&da[key], a);
-}
-
 // Block-wide sum of NV doubles; every thread receives the totals.  `scratch`
 // must hold NV * (blockDim/64) doubles and must not be reused by the caller
 // until a later __syncthreads(); the sum order is fixed (deterministic).
@@ -118,36 +64,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
     v[k] = s;
   }
 }
-
-// Block-level form: when every valid thread of the block has thread 0's
-// key (thread 0 valid), the block sums first and issues one pair of
-// atomics (a quotient piece or pixel region usually spans whole blocks;
-// per-wavefront atomics on one address serialise).  Otherwise as
-// acc_by_key.  Every thread of the block must call it; red must hold
-// 2 * (blockDim/64) doubles.
-template <class TB>
-__device__ __forceinline__ void acc_by_key_block(bool valid, int key, double a, TB b, double* da, TB* db,
-                                                 double* red) {
-  __shared__ int bkey, bvalid;
-  if (threadIdx.x == 0) {
-    bkey = key;
-    bvalid = valid ? 1 : 0;
-  }
-  __syncthreads();
-  const int k0 = bkey;
-  const bool uniform = bvalid && __syncthreads_and(!valid || key == k0);
-  if (uniform) {
-    double v[2] = {valid ? a : 0.0, valid ? (double)b : 0.0};
-    block_sum<2>(v, red);
-    if (threadIdx.x == 0) {
-      atomicAdd(&da[k0], v[0]);
-      atomicAdd(&db[k0], (TB)v[1]);
-    }
-  } else {
-    acc_by_key<TB>(valid, key, a, b, da, db);
-  }
-}
-
 
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
@@ -189,6 +105,12 @@ hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t
                             int bits, int* scan_tmp, hipStream_t st);
 size_t radix_tmp_ints(int n);
 
+// out[k] = sum of v[i] over every run of equal consecutive keys k = key[i]
+// (each key one run), summed in an order fixed by the positions alone
+// (reproducible run to run).  tmp: run_sums_tmp_bytes(n) of device memory.
+hipError_t run_sums(const uint32_t* key, const double* v, int n, double* out, void* tmp, hipStream_t st);
+size_t run_sums_tmp_bytes(int n);
+
 // arguments of the batched CG of the large fill components (ni_fill.hip)
 struct LargeArgs {
   const int *comp_off, *cbase, *nchunk, *chunk_comp, *chunk_start, *chunk_end;
@@ -222,13 +144,15 @@ double amg_fill_bytes(const Amg*, long long n_sys);
 // coarse-correction factor of the cycle (1 unless set)
 void amg_set_corr(Amg*, double corr);
 // Batched PCG of independent component systems on level 0 (block
-// diagonal): comp[node] (-1: no system), list[nl] the components; x holds
-// the start (warm != 0: a start no better than zero is dropped per
-// component) and receives the solution.  Per component: rr = |r|^2 at the
-// end, bb = |b|^2, iters = iterations to ||r_c|| <= rtol ||b_c||; stats[0]
-// counts components that hit maxit, stats[1] dropped starts.  rrc / reset
-// are K-sized scratch.  *its = iterations run.
-hipError_t amg_fill_solve(Amg*, const int* comp, const int* list, int nl, int K, const double* b, double* x,
+// diagonal), each component with its own scalars: comp[node] (-1: no
+// system), rkey[node] the component of every node (equal keys contiguous),
+// list[nl] the components; x holds the start (warm != 0: a start no better
+// than zero is dropped per component) and receives the solution.  Per
+// component: rr = |r|^2 at the end, bb = |b|^2, iters = iterations to
+// ||r_c|| <= rtol ||b_c||; stats[0] counts components that hit maxit,
+// stats[1] dropped starts.  *its = iterations run.
+hipError_t amg_fill_solve(Amg*, const int* comp, const uint32_t* rkey, const int* list, int nl, int K,
+                          const double* b, double* x,
                           double rtol, int maxit, int warm, double* rr, double* bb, int* iters, int* stats,
                           int* host_flag, int* its, hipStream_t st);
 hipError_t amg_update(Amg*, const double* qw, const double* diag, const double* pW, hipStream_t st);
@@ -255,8 +179,14 @@ struct IrlsArgs {
   const int *pair_start, *pair_lo, *pair_hi, *row_off;
   const uint32_t* ent;
   double *S, *ew, *erho, *pW, *pB, *diag, *rhs, *babs;
-  double *s, *psum;
-  int *pcnt, *parent;
+  double *s, *psum, *pcnt;  // piece sums and sizes
+  int* parent;
+  // the nodes sorted by piece (keys, nodes, sort scratch, gathered values,
+  // run-sum scratch)
+  uint32_t *pkey, *pnode, *pnode_in, *pk_tmp, *pv_tmp;
+  int* pscan;
+  double* pval;
+  void* prun;
   unsigned long long* wmax;
   double* energy_out;  // [t]
   int* qiters_out;     // [t] iterations of the first solve round
@@ -275,6 +205,16 @@ struct IrlsArgs {
   int* hints = nullptr;  // host [2]: iterations of the last first / refinement round (poll batching)
   int graphs; // replay the multigrid iteration from a HIP graph
 };
+// scratch of the output stage (ni_final.hip): g holds max(N, 2K) doubles,
+// k0..v2 K keys / values each, scan radix_tmp_ints(K) ints, rtmp
+// run_sums_tmp_bytes(max(N, K)) bytes
+struct FinalScratch {
+  double* g;
+  uint32_t *k0, *v0, *k1, *v1, *k2, *v2;
+  int* scan;
+  void* rtmp;
+};
+
 hipError_t merge_nodes(const IrlsArgs& a, int* grp, int* glabel_out, int P, unsigned long long* gkey, unsigned* gcode,
                        int* pa, int* pb, double* pkeep, int* parent, int* flag, int* rank, int* cnt, int* scan_tmp,
                        hipStream_t st);

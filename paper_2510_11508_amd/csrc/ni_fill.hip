@@ -896,24 +896,6 @@ __global__ void k_fill8_build(int N, int W, const uint32_t* __restrict__ cpix, c
   x64[i] = (double)x32[i];
 }
 
-// per-component sums of the solution over the component-major order
-__global__ void __launch_bounds__(1024) k_fill8_sums(int N, const uint32_t* __restrict__ skey,
-                                                     const double* __restrict__ x64, double* __restrict__ csum,
-                                                     int* __restrict__ ccnt) {
-  __shared__ double red[2 * (1024 / 64)];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool v = i < N;
-  ni::acc_by_key_block<int>(v, v ? (int)skey[i] : 0, v ? x64[i] : 0.0, 1, csum, ccnt, red);
-}
-
-__global__ void k_fill8_zero(int K, double* __restrict__ csum, int* __restrict__ ccnt) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < K) {
-    csum[c] = 0.0;
-    ccnt[c] = 0;
-  }
-}
-
 // zero mean per component (the gauge of Eq. 15), scattered to the grid;
 // a singleton's log-depth is 0
 __global__ void k_fill8_out(int N, const uint32_t* __restrict__ cpix, const uint32_t* __restrict__ skey,
@@ -1127,11 +1109,13 @@ hipError_t fill8_build(int N, int W, const uint32_t* cpix, const uint32_t* skey,
   return hipGetLastError();
 }
 
+// per-component sums of the solution (run_sums over the component-major
+// order), then the centred output
 hipError_t fill8_out(int N, int K, const uint32_t* cpix, const uint32_t* skey, const int* comp_off,
-                     const double* x64, double* csum, int* ccnt, float* z, hipStream_t st) {
+                     const double* x64, double* csum, void* rtmp, float* z, hipStream_t st) {
   if (N <= 0 || K <= 0) return hipSuccess;
-  k_fill8_zero<<<ni::ceil_div(K, 256), 256, 0, st>>>(K, csum, ccnt);
-  k_fill8_sums<<<ni::ceil_div(N, 1024), 1024, 0, st>>>(N, skey, x64, csum, ccnt);
+  hipError_t e = run_sums(skey, x64, N, csum, rtmp, st);
+  if (e != hipSuccess) return e;
   k_fill8_out<<<ni::ceil_div(N, 256), 256, 0, st>>>(N, cpix, skey, comp_off, x64, csum, z);
   return hipGetLastError();
 }

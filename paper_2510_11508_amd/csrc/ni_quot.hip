@@ -368,31 +368,24 @@ __global__ void k_add_f64(double* __restrict__ a, const double* __restrict__ b, 
   if (i < n) a[i] += b[i];
 }
 
-// piece gauge: zero mean of s over every connected piece (root = parent)
-__global__ void __launch_bounds__(1024) k_piece_acc(const int* __restrict__ parent, const double* __restrict__ s,
-                                                   int K, double* __restrict__ psum, int* __restrict__ pcnt) {
-  __shared__ double red[2 * (1024 / 64)];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool v = c < K;
-  ni::acc_by_key_block<int>(v, v ? parent[c] : 0, v ? s[c] : 0.0, 1, psum, pcnt, red);
+// Piece sums: the nodes sorted by their piece's root (a stable sort, so
+// each piece is one run in node order) and summed per run by run_sums, in
+// an order that does not depend on scheduling.  g[i] = v of the i-th node
+// in that order (v null: 1, the piece sizes).
+__global__ void k_piece_gather(const uint32_t* __restrict__ node, const double* __restrict__ v, int K,
+                               double* __restrict__ g) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) g[i] = v ? v[node[i]] : 1.0;
 }
 
-// v -= its mean over the piece (a right-hand side made consistent with the
-// singular Laplacian: only rounding is removed)
+// v -= its mean over the piece (the piece gauge of s; for a right-hand side
+// of the singular Laplacian only rounding is removed)
 __global__ void k_piece_center(const int* __restrict__ parent, double* __restrict__ v, int K,
-                               const double* __restrict__ psum, const int* __restrict__ pcnt) {
+                               const double* __restrict__ psum, const double* __restrict__ pcnt) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= K) return;
   const int r = parent[c];
-  v[c] -= psum[r] / (double)pcnt[r];
-}
-
-__global__ void k_piece_apply(const int* __restrict__ parent, double* __restrict__ s, int K,
-                              const double* __restrict__ psum, const int* __restrict__ pcnt) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
-  int r = parent[c];
-  s[c] -= psum[r] / (double)pcnt[r];
+  v[c] -= psum[r] / pcnt[r];
 }
 
 // S_c += s of the node that holds component c (Eq. 12; every component of a
@@ -679,19 +672,33 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
                                                                    a.diag, a.rhs, a.babs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // pieces of the weighted quotient graph
+  // pieces of the weighted quotient graph, and the nodes in piece order
   e = list_components(a.K, a.pair_lo, a.pair_hi, a.pW, a.P, a.parent, st);
+  if (e != hipSuccess) return e;
+  {
+    int bits = 1;
+    while ((1ll << bits) < (long long)a.K) ++bits;
+    k_iota_u32<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pnode_in, a.K);
+    e = radix_sort_pairs(reinterpret_cast<const uint32_t*>(a.parent), a.pnode_in, a.pkey, a.pnode, a.pk_tmp,
+                         a.pv_tmp, a.K, bits, a.pscan, st);
+    if (e != hipSuccess) return e;
+  }
+  auto piece_sums = [&](const double* v, double* out) {
+    k_piece_gather<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pnode, v, a.K, a.pval);
+    return run_sums(a.pkey, a.pval, a.K, out, a.prun, st);
+  };
+  e = piece_sums(nullptr, a.pcnt);
   if (e != hipSuccess) return e;
   // a right-hand side of a singular system is consistent in exact
   // arithmetic (zero sum over every piece); rounding is taken out before
   // each solve round, so that the round's relative tolerance can be met
   auto center = [&](double* v) {
-    k_fill_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.psum, a.K, 0.0);
-    k_fill_i32<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pcnt, a.K, 0);
-    k_piece_acc<<<ni::ceil_div(a.K, 1024), 1024, 0, st>>>(a.parent, v, a.K, a.psum, a.pcnt);
+    hipError_t ce = piece_sums(v, a.psum);
     k_piece_center<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, v, a.K, a.psum, a.pcnt);
+    return ce;
   };
-  center(a.rhs);
+  e = center(a.rhs);
+  if (e != hipSuccess) return e;
   // quotient solve: multigrid-preconditioned CG on a hierarchy built from
   // this step's weights (the cut set and the weights change from step to
   // step; the uniform-weight steps t < align share one matrix and the
@@ -723,7 +730,7 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
                                                                     a.pair_lo, a.pair_hi, a.s, a.t0);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) center(a.t0);
+  if (e == hipSuccess) e = center(a.t0);
   if (e == hipSuccess)
     e = amg_solve(a.amg, a.t0, a.t0, a.babs, 1e-13, a.t1, a.q_rtol2, a.q_maxit, a.qiters2_out + t, a.host_flag,
                   a.graphs != 0, st, a.hints ? a.hints + 1 : nullptr);
@@ -733,10 +740,8 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   }
   if (e != hipSuccess) return e;
   // piece gauge and accumulate S
-  k_fill_f64<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.psum, a.K, 0.0);
-  k_fill_i32<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.pcnt, a.K, 0);
-  k_piece_acc<<<ni::ceil_div(a.K, 1024), 1024, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt);
-  k_piece_apply<<<ni::ceil_div(a.K, 256), 256, 0, st>>>(a.parent, a.s, a.K, a.psum, a.pcnt);
+  e = center(a.s);
+  if (e != hipSuccess) return e;
   k_scale_add<<<ni::ceil_div(a.K0, 256), 256, 0, st>>>(a.s, a.grp, a.K0, a.S);
   // energy
   if (a.P > 0) {

@@ -2,6 +2,8 @@
 // (uint32 key, uint32 value) pairs.  Both are deterministic: the scan is an
 // integer scan and the sort ranks equal digits by their input order using
 // wavefront ballots, so the output never depends on scheduling.
+#include <algorithm>
+
 #include "ni_common.h"
 
 namespace {
@@ -150,6 +152,129 @@ __global__ void __launch_bounds__(RS_NT) k_rs_scatter(const uint32_t* __restrict
   }
 }
 
+// ------------------------------------------------------------- run sums
+// out[k] = the sum of v over every run of equal keys (runs are maximal
+// stretches of equal consecutive keys), in an order fixed by the element
+// positions alone: 8 consecutive elements per thread in order, then a
+// fixed pairwise tree over the block's threads, then over the blocks.  A
+// record describes a stretch of elements: one key (single), or its first
+// and last runs (multi), whose inner runs are complete and already written.
+constexpr int RU_NT = 256, RU_PPT = 8, RU_TILE = RU_NT * RU_PPT, RU_TOP = 1024;
+
+struct RunRec {
+  uint32_t hk, tk;  // keys of the first and last runs (single: equal)
+  double hs, ts;    // their partial sums
+  int kind;         // 0 empty, 1 single, 2 multi
+};
+
+// A's stretch directly followed by B's; runs completed by the merge are
+// written to out
+__device__ __forceinline__ RunRec rr_merge(const RunRec& A, const RunRec& B, double* out) {
+  if (A.kind == 0) return B;
+  if (B.kind == 0) return A;
+  RunRec R;
+  if (A.kind == 1 && B.kind == 1) {
+    if (A.hk == B.hk) {
+      R = A;
+      R.hs = A.hs + B.hs;
+      R.ts = R.hs;
+      return R;
+    }
+    R.kind = 2;
+    R.hk = A.hk;
+    R.hs = A.hs;
+    R.tk = B.hk;
+    R.ts = B.hs;
+    return R;
+  }
+  if (A.kind == 1) {  // B multi
+    R = B;
+    if (A.hk == B.hk) {
+      R.hs = A.hs + B.hs;
+    } else {
+      out[B.hk] = B.hs;
+      R.hk = A.hk;
+      R.hs = A.hs;
+    }
+    return R;
+  }
+  if (B.kind == 1) {  // A multi
+    R = A;
+    if (A.tk == B.hk) {
+      R.ts = A.ts + B.hs;
+    } else {
+      out[A.tk] = A.ts;
+      R.tk = B.hk;
+      R.ts = B.hs;
+    }
+    return R;
+  }
+  if (A.tk == B.hk) {
+    out[A.tk] = A.ts + B.hs;
+  } else {
+    out[A.tk] = A.ts;
+    out[B.hk] = B.hs;
+  }
+  R.kind = 2;
+  R.hk = A.hk;
+  R.hs = A.hs;
+  R.tk = B.tk;
+  R.ts = B.ts;
+  return R;
+}
+
+// fixed pairwise tree over the block's records in LDS; the result in rec[0]
+__device__ __forceinline__ void rr_tree(RunRec* rec, double* out) {
+  for (int s = 1; s < (int)blockDim.x; s <<= 1) {
+    __syncthreads();
+    const int t = threadIdx.x;
+    if ((t & (2 * s - 1)) == 0 && t + s < (int)blockDim.x) rec[t] = rr_merge(rec[t], rec[t + s], out);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(RU_NT) k_runsum_tile(const uint32_t* __restrict__ key, const double* __restrict__ v,
+                                                       int n, double* __restrict__ out, RunRec* __restrict__ brec) {
+  __shared__ RunRec rec[RU_NT];
+  const long long base = (long long)blockIdx.x * RU_TILE + (long long)threadIdx.x * RU_PPT;
+  RunRec R;
+  R.kind = 0;
+  for (int j = 0; j < RU_PPT; ++j) {
+    const long long i = base + j;
+    if (i >= n) break;
+    RunRec e;
+    e.kind = 1;
+    e.hk = e.tk = key[i];
+    e.hs = e.ts = v[i];
+    R = rr_merge(R, e, out);
+  }
+  rec[threadIdx.x] = R;
+  rr_tree(rec, out);
+  if (threadIdx.x == 0) brec[blockIdx.x] = rec[0];
+}
+
+// one block of RU_TOP threads over the tile records; the first and last
+// runs of the whole array are complete at the end
+__global__ void __launch_bounds__(RU_TOP) k_runsum_top(const RunRec* __restrict__ brec, int nb,
+                                                       double* __restrict__ out) {
+  __shared__ RunRec rec[RU_TOP];
+  const int per = (nb + RU_TOP - 1) / RU_TOP;
+  RunRec R;
+  R.kind = 0;
+  for (int j = 0; j < per; ++j) {
+    const int b = threadIdx.x * per + j;
+    if (b >= nb) break;
+    R = rr_merge(R, brec[b], out);
+  }
+  rec[threadIdx.x] = R;
+  rr_tree(rec, out);
+  if (threadIdx.x == 0) {
+    const RunRec& F = rec[0];
+    if (F.kind >= 1) out[F.hk] = F.hs;
+    if (F.kind == 2) out[F.tk] = F.ts;
+  }
+}
+
 }  // namespace
 
 namespace nil {
@@ -219,6 +344,17 @@ hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t
     vs = vd;
   }
   return hipSuccess;
+}
+
+size_t run_sums_tmp_bytes(int n) { return sizeof(RunRec) * (size_t)std::max(ni::ceil_div(n, RU_TILE), 1); }
+
+hipError_t run_sums(const uint32_t* key, const double* v, int n, double* out, void* tmp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int nb = ni::ceil_div(n, RU_TILE);
+  RunRec* brec = static_cast<RunRec*>(tmp);
+  k_runsum_tile<<<nb, RU_NT, 0, st>>>(key, v, n, out, brec);
+  k_runsum_top<<<1, RU_TOP, 0, st>>>(brec, nb, out);
+  return hipGetLastError();
 }
 
 }  // namespace nil

@@ -550,6 +550,27 @@ def test_deterministic(ctx, theta):
         assert np.max(np.abs(d[v] - outs[0][1][v])) <= 1e-6 * np.max(np.abs(outs[0][1][v]))
 
 
+@pytest.mark.parametrize("name,conn", [("c3", 4), ("c3", 8), ("c5", 4)])
+def test_bitwise_reproducible(ctx, name, conn):
+    """Every sum that feeds the relative-scale loop and the outputs is taken in
+    an order fixed by positions alone (run sums, block partials, no floating
+    atomics), so repeated runs give identical bits.  This matters beyond
+    tidiness at 2048^2 and up: there the loop amplifies rounding differences
+    to visible changes of the output (see irls_chaos)."""
+    s = synth.make(name, 0)
+    p = params(theta_c_deg=2.0, irls_iters=15, connectivity=conn)
+    outs = []
+    for k in range(2):
+        log(f"[bitwise] {name} connectivity {conn} run {k}")
+        o = ctx.ni_integrate(dev(s.normals), dev(s.mask), s.cam.as_dict(), p)
+        outs.append((o["labels"].cpu().numpy(), o["depth"].cpu().numpy(), o["log_scale"].cpu().numpy(),
+                     o["report"]["energy"]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1], equal_nan=True)
+    assert np.array_equal(outs[0][2], outs[1][2])
+    assert outs[0][3] == outs[1][3]
+
+
 # ------------------------------------------------------------- edge cases
 def test_empty_mask(ctx):
     s = synth.tiny(0)
