@@ -100,7 +100,7 @@ def cpu_baseline(name, seed, params):
                        f"({n_valid} valid px), FP64 sparse-direct solves, {el:.1f} s")
 
 
-FILL_KERNELS = r"(k_cy_\w+<1>|k_cg_\w+<1>|k_fs_scal1|k_fs_xr)"
+FILL_KERNELS = r"(k_cy_\w+<1>|k_fs_rz|k_fs_scal1|k_fs_pq|k_fs_alpha|k_fs_xr|k_runsum_\w+<1>)"
 
 
 def _csv_rows(d, suffix):
@@ -476,8 +476,9 @@ def main():
     if mg:
         key = "multigrid"
         kernel = ("one multigrid-preconditioned PCG iteration of the large fill components (all of them at "
-                  "once): k_cy_down<1>, k_cy_restrict<1>, k_cy_up<1> on every level, k_cy_coarsest<1>, "
-                  "k_fs_scal1, k_cg_pq<1>, k_cg_scal<1>, k_fs_xr")
+                  "once, each with its own scalars): k_cy_down<1>, k_cy_restrict<1>, k_cy_up<1> on every level, "
+                  "k_cy_coarsest<1>, k_fs_rz, k_fs_scal1, k_fs_pq, k_fs_alpha, k_fs_xr, k_runsum_tile<1> and "
+                  "k_runsum_top<1> (three per-component sums)")
     else:
         key = f"{rep['fill_chunk']}:{rep['fill_split']}"
         kernel = (("k_lg_p + k_lg_q + k_lg_b" if rep["fill_split"] else "k_lg_a + k_lg_b")

@@ -1115,9 +1115,12 @@ int amg_levels(const Amg* a) { return a ? a->nlev : 0; }
 // (28 n + 12 e); restrict reads mem_off, mem, r and writes b' (12 n +
 // 12 n'); up reads row_off, col, w, b, diag, cid, y' and writes y (32 n +
 // 12 e + 8 n').  Coarsest: the inverse and two vectors (8 n^2 + 16 n).
-// Level 0 also: (p, q) reads row_off, col, w, z and updates p, q
-// (44 n + 12 e); the update reads comp of every row and updates x, r from
-// p, q on the rows of a system (4 n + 48 n_sys).
+// Level 0 also, per node: comp read and one per-node term written by each
+// of the three per-component kernels (12 n each), the three run sums
+// reading key and term (36 n); on the rows of a system: r z reads r, z
+// (16 n_sys), (p, q) reads row_off, z, p, q and the entries and writes p, q
+// (44 n_sys + 12 e), the update reads x, r, p, q and writes x, r
+// (48 n_sys): 72 n + 12 e + 108 n_sys.
 double amg_fill_bytes(const Amg* A, long long n_sys) {
   if (!A || A->nlev <= 0) return 0.0;
   double by = 0.0;
@@ -1132,7 +1135,7 @@ double amg_fill_bytes(const Amg* A, long long n_sys) {
     by += 28.0 * n + 12.0 * e + 12.0 * n + 12.0 * nc + 32.0 * n + 12.0 * e + 8.0 * nc;
   }
   const AmgLevel* L0 = A->lv[0];
-  by += 44.0 * L0->n + 12.0 * 2.0 * L0->np + 4.0 * L0->n + 48.0 * (double)n_sys;
+  by += 72.0 * L0->n + 12.0 * 2.0 * L0->np + 108.0 * (double)n_sys;
   return by;
 }
 
@@ -1684,8 +1687,8 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const i
   AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * K1, st));
   AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * K1, st));
   k_fs_init<<<nblk, ANT, 0, st>>>(V[0], comp, x, b, r, p, q, vn, vn + n);
-  AMG_TRY(run_sums(rkey, vn, n, rrc, rtmp, st));
-  AMG_TRY(run_sums(rkey, vn + n, n, bb, rtmp, st));
+  AMG_TRY(run_sums(rkey, vn, n, rrc, rtmp, st, 1));
+  AMG_TRY(run_sums(rkey, vn + n, n, bb, rtmp, st, 1));
   k_fs_scal0<<<1, ANT, 0, st>>>(list, nl, rrc, bb, rst, warm, iters, stats, sc, done, itc, flag, frozen, rzc, pqc,
                                 open);
   if (warm) k_fs_reset<<<nblk, ANT, 0, st>>>(n, comp, rst, b, x, r);
@@ -1699,14 +1702,14 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const i
     for (int k = 0; k < batch; ++k) {
       launch_cycle<1>(A, V, nullptr, 0, done, st);
       k_fs_rz<<<nblk, ANT, 0, st>>>(n, comp, r, V[0].y, frozen, vn, done);
-      AMG_TRY(run_sums(rkey, vn, n, rzc, rtmp, st));
+      AMG_TRY(run_sums(rkey, vn, n, rzc, rtmp, st, 1));
       k_fs_scal1<<<nbl, ANT, 0, st>>>(list, nl, rrc, rr, bb, rzc, rhop, beta, frozen, iters, stats, itc, rtol, maxit,
                                       open, done);
       k_fs_pq<<<nblk, ANT, 0, st>>>(V[0], comp, frozen, beta, p, q, vn, done);
-      AMG_TRY(run_sums(rkey, vn, n, pqc, rtmp, st));
+      AMG_TRY(run_sums(rkey, vn, n, pqc, rtmp, st, 1));
       k_fs_alpha<<<nbl, ANT, 0, st>>>(list, nl, frozen, rhop, pqc, alpha, open, itc, done, flag);
       k_fs_xr<<<nblk, ANT, 0, st>>>(n, comp, x, r, p, q, alpha, frozen, vn, done);
-      AMG_TRY(run_sums(rkey, vn, n, rrc, rtmp, st));
+      AMG_TRY(run_sums(rkey, vn, n, rrc, rtmp, st, 1));
     }
     AMG_TRY(hipGetLastError());
     AMG_TRY(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

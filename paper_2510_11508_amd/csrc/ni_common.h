@@ -108,7 +108,9 @@ size_t radix_tmp_ints(int n);
 // out[k] = sum of v[i] over every run of equal consecutive keys k = key[i]
 // (each key one run), summed in an order fixed by the positions alone
 // (reproducible run to run).  tmp: run_sums_tmp_bytes(n) of device memory.
-hipError_t run_sums(const uint32_t* key, const double* v, int n, double* out, void* tmp, hipStream_t st);
+// tag 1 marks the batched fill's calls in kernel traces.
+hipError_t run_sums(const uint32_t* key, const double* v, int n, double* out, void* tmp, hipStream_t st,
+                    int tag = 0);
 size_t run_sums_tmp_bytes(int n);
 
 // arguments of the batched CG of the large fill components (ni_fill.hip)

@@ -233,6 +233,8 @@ __device__ __forceinline__ void rr_tree(RunRec* rec, double* out) {
   __syncthreads();
 }
 
+// TAG only names the caller in kernel traces (1: the batched fill)
+template <int TAG>
 __global__ void __launch_bounds__(RU_NT) k_runsum_tile(const uint32_t* __restrict__ key, const double* __restrict__ v,
                                                        int n, double* __restrict__ out, RunRec* __restrict__ brec) {
   __shared__ RunRec rec[RU_NT];
@@ -255,6 +257,7 @@ __global__ void __launch_bounds__(RU_NT) k_runsum_tile(const uint32_t* __restric
 
 // one block of RU_TOP threads over the tile records; the first and last
 // runs of the whole array are complete at the end
+template <int TAG>
 __global__ void __launch_bounds__(RU_TOP) k_runsum_top(const RunRec* __restrict__ brec, int nb,
                                                        double* __restrict__ out) {
   __shared__ RunRec rec[RU_TOP];
@@ -348,12 +351,17 @@ hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t
 
 size_t run_sums_tmp_bytes(int n) { return sizeof(RunRec) * (size_t)std::max(ni::ceil_div(n, RU_TILE), 1); }
 
-hipError_t run_sums(const uint32_t* key, const double* v, int n, double* out, void* tmp, hipStream_t st) {
+hipError_t run_sums(const uint32_t* key, const double* v, int n, double* out, void* tmp, hipStream_t st, int tag) {
   if (n <= 0) return hipSuccess;
   const int nb = ni::ceil_div(n, RU_TILE);
   RunRec* brec = static_cast<RunRec*>(tmp);
-  k_runsum_tile<<<nb, RU_NT, 0, st>>>(key, v, n, out, brec);
-  k_runsum_top<<<1, RU_TOP, 0, st>>>(brec, nb, out);
+  if (tag == 1) {
+    k_runsum_tile<1><<<nb, RU_NT, 0, st>>>(key, v, n, out, brec);
+    k_runsum_top<1><<<1, RU_TOP, 0, st>>>(brec, nb, out);
+  } else {
+    k_runsum_tile<0><<<nb, RU_NT, 0, st>>>(key, v, n, out, brec);
+    k_runsum_top<0><<<1, RU_TOP, 0, st>>>(brec, nb, out);
+  }
   return hipGetLastError();
 }
 
