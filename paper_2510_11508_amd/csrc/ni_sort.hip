@@ -152,6 +152,43 @@ __global__ void __launch_bounds__(RS_NT) k_rs_scatter(const uint32_t* __restrict
   }
 }
 
+// ------------------------------------------------------------ small sort
+// Up to SB_N pairs in one workgroup: a bitonic sort in LDS of (masked key,
+// position) composites, which are distinct, so the result is the stable
+// order of the radix passes below, in one launch instead of four per pass.
+constexpr int SB_N = 4096, SB_NT = 1024;
+
+__global__ void __launch_bounds__(SB_NT) k_sort_small(const uint32_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin, int n, uint32_t mask,
+                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ unsigned long long a[SB_N];
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += SB_NT)
+    a[i] = i < n ? (((unsigned long long)(kin[i] & mask) << 32) | (unsigned long long)i) : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < m; i += SB_NT) {
+        const int p = i ^ j;
+        if (p > i) {
+          const unsigned long long x = a[i], y = a[p];
+          if ((x > y) == ((i & k) == 0)) {
+            a[i] = y;
+            a[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += SB_NT) {
+    const uint32_t pos = (uint32_t)(a[i] & 0xffffffffull);
+    kout[i] = kin[pos];
+    vout[i] = vin[pos];
+  }
+}
+
 // ------------------------------------------------------------- run sums
 // out[k] = the sum of v over every run of equal keys (runs are maximal
 // stretches of equal consecutive keys), in an order fixed by the element
@@ -324,6 +361,17 @@ hipError_t radix_sort_pairs(const uint32_t* k_in, const uint32_t* v_in, uint32_t
                             int* scan_tmp, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+  const void* outs[2] = {k_out, v_out};
+  const void* ins[2] = {k_in, v_in};
+  bool apart = true;
+  for (const void* o : outs)
+    for (const void* i : ins) apart = apart && o != i;
+  if (n <= SB_N && apart) {
+    // the same order as the passes below: stable on the low 8 * passes bits
+    const uint32_t mask = passes >= 4 ? 0xffffffffu : ((1u << (8 * passes)) - 1u);
+    k_sort_small<<<1, SB_NT, 0, st>>>(k_in, v_in, n, mask, k_out, v_out);
+    return hipGetLastError();
+  }
   int nblk = ni::ceil_div(n, RS_TILE);
   int* hist = scan_tmp;
   int* off = scan_tmp + 256 * nblk;
