@@ -213,7 +213,7 @@ def digest_trace(workload, d):
     with open(base, "w") as f:
         f.write(f"# Kernel time, whole integration, workload {workload} "
                 f"({line['config']['n_valid']:,} valid px, K = {line['config']['K']:,})\n\n")
-        f.write("Command (from the repository root on the GPU box):\n\n")
+        f.write("Command (from the repository root, on the GPU):\n\n")
         f.write(f"    cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 "
                 f"<repo>/bench.py --workload {workload} --steps {line['steps']} --warmup {line['warmup']} "
                 "--no-cpu-baseline --no-warm --no-pixel-level --no-merging --no-baseline --no-conn8 > <dir>/bench.json\n")

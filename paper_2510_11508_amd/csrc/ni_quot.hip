@@ -710,14 +710,14 @@ hipError_t irls_iteration(const IrlsArgs& a, int t, hipStream_t st) {
   if (e == hipSuccess && !same_as_previous)
     e = amg_build(a.amg, a.K, a.P, a.row_off, a.qcol, a.qw, a.diag, a.pair_lo, a.pair_hi, a.pW, st);
   if (e == hipSuccess) e = amg_update(a.amg, a.qw, a.diag, a.pW, st);
-  // round 1: s from zero to ||r|| <= q_rtol ||b_abs|| (b_abs = row sums of
+  // first solve: s from zero to ||r|| <= q_rtol ||b_abs|| (b_abs = row sums of
   // |B_p|, a scale of the right-hand side that does not cancel)
   if (e == hipSuccess)
     e = amg_solve(a.amg, a.rhs, a.babs, nullptr, 0.0, a.s, a.q_rtol, a.q_maxit, a.qiters_out + t, a.host_flag,
                   a.graphs != 0, st, a.hints);
-  // round 2 (refinement): the residual of s in flow form, then the
+  // second solve (refinement): the residual of s in flow form, then the
   // correction d from zero to ||r_d|| <= max(q_rtol2 ||b - L s||, 1e-13
-  // ||b_abs||), s += d.  The recursive residual of round 1 carries rounding
+  // ||b_abs||), s += d.  The recursive residual of the first solve carries rounding
   // at the scale of the heaviest rows; the flow-form residual restores what
   // the light links say, and the correction solve, whose right-hand side
   // is small, resolves it.  The floor is the rounding level of the
