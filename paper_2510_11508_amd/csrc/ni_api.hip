@@ -216,10 +216,12 @@ T* ensure(ni_ctx* c, Buf& b, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   bytes = (bytes + 255) & ~size_t(255);
   if (b.cap < bytes) {
+    // grow by a quarter at least, so that sizes creeping up from call to
+    // call do not reallocate every time
+    const size_t want = (std::max(bytes, b.cap + b.cap / 4) + 255) & ~size_t(255);
     if (b.p) check(c, hipFree(b.p), "hipFree");
     b.p = nullptr;
     b.cap = 0;
-    size_t want = std::max(bytes, b.cap + b.cap / 4);
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) {
       b.p = nullptr;
