@@ -246,6 +246,188 @@ __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict_
   }
 }
 
+// ------------------------------------------------------------------ tail
+// The coarse end of the cycle in one workgroup.  Below a few thousand
+// nodes a level's kernels are bound by their chain of dependent global
+// loads (offsets, entries, gathered neighbour values: ~6-10 us each, three
+// kernels per level).  From level t0 on, every level (the coarsest
+// included) is copied into LDS at the start of one kernel, and the down
+// sweep, the restrictions, the exact coarsest solve and the up sweep run
+// there between barriers.  The arithmetic is that of the per-level
+// kernels; rows with more than AH entries are summed by a wavefront
+// (lanes strided over the entries, then the butterfly) instead of a block,
+// and aggregates of any size in order.  The prolongation is a scatter:
+// each coarse node adds its correction to the x of its members.
+constexpr int TNT = 1024;              // threads of the tail workgroup
+constexpr int TMAXL = 10;              // tail levels at most
+constexpr int TAIL_LDS = 152 * 1024;   // bytes of LDS the tail may use
+static_assert(AMAXC * CO_P == TNT, "the coarsest solve takes CO_P threads per node");
+
+// one tail level: sizes, byte offsets of its arrays in LDS, global sources
+struct TLev {
+  int n, nnz, nh, nmem;  // rows, entries, rows with more than AH entries, members (finer rows with a node here)
+  int o_ro, o_col, o_w, o_dg, o_b, o_x, o_y, o_mo, o_mem, o_hv;
+  const int *row_off, *col, *mem_off, *mem, *heavy;
+  const double *w, *diag;
+};
+struct TailPlan {
+  int nl;            // tail levels, the coarsest included (at least 2)
+  int o_pin;         // pinned flags of the coarsest
+  double corr;       // coarse-correction factor
+  const double* bin; // b of the first tail level (written by the restriction above it)
+  double* yout;      // its y (read by the up sweep above it)
+  const double* ainv;
+  const uint8_t* pin;
+  TLev lv[TMAXL];
+};
+
+template <int FILL>
+__global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
+  if (is_done(done)) return;
+  __shared__ __align__(16) unsigned char sm[TAIL_LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  constexpr int NW = TNT / 64;
+  auto u16 = [&](int o) { return reinterpret_cast<uint16_t*>(sm + o); };
+  auto f64 = [&](int o) { return reinterpret_cast<double*>(sm + o); };
+  const int nl = T.nl;
+  uint8_t* pin = sm + T.o_pin;
+  // ---- copy: matrices of the smoothed levels, member lists, b and
+  // x = w D^-1 b of the first level, pinned flags of the coarsest
+  for (int k = 0; k < nl; ++k) {
+    const TLev& L = T.lv[k];
+    if (k + 1 < nl) {
+      uint16_t* ro = u16(L.o_ro);
+      for (int i = tid; i <= L.n; i += TNT) ro[i] = (uint16_t)L.row_off[i];
+      uint16_t* cl = u16(L.o_col);
+      double* w = f64(L.o_w);
+      for (int i = tid; i < L.nnz; i += TNT) {
+        cl[i] = (uint16_t)L.col[i];
+        w[i] = L.w[i];
+      }
+      double* dg = f64(L.o_dg);
+      if (k == 0) {
+        double *b = f64(L.o_b), *x = f64(L.o_x);
+        for (int i = tid; i < L.n; i += TNT) {
+          const double bi = T.bin[i], e = L.diag[i];
+          dg[i] = e;
+          b[i] = bi;
+          x[i] = e > 0 ? AOMEGA * bi / e : 0.0;
+        }
+      } else {
+        for (int i = tid; i < L.n; i += TNT) dg[i] = L.diag[i];
+      }
+      uint16_t* hv = u16(L.o_hv);
+      for (int i = tid; i < L.nh; i += TNT) hv[i] = (uint16_t)L.heavy[i];
+    } else {
+      for (int i = tid; i < L.n; i += TNT) pin[i] = T.pin[i];
+    }
+    if (k > 0) {
+      uint16_t* mo = u16(L.o_mo);
+      for (int i = tid; i <= L.n; i += TNT) mo[i] = (uint16_t)L.mem_off[i];
+      uint16_t* mem = u16(L.o_mem);
+      for (int i = tid; i < L.nmem; i += TNT) mem[i] = (uint16_t)L.mem[i];
+    }
+  }
+  __syncthreads();
+  // ---- down: residual r = b - A x (into y), restriction to the next level
+  for (int k = 0; k + 1 < nl; ++k) {
+    const TLev& L = T.lv[k];
+    const uint16_t *ro = u16(L.o_ro), *cl = u16(L.o_col), *hv = u16(L.o_hv);
+    const double *w = f64(L.o_w), *b = f64(L.o_b), *x = f64(L.o_x);
+    double* r = f64(L.o_y);
+    for (int c = tid; c < L.n; c += TNT) {
+      const int j0 = ro[c], j1 = ro[c + 1];
+      if (j1 - j0 > AH) continue;
+      const double xc = x[c];
+      double acc = 0.0;
+      for (int j = j0; j < j1; ++j) acc += w[j] * (xc - x[cl[j]]);
+      r[c] = b[c] - acc;
+    }
+    for (int h = wid; h < L.nh; h += NW) {
+      const int c = hv[h], j0 = ro[c], j1 = ro[c + 1];
+      const double xc = x[c];
+      double acc = 0.0;
+      for (int j = j0 + lane; j < j1; j += 64) acc += w[j] * (xc - x[cl[j]]);
+      acc = ni::wave_sum(acc);
+      if (lane == 0) r[c] = b[c] - acc;
+    }
+    __syncthreads();
+    const TLev& C = T.lv[k + 1];
+    const bool coarsest = k + 2 == nl;
+    const uint16_t *mo = u16(C.o_mo), *mem = u16(C.o_mem);
+    double* bc = f64(C.o_b);
+    for (int c = tid; c < C.n; c += TNT) {
+      double s = 0.0;
+      for (int i = mo[c]; i < mo[c + 1]; ++i) s += r[mem[i]];
+      if (coarsest) {
+        bc[c] = pin[c] ? 0.0 : s;
+      } else {
+        bc[c] = s;
+        const double e = f64(C.o_dg)[c];
+        f64(C.o_x)[c] = e > 0 ? AOMEGA * s / e : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- exact coarsest solve (CO_P threads per node, as k_cy_coarsest),
+  // prolonged into the x of the level above
+  {
+    const TLev& C = T.lv[nl - 1];
+    const int n = C.n;
+    const double* bc = f64(C.o_b);
+    const int c = tid / CO_P, part = tid % CO_P;
+    double acc = 0.0;
+    if (c < n)
+      for (int j = part; j < n; j += CO_P) acc += T.ainv[(size_t)j * n + c] * bc[j];
+#pragma unroll
+    for (int o = 1; o < CO_P; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (c < n && part == 0) {
+      const uint16_t *mo = u16(C.o_mo), *mem = u16(C.o_mem);
+      double* xf = f64(T.lv[nl - 2].o_x);
+      for (int i = mo[c]; i < mo[c + 1]; ++i) xf[mem[i]] += T.corr * acc;
+    }
+    __syncthreads();
+  }
+  // ---- up: y = x + w D^-1 (b - A x), prolonged into the level above (or
+  // written out on the first tail level)
+  for (int k = nl - 2; k >= 0; --k) {
+    const TLev& L = T.lv[k];
+    const uint16_t *ro = u16(L.o_ro), *cl = u16(L.o_col), *hv = u16(L.o_hv);
+    const double *w = f64(L.o_w), *b = f64(L.o_b), *x = f64(L.o_x), *dg = f64(L.o_dg);
+    const uint16_t *mo = k > 0 ? u16(L.o_mo) : nullptr, *mem = k > 0 ? u16(L.o_mem) : nullptr;
+    double* xf = k > 0 ? f64(T.lv[k - 1].o_x) : nullptr;
+    for (int c = tid; c < L.n; c += TNT) {
+      const int j0 = ro[c], j1 = ro[c + 1];
+      if (j1 - j0 > AH) continue;
+      const double xc = x[c];
+      double acc = 0.0;
+      for (int j = j0; j < j1; ++j) acc += w[j] * (xc - x[cl[j]]);
+      const double e = dg[c];
+      const double yc = e > 0 ? xc + AOMEGA * (b[c] - acc) / e : 0.0;
+      if (k == 0) {
+        T.yout[c] = yc;
+      } else {
+        for (int i = mo[c]; i < mo[c + 1]; ++i) xf[mem[i]] += T.corr * yc;
+      }
+    }
+    for (int h = wid; h < L.nh; h += NW) {
+      const int c = hv[h], j0 = ro[c], j1 = ro[c + 1];
+      const double xc = x[c];
+      double acc = 0.0;
+      for (int j = j0 + lane; j < j1; j += 64) acc += w[j] * (xc - x[cl[j]]);
+      acc = ni::wave_sum(acc);
+      const double e = dg[c];
+      const double yc = e > 0 ? xc + AOMEGA * (b[c] - acc) / e : 0.0;
+      if (k == 0) {
+        if (lane == 0) T.yout[c] = yc;
+      } else {
+        for (int i = mo[c] + lane; i < mo[c + 1]; i += 64) xf[mem[i]] += T.corr * yc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // -------------------------------------------------------------------- PCG
 // x = 0, r = b, p = q = 0; partials of (r, r), |scale|^2 and |floor|^2
 __global__ void __launch_bounds__(ANT) k_cg_init(int n, const double* __restrict__ rhs, const double* __restrict__ scale,
@@ -1048,6 +1230,7 @@ namespace nil {
 
 struct AmgLevel {
   int n = 0, np = 0, nheavy = 0, nmheavy = 0;
+  int nmem = 0;  // levels >= 1: finer nodes that belong to a node of this level
   // levels >= 1: members of every node, Galerkin lists (fine pairs per pair)
   DBuf mem_off_b, mem_b, mheavy_b, gal_off_b, gal_src_b;
   // map of this level's nodes to the next level
@@ -1396,6 +1579,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
       AMG_TRY(scan_exclusive_i32(flag, fpos, n, tot, scan, st));
       int m = 0;
       AMG_TRY(read_int(A, tot, &m, st));
+      C->nmem = m;
       k_am_compact<<<nb256(n), 256, 0, st>>>(n, flag, fpos, cid, ko, vo);
       AMG_TRY(radix_sort_pairs(ko, vo, ks, vs, kt, vt, m, bits_for(nc), scan, st));
       k_am_u32<<<nb256(m), 256, 0, st>>>(vs, m, mem);
@@ -1525,11 +1709,97 @@ static ALev view(const AmgLevel* L, double* b) {
   return v;
 }
 
+// The LDS layout of the tail from level t0 on; its size in bytes, or -1
+// when a level is too large for 16-bit indices
+static long long tail_layout(const Amg* A, int t0, TailPlan* T) {
+  long long off = 0;
+  auto take = [&](long long bytes) {
+    const long long o = off;
+    off += (bytes + 15) & ~15ll;
+    return (int)o;
+  };
+  const int nl = A->nlev - t0;
+  for (int k = 0; k < nl; ++k) {
+    const AmgLevel* L = A->lv[t0 + k];
+    const long long n = L->n, nnz = 2ll * L->np;
+    if (n >= 65535 || nnz >= 65535 || L->nmem >= 65535) return -1;
+    TLev v{};
+    v.n = L->n;
+    v.nnz = (int)nnz;
+    v.nh = L->nheavy;
+    v.nmem = k > 0 ? L->nmem : 0;
+    if (k + 1 < nl) {
+      v.o_ro = take(2 * (n + 1));
+      v.o_col = take(2 * nnz);
+      v.o_w = take(8 * nnz);
+      v.o_dg = take(8 * n);
+      v.o_x = take(8 * n);
+      v.o_y = take(8 * n);
+      v.o_hv = take(2ll * L->nheavy);
+    }
+    v.o_b = take(8 * n);
+    if (k > 0) {
+      v.o_mo = take(2 * (n + 1));
+      v.o_mem = take(2ll * L->nmem);
+    }
+    v.row_off = L->row_off;
+    v.col = L->col;
+    v.mem_off = L->mem_off;
+    v.mem = L->mem;
+    v.heavy = L->heavy;
+    v.w = L->w;
+    v.diag = L->diag;
+    if (T) T->lv[k] = v;
+  }
+  const int o_pin = take(A->lv[A->nlev - 1]->n);
+  if (T) T->o_pin = o_pin;
+  return off;
+}
+
+// the tail for this hierarchy: the first tail level is the largest that
+// still fits in TAIL_LDS (and is not the finest); returns t0, or -1 for no
+// tail (no exact coarsest, or not even one smoothed level fits)
+static int plan_tail(const Amg* A, const std::vector<ALev>& V, TailPlan& T) {
+  if (!A->dense || A->nlev < 3) return -1;
+  int t0 = -1;
+  for (int t = A->nlev - 2; t >= 1 && A->nlev - t <= TMAXL; --t) {
+    const long long by = tail_layout(A, t, nullptr);
+    if (by < 0 || by > TAIL_LDS) break;
+    t0 = t;
+  }
+  if (t0 < 0) return -1;
+  tail_layout(A, t0, &T);
+  T.nl = A->nlev - t0;
+  T.corr = A->corr;
+  T.bin = V[t0].b;
+  T.yout = V[t0].y;
+  T.ainv = static_cast<const double*>(A->ainv.p);
+  T.pin = static_cast<const uint8_t*>(A->pin.p);
+  return t0;
+}
+
 // one V-cycle on V[0].b -> V[0].y; the finest level writes the block
-// partials of (b, y) to parts
+// partials of (b, y) to parts.  With t0 >= 1 the levels from t0 on run in
+// the tail kernel (plan T).
 template <int FILL>
 static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts, int pstride, const int* done,
-                         hipStream_t q_) {
+                         hipStream_t q_, int t0, const TailPlan& T) {
+  if (t0 >= 1) {
+    for (int l = 0; l < t0; ++l) {
+      const ALev& L = V[l];
+      k_cy_down<FILL><<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
+      const AmgLevel* C = A->lv[l + 1];
+      k_cy_restrict<FILL><<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem,
+                                                                    C->mheavy, L.r, V[l + 1].b, done);
+    }
+    k_cy_tail<FILL><<<1, TNT, 0, q_>>>(T, done);
+    for (int l = t0 - 1; l >= 0; --l) {
+      const ALev& L = V[l];
+      k_cy_up<FILL><<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, A->corr,
+                                                       done);
+    }
+    return;
+  }
   for (int l = 0; l + 1 < A->nlev; ++l) {
     const ALev& L = V[l];
     k_cy_down<FILL><<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, done);
@@ -1579,10 +1849,12 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const doubl
   k_cg_scal<0><<<1, SC_NT, 0, st>>>(0, parts, nblk, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
+  TailPlan tp{};
+  const int t0 = plan_tail(A, V, tp);
   // one PCG iteration: V-cycle on r -> z (= y of level 0), then the CG
   // update; every kernel returns at once after convergence
   auto iteration = [&](hipStream_t q_) {
-    launch_cycle<0>(A, V, parts, pstride, done, q_);
+    launch_cycle<0>(A, V, parts, pstride, done, q_, t0, tp);
     // rho = (r, z) -> beta; convergence on ||r||
     k_cg_scal<0><<<1, SC_NT, 0, q_>>>(1, parts, pstride, pstride, nblk, sc, done, itc, rtol, maxit, iters_out, flag);
     k_cg_pq<0><<<V[0].nblk + V[0].nheavy, ANT, 0, q_>>>(V[0], p, q, sc, parts, pstride, done);
@@ -1618,7 +1890,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const doubl
   constexpr int FUSE_MAX = 1024;
   const bool fuse = pstride <= FUSE_MAX;
   auto fused = [&](int it) {
-    launch_cycle<0>(A, V, parts, pstride, done, st);
+    launch_cycle<0>(A, V, parts, pstride, done, st, t0, tp);
     k_cg_pq_f<<<V[0].nblk + V[0].nheavy, ANT, 0, st>>>(V[0], p, q, sc, parts, pstride, pstride, nblk, it, rtol,
                                                       maxit, done, flag, iters_out);
     k_cg_xr_f<<<nblk, ANT, 0, st>>>(n, s, r, p, q, sc, parts, pstride, pstride, it, done);
@@ -1683,6 +1955,8 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const i
   int* open = ctr + 3;
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
+  TailPlan tp{};
+  const int t0 = plan_tail(A, V, tp);
   // components without a node on this level keep zero sums
   AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * K1, st));
   AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * K1, st));
@@ -1700,7 +1974,7 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const i
   const int batch = 8;
   for (int it = 0; it <= maxit + 1; it += batch) {
     for (int k = 0; k < batch; ++k) {
-      launch_cycle<1>(A, V, nullptr, 0, done, st);
+      launch_cycle<1>(A, V, nullptr, 0, done, st, t0, tp);
       k_fs_rz<<<nblk, ANT, 0, st>>>(n, comp, r, V[0].y, frozen, vn, done);
       AMG_TRY(run_sums(rkey, vn, n, rzc, rtmp, st, 1));
       k_fs_scal1<<<nbl, ANT, 0, st>>>(list, nl, rrc, rr, bb, rzc, rhop, beta, frozen, iters, stats, itc, rtol, maxit,
