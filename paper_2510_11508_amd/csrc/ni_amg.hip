@@ -57,6 +57,7 @@ struct ALev {
   const double* diag;  // row sums
   const int* heavy;    // rows with more than AH entries
   const int* cid;      // node -> node of the next level (-1: none); null on the coarsest
+  const int* ccol;     // entry -> node of the next level of its neighbour (cid of col); null on the coarsest
   double *b, *x, *r, *y;
 };
 
@@ -82,24 +83,26 @@ __device__ __forceinline__ RowSel row_sel(const ALev& L) {
   return s;
 }
 
-// sum over the entries of row c of w_j * (vc - val(col_j)); a heavy row is
-// split over the block's threads (then summed by the caller)
+// sum over the entries j of row c of w_j * (vc - val(col_j, j)); a heavy
+// row is split over the block's threads (then summed by the caller).
+// Entries past the row's end enter as w = 0 with val(c, -1).
 template <class V>
 __device__ __forceinline__ double row_diff_sum(const ALev& L, const RowSel& s, double vc, V val) {
   const int j0 = L.row_off[s.c], j1 = L.row_off[s.c + 1];
   const int t0 = s.big ? threadIdx.x : 0, st = s.big ? ANT : 1;
   double acc = 0.0;
   for (int base = j0 + t0; base < j1; base += 8 * st) {
-    int d[8];
+    int d[8], e[8];
     double q[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int j = base + u * st;
       d[u] = j < j1 ? L.col[j] : s.c;
+      e[u] = j < j1 ? j : -1;
       q[u] = j < j1 ? L.w[j] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += q[u] * (vc - val(d[u]));
+    for (int u = 0; u < 8; ++u) acc += q[u] * (vc - val(d[u], e[u]));
   }
   return acc;
 }
@@ -123,9 +126,9 @@ __global__ void __launch_bounds__(ANT) k_cy_down(ALev L, const int* done) {
   const RowSel s = row_sel(L);
   const double* b = L.b;
   const double* dg = L.diag;
-  auto xv = [&](int d) { const double e = dg[d]; return e > 0 ? AOMEGA * b[d] / e : 0.0; };
+  auto xv = [&](int d, int) { const double e = dg[d]; return e > 0 ? AOMEGA * b[d] / e : 0.0; };
   double acc = 0.0;
-  if (s.c >= 0) acc = row_diff_sum(L, s, xv(s.c), xv);
+  if (s.c >= 0) acc = row_diff_sum(L, s, xv(s.c, -1), xv);
   if (s.big) {
     double t[1] = {acc};
     ni::block_sum<1>(t, red);
@@ -214,7 +217,10 @@ __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict_
   const double* b = L.b;
   const double* dg = L.diag;
   const int* cid = L.cid;
-  auto xv = [&](int d) {
+  const int* ccol = L.ccol;
+  // the own row's value; a neighbour's takes its coarse node from the
+  // entry (ccol), which saves a dependent load of cid
+  auto xown = [&](int d) {
     const double e = dg[d];
     double v = e > 0 ? AOMEGA * b[d] / e : 0.0;
     if (yn) {
@@ -225,7 +231,17 @@ __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict_
   };
   double acc = 0.0, xc = 0.0;
   if (s.c >= 0) {
-    xc = xv(s.c);
+    xc = xown(s.c);
+    auto xv = [&](int d, int j) {
+      if (j < 0) return xc;
+      const double e = dg[d];
+      double v = e > 0 ? AOMEGA * b[d] / e : 0.0;
+      if (yn) {
+        const int k = ccol[j];
+        if (k >= 0) v += corr * yn[k];
+      }
+      return v;
+    };
     acc = row_diff_sum(L, s, xc, xv);
   }
   if (s.big) {
@@ -262,27 +278,100 @@ constexpr int TNT = 1024;              // threads of the tail workgroup
 constexpr int TMAXL = 10;              // tail levels at most
 constexpr int TAIL_LDS = 152 * 1024;   // bytes of LDS the tail may use
 static_assert(AMAXC * CO_P == TNT, "the coarsest solve takes CO_P threads per node");
+static_assert(TAIL_LDS <= 10 * 16 * TNT, "the image is copied with ten 16-byte loads per thread");
+static_assert(sizeof(uint4) == 16, "16-byte copies");
 
-// one tail level: sizes, byte offsets of its arrays in LDS, global sources
-struct TLev {
+// one tail level: sizes and byte offsets of its arrays in LDS (this table
+// heads the image), then the global sources of the packed arrays
+struct TOff {
   int n, nnz, nh, nmem;  // rows, entries, rows with more than AH entries, members (finer rows with a node here)
   int o_ro, o_col, o_w, o_dg, o_b, o_x, o_y, o_mo, o_mem, o_hv;
+};
+struct TLev : TOff {
   const int *row_off, *col, *mem_off, *mem, *heavy;
   const double *w, *diag;
 };
+constexpr int TTAB = (TMAXL * (int)sizeof(TOff) + 15) & ~15;  // bytes of the table
+// The LDS arena: the level table, the per-step arrays of every level
+// (16-bit row offsets, columns and member lists, FP64 weights and row
+// sums, pinned flags), all packed once per solve into a global image of
+// the same layout and copied in with one 16-byte load per thread and
+// chunk; then the vectors of the cycle (b, x, y), which the kernel writes
+// before it reads them.
 struct TailPlan {
-  int nl;            // tail levels, the coarsest included (at least 2)
-  int o_pin;         // pinned flags of the coarsest
-  double corr;       // coarse-correction factor
-  const double* bin; // b of the first tail level (written by the restriction above it)
-  double* yout;      // its y (read by the up sweep above it)
+  int nl;             // tail levels, the coarsest included (at least 2)
+  int o_pin;          // pinned flags of the coarsest
+  int img_bytes;      // bytes of the packed image (a multiple of 16)
+  double corr;        // coarse-correction factor
+  const double* bin;  // b of the first tail level (written by the restriction above it)
+  double* yout;       // its y (read by the up sweep above it)
   const double* ainv;
   const uint8_t* pin;
+  unsigned char* img;
   TLev lv[TMAXL];
 };
+// the tail kernel's arguments: the image and what the first level needs
+// before the image has landed
+struct TailHead {
+  int nl, o_pin, img_bytes, n0, o_b0, o_x0;
+  double corr;
+  const double *bin, *diag0, *ainv;
+  double* yout;
+  const unsigned char* img;
+};
+
+// pack the per-step arrays of tail level blockIdx.y into the image
+__global__ void k_tail_pack(TailPlan T) {
+  const int k = blockIdx.y;
+  const TLev& L = T.lv[k];
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
+  unsigned char* im = T.img;
+  if (k + 1 < T.nl) {
+    uint16_t* ro = reinterpret_cast<uint16_t*>(im + L.o_ro);
+    for (int i = i0; i <= L.n; i += st) ro[i] = (uint16_t)L.row_off[i];
+    uint16_t* cl = reinterpret_cast<uint16_t*>(im + L.o_col);
+    double* w = reinterpret_cast<double*>(im + L.o_w);
+    for (int i = i0; i < L.nnz; i += st) {
+      cl[i] = (uint16_t)L.col[i];
+      w[i] = L.w[i];
+    }
+    double* dg = reinterpret_cast<double*>(im + L.o_dg);
+    for (int i = i0; i < L.n; i += st) dg[i] = L.diag[i];
+    uint16_t* hv = reinterpret_cast<uint16_t*>(im + L.o_hv);
+    for (int i = i0; i < L.nh; i += st) hv[i] = (uint16_t)L.heavy[i];
+  } else {
+    for (int i = i0; i < L.n; i += st) im[T.o_pin + i] = T.pin[i];
+  }
+  if (k > 0) {
+    uint16_t* mo = reinterpret_cast<uint16_t*>(im + L.o_mo);
+    for (int i = i0; i <= L.n; i += st) mo[i] = (uint16_t)L.mem_off[i];
+    uint16_t* mem = reinterpret_cast<uint16_t*>(im + L.o_mem);
+    for (int i = i0; i < L.nmem; i += st) mem[i] = (uint16_t)L.mem[i];
+  }
+}
+
+// sum over the entries j0 <= j < j1 of w_j (xc - x[col_j]), in entry
+// order (the order of row_diff_sum on a regular row)
+__device__ __forceinline__ double lds_row_sum(const uint16_t* cl, const double* w, const double* x, int j0, int j1,
+                                              int c, double xc) {
+  double acc = 0.0;
+  for (int base = j0; base < j1; base += 8) {
+    int d[8];
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = base + u;
+      d[u] = j < j1 ? cl[j] : c;
+      q[u] = j < j1 ? w[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += q[u] * (xc - x[d[u]]);
+  }
+  return acc;
+}
 
 template <int FILL>
-__global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
+__global__ void __launch_bounds__(TNT) k_cy_tail(TailHead T, const int* done) {
   if (is_done(done)) return;
   __shared__ __align__(16) unsigned char sm[TAIL_LDS];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -290,58 +379,40 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
   auto u16 = [&](int o) { return reinterpret_cast<uint16_t*>(sm + o); };
   auto f64 = [&](int o) { return reinterpret_cast<double*>(sm + o); };
   const int nl = T.nl;
-  uint8_t* pin = sm + T.o_pin;
-  // ---- copy: matrices of the smoothed levels, member lists, b and
-  // x = w D^-1 b of the first level, pinned flags of the coarsest
-  for (int k = 0; k < nl; ++k) {
-    const TLev& L = T.lv[k];
-    if (k + 1 < nl) {
-      uint16_t* ro = u16(L.o_ro);
-      for (int i = tid; i <= L.n; i += TNT) ro[i] = (uint16_t)L.row_off[i];
-      uint16_t* cl = u16(L.o_col);
-      double* w = f64(L.o_w);
-      for (int i = tid; i < L.nnz; i += TNT) {
-        cl[i] = (uint16_t)L.col[i];
-        w[i] = L.w[i];
-      }
-      double* dg = f64(L.o_dg);
-      if (k == 0) {
-        double *b = f64(L.o_b), *x = f64(L.o_x);
-        for (int i = tid; i < L.n; i += TNT) {
-          const double bi = T.bin[i], e = L.diag[i];
-          dg[i] = e;
-          b[i] = bi;
-          x[i] = e > 0 ? AOMEGA * bi / e : 0.0;
-        }
-      } else {
-        for (int i = tid; i < L.n; i += TNT) dg[i] = L.diag[i];
-      }
-      uint16_t* hv = u16(L.o_hv);
-      for (int i = tid; i < L.nh; i += TNT) hv[i] = (uint16_t)L.heavy[i];
-    } else {
-      for (int i = tid; i < L.n; i += TNT) pin[i] = T.pin[i];
+  const uint8_t* pin = sm + T.o_pin;
+  const TOff* lv = reinterpret_cast<const TOff*>(sm);
+  // ---- the image, all loads in flight at once; b and x = w D^-1 b of
+  // the first level (its row sums taken from global memory)
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(T.img);
+    uint4* dst = reinterpret_cast<uint4*>(sm);
+    const int nv = T.img_bytes / 16;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    uint4 v0 = z, v1 = z, v2 = z, v3 = z, v4 = z, v5 = z, v6 = z, v7 = z, v8 = z, v9 = z;
+#define TAIL_LD(u) if (tid + (u) * TNT < nv) v##u = src[tid + (u) * TNT];
+#define TAIL_ST(u) if (tid + (u) * TNT < nv) dst[tid + (u) * TNT] = v##u;
+    TAIL_LD(0) TAIL_LD(1) TAIL_LD(2) TAIL_LD(3) TAIL_LD(4) TAIL_LD(5) TAIL_LD(6) TAIL_LD(7) TAIL_LD(8) TAIL_LD(9)
+    double *b = f64(T.o_b0), *x = f64(T.o_x0);
+    for (int i = tid; i < T.n0; i += TNT) {
+      const double bi = T.bin[i], e = T.diag0[i];
+      b[i] = bi;
+      x[i] = e > 0 ? AOMEGA * bi / e : 0.0;
     }
-    if (k > 0) {
-      uint16_t* mo = u16(L.o_mo);
-      for (int i = tid; i <= L.n; i += TNT) mo[i] = (uint16_t)L.mem_off[i];
-      uint16_t* mem = u16(L.o_mem);
-      for (int i = tid; i < L.nmem; i += TNT) mem[i] = (uint16_t)L.mem[i];
-    }
+    TAIL_ST(0) TAIL_ST(1) TAIL_ST(2) TAIL_ST(3) TAIL_ST(4) TAIL_ST(5) TAIL_ST(6) TAIL_ST(7) TAIL_ST(8) TAIL_ST(9)
+#undef TAIL_LD
+#undef TAIL_ST
   }
   __syncthreads();
   // ---- down: residual r = b - A x (into y), restriction to the next level
   for (int k = 0; k + 1 < nl; ++k) {
-    const TLev& L = T.lv[k];
+    const TOff L = lv[k];
     const uint16_t *ro = u16(L.o_ro), *cl = u16(L.o_col), *hv = u16(L.o_hv);
     const double *w = f64(L.o_w), *b = f64(L.o_b), *x = f64(L.o_x);
     double* r = f64(L.o_y);
     for (int c = tid; c < L.n; c += TNT) {
       const int j0 = ro[c], j1 = ro[c + 1];
       if (j1 - j0 > AH) continue;
-      const double xc = x[c];
-      double acc = 0.0;
-      for (int j = j0; j < j1; ++j) acc += w[j] * (xc - x[cl[j]]);
-      r[c] = b[c] - acc;
+      r[c] = b[c] - lds_row_sum(cl, w, x, j0, j1, c, x[c]);
     }
     for (int h = wid; h < L.nh; h += NW) {
       const int c = hv[h], j0 = ro[c], j1 = ro[c + 1];
@@ -352,7 +423,7 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
       if (lane == 0) r[c] = b[c] - acc;
     }
     __syncthreads();
-    const TLev& C = T.lv[k + 1];
+    const TOff C = lv[k + 1];
     const bool coarsest = k + 2 == nl;
     const uint16_t *mo = u16(C.o_mo), *mem = u16(C.o_mem);
     double* bc = f64(C.o_b);
@@ -372,7 +443,7 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
   // ---- exact coarsest solve (CO_P threads per node, as k_cy_coarsest),
   // prolonged into the x of the level above
   {
-    const TLev& C = T.lv[nl - 1];
+    const TOff C = lv[nl - 1];
     const int n = C.n;
     const double* bc = f64(C.o_b);
     const int c = tid / CO_P, part = tid % CO_P;
@@ -383,7 +454,7 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
     for (int o = 1; o < CO_P; o <<= 1) acc += __shfl_xor(acc, o, 64);
     if (c < n && part == 0) {
       const uint16_t *mo = u16(C.o_mo), *mem = u16(C.o_mem);
-      double* xf = f64(T.lv[nl - 2].o_x);
+      double* xf = f64(lv[nl - 2].o_x);
       for (int i = mo[c]; i < mo[c + 1]; ++i) xf[mem[i]] += T.corr * acc;
     }
     __syncthreads();
@@ -391,17 +462,16 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailPlan T, const int* done) {
   // ---- up: y = x + w D^-1 (b - A x), prolonged into the level above (or
   // written out on the first tail level)
   for (int k = nl - 2; k >= 0; --k) {
-    const TLev& L = T.lv[k];
+    const TOff L = lv[k];
     const uint16_t *ro = u16(L.o_ro), *cl = u16(L.o_col), *hv = u16(L.o_hv);
     const double *w = f64(L.o_w), *b = f64(L.o_b), *x = f64(L.o_x), *dg = f64(L.o_dg);
     const uint16_t *mo = k > 0 ? u16(L.o_mo) : nullptr, *mem = k > 0 ? u16(L.o_mem) : nullptr;
-    double* xf = k > 0 ? f64(T.lv[k - 1].o_x) : nullptr;
+    double* xf = k > 0 ? f64(lv[k - 1].o_x) : nullptr;
     for (int c = tid; c < L.n; c += TNT) {
       const int j0 = ro[c], j1 = ro[c + 1];
       if (j1 - j0 > AH) continue;
       const double xc = x[c];
-      double acc = 0.0;
-      for (int j = j0; j < j1; ++j) acc += w[j] * (xc - x[cl[j]]);
+      const double acc = lds_row_sum(cl, w, x, j0, j1, c, xc);
       const double e = dg[c];
       const double yc = e > 0 ? xc + AOMEGA * (b[c] - acc) / e : 0.0;
       if (k == 0) {
@@ -461,7 +531,7 @@ __global__ void __launch_bounds__(ANT) k_cg_pq(ALev L, double* __restrict__ p, d
   __shared__ double red[ANT / 64];
   const RowSel s = row_sel(L);
   const double* z = L.y;
-  auto zv = [&](int d) { return z[d]; };
+  auto zv = [&](int d, int) { return z[d]; };
   double acc = 0.0;
   if (s.c >= 0) acc = row_diff_sum(L, s, z[s.c], zv);
   if (s.big) {
@@ -597,7 +667,7 @@ __global__ void __launch_bounds__(ANT) k_cg_pq_f(ALev L, double* __restrict__ p,
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_RH0 + (it & 1)] = rho;
   const RowSel s = row_sel(L);
   const double* z = L.y;
-  auto zv = [&](int d) { return z[d]; };
+  auto zv = [&](int d, int) { return z[d]; };
   double acc = 0.0;
   if (s.c >= 0) acc = row_diff_sum(L, s, z[s.c], zv);
   __syncthreads();  // red is reused below
@@ -744,6 +814,12 @@ __global__ void k_am_cid(int n, const int* __restrict__ agg2, const int* __restr
   const int a = agg2[c];
   cid[c] = a >= 0 ? pos[a] : -1;
   flag[c] = a >= 0 ? 1 : 0;
+}
+
+// coarse node of every entry's neighbour
+__global__ void k_am_ccol(int ne, const int* __restrict__ col, const int* __restrict__ cid, int* __restrict__ ccol) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < ne) ccol[j] = cid[col[j]];
 }
 
 // compact (key, value) of the flagged entries
@@ -1233,8 +1309,9 @@ struct AmgLevel {
   int nmem = 0;  // levels >= 1: finer nodes that belong to a node of this level
   // levels >= 1: members of every node, Galerkin lists (fine pairs per pair)
   DBuf mem_off_b, mem_b, mheavy_b, gal_off_b, gal_src_b;
-  // map of this level's nodes to the next level
-  DBuf cid_b;
+  // map of this level's nodes to the next level, and of its entries'
+  // neighbours
+  DBuf cid_b, ccol_b;
   // pairs and CSR (level 0: views of the quotient arrays)
   DBuf plo_b, phi_b, row_off_b, ent_b, col_b, heavy_b;
   // per step
@@ -1249,8 +1326,8 @@ struct AmgLevel {
   const int *mem_off = nullptr, *mem = nullptr, *mheavy = nullptr, *gal_off = nullptr, *gal_src = nullptr;
   const int* heavy = nullptr;
   int* cid = nullptr;
+  const int* ccol = nullptr;
   double *bv = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;
-  DBuf* all() { return &mem_off_b; }
 };
 
 constexpr int NSCR = 16;
@@ -1261,7 +1338,7 @@ struct Amg {
   bool dense = false;  // coarsest solved exactly
   double corr = 1.0;   // coarse-correction factor
   DBuf s[NSCR];
-  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst, fs_c, fs_frozen, fs_v, fs_rt;
+  DBuf scan, ainv, pin, p, q, r, parts, sc, ctr, rrc, rst, fs_c, fs_frozen, fs_v, fs_rt, timg;
   // host readbacks of the build: a pinned landing area, and the counts
   // that only the solve needs (heavy rows and aggregates per level),
   // gathered in device slots and read once at the end of the build
@@ -1273,7 +1350,7 @@ struct Amg {
     if (cap) (void)hipStreamDestroy(cap);
     if (hpin) (void)hipHostFree(hpin);
     for (AmgLevel* L : lv) {
-      DBuf* b[] = {&L->mem_off_b, &L->mem_b, &L->mheavy_b, &L->gal_off_b, &L->gal_src_b, &L->cid_b, &L->plo_b,
+      DBuf* b[] = {&L->mem_off_b, &L->mem_b, &L->mheavy_b, &L->gal_off_b, &L->gal_src_b, &L->cid_b, &L->ccol_b, &L->plo_b,
                    &L->phi_b, &L->row_off_b, &L->ent_b, &L->col_b, &L->heavy_b, &L->pw_b, &L->w_b, &L->diag_b,
                    &L->bv_b, &L->x_b, &L->r_b, &L->y_b, &L->gy_b, &L->gx_b, &L->gc_b};
       for (DBuf* d : b)
@@ -1282,7 +1359,7 @@ struct Amg {
     }
     for (DBuf& d : s)
       if (d.p) (void)hipFree(d.p);
-    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts, &fs_c, &fs_frozen, &fs_v, &fs_rt};
+    DBuf* own[] = {&scan, &ainv, &pin, &p, &q, &r, &parts, &sc, &ctr, &rrc, &rst, &cnts, &fs_c, &fs_frozen, &fs_v, &fs_rt, &timg};
     for (DBuf* d : own)
       if (d->p) (void)hipFree(d->p);
   }
@@ -1549,6 +1626,13 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
     if (nc <= 0 || nc > (int)(0.9 * n)) break;  // no edges left, or coarsening stalled
     k_am_cid<<<nb256(n), 256, 0, st>>>(n, agg2, pos, cid, flag);
     F->cid = cid;
+    {
+      const int ne = 2 * F->np;
+      int* ccol = grow<int>(F->ccol_b, ne, err);
+      AMG_TRY(err);
+      if (ne > 0) k_am_ccol<<<nb256(ne), 256, 0, st>>>(ne, F->col, cid, ccol);
+      F->ccol = ccol;
+    }
     if (l + 1 >= (int)A->lv.size()) A->lv.push_back(new AmgLevel());
     AmgLevel* C = A->lv[l + 1];
     C->n = nc;
@@ -1657,6 +1741,7 @@ hipError_t amg_build(Amg* A, int K, int P, const int* row_off, const int* qcol, 
   A->nlev = l + 1;
   AmgLevel* Lc = A->lv[l];
   Lc->cid = nullptr;
+  Lc->ccol = nullptr;
   AMG_TRY(flush_counts(A, st));
   // cycle vectors
   for (int k = 0; k < A->nlev; ++k) {
@@ -1702,6 +1787,7 @@ static ALev view(const AmgLevel* L, double* b) {
   v.diag = L->diag;
   v.heavy = L->heavy;
   v.cid = L->cid;
+  v.ccol = L->ccol;
   v.b = b;
   v.x = L->x;
   v.r = L->r;
@@ -1709,73 +1795,96 @@ static ALev view(const AmgLevel* L, double* b) {
   return v;
 }
 
-// The LDS layout of the tail from level t0 on; its size in bytes, or -1
-// when a level is too large for 16-bit indices
-static long long tail_layout(const Amg* A, int t0, TailPlan* T) {
-  long long off = 0;
+// The LDS layout of the tail from level t0 on (the packed per-step arrays
+// first, then the cycle vectors); its size in bytes, or -1 when a level is
+// too large for 16-bit indices.  *img_bytes: the packed part.
+static long long tail_layout(const Amg* A, int t0, TailPlan* T, long long* img_bytes) {
+  long long off = TTAB;
   auto take = [&](long long bytes) {
     const long long o = off;
     off += (bytes + 15) & ~15ll;
     return (int)o;
   };
   const int nl = A->nlev - t0;
+  TLev v[TMAXL] = {};
   for (int k = 0; k < nl; ++k) {
     const AmgLevel* L = A->lv[t0 + k];
     const long long n = L->n, nnz = 2ll * L->np;
     if (n >= 65535 || nnz >= 65535 || L->nmem >= 65535) return -1;
-    TLev v{};
-    v.n = L->n;
-    v.nnz = (int)nnz;
-    v.nh = L->nheavy;
-    v.nmem = k > 0 ? L->nmem : 0;
+    TLev& t = v[k];
+    t.n = L->n;
+    t.nnz = (int)nnz;
+    t.nh = L->nheavy;
+    t.nmem = k > 0 ? L->nmem : 0;
     if (k + 1 < nl) {
-      v.o_ro = take(2 * (n + 1));
-      v.o_col = take(2 * nnz);
-      v.o_w = take(8 * nnz);
-      v.o_dg = take(8 * n);
-      v.o_x = take(8 * n);
-      v.o_y = take(8 * n);
-      v.o_hv = take(2ll * L->nheavy);
+      t.o_ro = take(2 * (n + 1));
+      t.o_col = take(2 * nnz);
+      t.o_w = take(8 * nnz);
+      t.o_dg = take(8 * n);
+      t.o_hv = take(2ll * L->nheavy);
     }
-    v.o_b = take(8 * n);
     if (k > 0) {
-      v.o_mo = take(2 * (n + 1));
-      v.o_mem = take(2ll * L->nmem);
+      t.o_mo = take(2 * (n + 1));
+      t.o_mem = take(2ll * L->nmem);
     }
-    v.row_off = L->row_off;
-    v.col = L->col;
-    v.mem_off = L->mem_off;
-    v.mem = L->mem;
-    v.heavy = L->heavy;
-    v.w = L->w;
-    v.diag = L->diag;
-    if (T) T->lv[k] = v;
+    t.row_off = L->row_off;
+    t.col = L->col;
+    t.mem_off = L->mem_off;
+    t.mem = L->mem;
+    t.heavy = L->heavy;
+    t.w = L->w;
+    t.diag = L->diag;
   }
   const int o_pin = take(A->lv[A->nlev - 1]->n);
-  if (T) T->o_pin = o_pin;
+  *img_bytes = off;
+  for (int k = 0; k < nl; ++k) {
+    const long long n = v[k].n;
+    v[k].o_b = take(8 * n);
+    if (k + 1 < nl) {
+      v[k].o_x = take(8 * n);
+      v[k].o_y = take(8 * n);
+    }
+  }
+  if (T) {
+    for (int k = 0; k < nl; ++k) T->lv[k] = v[k];
+    T->o_pin = o_pin;
+  }
   return off;
 }
 
-// the tail for this hierarchy: the first tail level is the largest that
-// still fits in TAIL_LDS (and is not the finest); returns t0, or -1 for no
-// tail (no exact coarsest, or not even one smoothed level fits)
-static int plan_tail(const Amg* A, const std::vector<ALev>& V, TailPlan& T) {
-  if (!A->dense || A->nlev < 3) return -1;
+// The tail for this hierarchy: the first tail level is the largest that
+// still fits in TAIL_LDS (and is not the finest).  Packs the image (img:
+// at least TAIL_LDS bytes) on st.  Returns t0, or -1 for no tail (no
+// exact coarsest, or not even one smoothed level fits).
+static int plan_tail(const Amg* A, const std::vector<ALev>& V, unsigned char* img, TailPlan& T, hipStream_t st) {
+  if (!A->dense || A->nlev < 3 || !img) return -1;
   int t0 = -1;
+  long long ib = 0;
   for (int t = A->nlev - 2; t >= 1 && A->nlev - t <= TMAXL; --t) {
-    const long long by = tail_layout(A, t, nullptr);
+    const long long by = tail_layout(A, t, nullptr, &ib);
     if (by < 0 || by > TAIL_LDS) break;
     t0 = t;
   }
   if (t0 < 0) return -1;
-  tail_layout(A, t0, &T);
+  tail_layout(A, t0, &T, &ib);
   T.nl = A->nlev - t0;
+  T.img_bytes = (int)ib;
   T.corr = A->corr;
   T.bin = V[t0].b;
   T.yout = V[t0].y;
   T.ainv = static_cast<const double*>(A->ainv.p);
   T.pin = static_cast<const uint8_t*>(A->pin.p);
-  return t0;
+  T.img = img;
+  TOff tab[TMAXL] = {};
+  int most = 0;
+  for (int k = 0; k < T.nl; ++k) {
+    tab[k] = T.lv[k];
+    most = std::max(most, std::max(T.lv[k].n + 1, std::max(T.lv[k].nnz, T.lv[k].nmem)));
+  }
+  // a pageable source: the copy is staged when it is enqueued
+  if (hipMemcpyAsync(img, tab, sizeof(tab), hipMemcpyHostToDevice, st) != hipSuccess) return -1;
+  k_tail_pack<<<dim3(std::min(nb256(most), 64), T.nl), 256, 0, st>>>(T);
+  return hipGetLastError() == hipSuccess ? t0 : -1;
 }
 
 // one V-cycle on V[0].b -> V[0].y; the finest level writes the block
@@ -1792,7 +1901,20 @@ static void launch_cycle(const Amg* A, const std::vector<ALev>& V, double* parts
       k_cy_restrict<FILL><<<nb256(C->n) + C->nmheavy, ANT, 0, q_>>>(C->n, nb256(C->n), C->mem_off, C->mem,
                                                                     C->mheavy, L.r, V[l + 1].b, done);
     }
-    k_cy_tail<FILL><<<1, TNT, 0, q_>>>(T, done);
+    TailHead h;
+    h.nl = T.nl;
+    h.o_pin = T.o_pin;
+    h.img_bytes = T.img_bytes;
+    h.n0 = T.lv[0].n;
+    h.o_b0 = T.lv[0].o_b;
+    h.o_x0 = T.lv[0].o_x;
+    h.corr = T.corr;
+    h.bin = T.bin;
+    h.diag0 = T.lv[0].diag;
+    h.ainv = T.ainv;
+    h.yout = T.yout;
+    h.img = T.img;
+    k_cy_tail<FILL><<<1, TNT, 0, q_>>>(h, done);
     for (int l = t0 - 1; l >= 0; --l) {
       const ALev& L = V[l];
       k_cy_up<FILL><<<L.nblk + L.nheavy, ANT, 0, q_>>>(L, V[l + 1].y, l == 0 ? parts : nullptr, pstride, A->corr,
@@ -1840,6 +1962,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const doubl
   double* parts = grow<double>(A->parts, 3 * (size_t)pstride, err);
   double* sc = grow<double>(A->sc, S_N, err);
   int* ctr = grow<int>(A->ctr, 8, err);  // [0] done, [1] iteration, [2] flag
+  unsigned char* timg = grow<unsigned char>(A->timg, TAIL_LDS, err);
   AMG_TRY(err);
   int* done = ctr;
   int* itc = ctr + 1;
@@ -1850,7 +1973,7 @@ hipError_t amg_solve(Amg* A, const double* rhs, const double* scale, const doubl
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
   TailPlan tp{};
-  const int t0 = plan_tail(A, V, tp);
+  const int t0 = plan_tail(A, V, timg, tp, st);
   // one PCG iteration: V-cycle on r -> z (= y of level 0), then the CG
   // update; every kernel returns at once after convergence
   auto iteration = [&](hipStream_t q_) {
@@ -1947,6 +2070,7 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const i
   // per-node terms of the per-component sums, and the run-sum scratch
   double* vn = grow<double>(A->fs_v, 2 * (size_t)n, err);
   void* rtmp = grow<uint8_t>(A->fs_rt, run_sums_tmp_bytes(n), err);
+  unsigned char* timg = grow<unsigned char>(A->timg, TAIL_LDS, err);
   AMG_TRY(err);
   double *rzc = cs, *pqc = cs + K1, *rhop = cs + 2 * K1, *beta = cs + 3 * K1, *alpha = cs + 4 * K1;
   int* done = ctr;
@@ -1956,7 +2080,7 @@ hipError_t amg_fill_solve(Amg* A, const int* comp, const uint32_t* rkey, const i
   std::vector<ALev> V(A->nlev);
   for (int k = 0; k < A->nlev; ++k) V[k] = view(A->lv[k], k == 0 ? r : A->lv[k]->bv);
   TailPlan tp{};
-  const int t0 = plan_tail(A, V, tp);
+  const int t0 = plan_tail(A, V, timg, tp, st);
   // components without a node on this level keep zero sums
   AMG_TRY(hipMemsetAsync(rrc, 0, sizeof(double) * K1, st));
   AMG_TRY(hipMemsetAsync(bb, 0, sizeof(double) * K1, st));
