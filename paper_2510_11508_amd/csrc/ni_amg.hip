@@ -350,24 +350,58 @@ __global__ void k_tail_pack(TailPlan T) {
   }
 }
 
-// sum over the entries j0 <= j < j1 of w_j (xc - x[col_j]), in entry
-// order (the order of row_diff_sum on a regular row)
+// LDS loops of the tail, eight independent loads in flight per step:
+// indices past the end are clamped to the last element (in bounds, its
+// term discarded), so the loads need no branches.
+// Sum over the entries j0 <= j < j1 of w_j (xc - x[col_j]), in entry order
+// (the order of row_diff_sum on a regular row); j0 < j1.
 __device__ __forceinline__ double lds_row_sum(const uint16_t* cl, const double* w, const double* x, int j0, int j1,
-                                              int c, double xc) {
+                                              double xc) {
   double acc = 0.0;
   for (int base = j0; base < j1; base += 8) {
     int d[8];
-    double q[8];
+    double q[8], v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int j = base + u;
-      d[u] = j < j1 ? cl[j] : c;
-      q[u] = j < j1 ? w[j] : 0.0;
+      const int j = min(base + u, j1 - 1);
+      d[u] = cl[j];
+      q[u] = base + u < j1 ? w[j] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += q[u] * (xc - x[d[u]]);
+    for (int u = 0; u < 8; ++u) v[u] = x[d[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += q[u] * (xc - v[u]);
   }
   return acc;
+}
+
+// sum of v[mem[i]] over i0 <= i < i1, in order
+__device__ __forceinline__ double lds_gather_sum(const uint16_t* mem, const double* v, int i0, int i1) {
+  double s = 0.0;
+  for (int base = i0; base < i1; base += 8) {
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = v[mem[min(base + u, i1 - 1)]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (base + u < i1) s += q[u];
+  }
+  return s;
+}
+
+// v[mem[i]] += a for i0 <= i < i1 (members are distinct)
+__device__ __forceinline__ void lds_scatter_add(const uint16_t* mem, double* v, int i0, int i1, double a) {
+  for (int base = i0; base < i1; base += 8) {
+    int m[8];
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m[u] = mem[min(base + u, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = v[m[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (base + u < i1) v[m[u]] = q[u] + a;
+  }
 }
 
 template <int FILL>
@@ -412,7 +446,7 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailHead T, const int* done) {
     for (int c = tid; c < L.n; c += TNT) {
       const int j0 = ro[c], j1 = ro[c + 1];
       if (j1 - j0 > AH) continue;
-      r[c] = b[c] - lds_row_sum(cl, w, x, j0, j1, c, x[c]);
+      r[c] = j1 > j0 ? b[c] - lds_row_sum(cl, w, x, j0, j1, x[c]) : b[c] - 0.0;
     }
     for (int h = wid; h < L.nh; h += NW) {
       const int c = hv[h], j0 = ro[c], j1 = ro[c + 1];
@@ -428,8 +462,7 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailHead T, const int* done) {
     const uint16_t *mo = u16(C.o_mo), *mem = u16(C.o_mem);
     double* bc = f64(C.o_b);
     for (int c = tid; c < C.n; c += TNT) {
-      double s = 0.0;
-      for (int i = mo[c]; i < mo[c + 1]; ++i) s += r[mem[i]];
+      const double s = lds_gather_sum(mem, r, mo[c], mo[c + 1]);
       if (coarsest) {
         bc[c] = pin[c] ? 0.0 : s;
       } else {
@@ -455,7 +488,7 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailHead T, const int* done) {
     if (c < n && part == 0) {
       const uint16_t *mo = u16(C.o_mo), *mem = u16(C.o_mem);
       double* xf = f64(lv[nl - 2].o_x);
-      for (int i = mo[c]; i < mo[c + 1]; ++i) xf[mem[i]] += T.corr * acc;
+      lds_scatter_add(mem, xf, mo[c], mo[c + 1], T.corr * acc);
     }
     __syncthreads();
   }
@@ -471,13 +504,13 @@ __global__ void __launch_bounds__(TNT) k_cy_tail(TailHead T, const int* done) {
       const int j0 = ro[c], j1 = ro[c + 1];
       if (j1 - j0 > AH) continue;
       const double xc = x[c];
-      const double acc = lds_row_sum(cl, w, x, j0, j1, c, xc);
+      const double acc = j1 > j0 ? lds_row_sum(cl, w, x, j0, j1, xc) : 0.0;
       const double e = dg[c];
       const double yc = e > 0 ? xc + AOMEGA * (b[c] - acc) / e : 0.0;
       if (k == 0) {
         T.yout[c] = yc;
       } else {
-        for (int i = mo[c]; i < mo[c + 1]; ++i) xf[mem[i]] += T.corr * yc;
+        lds_scatter_add(mem, xf, mo[c], mo[c + 1], T.corr * yc);
       }
     }
     for (int h = wid; h < L.nh; h += NW) {
