@@ -253,7 +253,7 @@ def digest_trace(workload, d):
                     f"{float(r['AverageNs']) / 1e3:,.2f} | {float(r['MinNs']) / 1e3:,.2f} | "
                     f"{float(r['MaxNs']) / 1e3:,.2f} | {100 * float(r['TotalDurationNs']) / tot:.1f}% |\n")
         f.write("\nbench.py line of the same run:\n\n    " + json.dumps({k: line[k] for k in (
-            "value", "unit", "ms_per_step", "stages_ms", "quot_iters", "roofline") if k in line}) + "\n")
+            "value", "unit", "ms_per_step", "stages_ms", "quot_iters", "quot_iters_refine", "roofline") if k in line}) + "\n")
     print(base)
 
 
@@ -476,8 +476,9 @@ def main():
     if mg:
         key = "multigrid"
         kernel = ("one multigrid-preconditioned PCG iteration of the large fill components (all of them at "
-                  "once, each with its own scalars): k_cy_down<1>, k_cy_restrict<1>, k_cy_up<1> on every level, "
-                  "k_cy_coarsest<1>, k_fs_rz, k_fs_scal1, k_fs_pq, k_fs_alpha, k_fs_xr, k_runsum_tile<1> and "
+                  "once, each with its own scalars): k_cy_down<1>, k_cy_restrict<1>, k_cy_up<1> on the levels above "
+                  "the tail, k_cy_tail<1> (the coarse levels and the exact coarsest solve in one workgroup, from "
+                  "LDS), k_fs_rz, k_fs_scal1, k_fs_pq, k_fs_alpha, k_fs_xr, k_runsum_tile<1> and "
                   "k_runsum_top<1> (three per-component sums)")
     else:
         key = f"{rep['fill_chunk']}:{rep['fill_split']}"
@@ -513,6 +514,7 @@ def main():
                              if mg else dict(tuned_schedule=dict(chunk_px=rep["fill_chunk"],
                                                                  launches_per_iteration=3 if rep["fill_split"] else 2)))),
                 quot_iters=rep["quot_iters"],
+                quot_iters_refine=rep["quot_iters_refine"],
                 roofline=roof)
     if warm is not None:
         line["warm_start"] = warm

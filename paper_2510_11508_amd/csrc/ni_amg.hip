@@ -1401,31 +1401,42 @@ struct Amg {
 Amg* amg_new() { return new Amg(); }
 void amg_free(Amg* a) { delete a; }
 int amg_levels(const Amg* a) { return a ? a->nlev : 0; }
+static int tail_start(const Amg* A, long long* img_bytes);
+
 // Algorithmic HBM bytes of one batched-fill PCG iteration on this
 // hierarchy (values FP64, indices int32; neighbour re-reads are cache hits
-// and not counted).  Per level l with n rows and e entries, below the
-// coarsest: down reads row_off, col, w, b, diag and writes r
-// (28 n + 12 e); restrict reads mem_off, mem, r and writes b' (12 n +
-// 12 n'); up reads row_off, col, w, b, diag, cid, y' and writes y (32 n +
-// 12 e + 8 n').  Coarsest: the inverse and two vectors (8 n^2 + 16 n).
-// Level 0 also, per node: comp read and one per-node term written by each
-// of the three per-component kernels (12 n each), the three run sums
-// reading key and term (36 n); on the rows of a system: r z reads r, z
-// (16 n_sys), (p, q) reads row_off, z, p, q and the entries and writes p, q
-// (44 n_sys + 12 e), the update reads x, r, p, q and writes x, r
-// (48 n_sys): 72 n + 12 e + 108 n_sys.
+// and not counted).  Per level l with n rows and e entries, above the
+// tail: down reads row_off, col, w, b, diag and writes r (28 n + 12 e);
+// restrict reads mem_off, mem, r and writes b' (12 n + 12 n'); up reads
+// row_off, col, ccol, w, b, diag, cid, y' and writes y (32 n + 16 e +
+// 8 n').  The tail reads its packed image, the inverse of the coarsest
+// and b, diag of its first level and writes y there (image + 8 n_c^2 +
+// 24 n).  Without a tail the coarsest reads the inverse and two vectors
+// (8 n^2 + 16 n).  Level 0 also, per node: comp read and one per-node term
+// written by each of the three per-component kernels (12 n each), the
+// three run sums reading key and term (36 n); on the rows of a system:
+// r z reads r, z (16 n_sys), (p, q) reads row_off, z, p, q and the
+// entries and writes p, q (44 n_sys + 12 e), the update reads x, r, p, q
+// and writes x, r (48 n_sys): 72 n + 12 e + 108 n_sys.
 double amg_fill_bytes(const Amg* A, long long n_sys) {
   if (!A || A->nlev <= 0) return 0.0;
   double by = 0.0;
+  long long img = 0;
+  const int t0 = tail_start(A, &img);
   for (int l = 0; l < A->nlev; ++l) {
     const AmgLevel* L = A->lv[l];
     const double n = L->n, e = 2.0 * L->np;
+    if (l == t0) {
+      const double nc = A->lv[A->nlev - 1]->n;
+      by += (double)img + 8.0 * nc * nc + 24.0 * n;
+      break;
+    }
     if (l == A->nlev - 1) {
       by += A->dense ? 8.0 * n * n + 16.0 * n : 60.0 * n + 24.0 * e;
       break;
     }
     const double nc = A->lv[l + 1]->n;
-    by += 28.0 * n + 12.0 * e + 12.0 * n + 12.0 * nc + 32.0 * n + 12.0 * e + 8.0 * nc;
+    by += 28.0 * n + 12.0 * e + 12.0 * n + 12.0 * nc + 32.0 * n + 16.0 * e + 8.0 * nc;
   }
   const AmgLevel* L0 = A->lv[0];
   by += 72.0 * L0->n + 12.0 * 2.0 * L0->np + 108.0 * (double)n_sys;
@@ -1889,15 +1900,22 @@ static long long tail_layout(const Amg* A, int t0, TailPlan* T, long long* img_b
 // still fits in TAIL_LDS (and is not the finest).  Packs the image (img:
 // at least TAIL_LDS bytes) on st.  Returns t0, or -1 for no tail (no
 // exact coarsest, or not even one smoothed level fits).
-static int plan_tail(const Amg* A, const std::vector<ALev>& V, unsigned char* img, TailPlan& T, hipStream_t st) {
-  if (!A->dense || A->nlev < 3 || !img) return -1;
+static int tail_start(const Amg* A, long long* img_bytes) {
+  if (!A->dense || A->nlev < 3) return -1;
   int t0 = -1;
   long long ib = 0;
   for (int t = A->nlev - 2; t >= 1 && A->nlev - t <= TMAXL; --t) {
     const long long by = tail_layout(A, t, nullptr, &ib);
     if (by < 0 || by > TAIL_LDS) break;
     t0 = t;
+    *img_bytes = ib;
   }
+  return t0;
+}
+
+static int plan_tail(const Amg* A, const std::vector<ALev>& V, unsigned char* img, TailPlan& T, hipStream_t st) {
+  long long ib = 0;
+  const int t0 = img ? tail_start(A, &ib) : -1;
   if (t0 < 0) return -1;
   tail_layout(A, t0, &T, &ib);
   T.nl = A->nlev - t0;
