@@ -269,10 +269,10 @@ __global__ void __launch_bounds__(ANT) k_cy_up(ALev L, const double* __restrict_
 // kernels per level).  From level t0 on, every level (the coarsest
 // included) is copied into LDS at the start of one kernel, and the down
 // sweep, the restrictions, the exact coarsest solve and the up sweep run
-// there between barriers.  The arithmetic is that of the per-level
-// kernels; rows with more than AH entries are summed by a wavefront
-// (lanes strided over the entries, then the butterfly) instead of a block,
-// and aggregates of any size in order.  The prolongation is a scatter:
+// there between barriers.  Rows of at most AH entries are summed in the
+// order of the per-level kernels; longer rows by a wavefront (lanes
+// strided over the entries, then the butterfly) instead of a block, and
+// aggregates of any size in member order.  The prolongation is a scatter:
 // each coarse node adds its correction to the x of its members.
 constexpr int TNT = 1024;              // threads of the tail workgroup
 constexpr int TMAXL = 10;              // tail levels at most
