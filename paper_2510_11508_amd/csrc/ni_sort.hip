@@ -153,39 +153,86 @@ __global__ void __launch_bounds__(RS_NT) k_rs_scatter(const uint32_t* __restrict
 }
 
 // ------------------------------------------------------------ small sort
-// Up to SB_N pairs in one workgroup: a bitonic sort in LDS of (masked key,
+// Up to SB_N pairs in one workgroup: a bitonic sort of (masked key,
 // position) composites, which are distinct, so the result is the stable
 // order of the radix passes below, in one launch instead of four per pass.
-constexpr int SB_N = 4096, SB_NT = 1024;
+// Element i = t + k * SB_NT is held in register k of thread t.  A
+// compare-exchange partner at distance j is in the same thread for
+// j >= SB_NT, in the same wavefront for j < 64 (exchanged by shuffles) and
+// in another wavefront otherwise (exchanged through LDS, between barriers).
+constexpr int SB_N = 4096, SB_NT = 1024, SB_E = SB_N / SB_NT;
+
+// the element kept at position i of the pair (i, i ^ j) inside a bitonic
+// block of size kk: the smaller on the ascending side
+__device__ __forceinline__ unsigned long long sb_keep(unsigned long long mine, unsigned long long other, int i, int j,
+                                                      int kk) {
+  const bool asc = (i & kk) == 0;
+  const bool low = (i & j) == 0;
+  const unsigned long long lo = mine < other ? mine : other, hi = mine < other ? other : mine;
+  return (asc == low) ? lo : hi;
+}
 
 __global__ void __launch_bounds__(SB_NT) k_sort_small(const uint32_t* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin, int n, uint32_t mask,
                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ unsigned long long a[SB_N];
+  __shared__ unsigned long long sh[SB_N];
+  const int t = threadIdx.x;
   int m = 1;
   while (m < n) m <<= 1;
-  for (int i = threadIdx.x; i < m; i += SB_NT)
-    a[i] = i < n ? (((unsigned long long)(kin[i] & mask) << 32) | (unsigned long long)i) : ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= m; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < m; i += SB_NT) {
-        const int p = i ^ j;
-        if (p > i) {
-          const unsigned long long x = a[i], y = a[p];
-          if ((x > y) == ((i & k) == 0)) {
-            a[i] = y;
-            a[p] = x;
+  const int E = m > SB_NT ? m / SB_NT : 1;  // registers that hold elements below m
+  unsigned long long a[SB_E];
+#pragma unroll
+  for (int k = 0; k < SB_E; ++k) {
+    const int i = t + k * SB_NT;
+    a[k] = i < n ? (((unsigned long long)(kin[i] & mask) << 32) | (unsigned long long)i) : ~0ull;
+  }
+  for (int kk = 2; kk <= m; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= SB_NT) {
+        // partners in the same thread: registers k and k ^ (j / SB_NT)
+        auto cx = [&](unsigned long long& x, unsigned long long& y, int k, int k2) {
+          const unsigned long long u = x, v = y;
+          x = sb_keep(u, v, t + k * SB_NT, j, kk);
+          y = sb_keep(v, u, t + k2 * SB_NT, j, kk);
+        };
+        static_assert(SB_E == 4, "register pairs below are written for four elements per thread");
+        if (j == SB_NT) {
+          cx(a[0], a[1], 0, 1);
+          if (E > 2) cx(a[2], a[3], 2, 3);
+        } else {
+          cx(a[0], a[2], 0, 2);
+          cx(a[1], a[3], 1, 3);
+        }
+      } else if (j < 64) {
+#pragma unroll
+        for (int k = 0; k < SB_E; ++k) {
+          if (k < E) {
+            const unsigned long long o = __shfl_xor(a[k], j, 64);
+            a[k] = sb_keep(a[k], o, t + k * SB_NT, j, kk);
           }
         }
+      } else {
+#pragma unroll
+        for (int k = 0; k < SB_E; ++k)
+          if (k < E) sh[t + k * SB_NT] = a[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SB_E; ++k) {
+          const int i = t + k * SB_NT;
+          if (k < E) a[k] = sb_keep(a[k], sh[i ^ j], i, j, kk);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < n; i += SB_NT) {
-    const uint32_t pos = (uint32_t)(a[i] & 0xffffffffull);
-    kout[i] = kin[pos];
-    vout[i] = vin[pos];
+#pragma unroll
+  for (int k = 0; k < SB_E; ++k) {
+    const int i = t + k * SB_NT;
+    if (i < n) {
+      const uint32_t pos = (uint32_t)(a[k] & 0xffffffffull);
+      kout[i] = kin[pos];
+      vout[i] = vin[pos];
+    }
   }
 }
 
