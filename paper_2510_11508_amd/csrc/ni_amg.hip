@@ -350,31 +350,21 @@ __global__ void k_tail_pack(TailPlan T) {
   }
 }
 
-// LDS loops of the tail, eight independent loads in flight per step:
-// indices past the end are clamped to the last element (in bounds, its
-// term discarded), so the loads need no branches.
-// Sum over the entries j0 <= j < j1 of w_j (xc - x[col_j]), in entry order
-// (the order of row_diff_sum on a regular row); j0 < j1.
+// LDS loops of the tail.  Sum over the entries j0 <= j < j1 of
+// w_j (xc - x[col_j]), in entry order (the order of row_diff_sum on a
+// regular row).  A plain loop: in a synthetic one-workgroup phase of 889
+// rows it took 1.1 us against 1.8 us for eight predicated loads per step;
+// in the tail itself the two are within the noise.
 __device__ __forceinline__ double lds_row_sum(const uint16_t* cl, const double* w, const double* x, int j0, int j1,
                                               double xc) {
   double acc = 0.0;
-  for (int base = j0; base < j1; base += 8) {
-    int d[8];
-    double q[8], v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = min(base + u, j1 - 1);
-      d[u] = cl[j];
-      q[u] = base + u < j1 ? w[j] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = x[d[u]];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc += q[u] * (xc - v[u]);
-  }
+  for (int j = j0; j < j1; ++j) acc += w[j] * (xc - x[cl[j]]);
   return acc;
 }
 
+// The member loops keep eight independent loads in flight per step:
+// indices past the end are clamped to the last element (in bounds, its
+// term discarded), so the loads need no branches.
 // sum of v[mem[i]] over i0 <= i < i1, in order
 __device__ __forceinline__ double lds_gather_sum(const uint16_t* mem, const double* v, int i0, int i1) {
   double s = 0.0;
